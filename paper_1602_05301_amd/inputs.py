@@ -1,0 +1,215 @@
+"""Seeded synthetic workloads: curve discretisations, targets and densities.
+
+This module is shared by the oracle's tests, the GPU tests and the benchmark.
+It holds none of the method's arithmetic (no kernels, expansions or Bessel
+functions): it only produces the inputs that the paper's problem statement
+takes, i.e. Gauss-Legendre panel nodes on a closed curve with their arclength
+weights, outward unit normals and panel lengths (Sec. 2.2, "Geometry
+discretization"), one QBX centre per node at distance h_k/2 along the normal
+(Sec. 2.2), targets, and complex densities.
+
+Conventions
+-----------
+* A curve is traversed counter-clockwise; the outward normal is the unit
+  tangent rotated by -90 degrees.
+* Panels are equal intervals of the curve parameter theta; each carries q
+  Gauss-Legendre nodes in theta.  The weight of node j on panel k is
+  w_j^GL * (dtheta/2) * |gamma'(theta_j)|, so that sum_j w_j f(s_j) is the
+  composite Gauss rule for the arclength integral.  The panel length h_k is
+  the sum of its weights.
+* Seeds: ``np.random.default_rng([workload_id, purpose])`` with purpose
+  0 = geometry, 1 = targets, 2 = densities.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PURPOSE_GEOMETRY = 0
+PURPOSE_TARGETS = 1
+PURPOSE_DENSITY = 2
+
+
+def rng_for(workload_id: int, purpose: int) -> np.random.Generator:
+    return np.random.default_rng([int(workload_id), int(purpose)])
+
+
+@dataclass
+class Geometry:
+    """Discretised closed curve(s) with one QBX centre per node.
+
+    Arrays are float64 of length n (nodes = sources = centres)."""
+
+    sx: np.ndarray
+    sy: np.ndarray
+    w: np.ndarray        # arclength quadrature weights w_{j,k}
+    nx: np.ndarray
+    ny: np.ndarray
+    h: np.ndarray        # length of the panel each node belongs to
+    cx: np.ndarray       # QBX centre  s + (h/2) n
+    cy: np.ndarray
+    cr: np.ndarray       # expansion radius h/2
+    panel: np.ndarray    # panel index of each node (int64)
+    q: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.sx.size)
+
+
+def _gl(q: int):
+    x, wq = np.polynomial.legendre.leggauss(q)
+    return x, wq
+
+
+def _panelize(theta_edges, q, gamma, dgamma):
+    """Gauss-Legendre nodes in theta on each interval of ``theta_edges``."""
+    x, wq = _gl(q)
+    a = theta_edges[:-1][:, None]
+    b = theta_edges[1:][:, None]
+    half = 0.5 * (b - a)
+    th = (0.5 * (a + b) + half * x[None, :]).ravel()
+    px, py = gamma(th)
+    dx, dy = dgamma(th)
+    speed = np.hypot(dx, dy)
+    w = (wq[None, :] * half).ravel() * speed
+    npan = theta_edges.size - 1
+    h = w.reshape(npan, q).sum(axis=1)
+    nx = dy / speed
+    ny = -dx / speed
+    panel = np.repeat(np.arange(npan, dtype=np.int64), q)
+    return px, py, w, nx, ny, np.repeat(h, q), panel
+
+
+def _finish(px, py, w, nx, ny, h, panel, q, meta) -> Geometry:
+    r = 0.5 * h
+    return Geometry(sx=px, sy=py, w=w, nx=nx, ny=ny, h=h,
+                    cx=px + r * nx, cy=py + r * ny, cr=r, panel=panel, q=q,
+                    meta=meta)
+
+
+def star(n_panels: int, q: int = 16, lobes: int = 5, amp: float = 0.3,
+         radius: float = 1.0, center=(0.0, 0.0), rotation: float = 0.0) -> Geometry:
+    """Star curve r(theta) = radius*(1 + amp*cos(lobes*theta)), equal-theta panels."""
+    c0, s0 = np.cos(rotation), np.sin(rotation)
+
+    def gamma(t):
+        r = radius * (1.0 + amp * np.cos(lobes * t))
+        x, y = r * np.cos(t), r * np.sin(t)
+        return center[0] + c0 * x - s0 * y, center[1] + s0 * x + c0 * y
+
+    def dgamma(t):
+        r = radius * (1.0 + amp * np.cos(lobes * t))
+        dr = -radius * amp * lobes * np.sin(lobes * t)
+        x = dr * np.cos(t) - r * np.sin(t)
+        y = dr * np.sin(t) + r * np.cos(t)
+        return c0 * x - s0 * y, s0 * x + c0 * y
+
+    edges = np.linspace(0.0, 2.0 * np.pi, n_panels + 1)
+    out = _panelize(edges, q, gamma, dgamma)
+    return _finish(*out, q, dict(kind="star", lobes=lobes, amp=amp, radius=radius,
+                                  n_panels=n_panels))
+
+
+def ellipse(n_panels: int, q: int = 16, a: float = 1.0, b: float = 0.5,
+            center=(0.0, 0.0), rotation: float = 0.0) -> Geometry:
+    c0, s0 = np.cos(rotation), np.sin(rotation)
+
+    def gamma(t):
+        x, y = a * np.cos(t), b * np.sin(t)
+        return center[0] + c0 * x - s0 * y, center[1] + s0 * x + c0 * y
+
+    def dgamma(t):
+        x, y = -a * np.sin(t), b * np.cos(t)
+        return c0 * x - s0 * y, s0 * x + c0 * y
+
+    edges = np.linspace(0.0, 2.0 * np.pi, n_panels + 1)
+    out = _panelize(edges, q, gamma, dgamma)
+    return _finish(*out, q, dict(kind="ellipse", a=a, b=b, n_panels=n_panels))
+
+
+def circle(n_panels: int, q: int = 16, radius: float = 1.0) -> Geometry:
+    return star(n_panels, q, lobes=1, amp=0.0, radius=radius)
+
+
+def concat(geoms) -> Geometry:
+    """Several disjoint curves as one discretisation (panel ids renumbered)."""
+    off = 0
+    panels = []
+    for g in geoms:
+        panels.append(g.panel + off)
+        off += int(g.panel.max()) + 1
+    cat = lambda name: np.concatenate([getattr(g, name) for g in geoms])
+    return Geometry(sx=cat("sx"), sy=cat("sy"), w=cat("w"), nx=cat("nx"),
+                    ny=cat("ny"), h=cat("h"), cx=cat("cx"), cy=cat("cy"),
+                    cr=cat("cr"), panel=np.concatenate(panels), q=geoms[0].q,
+                    meta=dict(kind="multi", parts=[g.meta for g in geoms]))
+
+
+def annulus_targets(rng: np.random.Generator, n: int, r_in: float, r_out: float):
+    """Area-uniform points in r_in < |x| < r_out."""
+    rho = np.sqrt(rng.uniform(r_in ** 2, r_out ** 2, size=n))
+    th = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    return rho * np.cos(th), rho * np.sin(th)
+
+
+def complex_gaussian(rng: np.random.Generator, shape) -> np.ndarray:
+    """iid N(0,1) real and imaginary parts."""
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------------------
+# The named workloads.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    geom: Geometry
+    omega: float
+    p: int
+    eps: float
+    tx: np.ndarray
+    ty: np.ndarray
+    tgt_ctr: np.ndarray      # explicit centre per target, -1 = let the library decide
+    sigma_s: np.ndarray      # [n_dens][n] complex128
+    sigma_d: np.ndarray
+    leaf_max: int = 32
+    direct: bool = False
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_dens(self) -> int:
+        return int(self.sigma_s.shape[0])
+
+
+def direct_star512(n_dens: int = 1, n_annulus: int = 1024) -> Workload:
+    """Direct QBX on the 5-lobe star: 32 panels x 16 nodes, p = 12, omega = 10,
+    512 on-surface targets (own centre) + area-uniform annulus targets."""
+    wid = 0
+    g = star(32, 16, lobes=5, amp=0.3)
+    tx_a, ty_a = annulus_targets(rng_for(wid, PURPOSE_TARGETS), n_annulus, 1.4, 2.0)
+    tx = np.concatenate([g.sx, tx_a])
+    ty = np.concatenate([g.sy, ty_a])
+    tgt_ctr = np.concatenate([np.arange(g.n, dtype=np.int32),
+                              -np.ones(n_annulus, dtype=np.int32)])
+    r = rng_for(wid, PURPOSE_DENSITY)
+    ss = complex_gaussian(r, (n_dens, g.n))
+    sd = complex_gaussian(r, (n_dens, g.n))
+    return Workload("direct_star5_512", g, 10.0, 12, 1e-10, tx, ty, tgt_ctr, ss, sd,
+                    direct=True)
+
+
+def fmm_star(n_panels: int = 2048, n_dens: int = 1, omega: float = 50.0,
+             eps: float = 1e-10, p: int = 14, lobes: int = 7, leaf_max: int = 32,
+             workload_id: int = 1) -> Workload:
+    """QBX-FMM on the 7-lobe star with on-surface targets (own centres).
+    Defaults: 2048 panels x 16 nodes = 32768 sources = centres = targets."""
+    g = star(n_panels, 16, lobes=lobes, amp=0.3)
+    r = rng_for(workload_id, PURPOSE_DENSITY)
+    ss = complex_gaussian(r, (n_dens, g.n))
+    sd = complex_gaussian(r, (n_dens, g.n))
+    return Workload(f"fmm_star{lobes}_{g.n}", g, omega, p, eps, g.sx.copy(), g.sy.copy(),
+                    np.arange(g.n, dtype=np.int32), ss, sd, leaf_max=leaf_max)
