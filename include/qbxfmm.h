@@ -1,0 +1,180 @@
+/*
+ * qbxfmm: FMM-accelerated Global QBX for 2D Helmholtz single- and
+ * double-layer potentials on MI355X (gfx950).
+ *
+ * Method: Rachh, Kloeckner, O'Neil, "Fast algorithms for Quadrature by
+ * Expansion I: Globally valid expansions".  For a curve discretised by
+ * Gauss-Legendre panels (Sec. 2.2) with one QBX centre per node, the library
+ * evaluates
+ *
+ *     u(t) = S[sigma_s](t) + D[sigma_d](t),
+ *     S[s](t) = sum_j (i/4) w_j H0(omega |t - s_j|) s_j        (Sec. 1, 3.2)
+ *     D[s](t) = sum_j (i/4) w_j d/dn_j H0(omega |t - s_j|) s_j
+ *
+ * with QBX (Sec. 2.1, eqs. (jexp), (graf-coefficient), (phiapprox)) at every
+ * target associated with a centre and the plain Gauss rule elsewhere
+ * (Sec. 3.2, eq. (gauss-layerpot)).  QBX coefficients are formed either
+ * directly over all sources, or by the FMM of Sec. 7.2 (Stages 1-8 with the
+ * QBX additions P2QBXL, M2QBXL and L2QBXL).  Centres lie on the exterior
+ * side, so on-curve targets receive the exterior one-sided limits (Sec. 2,
+ * eq. (oneside)); no jump term is added.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - All functions are extern "C", never throw, and return a qbx_status.  On
+ *   failure qbx_last_error() returns a message for the calling thread.
+ * - Geometry arrays (qbx_plan_create, qbx_geom_create) are HOST pointers to
+ *   float64 arrays; the library copies what it needs.  The caller keeps
+ *   ownership.
+ * - Density, potential and coefficient arrays of qbx_eval are DEVICE
+ *   pointers (HBM of the context's device) to complex128 data, i.e.
+ *   interleaved (re, im) float64.  They are read and written asynchronously
+ *   on the context's stream; the caller synchronises that stream before
+ *   reading the results on the host.
+ * - Indices are 0-based; counts are int64_t.
+ */
+#ifndef QBXFMM_H
+#define QBXFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QBX_ABI_VERSION 1
+
+typedef enum {
+    QBX_OK = 0,
+    QBX_E_INVAL = -1,        /* invalid argument (size, non-finite value, range) */
+    QBX_E_NOMEM = -2,        /* host or device allocation failed */
+    QBX_E_DEVICE = -3,       /* a HIP call failed (no device, launch error) */
+    QBX_E_ASSOC = -4,        /* a target in Gamma_near has no eligible centre (Sec. 6.1) */
+    QBX_E_UNSUPPORTED = -5   /* valid request outside what this build implements */
+} qbx_status;
+
+typedef struct qbx_ctx_s *qbx_ctx;    /* device + stream */
+typedef struct qbx_plan_s *qbx_plan;  /* host-side tree, lists, orders, association */
+typedef struct qbx_geom_s *qbx_geom;  /* device-resident plan + translation tables */
+
+typedef struct {
+    int32_t p;            /* QBX expansion order (Sec. 2.1, eq. (phiapprox)); 0..40 */
+    int32_t p_add;        /* FMM order increment (Sec. 7.1, Table p_add); -1 = default rule */
+    int32_t leaf_max;     /* n_max: split a box holding more sources + centres (Stage 1) */
+    int32_t direct;       /* 1 = form QBX coefficients directly over all sources (no FMM) */
+    int32_t far_fp32;     /* reserved: FP32 far field; must be 0 in this build */
+    int32_t reserved;
+    double eps_assoc;     /* association slack epsilon_assoc (Sec. 6.1); default 0.05 */
+} qbx_options;
+
+typedef struct {
+    int64_t n_src, n_ctr, n_tgt;
+    int32_t n_levels;     /* levels 0 .. n_levels-1 */
+    int32_t n_boxes, n_leaves;
+    int32_t p, p_add;
+    int64_t n_u_pairs, n_v_pairs, n_w_pairs, n_x_pairs;  /* box-box list entries */
+    int64_t n_p2qbxl_pairs;   /* (centre, source) pairs over U lists */
+    int64_t n_m2qbxl_pairs;   /* (centre, W-box) pairs */
+    int64_t n_x_src_pairs;    /* (box, source) pairs over X lists */
+    int64_t n_smooth_targets; /* targets served by the smooth rule */
+    double root_radius;       /* |b0| (half the side of the root square) */
+    size_t device_bytes;      /* resident device footprint of the geometry */
+} qbx_stats;
+
+enum { QBX_LIST_U = 0, QBX_LIST_V = 1, QBX_LIST_W = 2, QBX_LIST_X = 3 };
+
+int32_t qbx_abi_version(void);
+const char *qbx_last_error(void);
+void qbx_options_default(qbx_options *opt);
+
+/* ---- context ------------------------------------------------------------
+ * qbx_ctx_create: bind a device and a HIP stream (hipStream_t passed as
+ * void*; NULL = the null stream).  Errors: QBX_E_DEVICE if the device cannot
+ * be set. */
+qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out);
+qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream);
+qbx_status qbx_ctx_destroy(qbx_ctx ctx);
+
+/* ---- host planning (no GPU needed) ---------------------------------------
+ * qbx_plan_create builds, on the host:
+ *  - the adaptive quadtree over sources and centres (Sec. 4; Sec. 7.2,
+ *    Stage 1): root = smallest origin-centred square holding all sources and
+ *    centres (enlarged by a relative 1e-12), split while a box holds more
+ *    than leaf_max sources + centres;
+ *  - the U, V, W, X lists (Sec. 7.2 definitions);
+ *  - FMM orders P_l = p_FMM(l) + p_add, with p_FMM(l) the smallest P such
+ *    that |H_n(3 omega R_l) J_n(sqrt(2) omega R_l)| <= eps for all n > P,
+ *    R_l the box radius at level l (Sec. 7.1);
+ *  - target association (Sec. 6.1): for targets with tgt_ctr[m] == -1 (or
+ *    every target when tgt_ctr is NULL) the nearest centre i with
+ *    |t - c_i| <= cr_i (1 + eps_assoc), ties to the lowest index; with no
+ *    such centre a target within sh_j/4 of a source j fails (QBX_E_ASSOC),
+ *    any other is served by the smooth rule.  tgt_ctr[m] >= 0 fixes target
+ *    m to that centre (e.g. on-curve nodes and their own centres).
+ * Arguments: sources (sx, sy) with full arclength weights w, outward unit
+ * normals (nx, ny) and the length sh of the panel each source lies on;
+ * centres (cx, cy) with expansion radii cr; targets (tx, ty).  Sources and
+ * centres may be different point sets (oversampled sources, Sec. 2.2).
+ * Errors: QBX_E_INVAL (n < 0, non-finite input, cr <= 0, w < 0, |n| not 1
+ * within 1e-6, omega <= 0, eps outside [1e-15, 1e-2], p outside 0..40,
+ * leaf_max < 1, far_fp32 != 0), QBX_E_ASSOC, QBX_E_NOMEM. */
+qbx_status qbx_plan_create(double omega, double eps, const qbx_options *opt,
+                           int64_t n_src, const double *sx, const double *sy,
+                           const double *w, const double *nx, const double *ny,
+                           const double *sh,
+                           int64_t n_ctr, const double *cx, const double *cy,
+                           const double *cr,
+                           int64_t n_tgt, const double *tx, const double *ty,
+                           const int32_t *tgt_ctr, qbx_plan *out);
+qbx_status qbx_plan_destroy(qbx_plan plan);
+qbx_status qbx_plan_stats(qbx_plan plan, qbx_stats *out);
+/* Boxes in (level, Morton) order: level, integer index (ix, iy) at that
+ * level, parent (-1 for the root), leaf flag, source and centre counts.
+ * Each array holds n_boxes entries; any pointer may be NULL. */
+qbx_status qbx_plan_boxes(qbx_plan plan, int32_t *level, int32_t *ix, int32_t *iy,
+                          int32_t *parent, int32_t *leaf, int32_t *n_src_in,
+                          int32_t *n_ctr_in);
+/* One list in CSR form: start[n_boxes + 1], idx[start[n_boxes]] (box
+ * indices, ascending within a box).  which = QBX_LIST_U/V/W/X.  With idx
+ * NULL only start is written. */
+qbx_status qbx_plan_list(qbx_plan plan, int32_t which, int32_t *start, int32_t *idx);
+/* FMM order P_l per level (n_levels entries). */
+qbx_status qbx_plan_orders(qbx_plan plan, int32_t *P);
+/* Centre index per target (user numbering) or -1 for the smooth rule. */
+qbx_status qbx_plan_association(qbx_plan plan, int32_t *tgt_ctr_out);
+
+/* ---- device geometry -----------------------------------------------------
+ * qbx_geom_create = qbx_plan_create + upload to the context's device of the
+ * sorted points, tree, lists and translation tables; they stay resident
+ * until qbx_geom_destroy.  Same arguments and errors as qbx_plan_create,
+ * plus QBX_E_DEVICE / QBX_E_NOMEM for device failures. */
+qbx_status qbx_geom_create(qbx_ctx ctx, double omega, double eps, const qbx_options *opt,
+                           int64_t n_src, const double *sx, const double *sy,
+                           const double *w, const double *nx, const double *ny,
+                           const double *sh,
+                           int64_t n_ctr, const double *cx, const double *cy,
+                           const double *cr,
+                           int64_t n_tgt, const double *tx, const double *ty,
+                           const int32_t *tgt_ctr, qbx_geom *out);
+qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out);
+qbx_status qbx_geom_destroy(qbx_geom geom);
+qbx_status qbx_geom_stats(qbx_geom geom, qbx_stats *out);
+qbx_status qbx_geom_association(qbx_geom geom, int32_t *tgt_ctr_out);
+
+/* ---- evaluation ----------------------------------------------------------
+ * u[d][m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m) for d < n_dens, m < n_tgt.
+ * sigma_s, sigma_d: device complex128 [n_dens][n_src] (either may be NULL,
+ * meaning zero density); u: device complex128 [n_dens][n_tgt]; coef:
+ * optional device complex128 [n_dens][2p+1][n_ctr] receiving the QBX
+ * coefficients alpha_l (paper's convention, l = -p..p) per centre.
+ * Work is enqueued on the context's stream; scratch device memory is owned
+ * by the geometry and grows to fit n_dens.  Errors: QBX_E_INVAL (n_dens < 1
+ * or > 64, u NULL, both densities NULL), QBX_E_DEVICE, QBX_E_NOMEM. */
+qbx_status qbx_eval(qbx_geom geom, int32_t n_dens, const void *sigma_s,
+                    const void *sigma_d, void *u, void *coef);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -39,8 +39,9 @@ def root_radius(*coords) -> float:
 
 
 def build(sx, sy, cx, cy, n_max):
-    """Returns dict(R0, level, ix, iy, parent, leaf, nsrc, nctr) with boxes
-    ordered by (level, Morton order of (ix, iy))."""
+    """Returns dict(R0, level, ix, iy, parent, leaf, nsrc, nctr, src, ctr) with
+    boxes ordered by (level, Morton order of (ix, iy)); src / ctr hold the
+    source and centre indices inside each box."""
     sx, sy, cx, cy = (np.asarray(a, dtype=np.float64) for a in (sx, sy, cx, cy))
     R0 = root_radius(sx, sy, cx, cy)
     px = np.concatenate([sx, cx])
@@ -84,6 +85,9 @@ def build(sx, sy, cx, cy, n_max):
     res["leaf"] = np.array([b not in has_child for b in order], dtype=bool)
     res["nsrc"] = np.array([int(is_src[members[b]].sum()) for b in order], dtype=np.int64)
     res["nctr"] = np.array([int((~is_src[members[b]]).sum()) for b in order], dtype=np.int64)
+    ns = sx.size
+    res["src"] = [np.sort(members[b][is_src[members[b]]]) for b in order]
+    res["ctr"] = [np.sort(members[b][~is_src[members[b]]] - ns) for b in order]
     return res
 
 

@@ -1,0 +1,409 @@
+// Device part of the C ABI: contexts, resident geometries and evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "abi_common.hpp"
+#include "kernels.hpp"
+
+using namespace qbx;
+
+struct qbx_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+constexpr int kDensChunk = 4;   // densities per pass through the pipeline
+
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    hipError_t err = hipSuccess;
+    template <class T>
+    T *upload(const std::vector<T> &v)
+    {
+        if (err != hipSuccess) return nullptr;
+        size_t n = std::max<size_t>(v.size(), 1) * sizeof(T);
+        void *p = nullptr;
+        err = hipMalloc(&p, n);
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        bytes += n;
+        if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        return static_cast<T *>(p);
+    }
+    void *alloc(size_t n)
+    {
+        if (err != hipSuccess) return nullptr;
+        void *p = nullptr;
+        err = hipMalloc(&p, std::max<size_t>(n, 16));
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        bytes += n;
+        return p;
+    }
+    void release()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+struct WorkList {
+    int *d = nullptr;
+    int n = 0;
+    int Pmax = 0;
+};
+
+}  // namespace
+
+struct qbx_geom_s {
+    qbx_ctx ctx = nullptr;
+    Plan pl;
+    DevGeom g{};
+    DeviceArena arena;
+    WorkList p2m, xl, qbx, wl, l2q;
+    long long total_coef = 0;     // sum over boxes of (2 P_l + 1)
+    // per-eval scratch, sized for kDensChunk densities
+    DeviceArena scratch;
+    cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
+};
+
+namespace {
+
+template <class F>
+WorkList make_list(DeviceArena &ar, const Plan &pl, F pred)
+{
+    std::vector<int> v;
+    WorkList w;
+    for (int b = 0; b < pl.n_boxes(); ++b)
+        if (pred(b)) {
+            v.push_back(b);
+            w.Pmax = std::max(w.Pmax, pl.P[pl.lev[b]]);
+        }
+    w.n = (int)v.size();
+    w.d = ar.upload(v);
+    return w;
+}
+
+qbx_status upload(qbx_geom_s *G)
+{
+    const Plan &pl = G->pl;
+    DeviceArena &ar = G->arena;
+    DevGeom &g = G->g;
+    int nb = pl.n_boxes();
+    g.ns = (int)pl.ns; g.nc = (int)pl.nc; g.nt = (int)pl.nt; g.nb = nb; g.nlev = pl.nlev;
+    g.p = pl.p; g.omega = pl.omega;
+
+    std::vector<double> a(pl.ns), bq(pl.ns), c(pl.ns), d(pl.ns), e(pl.ns);
+    std::vector<int> perm(pl.ns);
+    for (int64_t j = 0; j < pl.ns; ++j) {
+        int64_t u = pl.src_order[j];
+        a[j] = pl.sx[u]; bq[j] = pl.sy[u]; c[j] = pl.w[u]; d[j] = pl.nx[u]; e[j] = pl.ny[u];
+        perm[j] = (int)u;
+    }
+    g.sx = ar.upload(a); g.sy = ar.upload(bq); g.sw = ar.upload(c); g.snx = ar.upload(d); g.sny = ar.upload(e);
+    g.src_perm = ar.upload(perm);
+
+    std::vector<double> ccx(pl.nc), ccy(pl.nc);
+    std::vector<int> cperm(pl.nc), rank(pl.nc);
+    for (int64_t i = 0; i < pl.nc; ++i) {
+        int64_t u = pl.ctr_order[i];
+        ccx[i] = pl.cx[u]; ccy[i] = pl.cy[u]; cperm[i] = (int)u; rank[u] = (int)i;
+    }
+    g.cx = ar.upload(ccx); g.cy = ar.upload(ccy); g.ctr_perm = ar.upload(cperm);
+
+    std::vector<int> tcs(pl.nt), smooth;
+    for (int64_t m = 0; m < pl.nt; ++m) {
+        int v = pl.tgt_ctr[m];
+        tcs[m] = v >= 0 ? rank[v] : -1;
+        if (v < 0) smooth.push_back((int)m);
+    }
+    g.tx = ar.upload(pl.tx); g.ty = ar.upload(pl.ty); g.tgt_cs = ar.upload(tcs);
+    g.smooth_list = ar.upload(smooth);
+    g.n_smooth = (int)smooth.size();
+
+    std::vector<double> bcx(nb), bcy(nb);
+    for (int b = 0; b < nb; ++b) pl.box_center(b, &bcx[b], &bcy[b]);
+    g.bcx = ar.upload(bcx); g.bcy = ar.upload(bcy);
+    g.blev = ar.upload(pl.lev); g.leaf = ar.upload(pl.leaf); g.parent = ar.upload(pl.parent);
+    g.child_begin = ar.upload(pl.child_begin); g.child_count = ar.upload(pl.child_count);
+    g.src_begin = ar.upload(pl.src_begin); g.src_end = ar.upload(pl.src_end);
+    g.ctr_begin = ar.upload(pl.ctr_begin); g.ctr_end = ar.upload(pl.ctr_end);
+    g.level_start = ar.upload(pl.level_start);
+    g.U_start = ar.upload(pl.U_start); g.U_idx = ar.upload(pl.U_idx);
+    g.V_start = ar.upload(pl.V_start); g.V_idx = ar.upload(pl.V_idx); g.V_off = ar.upload(pl.V_off);
+    g.W_start = ar.upload(pl.W_start); g.W_idx = ar.upload(pl.W_idx);
+    g.X_start = ar.upload(pl.X_start); g.X_idx = ar.upload(pl.X_idx);
+    g.Plev = ar.upload(pl.P);
+
+    std::vector<int> woff(pl.nlev + 1, 0);
+    std::vector<double> W, iW, lW;
+    for (int l = 0; l < pl.nlev; ++l) {
+        woff[l] = (int)W.size();
+        auto s = level_scales(pl.omega, pl.box_radius(l), pl.P[l]);
+        for (double v : s) { W.push_back(v); iW.push_back(1.0 / v); lW.push_back(std::log(v)); }
+    }
+    woff[pl.nlev] = (int)W.size();
+    g.Woff = ar.upload(woff); g.Wtab = ar.upload(W); g.invW = ar.upload(iW); g.logW = ar.upload(lW);
+
+    std::vector<long long> boff(nb);
+    long long tot = 0;
+    for (int b = 0; b < nb; ++b) { boff[b] = tot; tot += 2 * pl.P[pl.lev[b]] + 1; }
+    G->total_coef = tot;
+    g.box_off = ar.upload(boff);
+
+    // translation tables, [in][out] (column of the scaled matrix per input index)
+    std::vector<cd> m2m, l2l, m2l;
+    std::vector<long long> m2m_off(4 * (size_t)std::max(pl.nlev, 1), -1),
+        l2l_off(4 * (size_t)std::max(pl.nlev, 1), -1), m2l_off(40 * (size_t)std::max(pl.nlev, 1), -1);
+    auto append_T = [](std::vector<cd> &dst, const std::vector<std::complex<double>> &T, int nout,
+                       int nin) {
+        long long off = (long long)dst.size();
+        dst.resize(dst.size() + (size_t)nout * nin);
+        for (int j = 0; j < nout; ++j)
+            for (int k = 0; k < nin; ++k) {
+                const auto &v = T[(size_t)j * nin + k];
+                dst[off + (size_t)k * nout + j] = mk(v.real(), v.imag());
+            }
+        return off;
+    };
+    if (!pl.opt.direct) {
+        for (int l = 2; l + 1 < pl.nlev; ++l)
+            for (int q = 0; q < 4; ++q) {
+                int np = 2 * pl.P[l] + 1, nc = 2 * pl.P[l + 1] + 1;
+                m2m_off[l * 4 + q] = append_T(m2m, m2m_matrix(pl, l, q), np, nc);
+                l2l_off[l * 4 + q] = append_T(l2l, l2l_matrix(pl, l, q), nc, np);
+            }
+        for (int l = 2; l < pl.nlev; ++l) {
+            std::vector<char> used(40, 0);
+            for (int b = pl.level_start[l]; b < pl.level_start[l + 1]; ++b)
+                for (int v = pl.V_start[b]; v < pl.V_start[b + 1]; ++v) used[pl.V_off[v]] = 1;
+            for (int o = 0; o < 40; ++o) {
+                if (!used[o]) continue;
+                int dx, dy;
+                v_offset_from_id(o, &dx, &dy);
+                int n = 2 * pl.P[l] + 1;
+                m2l_off[l * 40 + o] = append_T(m2l, m2l_matrix(pl, l, dx, dy), n, n);
+            }
+        }
+    }
+    g.m2m_tab = ar.upload(m2m); g.l2l_tab = ar.upload(l2l); g.m2l_tab = ar.upload(m2l);
+    g.m2m_off = ar.upload(m2m_off); g.l2l_off = ar.upload(l2l_off); g.m2l_off = ar.upload(m2l_off);
+
+    auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
+    G->p2m = make_list(ar, pl, [&](int b) { return pl.leaf[b] && pl.lev[b] >= 2; });
+    G->xl = make_list(ar, pl, [&](int b) { return pl.X_start[b + 1] > pl.X_start[b]; });
+    G->qbx = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b); });
+    G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
+    G->wl = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.W_start[b + 1] > pl.W_start[b]; });
+    // the W list needs the largest order among W boxes, not among the leaves
+    int pw = 0;
+    for (int b = 0; b < nb; ++b)
+        if (pl.leaf[b] && has_ctr(b))
+            for (int i = pl.W_start[b]; i < pl.W_start[b + 1]; ++i) pw = std::max(pw, pl.P[pl.lev[pl.W_idx[i]]]);
+    G->wl.Pmax = pw;
+
+    if (ar.err != hipSuccess) return fail(ar.err == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
+                                          std::string("device upload failed: ") + hipGetErrorString(ar.err));
+    return QBX_OK;
+}
+
+qbx_status ensure_scratch(qbx_geom_s *G)
+{
+    if (G->qs) return QBX_OK;
+    DeviceArena &s = G->scratch;
+    const Plan &pl = G->pl;
+    size_t nd = kDensChunk;
+    G->qs = (cd *)s.alloc(sizeof(cd) * nd * std::max<int64_t>(pl.ns, 1));
+    G->qd = (cd *)s.alloc(sizeof(cd) * nd * std::max<int64_t>(pl.ns, 1));
+    G->coef = (cd *)s.alloc(sizeof(cd) * nd * (2 * pl.p + 1) * std::max<int64_t>(pl.nc, 1));
+    if (!pl.opt.direct) {
+        G->mp = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
+        G->loc = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
+    }
+    if (s.err != hipSuccess) {
+        hipError_t e = s.err;
+        s.release();
+        s.err = hipSuccess;
+        G->qs = G->qd = G->coef = G->mp = G->loc = nullptr;
+        return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
+                    std::string("scratch allocation failed: ") + hipGetErrorString(e));
+    }
+    return QBX_OK;
+}
+
+#define CHK(expr)                                                                    \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) return fail(QBX_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out)
+{
+    const Plan &pl = G->pl;
+    const DevGeom &g = G->g;
+    hipStream_t st = G->ctx->stream;
+    CHK(launch_charges(g, nd, ss, sd, G->qs, G->qd, st));
+    if (pl.opt.direct) {
+        CHK(launch_p2qbxl_direct(g, nd, G->qs, G->qd, G->coef, st));
+    } else {
+        CHK(launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->mp, st));
+        for (int l = pl.nlev - 2; l >= 2; --l)
+            CHK(launch_m2m(g, nd, l, pl.level_start[l + 1] - pl.level_start[l], pl.P[l + 1], G->mp, st));
+        CHK(launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
+        for (int l = 2; l < pl.nlev; ++l)
+            CHK(launch_m2l(g, nd, l, pl.level_start[l + 1] - pl.level_start[l], pl.P[l], G->mp, G->loc, st));
+        CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
+        for (int l = 2; l + 1 < pl.nlev; ++l)
+            CHK(launch_l2l(g, nd, l, pl.level_start[l + 2] - pl.level_start[l + 1], pl.P[l], G->loc, st));
+        CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
+        CHK(launch_m2qbxl(g, nd, G->wl.d, G->wl.n, G->wl.Pmax, G->mp, G->coef, st));
+        CHK(launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->loc, G->coef, st));
+    }
+    CHK(launch_qbx_eval(g, nd, G->coef, u, st));
+    CHK(launch_smooth(g, nd, G->qs, G->qd, u, st));
+    if (coef_out) CHK(launch_coef_out(g, nd, G->coef, coef_out, st));
+    return QBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
+{
+    if (!out) return fail(QBX_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0)
+        return fail(QBX_E_DEVICE, std::string("no HIP device available (hipGetDeviceCount: ") +
+                                      hipGetErrorString(e) + ", count " + std::to_string(n) + ")");
+    if (device < 0 || device >= n) return fail(QBX_E_INVAL, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    auto *c = new (std::nothrow) qbx_ctx_s();
+    if (!c) return fail(QBX_E_NOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    *out = c;
+    return QBX_OK;
+}
+
+qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream)
+{
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return QBX_OK;
+}
+
+qbx_status qbx_ctx_destroy(qbx_ctx ctx)
+{
+    delete ctx;
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
+{
+    if (!ctx || !plan || !out) return fail(QBX_E_INVAL, "null argument");
+    *out = nullptr;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    qbx_geom_s *G = nullptr;
+    try {
+        G = new qbx_geom_s();
+        G->ctx = ctx;
+        G->pl = plan->pl;
+        qbx_status st = upload(G);
+        if (st != QBX_OK) {
+            G->arena.release();
+            delete G;
+            return st;
+        }
+    } catch (const std::bad_alloc &) {
+        if (G) { G->arena.release(); delete G; }
+        return fail(QBX_E_NOMEM, "host allocation failed while building tables");
+    }
+    *out = G;
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_create(qbx_ctx ctx, double omega, double eps, const qbx_options *opt,
+                           int64_t n_src, const double *sx, const double *sy, const double *w,
+                           const double *nx, const double *ny, const double *sh, int64_t n_ctr,
+                           const double *cx, const double *cy, const double *cr, int64_t n_tgt,
+                           const double *tx, const double *ty, const int32_t *tgt_ctr,
+                           qbx_geom *out)
+{
+    if (!out) return fail(QBX_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    qbx_plan plan = nullptr;
+    qbx_status st = qbx_plan_create(omega, eps, opt, n_src, sx, sy, w, nx, ny, sh, n_ctr, cx, cy,
+                                    cr, n_tgt, tx, ty, tgt_ctr, &plan);
+    if (st != QBX_OK) return st;
+    st = qbx_geom_from_plan(ctx, plan, out);
+    qbx_plan_destroy(plan);
+    return st;
+}
+
+qbx_status qbx_geom_destroy(qbx_geom G)
+{
+    if (!G) return QBX_OK;
+    (void)hipSetDevice(G->ctx->device);
+    if (G->ctx->stream) (void)hipStreamSynchronize(G->ctx->stream);
+    else (void)hipDeviceSynchronize();
+    G->scratch.release();
+    G->arena.release();
+    delete G;
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_stats(qbx_geom G, qbx_stats *out)
+{
+    if (!G || !out) return fail(QBX_E_INVAL, "null argument");
+    fill_stats(G->pl, out);
+    out->device_bytes = G->arena.bytes + G->scratch.bytes;
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_association(qbx_geom G, int32_t *tgt_ctr_out)
+{
+    if (!G || (!tgt_ctr_out && G->pl.nt)) return fail(QBX_E_INVAL, "null argument");
+    std::copy(G->pl.tgt_ctr.begin(), G->pl.tgt_ctr.end(), tgt_ctr_out);
+    return QBX_OK;
+}
+
+qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
+                    void *coef)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
+    if (!u && G->pl.nt) return fail(QBX_E_INVAL, "u is NULL");
+    if (!sigma_s && !sigma_d) return fail(QBX_E_INVAL, "both densities are NULL");
+    hipError_t e = hipSetDevice(G->ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    qbx_status st = ensure_scratch(G);
+    if (st != QBX_OK) return st;
+    const Plan &pl = G->pl;
+    long long nq = 2 * pl.p + 1;
+    for (int d0 = 0; d0 < n_dens; d0 += kDensChunk) {
+        int nd = std::min(kDensChunk, n_dens - d0);
+        const cd *ss = sigma_s ? static_cast<const cd *>(sigma_s) + (long long)d0 * pl.ns : nullptr;
+        const cd *sd = sigma_d ? static_cast<const cd *>(sigma_d) + (long long)d0 * pl.ns : nullptr;
+        cd *uu = static_cast<cd *>(u) + (long long)d0 * pl.nt;
+        cd *co = coef ? static_cast<cd *>(coef) + (long long)d0 * nq * pl.nc : nullptr;
+        st = run_pipeline(G, nd, ss, sd, uu, co);
+        if (st != QBX_OK) return st;
+    }
+    return QBX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,819 @@
+// gfx950 kernels for FMM-accelerated Global QBX (2D Helmholtz S + D).
+//
+// Notation (Sec. 7 of the paper, translation formulas derived from Graf's
+// addition theorem, Sec. 2.1):
+//   O_n(z) = H_n(w|z|) e^{i n arg z},  I_n(z) = J_n(w|z|) e^{i n arg z},
+//   L_n(z) = J_n(w|z|) e^{-i n arg z}  (the paper's J-expansion basis).
+// Charges: qS = (i/4) w sigma_S, qD = (i/4) w sigma_D; nu = n_x + i n_y.
+// Box expansions are stored scaled: multipole a_k / W_|k|, local g_k W_|k|,
+// with the per-level W_k = min(1, s^k/k!), s = w R_l / sqrt(2).
+#include <hip/hip_runtime.h>
+
+#include "devmath.hpp"
+#include "kernels.hpp"
+
+namespace qbx {
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_zero(cd *p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long step = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += step) p[i] = mk(0.0, 0.0);
+}
+
+// qS[d][j] = (i/4) w_j sigma_S[d][perm[j]] (sorted source order); same for qD.
+__global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, cd *qs, cd *qd)
+{
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long n = (long long)nd * g.ns;
+    if (idx >= n) return;
+    int d = (int)(idx / g.ns), j = (int)(idx % g.ns);
+    int u = g.src_perm[j];
+    double s = 0.25 * g.sw[j];
+    cd a = sig_s ? sig_s[(long long)d * g.ns + u] : mk(0.0, 0.0);
+    cd b = sig_d ? sig_d[(long long)d * g.ns + u] : mk(0.0, 0.0);
+    qs[idx] = mk(-s * a.y, s * a.x);
+    qd[idx] = mk(-s * b.y, s * b.x);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2a: P2M at leaves (a_k = q L_k(s - m), dipole via L_{k +- 1}).
+// One block per leaf; sources in chunks of P2M_CH; J sequences in LDS.
+// ---------------------------------------------------------------------------
+constexpr int P2M_CH = 8;
+
+__global__ void k_p2m(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *mp)
+{
+    extern __shared__ double lds[];
+    int b = list[blockIdx.x];
+    int l = g.blev[b];
+    int P = g.Plev[l];
+    int J = P + 2;
+    double *Jb = lds;                    // [P2M_CH][J]
+    double *th = lds + P2M_CH * J;       // [P2M_CH]
+    double mx = g.bcx[b], my = g.bcy[b];
+    int np = 2 * P + 1;
+    cd *out = mp + g.box_off[b] * nd;
+    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) out[i] = mk(0.0, 0.0);
+    int s_begin = g.src_begin[b], s_end = g.src_end[b];
+    double hw = 0.5 * g.omega;
+    for (int s0 = s_begin; s0 < s_end; s0 += P2M_CH) {
+        int cnt = min(P2M_CH, s_end - s0);
+        if ((int)threadIdx.x < cnt) {
+            int j = s0 + threadIdx.x;
+            double dx = g.sx[j] - mx, dy = g.sy[j] - my;
+            double r = sqrt(dx * dx + dy * dy);
+            besselj_seq(g.omega * r, P + 1, Jb + threadIdx.x * J, 1);
+            th[threadIdx.x] = atan2(dy, dx);
+        }
+        __syncthreads();
+        for (int kk = threadIdx.x; kk < np; kk += blockDim.x) {
+            int k = kk - P;
+            for (int t = 0; t < cnt; ++t) {
+                int j = s0 + t;
+                const double *Jt = Jb + t * J;
+                double L[3][2];
+                for (int e = 0; e < 3; ++e) {
+                    int n = k - 1 + e;
+                    int an = n < 0 ? -n : n;
+                    double jv = Jt[an];
+                    if (n < 0 && (an & 1)) jv = -jv;
+                    double sn, cs;
+                    sincos(-(double)n * th[t], &sn, &cs);
+                    L[e][0] = jv * cs;
+                    L[e][1] = jv * sn;
+                }
+                cd Lm = mk(L[0][0], L[0][1]), L0 = mk(L[1][0], L[1][1]), Lp = mk(L[2][0], L[2][1]);
+                cd nu = mk(g.snx[j], g.sny[j]);
+                cd dip = hw * (conj(nu) * Lm - nu * Lp);
+                for (int d = 0; d < nd; ++d) {
+                    cd acc = out[d * np + kk];
+                    cfma(acc, qs[(long long)d * g.ns + j], L0);
+                    cfma(acc, qd[(long long)d * g.ns + j], dip);
+                    out[d * np + kk] = acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const double *iw = g.invW + g.Woff[l];
+    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) {
+        int k = i % np - P;
+        out[i] = iw[k < 0 ? -k : k] * out[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense scaled translation (M2M, L2L, M2L): out[d][j] (+)= sum_k T[k][j] in[d][k].
+// ---------------------------------------------------------------------------
+__device__ inline void apply_table(const cd *T, int nin, int nout, const cd *in_lds, int nd,
+                                   cd *out, bool accumulate)
+{
+    for (int j = threadIdx.x; j < nout; j += blockDim.x) {
+        for (int d = 0; d < nd; ++d) {
+            cd acc = accumulate ? out[d * nout + j] : mk(0.0, 0.0);
+            const cd *x = in_lds + d * nin;
+            for (int k = 0; k < nin; ++k) cfma(acc, T[(long long)k * nout + j], x[k]);
+            out[d * nout + j] = acc;
+        }
+    }
+}
+
+// Stage 2b: M2M into every non-leaf box of level l from its children.
+__global__ void k_m2m(DevGeom g, int nd, int l, cd *mp)
+{
+    extern __shared__ double lds_raw[];
+    cd *buf = reinterpret_cast<cd *>(lds_raw);
+    int b = g.level_start[l] + blockIdx.x;
+    if (g.leaf[b]) return;
+    int Pp = g.Plev[l], Pc = g.Plev[l + 1];
+    int np = 2 * Pp + 1, nc = 2 * Pc + 1;
+    cd *out = mp + g.box_off[b] * nd;
+    bool first = true;
+    for (int c = g.child_begin[b]; c < g.child_begin[b] + g.child_count[b]; ++c) {
+        int q = (g.bcx[c] > g.bcx[b] ? 1 : 0) | (g.bcy[c] > g.bcy[b] ? 2 : 0);
+        const cd *src = mp + g.box_off[c] * nd;
+        for (int i = threadIdx.x; i < nd * nc; i += blockDim.x) buf[i] = src[i];
+        __syncthreads();
+        apply_table(g.m2m_tab + g.m2m_off[l * 4 + q], nc, np, buf, nd, out, !first);
+        first = false;
+        __syncthreads();
+    }
+}
+
+// Stage 4: M2L over the V list of every box of level l (locals must be zeroed).
+__global__ void k_m2l(DevGeom g, int nd, int l, const cd *mp, cd *loc)
+{
+    extern __shared__ double lds_raw[];
+    cd *buf = reinterpret_cast<cd *>(lds_raw);
+    int b = g.level_start[l] + blockIdx.x;
+    int v0 = g.V_start[b], v1 = g.V_start[b + 1];
+    if (v0 == v1) return;
+    int P = g.Plev[l], n = 2 * P + 1;
+    cd *out = loc + g.box_off[b] * nd;
+    for (int v = v0; v < v1; ++v) {
+        int s = g.V_idx[v], o = g.V_off[v];
+        const cd *src = mp + g.box_off[s] * nd;
+        for (int i = threadIdx.x; i < nd * n; i += blockDim.x) buf[i] = src[i];
+        __syncthreads();
+        apply_table(g.m2l_tab + g.m2l_off[l * 40 + o], n, n, buf, nd, out, true);
+        __syncthreads();
+    }
+}
+
+// Stage 7: L2L from the parent (level l) into every box of level l + 1.
+__global__ void k_l2l(DevGeom g, int nd, int l, cd *loc)
+{
+    extern __shared__ double lds_raw[];
+    cd *buf = reinterpret_cast<cd *>(lds_raw);
+    int c = g.level_start[l + 1] + blockIdx.x;
+    int b = g.parent[c];
+    int Pp = g.Plev[l], Pc = g.Plev[l + 1];
+    int np = 2 * Pp + 1, nc = 2 * Pc + 1;
+    int q = (g.bcx[c] > g.bcx[b] ? 1 : 0) | (g.bcy[c] > g.bcy[b] ? 2 : 0);
+    const cd *src = loc + g.box_off[b] * nd;
+    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) buf[i] = src[i];
+    __syncthreads();
+    apply_table(g.l2l_tab + g.l2l_off[l * 4 + q], np, nc, buf, nd, loc + g.box_off[c] * nd, true);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 6: X-list P2L, g_l += q O_l(s - m_b) (+ dipole), stored as W_l g_l.
+// O_n = s_n tau^{-|n|} A_|n| e^{i n theta}, A_n = tau^n H_n(x), tau = min(1, x/2),
+// s_n = (-1)^n for n < 0.
+// ---------------------------------------------------------------------------
+constexpr int X_CH = 8;
+
+__global__ void k_p2l_x(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *loc)
+{
+    extern __shared__ double lds_raw[];
+    int b = list[blockIdx.x];
+    int l = g.blev[b];
+    int P = g.Plev[l];
+    int NA = P + 2;
+    cd *Ab = reinterpret_cast<cd *>(lds_raw);            // [X_CH][NA]
+    double *th = reinterpret_cast<double *>(Ab + X_CH * NA);
+    double *ltau = th + X_CH;
+    double mx = g.bcx[b], my = g.bcy[b];
+    int np = 2 * P + 1;
+    cd *out = loc + g.box_off[b] * nd;
+    const double *lw = g.logW + g.Woff[l];
+    double hw = 0.5 * g.omega;
+    for (int xi = g.X_start[b]; xi < g.X_start[b + 1]; ++xi) {
+        int c = g.X_idx[xi];
+        int s_begin = g.src_begin[c], s_end = g.src_end[c];
+        for (int s0 = s_begin; s0 < s_end; s0 += X_CH) {
+            int cnt = min(X_CH, s_end - s0);
+            if ((int)threadIdx.x < cnt) {
+                int j = s0 + threadIdx.x;
+                double dx = g.sx[j] - mx, dy = g.sy[j] - my;
+                double x = g.omega * sqrt(dx * dx + dy * dy);
+                double tau = fmin(1.0, 0.5 * x);
+                scaled_hankel_seq(x, tau, P + 1, Ab + threadIdx.x * NA, 1);
+                th[threadIdx.x] = atan2(dy, dx);
+                ltau[threadIdx.x] = log(tau);
+            }
+            __syncthreads();
+            for (int jj = threadIdx.x; jj < np; jj += blockDim.x) {
+                int ell = jj - P;
+                int al = ell < 0 ? -ell : ell;
+                for (int t = 0; t < cnt; ++t) {
+                    int j = s0 + t;
+                    const cd *A = Ab + t * NA;
+                    double base = exp(lw[al] - al * ltau[t]);   // W_|l| tau^{-|l|}
+                    double tau = exp(ltau[t]);
+                    cd O[3];
+                    for (int e = 0; e < 3; ++e) {
+                        int n = ell - 1 + e;
+                        int an = n < 0 ? -n : n;
+                        double f = base;
+                        if (an > al) f /= tau;
+                        else if (an < al) f *= tau;
+                        if (n < 0 && (an & 1)) f = -f;
+                        double sn, cs;
+                        sincos((double)n * th[t], &sn, &cs);
+                        O[e] = f * (A[an] * mk(cs, sn));
+                    }
+                    cd nu = mk(g.snx[j], g.sny[j]);
+                    cd dip = hw * (nu * O[0] - conj(nu) * O[2]);
+                    for (int d = 0; d < nd; ++d) {
+                        cd acc = out[d * np + jj];
+                        cfma(acc, qs[(long long)d * g.ns + j], O[1]);
+                        cfma(acc, qd[(long long)d * g.ns + j], dip);
+                        out[d * np + jj] = acc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3 (new): P2QBXL.  alpha_l(c) += qS O_l(s-c) + qD (w/2)(nu O_{l-1} - conj(nu) O_{l+1}).
+// One wave per centre group; lanes split the sources; wave shuffles reduce.
+// ---------------------------------------------------------------------------
+template <int PB>
+__device__ __forceinline__ void p2qbxl_pair(double omega, int p, double cx, double cy, double sx,
+                                            double sy, double nx, double ny, cd qS, cd qD, cd *acc)
+{
+    double dx = sx - cx, dy = sy - cy;
+    double r = sqrt(dx * dx + dy * dy);
+    double x = omega * r;
+    double ir = 1.0 / r;
+    cd u = mk(dx * ir, dy * ir);
+    cd H0, H1;
+    hankel01(x, H0, H1);
+    cd c = (0.5 * omega) * qD;
+    cd cnu = c * mk(nx, ny);            // c nu
+    cd cnub = c * mk(nx, -ny);          // c conj(nu)
+    // window: O_{n-1}, O_n, O_{n+1} and O_{-(n-1)}, O_{-n}, O_{-(n+1)}
+    cd Hprev = H0, Hcur = H1;
+    cd upow = u;                        // u^1
+    cd Op_prev, Op_cur = H0, Op_next = H1 * u;
+    cd Om_prev, Om_cur = H0, Om_next = neg(H1 * conj(u));
+    // alpha_0
+    {
+        cd t = qS * Op_cur;
+        cfma(t, cnu, Om_next);
+        cfma(t, neg(cnub), Op_next);
+        acc[PB] = acc[PB] + t;
+    }
+#pragma unroll
+    for (int n = 1; n <= PB; ++n) {
+        if (n > p) break;
+        // advance to index n + 1
+        cd Hnext = ((2.0 * n / x) * Hcur) - Hprev;
+        Hprev = Hcur;
+        Hcur = Hnext;
+        upow = upow * u;
+        Op_prev = Op_cur; Op_cur = Op_next; Op_next = Hcur * upow;
+        Om_prev = Om_cur; Om_cur = Om_next;
+        Om_next = Hcur * conj(upow);
+        if ((n + 1) & 1) Om_next = neg(Om_next);
+        cd t = qS * Op_cur;
+        cfma(t, cnu, Op_prev);
+        cfma(t, neg(cnub), Op_next);
+        acc[PB + n] = acc[PB + n] + t;
+        cd v = qS * Om_cur;
+        cfma(v, cnu, Om_next);
+        cfma(v, neg(cnub), Om_prev);
+        acc[PB - n] = acc[PB - n] + v;
+    }
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m)
+{
+    return __shfl_xor(v, m, 64);
+}
+
+template <int PB>
+__device__ void p2qbxl_finish(cd *acc, int G, int p, bool write, cd *dst, long long stride, bool add)
+{
+    // reduce over the lanes that share a centre (lane bits >= log2 G)
+#pragma unroll
+    for (int e = 0; e < 2 * PB + 1; ++e) {
+        double re = acc[e].x, im = acc[e].y;
+        for (int m = G; m < 64; m <<= 1) {
+            re += shfl_xor_d(re, m);
+            im += shfl_xor_d(im, m);
+        }
+        acc[e] = mk(re, im);
+    }
+    if (write) {
+#pragma unroll
+        for (int e = 0; e < 2 * PB + 1; ++e) {
+            int ell = e - PB;
+            if (ell < -p || ell > p) continue;
+            cd *o = dst + (long long)(ell + p) * stride;
+            *o = add ? (*o + acc[e]) : acc[e];
+        }
+    }
+}
+
+template <int PB>
+__global__ void __launch_bounds__(64) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
+                                                const cd *qd, cd *coef)
+{
+    int b = list[blockIdx.x];
+    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    int nct = c1 - c0;
+    int G = 1;
+    while (G < nct && G < 64) G <<= 1;
+    int parts = 64 / G;
+    int lane = threadIdx.x, gi = lane % G, part = lane / G;
+    int p = g.p;
+    long long ncoef = 2 * p + 1;
+    for (int cg = c0; cg < c1; cg += G) {
+        int i = cg + gi;
+        bool active = i < c1;
+        double cx = active ? g.cx[i] : 0.0, cy = active ? g.cy[i] : 0.0;
+        for (int d = 0; d < nd; ++d) {
+            cd acc[2 * PB + 1];
+#pragma unroll
+            for (int e = 0; e < 2 * PB + 1; ++e) acc[e] = mk(0.0, 0.0);
+            if (active) {
+                for (int ui = g.U_start[b]; ui < g.U_start[b + 1]; ++ui) {
+                    int ub = g.U_idx[ui];
+                    for (int j = g.src_begin[ub] + part; j < g.src_end[ub]; j += parts)
+                        p2qbxl_pair<PB>(g.omega, p, cx, cy, g.sx[j], g.sy[j], g.snx[j], g.sny[j],
+                                        qs[(long long)d * g.ns + j], qd[(long long)d * g.ns + j], acc);
+                }
+            }
+            p2qbxl_finish<PB>(acc, G, p, active && part == 0,
+                              coef + (long long)d * ncoef * g.nc + i, g.nc, false);
+        }
+    }
+}
+
+// Direct mode: all sources to every centre (Sec. 3.2, oversampled coefficient sum).
+template <int PB>
+__global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, const cd *qs,
+                                                       const cd *qd, cd *coef)
+{
+    int parts = 64 / G;
+    int lane = threadIdx.x, gi = lane % G, part = lane / G;
+    int i = blockIdx.x * G + gi;
+    bool active = i < g.nc;
+    int p = g.p;
+    long long ncoef = 2 * p + 1;
+    double cx = active ? g.cx[i] : 0.0, cy = active ? g.cy[i] : 0.0;
+    for (int d = 0; d < nd; ++d) {
+        cd acc[2 * PB + 1];
+#pragma unroll
+        for (int e = 0; e < 2 * PB + 1; ++e) acc[e] = mk(0.0, 0.0);
+        if (active)
+            for (int j = part; j < g.ns; j += parts)
+                p2qbxl_pair<PB>(g.omega, p, cx, cy, g.sx[j], g.sy[j], g.snx[j], g.sny[j],
+                                qs[(long long)d * g.ns + j], qd[(long long)d * g.ns + j], acc);
+        p2qbxl_finish<PB>(acc, G, p, active && part == 0,
+                          coef + (long long)d * ncoef * g.nc + (active ? i : 0), g.nc, false);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 5 (new): M2QBXL.  beta_l(c) += (-1)^l sum_k a_k O_{k+l}(c - m_w) for
+// every W box w of the leaf holding c.  With B_k = a_k = Ahat_k W_|k|,
+//   beta_l = (-1)^l tau^{-l} S+_l + tau^{l} S-_l,
+//   S+_l = sum_{k >= -l} B_k tau^{-k} A+_{k+l},  A+_n = tau^n H_n e^{+i n theta},
+//   S-_l = sum_{k < -l} B_k (-1)^k tau^{k} A-_{-k-l}, A-_n = tau^n H_n e^{-i n theta}.
+// ---------------------------------------------------------------------------
+constexpr int QCG_MAX = 16;   // centres per group (upper bound)
+constexpr size_t LDS_BUDGET = 64 * 1024;
+
+__global__ void k_m2qbxl(DevGeom g, int nd, const int *list, const cd *mp, cd *coef, int QCG)
+{
+    extern __shared__ double lds_raw[];
+    int b = list[blockIdx.x];
+    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    int p = g.p, nq = 2 * p + 1;
+    long long ncoef = nq;
+    for (int wi = g.W_start[b]; wi < g.W_start[b + 1]; ++wi) {
+        int w = g.W_idx[wi];
+        int lw = g.blev[w];
+        int Pw = g.Plev[lw], nw = 2 * Pw + 1;
+        int N = Pw + p;
+        const double *logW = g.logW + g.Woff[lw];
+        // LDS layout
+        cd *Bw = reinterpret_cast<cd *>(lds_raw);                 // [nd][nw] scaled multipole
+        cd *Ap = Bw + nd * nw;                                    // [QCG][N+1]
+        cd *Am = Ap + QCG * (N + 1);                              // [QCG][N+1]
+        double *wp = reinterpret_cast<double *>(Am + QCG * (N + 1));  // [QCG][nw]
+        double *wm = wp + QCG * nw;                               // [QCG][nw]
+        double *ltau = wm + QCG * nw;                             // [QCG]
+        // scaled multipole ahat_k; W_|k| enters through the per-centre weights
+        const cd *src = mp + g.box_off[w] * nd;
+        for (int i = threadIdx.x; i < nd * nw; i += blockDim.x) Bw[i] = src[i];
+        double mx = g.bcx[w], my = g.bcy[w];
+        for (int cg = c0; cg < c1; cg += QCG) {
+            int cnt = min(QCG, c1 - cg);
+            if ((int)threadIdx.x < cnt) {
+                int i = cg + threadIdx.x;
+                double dx = g.cx[i] - mx, dy = g.cy[i] - my;
+                double x = g.omega * sqrt(dx * dx + dy * dy);
+                double tau = fmin(1.0, 0.5 * x);
+                double th = atan2(dy, dx);
+                cd *ap = Ap + threadIdx.x * (N + 1);
+                cd *am = Am + threadIdx.x * (N + 1);
+                scaled_hankel_seq(x, tau, N, ap, 1);
+                for (int n = 0; n <= N; ++n) {
+                    double sn, cs;
+                    sincos((double)n * th, &sn, &cs);
+                    cd a = ap[n];
+                    ap[n] = a * mk(cs, sn);
+                    am[n] = a * mk(cs, -sn);
+                }
+                ltau[threadIdx.x] = log(tau);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt * nw; i += blockDim.x) {
+                int t = i / nw, k = i % nw - Pw;
+                double lt = ltau[t];
+                double lwk = logW[k < 0 ? -k : k];
+                wp[t * nw + k + Pw] = exp(lwk - k * lt);
+                double v = exp(lwk + k * lt);
+                wm[t * nw + k + Pw] = (k & 1) ? -v : v;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt * nq; i += blockDim.x) {
+                int t = i / nq, ell = i % nq - p;
+                const cd *ap = Ap + t * (N + 1);
+                const cd *am = Am + t * (N + 1);
+                const double *wpt = wp + t * nw + Pw;
+                const double *wmt = wm + t * nw + Pw;
+                double lt = ltau[t];
+                double fp = exp(-ell * lt), fm = exp(ell * lt);
+                if (ell & 1) fp = -fp;
+                int ci = cg + t;
+                for (int d = 0; d < nd; ++d) {
+                    const cd *B = Bw + d * nw + Pw;
+                    cd sp = mk(0.0, 0.0), sm = mk(0.0, 0.0);
+                    int klo = max(-Pw, -ell);
+                    for (int k = klo; k <= Pw; ++k) cfma(sp, wpt[k] * B[k], ap[k + ell]);
+                    int khi = min(Pw, -ell - 1);
+                    for (int k = -Pw; k <= khi; ++k) cfma(sm, wmt[k] * B[k], am[-k - ell]);
+                    cd beta = fp * sp + fm * sm;
+                    cd *o = coef + ((long long)d * ncoef + ell + p) * g.nc + ci;
+                    *o = *o + beta;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 8 (new): L2QBXL.  gamma_l(c) += sum_k g_k I_{l-k}(m_b - c), with the
+// box local g_k = ghat_k / W_|k|.
+// ---------------------------------------------------------------------------
+__global__ void k_l2qbxl(DevGeom g, int nd, const int *list, const cd *loc, cd *coef, int QCG)
+{
+    extern __shared__ double lds_raw[];
+    int b = list[blockIdx.x];
+    int l = g.blev[b];
+    int P = g.Plev[l], np = 2 * P + 1;
+    int p = g.p, nq = 2 * p + 1;
+    int N = P + p;
+    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    cd *Gb = reinterpret_cast<cd *>(lds_raw);          // [nd][np]
+    cd *Iv = Gb + nd * np;                             // [QCG][2N+1]
+    double *Jt = reinterpret_cast<double *>(Iv + QCG * (2 * N + 1));  // [QCG][N+1]
+    const double *iw = g.invW + g.Woff[l];
+    const cd *src = loc + g.box_off[b] * nd;
+    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) {
+        int k = i % np - P;
+        Gb[i] = iw[k < 0 ? -k : k] * src[i];
+    }
+    double mx = g.bcx[b], my = g.bcy[b];
+    for (int cg = c0; cg < c1; cg += QCG) {
+        int cnt = min(QCG, c1 - cg);
+        if ((int)threadIdx.x < cnt) {
+            int i = cg + threadIdx.x;
+            double dx = mx - g.cx[i], dy = my - g.cy[i];
+            double x = g.omega * sqrt(dx * dx + dy * dy);
+            double th = atan2(dy, dx);
+            double *jt = Jt + threadIdx.x * (N + 1);
+            besselj_seq(x, N, jt, 1);
+            cd *iv = Iv + threadIdx.x * (2 * N + 1) + N;
+            for (int n = 0; n <= N; ++n) {
+                double sn, cs;
+                sincos((double)n * th, &sn, &cs);
+                iv[n] = jt[n] * mk(cs, sn);
+                double jm = (n & 1) ? -jt[n] : jt[n];
+                iv[-n] = jm * mk(cs, -sn);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt * nq; i += blockDim.x) {
+            int t = i / nq, ell = i % nq - p;
+            const cd *iv = Iv + t * (2 * N + 1) + N;
+            int ci = cg + t;
+            for (int d = 0; d < nd; ++d) {
+                const cd *G = Gb + d * np + P;
+                cd acc = mk(0.0, 0.0);
+                for (int k = -P; k <= P; ++k) cfma(acc, G[k], iv[ell - k]);
+                cd *o = coef + ((long long)d * nq + ell + p) * g.nc + ci;
+                *o = *o + acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// QBX evaluation at associated targets: u = sum_{|l|<=p} alpha_l J_l(w rho) e^{-i l theta}.
+// Miller's recurrence runs downward and the series is summed on the fly.
+// ---------------------------------------------------------------------------
+__global__ void k_qbx_eval(DevGeom g, int nd, const cd *coef, cd *u)
+{
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= g.nt) return;
+    int i = g.tgt_cs[m];
+    if (i < 0) return;
+    int p = g.p;
+    long long nq = 2 * p + 1;
+    double dx = g.tx[m] - g.cx[i], dy = g.ty[m] - g.cy[i];
+    double rho = sqrt(dx * dx + dy * dy);
+    double x = g.omega * rho;
+    double th = atan2(dy, dx);
+    for (int d = 0; d < nd; ++d) {
+        const cd *a = coef + (long long)d * nq * g.nc + i;
+        cd a0 = a[(long long)p * g.nc];
+        if (x == 0.0) {
+            u[(long long)d * g.nt + m] = a0;
+            continue;
+        }
+        int M = miller_start(x, p);
+        double inv = 2.0 / x;
+        double fp1 = 0.0, f = 1e-280, f1 = 0.0;
+        cd S = mk(0.0, 0.0);
+        for (int n = M; n > 0; --n) {
+            if (n <= p) {
+                double sn, cs;
+                sincos((double)n * th, &sn, &cs);
+                cd ep = mk(cs, -sn);    // e^{-i n theta}
+                cd t = a[(long long)(p + n) * g.nc] * ep;
+                cd tm = a[(long long)(p - n) * g.nc] * conj(ep);
+                if (n & 1) tm = neg(tm);
+                S = S + f * (t + tm);
+            }
+            if (n == 1) f1 = f;
+            double fm = (n * inv) * f - fp1;
+            fp1 = f;
+            f = fm;
+            if (fabs(f) > 1e250) {
+                f *= 1e-250; fp1 *= 1e-250; f1 *= 1e-250;
+                S = 1e-250 * S;
+            }
+        }
+        double jz = j0(x), jo = j1(x);
+        double s = fabs(jz) >= fabs(jo) ? jz / f : jo / f1;
+        u[(long long)d * g.nt + m] = s * S + jz * a0;
+    }
+}
+
+// Smooth (unmodified Gauss) rule at unassociated targets, over all sources.
+__global__ void k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.n_smooth) return;
+    int m = g.smooth_list[idx];
+    double tx = g.tx[m], ty = g.ty[m];
+    for (int d = 0; d < nd; ++d) {
+        cd acc = mk(0.0, 0.0);
+        for (int j = 0; j < g.ns; ++j) {
+            double dx = tx - g.sx[j], dy = ty - g.sy[j];
+            double r = sqrt(dx * dx + dy * dy);
+            double x = g.omega * r;
+            cd h0, h1;
+            hankel01(x, h0, h1);
+            double ca = g.omega * (dx * g.snx[j] + dy * g.sny[j]) / r;
+            cfma(acc, qs[(long long)d * g.ns + j], h0);
+            cfma(acc, qd[(long long)d * g.ns + j], ca * h1);
+        }
+        u[(long long)d * g.nt + m] = acc;
+    }
+}
+
+// coef_user[d][l][user(i)] = coef[d][l][i]
+__global__ void k_coef_out(DevGeom g, int nd, const cd *coef, cd *out)
+{
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long nq = 2 * g.p + 1;
+    long long n = nd * nq * g.nc;
+    if (idx >= n) return;
+    long long row = idx / g.nc;
+    int i = (int)(idx % g.nc);
+    out[row * g.nc + g.ctr_perm[i]] = coef[idx];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define QBX_LAUNCH_CHECK()                                   \
+    do {                                                     \
+        hipError_t e_ = hipGetLastError();                   \
+        if (e_ != hipSuccess) return e_;                     \
+    } while (0)
+
+hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    k_fill_zero<<<blocks, 256, 0, s>>>(p, n);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,
+                          hipStream_t s)
+{
+    long long n = (long long)nd * g.ns;
+    if (n == 0) return hipSuccess;
+    k_charges<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, nd, ss, sd, qs, qd);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
+                      const cd *qd, cd *mp, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    size_t lds = sizeof(double) * (P2M_CH * (Pmax + 2) + P2M_CH);
+    k_p2m<<<n, 256, lds, s>>>(g, nd, list, qs, qd, mp);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp, hipStream_t s)
+{
+    if (!nbox) return hipSuccess;
+    size_t lds = sizeof(cd) * nd * (2 * Pc + 1);
+    k_m2m<<<nbox, 256, lds, s>>>(g, nd, l, mp);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_m2l(const DevGeom &g, int nd, int l, int nbox, int P, const cd *mp, cd *loc,
+                      hipStream_t s)
+{
+    if (!nbox) return hipSuccess;
+    size_t lds = sizeof(cd) * nd * (2 * P + 1);
+    k_m2l<<<nbox, 256, lds, s>>>(g, nd, l, mp, loc);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_l2l(const DevGeom &g, int nd, int l, int nchild, int Pp, cd *loc, hipStream_t s)
+{
+    if (!nchild) return hipSuccess;
+    size_t lds = sizeof(cd) * nd * (2 * Pp + 1);
+    k_l2l<<<nchild, 256, lds, s>>>(g, nd, l, loc);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
+                        const cd *qd, cd *loc, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    size_t lds = sizeof(cd) * X_CH * (Pmax + 2) + sizeof(double) * 2 * X_CH;
+    k_p2l_x<<<n, 256, lds, s>>>(g, nd, list, qs, qd, loc);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+template <int PB>
+static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+                                  const cd *qd, cd *coef, hipStream_t s)
+{
+    k_p2qbxl<PB><<<n, 64, 0, s>>>(g, nd, list, qs, qd, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+                         const cd *qd, cd *coef, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, list, n, qs, qd, coef, s);
+    return p2qbxl_dispatch<40>(g, nd, list, n, qs, qd, coef, s);
+}
+
+template <int PB>
+static hipError_t p2qbxl_direct_dispatch(const DevGeom &g, int nd, const cd *qs, const cd *qd,
+                                         cd *coef, hipStream_t s)
+{
+    int G = 4;
+    int blocks = (g.nc + G - 1) / G;
+    k_p2qbxl_direct<PB><<<blocks, 64, 0, s>>>(g, nd, G, qs, qd, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *coef,
+                                hipStream_t s)
+{
+    if (!g.nc) return hipSuccess;
+    if (g.p <= 8) return p2qbxl_direct_dispatch<8>(g, nd, qs, qd, coef, s);
+    if (g.p <= 16) return p2qbxl_direct_dispatch<16>(g, nd, qs, qd, coef, s);
+    if (g.p <= 24) return p2qbxl_direct_dispatch<24>(g, nd, qs, qd, coef, s);
+    if (g.p <= 32) return p2qbxl_direct_dispatch<32>(g, nd, qs, qd, coef, s);
+    return p2qbxl_direct_dispatch<40>(g, nd, qs, qd, coef, s);
+}
+
+size_t m2qbxl_lds_bytes(int nd, int Pw, int p, int cg)
+{
+    int nw = 2 * Pw + 1, N = Pw + p;
+    return sizeof(cd) * ((size_t)nd * nw + 2 * (size_t)cg * (N + 1)) +
+           sizeof(double) * (2 * (size_t)cg * nw + cg);
+}
+
+static int pick_cg(size_t (*bytes)(int, int, int, int), int nd, int P, int p)
+{
+    int cg = QCG_MAX;
+    while (cg > 1 && bytes(nd, P, p, cg) > LDS_BUDGET) cg >>= 1;
+    return cg;
+}
+
+hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int *list, int n, int PWmax,
+                         const cd *mp, cd *coef, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    int cg = pick_cg(m2qbxl_lds_bytes, nd, PWmax, g.p);
+    size_t lds = m2qbxl_lds_bytes(nd, PWmax, g.p, cg);
+    if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+    k_m2qbxl<<<n, 256, lds, s>>>(g, nd, list, mp, coef, cg);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
+{
+    int np = 2 * P + 1, N = P + p;
+    return sizeof(cd) * ((size_t)nd * np + (size_t)cg * (2 * N + 1)) + sizeof(double) * (size_t)cg * (N + 1);
+}
+
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
+                         const cd *loc, cd *coef, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    int cg = pick_cg(l2qbxl_lds_bytes, nd, Pmax, g.p);
+    size_t lds = l2qbxl_lds_bytes(nd, Pmax, g.p, cg);
+    if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+    k_l2qbxl<<<n, 256, lds, s>>>(g, nd, list, loc, coef, cg);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s)
+{
+    if (!g.nt) return hipSuccess;
+    k_qbx_eval<<<(g.nt + 255) / 256, 256, 0, s>>>(g, nd, coef, u);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_smooth(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, hipStream_t s)
+{
+    if (!g.n_smooth) return hipSuccess;
+    k_smooth<<<(g.n_smooth + 127) / 128, 128, 0, s>>>(g, nd, qs, qd, u);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hipStream_t s)
+{
+    long long n = (long long)nd * (2 * g.p + 1) * g.nc;
+    if (!n) return hipSuccess;
+    k_coef_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, nd, coef, out);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace qbx

@@ -1,0 +1,57 @@
+// Device-side view of a resident geometry and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "devmath.hpp"
+
+namespace qbx {
+
+// All pointers are device pointers.  Points are in tree (Morton) order.
+struct DevGeom {
+    int ns, nc, nt, nb, nlev, p, n_smooth;
+    double omega;
+    const double *sx, *sy, *sw, *snx, *sny;   // sorted sources
+    const int *src_perm;                       // sorted -> user source index
+    const double *cx, *cy;                     // sorted centres
+    const int *ctr_perm;                       // sorted -> user centre index
+    const double *tx, *ty;                     // targets, user order
+    const int *tgt_cs;                         // per target: sorted centre or -1
+    const int *smooth_list;                    // targets served by the smooth rule
+    const double *bcx, *bcy;                   // box centres
+    const int *blev, *leaf, *parent, *child_begin, *child_count;
+    const int *src_begin, *src_end, *ctr_begin, *ctr_end;
+    const int *level_start;
+    const int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
+    const int *Plev;                           // FMM order per level
+    const int *Woff;                           // per level offset into Wtab/invW/logW
+    const double *Wtab, *invW, *logW;
+    const long long *box_off;                  // per box, in coefficients of one density
+    const cd *m2m_tab, *l2l_tab, *m2l_tab;
+    const long long *m2m_off, *l2l_off, *m2l_off;   // [level*4+q], [level*4+q], [level*40+o]
+};
+
+hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
+hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,
+                          hipStream_t s);
+hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
+                      const cd *qd, cd *mp, hipStream_t s);
+hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp, hipStream_t s);
+hipError_t launch_m2l(const DevGeom &g, int nd, int l, int nbox, int P, const cd *mp, cd *loc,
+                      hipStream_t s);
+hipError_t launch_l2l(const DevGeom &g, int nd, int l, int nchild, int Pp, cd *loc, hipStream_t s);
+hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
+                        const cd *qd, cd *loc, hipStream_t s);
+hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+                         const cd *qd, cd *coef, hipStream_t s);
+hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *coef,
+                                hipStream_t s);
+hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int *list, int n, int PWmax,
+                         const cd *mp, cd *coef, hipStream_t s);
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
+                         const cd *loc, cd *coef, hipStream_t s);
+hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s);
+hipError_t launch_smooth(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, hipStream_t s);
+hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hipStream_t s);
+
+}  // namespace qbx

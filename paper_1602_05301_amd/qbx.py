@@ -1,0 +1,251 @@
+"""Python binding of ``libqbxfmm.so`` (ctypes; argument marshalling only).
+
+Every numerical step runs in the library: the host planner (C++) and the
+gfx950 kernels.  PyTorch only provides device memory and the stream.  The
+binding fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqbxfmm.so")
+
+QBX_OK, QBX_E_INVAL, QBX_E_NOMEM, QBX_E_DEVICE, QBX_E_ASSOC, QBX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
+_STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "ASSOC", -5: "UNSUPPORTED"}
+
+# Every symbol declared in include/qbxfmm.h.
+EXPORTS = [
+    "qbx_abi_version", "qbx_last_error", "qbx_options_default",
+    "qbx_ctx_create", "qbx_ctx_set_stream", "qbx_ctx_destroy",
+    "qbx_plan_create", "qbx_plan_destroy", "qbx_plan_stats", "qbx_plan_boxes",
+    "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
+    "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
+    "qbx_geom_association", "qbx_eval",
+]
+
+
+class QbxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qbxfmm {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("p_add", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
+                ("direct", ctypes.c_int32), ("far_fp32", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eps_assoc", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_src", ctypes.c_int64), ("n_ctr", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
+                ("n_levels", ctypes.c_int32), ("n_boxes", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int32), ("p", ctypes.c_int32), ("p_add", ctypes.c_int32),
+                ("n_u_pairs", ctypes.c_int64), ("n_v_pairs", ctypes.c_int64),
+                ("n_w_pairs", ctypes.c_int64), ("n_x_pairs", ctypes.c_int64),
+                ("n_p2qbxl_pairs", ctypes.c_int64), ("n_m2qbxl_pairs", ctypes.c_int64),
+                ("n_x_src_pairs", ctypes.c_int64), ("n_smooth_targets", ctypes.c_int64),
+                ("root_radius", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                          "(or python -m paper_1602_05301_amd.build) first")
+    # Load PyTorch's HIP runtime first: the library's libamdhip64.so.7
+    # dependency then binds to that already-loaded copy, so the process holds
+    # a single HIP runtime shared by torch tensors, streams and our kernels.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.qbx_abi_version.restype = i32
+    L.qbx_last_error.restype = ctypes.c_char_p
+    L.qbx_options_default.argtypes = [ctypes.POINTER(Options)]
+    L.qbx_ctx_create.argtypes = [i32, _vp, ctypes.POINTER(_vp)]
+    L.qbx_ctx_set_stream.argtypes = [_vp, _vp]
+    L.qbx_ctx_destroy.argtypes = [_vp]
+    geom_args = [dbl, dbl, ctypes.POINTER(Options), i64, _dp, _dp, _dp, _dp, _dp, _dp,
+                 i64, _dp, _dp, _dp, i64, _dp, _dp, _ip]
+    L.qbx_plan_create.argtypes = geom_args + [ctypes.POINTER(_vp)]
+    L.qbx_plan_destroy.argtypes = [_vp]
+    L.qbx_plan_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+    L.qbx_plan_boxes.argtypes = [_vp] + [_ip] * 7
+    L.qbx_plan_list.argtypes = [_vp, i32, _ip, _ip]
+    L.qbx_plan_orders.argtypes = [_vp, _ip]
+    L.qbx_plan_association.argtypes = [_vp, _ip]
+    L.qbx_geom_create.argtypes = [_vp] + geom_args + [ctypes.POINTER(_vp)]
+    L.qbx_geom_from_plan.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+    L.qbx_geom_destroy.argtypes = [_vp]
+    L.qbx_geom_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+    L.qbx_geom_association.argtypes = [_vp, _ip]
+    L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default"):
+            f.restype = st
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != QBX_OK:
+        raise QbxError(status, lib().qbx_last_error().decode())
+
+
+def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05) -> Options:
+    o = Options()
+    lib().qbx_options_default(ctypes.byref(o))
+    o.p, o.p_add, o.leaf_max, o.direct, o.eps_assoc = int(p), int(p_add), int(leaf_max), int(bool(direct)), float(eps_assoc)
+    return o
+
+
+def _arr(a, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a
+
+
+def _geom_args(geom, tx, ty, tgt_ctr):
+    arrs = [_arr(getattr(geom, n)) for n in ("sx", "sy", "w", "nx", "ny", "h", "cx", "cy", "cr")]
+    tx, ty = _arr(tx), _arr(ty)
+    tc = None if tgt_ctr is None else _arr(tgt_ctr, np.int32)
+    keep = arrs + [tx, ty] + ([tc] if tc is not None else [])
+    ptr = lambda a: a.ctypes.data_as(_dp)
+    ns, nc = arrs[0].size, arrs[6].size
+    args = [ns] + [ptr(a) for a in arrs[:6]] + [nc] + [ptr(a) for a in arrs[6:]] + \
+           [tx.size, ptr(tx), ptr(ty), None if tc is None else tc.ctypes.data_as(_ip)]
+    return args, keep
+
+
+class Plan:
+    """Host-only planning: tree, lists, orders, association."""
+
+    def __init__(self, geom, omega, eps, tx, ty, tgt_ctr=None, opts: Options | None = None):
+        opts = opts or options()
+        args, self._keep = _geom_args(geom, tx, ty, tgt_ctr)
+        h = _vp()
+        _check(lib().qbx_plan_create(float(omega), float(eps), ctypes.byref(opts), *args, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().qbx_plan_destroy(self._h)
+            self._h = None
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().qbx_plan_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def boxes(self) -> dict:
+        nb = self.stats()["n_boxes"]
+        out = {k: np.empty(nb, dtype=np.int32) for k in ("level", "ix", "iy", "parent", "leaf", "nsrc", "nctr")}
+        _check(lib().qbx_plan_boxes(self._h, *[out[k].ctypes.data_as(_ip) for k in
+                                              ("level", "ix", "iy", "parent", "leaf", "nsrc", "nctr")]))
+        return out
+
+    def list(self, which: int):
+        nb = self.stats()["n_boxes"]
+        start = np.empty(nb + 1, dtype=np.int32)
+        _check(lib().qbx_plan_list(self._h, which, start.ctypes.data_as(_ip), None))
+        idx = np.empty(max(int(start[-1]), 1), dtype=np.int32)
+        _check(lib().qbx_plan_list(self._h, which, start.ctypes.data_as(_ip), idx.ctypes.data_as(_ip)))
+        return start, idx[: start[-1]]
+
+    def orders(self) -> np.ndarray:
+        P = np.empty(self.stats()["n_levels"], dtype=np.int32)
+        _check(lib().qbx_plan_orders(self._h, P.ctypes.data_as(_ip)))
+        return P
+
+    def association(self) -> np.ndarray:
+        out = np.empty(max(self.stats()["n_tgt"], 1), dtype=np.int32)
+        _check(lib().qbx_plan_association(self._h, out.ctypes.data_as(_ip)))
+        return out[: self.stats()["n_tgt"]]
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = _vp()
+        _check(lib().qbx_ctx_create(int(device), _vp(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.stream = stream
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().qbx_ctx_destroy(self._h)
+            self._h = None
+
+
+class Geometry:
+    """A device-resident geometry (tree, lists, translation tables)."""
+
+    def __init__(self, ctx: Context, geom, omega, eps, tx, ty, tgt_ctr=None,
+                 opts: Options | None = None):
+        self.opts = opts or options()
+        args, keep = _geom_args(geom, tx, ty, tgt_ctr)
+        h = _vp()
+        _check(lib().qbx_geom_create(ctx._h, float(omega), float(eps), ctypes.byref(self.opts),
+                                     *args, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.n_src = int(np.asarray(geom.sx).size)
+        self.n_ctr = int(np.asarray(geom.cx).size)
+        self.n_tgt = int(np.asarray(tx).size)
+        self.p = int(self.opts.p)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().qbx_geom_destroy(self._h)
+            self._h = None
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().qbx_geom_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def association(self) -> np.ndarray:
+        out = np.empty(max(self.n_tgt, 1), dtype=np.int32)
+        _check(lib().qbx_geom_association(self._h, out.ctypes.data_as(_ip)))
+        return out[: self.n_tgt]
+
+    def eval(self, sigma_s, sigma_d, u=None, coef=None):
+        """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); device complex128 tensors."""
+        import torch
+        ref = sigma_s if sigma_s is not None else sigma_d
+        nd = int(ref.shape[0]) if ref.dim() == 2 else 1
+        dev = ref.device
+        for s in (sigma_s, sigma_d):
+            if s is not None:
+                if s.dtype != torch.complex128 or not s.is_cuda or not s.is_contiguous():
+                    raise ValueError("densities must be contiguous complex128 CUDA tensors")
+                if s.numel() != nd * self.n_src:
+                    raise ValueError("density shape must be [n_dens, n_src]")
+        if u is None:
+            u = torch.empty((nd, self.n_tgt), dtype=torch.complex128, device=dev)
+        if coef is True:
+            coef = torch.empty((nd, 2 * self.p + 1, self.n_ctr), dtype=torch.complex128, device=dev)
+        ptr = lambda t: None if t is None else _vp(t.data_ptr())
+        _check(lib().qbx_eval(self._h, nd, ptr(sigma_s), ptr(sigma_d), ptr(u),
+                              ptr(coef) if coef is not None and coef is not False else None))
+        return (u, coef) if coef is not None and coef is not False else u

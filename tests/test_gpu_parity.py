@@ -1,0 +1,154 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Direct mode must reproduce the oracle's discrete sums to rounding; the FMM
+mode must agree with the oracle's direct QBX to the requested tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_05301_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1602_05301_amd import qbx
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return qbx.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _eval(ctx, g, omega, eps, tx, ty, tc, ss, sd, coef=False, **opt):
+    from paper_1602_05301_amd import qbx
+    geo = qbx.Geometry(ctx, g, omega, eps, tx, ty, tc, qbx.options(**opt))
+    out = geo.eval(None if ss is None else _dev(ss), None if sd is None else _dev(sd),
+                   coef=True if coef else None)
+    torch.cuda.synchronize()
+    if coef:
+        return geo, out[0].cpu().numpy(), out[1].cpu().numpy()
+    return geo, out.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _coef_err(alpha_gpu, alpha_ref, omega, cr, p):
+    """Coefficient error weighted by J_|l|(omega r), the factor each alpha_l
+    carries at the edge of its disk, relative to the largest such term."""
+    l = np.abs(np.arange(-p, p + 1))
+    J = np.stack([oracle.besselj_seq(omega * r, p)[l] for r in cr], axis=1)  # [2p+1, nc]
+    num = np.max(np.abs(alpha_gpu - alpha_ref) * np.abs(J)[None], axis=1)
+    den = np.max(np.abs(alpha_ref) * np.abs(J)[None], axis=1)
+    return float(np.max(num / den))
+
+
+def test_direct_star512_matches_oracle(ctx):
+    """5-lobe star, 512 nodes, p = 12, omega = 10: on-curve targets at their own
+    centres, 1024 annulus targets associated by the library (smooth rule or a
+    centre), single and double layer."""
+    wl = inputs.direct_star512()
+    g = wl.geom
+    geo, u, coef = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s,
+                         wl.sigma_d, coef=True, p=wl.p, direct=True)
+    ref, alpha, ctr = oracle.direct_qbx(wl.omega, wl.p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d,
+                                        tgt_ctr=wl.tgt_ctr, return_coef=True)
+    assert np.array_equal(geo.association(), ctr)
+    assert _rel(u, ref) < 1e-12
+    assert np.max(np.abs(u - ref)) / np.max(np.abs(ref)) < 1e-12
+    assert _coef_err(coef, alpha, wl.omega, g.cr, wl.p) < 1e-11
+
+
+@pytest.mark.parametrize("which", ["S", "D"])
+def test_direct_single_layers(ctx, which):
+    g = inputs.star(16, 16, lobes=3)
+    r = np.random.default_rng(3)
+    s = inputs.complex_gaussian(r, (1, g.n))
+    ss, sd = (s, None) if which == "S" else (None, s)
+    tc = np.arange(g.n, dtype=np.int32)
+    _, u = _eval(ctx, g, 5.0, 1e-10, g.sx, g.sy, tc, ss, sd, p=9, direct=True)
+    ref = oracle.direct_qbx(5.0, 9, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    assert _rel(u, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n_panels,omega,eps,p", [(256, 50.0, 1e-10, 14), (128, 10.0, 1e-8, 10),
+                                                  (96, 80.0, 1e-6, 8)])
+def test_fmm_matches_direct_oracle(ctx, n_panels, omega, eps, p):
+    wl = inputs.fmm_star(n_panels=n_panels, omega=omega, eps=eps, p=p)
+    g = wl.geom
+    _, u, coef = _eval(ctx, g, omega, eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                       coef=True, p=p, leaf_max=32)
+    ref, alpha, _ = oracle.direct_qbx(omega, p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d,
+                                      tgt_ctr=wl.tgt_ctr, return_coef=True)
+    err = _rel(u, ref)
+    print(f"fmm n={g.n} omega={omega} eps={eps} p={p}: rel_l2={err:.3e} "
+          f"max={np.max(np.abs(u - ref)) / np.max(np.abs(ref)):.3e} "
+          f"coef={_coef_err(coef, alpha, omega, g.cr, p):.3e}", flush=True)
+    assert err < eps
+
+
+def test_fmm_full_size_sampled(ctx):
+    """2048 panels x 16 nodes = 32768 sources/centres/targets, omega = 50,
+    eps = 1e-10, p = 14: potentials at 512 sampled targets against the oracle
+    evaluated for exactly those targets' centres."""
+    wl = inputs.fmm_star()
+    g = wl.geom
+    _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                 p=wl.p, leaf_max=wl.leaf_max)
+    pick = np.sort(np.random.default_rng(0).choice(g.n, 512, replace=False))
+    alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny, wl.sigma_s,
+                                    wl.sigma_d, g.cx[pick], g.cy[pick])
+    ref = oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick],
+                          wl.ty[pick], np.arange(pick.size, dtype=np.int32))
+    err = _rel(u[:, pick], ref)
+    print(f"full-size sampled rel_l2={err:.3e}", flush=True)
+    assert err < wl.eps
+
+
+def test_multi_density_chunks_and_determinism(ctx):
+    g = inputs.star(64, 16, lobes=7)
+    r = np.random.default_rng(5)
+    ss = inputs.complex_gaussian(r, (5, g.n))
+    sd = inputs.complex_gaussian(r, (5, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    from paper_1602_05301_amd import qbx
+    geo = qbx.Geometry(ctx, g, 30.0, 1e-10, g.sx, g.sy, tc, qbx.options(p=12))
+    u5 = geo.eval(_dev(ss), _dev(sd)).cpu().numpy()
+    u5b = geo.eval(_dev(ss), _dev(sd)).cpu().numpy()
+    assert np.array_equal(u5, u5b)
+    for d in range(5):
+        u1 = geo.eval(_dev(ss[d:d + 1]), _dev(sd[d:d + 1])).cpu().numpy()
+        assert np.array_equal(u1[0], u5[d])
+
+
+def test_fmm_with_volume_targets(ctx):
+    """Targets off the curve: some inside expansion disks (QBX), the rest by
+    the smooth rule."""
+    g = inputs.star(64, 16, lobes=5)
+    rng = np.random.default_rng(9)
+    j = rng.integers(0, g.n, 300)
+    s = rng.uniform(0.05, 0.6, j.size) * g.h[j]
+    tx_a, ty_a = inputs.annulus_targets(rng, 200, 1.4, 2.0)
+    tx = np.concatenate([g.sx[j] + s * g.nx[j], tx_a])
+    ty = np.concatenate([g.sy[j] + s * g.ny[j], ty_a])
+    ss = inputs.complex_gaussian(rng, (1, g.n))
+    sd = inputs.complex_gaussian(rng, (1, g.n))
+    geo, u = _eval(ctx, g, 15.0, 1e-10, tx, ty, None, ss, sd, p=12)
+    ref = oracle.direct_qbx(15.0, 12, g, tx, ty, ss, sd)
+    assert np.array_equal(geo.association(), oracle.associate(tx, ty, g.cx, g.cy, g.cr, g.sx, g.sy, g.h))
+    assert _rel(u, ref) < 1e-10
+
+
+def test_no_targets(ctx):
+    g = inputs.star(16, 16, lobes=3)
+    from paper_1602_05301_amd import qbx
+    geo = qbx.Geometry(ctx, g, 10.0, 1e-8, np.zeros(0), np.zeros(0), None, qbx.options(p=8))
+    s = _dev(inputs.complex_gaussian(np.random.default_rng(1), (1, g.n)))
+    u = geo.eval(s, None)
+    torch.cuda.synchronize()
+    assert u.shape == (1, 0)
