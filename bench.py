@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of FMM-accelerated Global QBX on one MI355X.
+
+Workload: the 7-lobe star r = 1 + 0.3 cos(7 theta), 2048 equal-theta panels
+x 16 Gauss-Legendre nodes = 32768 sources = QBX centres = on-curve targets
+(each at its own centre), omega = 50, eps = 1e-10, p = 14, leaf occupancy
+<= 32 sources + centres, seeded Gaussian complex densities for S and D.
+One step = one complete evaluation u = S[sigma_s] + D[sigma_d] (all FMM
+stages, the QBX additions and the evaluation at every target) with the
+geometry, tree, tables and densities already resident in HBM.
+
+Prints one JSON line with the throughput (targets x densities per second),
+per-step latency percentiles, the roofline figure of the dominant kernel
+(HIP events on the library's stream over the timed region), and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--n-dens 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+METRIC = "QBX-FMM potential evals/s (targets·densities/s) at ε=1e-10; p50/p99 latency"
+
+
+def cpu_baseline(wl, target_seconds=12.0):
+    """The oracle (direct O(N_s N_c) QBX, C + OpenMP) on a sample of the
+    workload's targets: their centres' coefficients over all sources, then
+    the evaluation at those targets."""
+    import oracle
+    g = wl.geom
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(1234)
+
+    def run(n):
+        pick = np.sort(rng.choice(g.n, n, replace=False))
+        t0 = time.perf_counter()
+        alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny,
+                                        wl.sigma_s, wl.sigma_d, g.cx[pick], g.cy[pick], threads)
+        oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick], wl.ty[pick],
+                        np.arange(n, dtype=np.int32), threads)
+        return time.perf_counter() - t0
+
+    probe = max(threads, 16)
+    t = run(probe)
+    n = int(min(g.n, max(probe, probe * target_seconds / max(t, 1e-6))))
+    t = run(n)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n * wl.n_dens / t, "unit": "targets*densities/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} of {g.n} targets (their centres' coefficients over all {g.n} sources, "
+                      f"then QBX evaluation), {wl.n_dens} density, {t:.1f} s on {threads} "
+                      f"threads of {cpu}"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-dens", type=int, default=1)
+    ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1602_05301_amd import inputs, qbx
+
+    wl = inputs.fmm_star(n_dens=args.n_dens)
+    g = wl.geom
+    ctx = qbx.Context(0)
+    t0 = time.perf_counter()
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
+                       qbx.options(p=wl.p, leaf_max=wl.leaf_max))
+    setup_s = time.perf_counter() - t0
+    st = geo.stats()
+    ss = torch.from_numpy(wl.sigma_s).cuda()
+    sd = torch.from_numpy(wl.sigma_d).cuda()
+    u = torch.empty((wl.n_dens, g.n), dtype=torch.complex128, device="cuda")
+    for _ in range(args.warmup):
+        geo.eval(ss, sd, u=u)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-stage HIP events on the library's stream
+    geo.stage_times(reset=True)
+    geo.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        geo.eval(ss, sd, u=u)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    geo.profile(False)
+    stages = geo.stage_times(reset=True)
+    work = geo.work(wl.n_dens)
+
+    # latency: one synchronised evaluation at a time
+    lat = []
+    for _ in range(args.latency_steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        geo.eval(ss, sd, u=u)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+
+    ms_step = elapsed / args.steps * 1e3
+    value = g.n * wl.n_dens * args.steps / elapsed
+    dom = max(stages, key=lambda s: stages[s][0])
+    dom_ms = stages[dom][0] / args.steps
+    achieved = work[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "algorithmic_flops_per_step": work[dom], "ms_per_step": dom_ms,
+            "launches_per_step": stages[dom][1] / args.steps}
+
+    err = None
+    if not args.no_check:
+        import oracle
+        pick = np.sort(np.random.default_rng(0).choice(g.n, 64, replace=False))
+        alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny,
+                                        wl.sigma_s[:1], wl.sigma_d[:1], g.cx[pick], g.cy[pick])
+        ref = oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick],
+                              wl.ty[pick], np.arange(pick.size, dtype=np.int32))[0]
+        got = u[0].cpu().numpy()[pick]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "targets*densities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"qbx_fmm_star7_{g.n}", "n_src": g.n, "n_ctr": g.n,
+                   "n_tgt": g.n, "n_dens": wl.n_dens, "omega": wl.omega, "eps": wl.eps,
+                   "p": wl.p, "p_add": st["p_add"], "leaf_max": wl.leaf_max,
+                   "n_levels": st["n_levels"], "n_boxes": st["n_boxes"],
+                   "v_pairs": st["n_v_pairs"], "p2qbxl_pairs": st["n_p2qbxl_pairs"]},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "roofline": roof,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "setup_s": setup_s,
+        "rel_err_vs_oracle_sampled": err,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -162,6 +162,40 @@ qbx_status qbx_geom_destroy(qbx_geom geom);
 qbx_status qbx_geom_stats(qbx_geom geom, qbx_stats *out);
 qbx_status qbx_geom_association(qbx_geom geom, int32_t *tgt_ctr_out);
 
+/* ---- per-stage timing and work ----------------------------------------------
+ * Stages of one evaluation, in launch order (Sec. 7.2 stage names). */
+enum {
+    QBX_STAGE_CHARGES = 0,  /* qS, qD = (i/4) w sigma, reordered to tree order */
+    QBX_STAGE_P2M,          /* Stage 2, leaves */
+    QBX_STAGE_M2M,          /* Stage 2, upward pass */
+    QBX_STAGE_M2L,          /* Stage 4 */
+    QBX_STAGE_P2L_X,        /* Stage 6 */
+    QBX_STAGE_L2L,          /* Stage 7 */
+    QBX_STAGE_P2QBXL,       /* Stage 3, new */
+    QBX_STAGE_M2QBXL,       /* Stage 5, new */
+    QBX_STAGE_L2QBXL,       /* Stage 8, new */
+    QBX_STAGE_EVAL,         /* QBX evaluation at associated targets */
+    QBX_STAGE_SMOOTH,       /* smooth Gauss rule at the other targets */
+    QBX_STAGE_DIRECT,       /* direct-mode coefficient sum */
+    QBX_STAGE_COEF_OUT,     /* optional coefficient export */
+    QBX_N_STAGES
+};
+
+/* qbx_geom_profile: enable (1) or disable (0) HIP-event timing of every
+ * stage of later qbx_eval calls on this geometry (events are recorded on
+ * the context's stream around each stage's launches). */
+qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
+/* Accumulated milliseconds and launch counts per stage since the last reset
+ * (synchronises the stream).  ms and launches hold QBX_N_STAGES entries
+ * (either may be NULL); reset != 0 clears the accumulators. */
+qbx_status qbx_geom_stage_times(qbx_geom geom, double *ms, int64_t *launches, int32_t reset);
+/* Algorithmic floating-point work of one evaluation with n_dens densities,
+ * per stage (QBX_N_STAGES entries): the translations count 8 flops per
+ * complex multiply-add of the dense operator (M2L: 8 (2P+1)^2 per V pair and
+ * density), the near-field kernels the multiply-adds of their coefficient
+ * sums (P2QBXL: 24 (2p+1) per source-centre pair and density). */
+qbx_status qbx_geom_work(qbx_geom geom, int32_t n_dens, double *flops);
+
 /* ---- evaluation ----------------------------------------------------------
  * u[d][m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m) for d < n_dens, m < n_tgt.
  * sigma_s, sigma_d: device complex128 [n_dens][n_src] (either may be NULL,

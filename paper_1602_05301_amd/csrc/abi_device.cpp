@@ -73,6 +73,22 @@ struct qbx_geom_s {
     // per-eval scratch, sized for kDensChunk densities
     DeviceArena scratch;
     cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
+    // per-stage HIP-event timing (qbx_geom_profile)
+    struct StageRec {
+        int stage;
+        hipEvent_t a, b;
+        int launches;
+    };
+    bool profile = false;
+    std::vector<StageRec> pending;
+    std::vector<hipEvent_t> spare;
+    double acc_ms[QBX_N_STAGES] = {};
+    int64_t acc_n[QBX_N_STAGES] = {};
+    ~qbx_geom_s()
+    {
+        for (auto &r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : spare) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -245,32 +261,170 @@ qbx_status ensure_scratch(qbx_geom_s *G)
         if (e_ != hipSuccess) return fail(QBX_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+hipEvent_t take_event(qbx_geom_s *G)
+{
+    if (!G->spare.empty()) {
+        hipEvent_t e = G->spare.back();
+        G->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records events around one stage's launches when profiling is on.
+struct StageTimer {
+    qbx_geom_s *G;
+    int stage;
+    int launches = 0;
+    hipEvent_t a = nullptr;
+    StageTimer(qbx_geom_s *g, int s) : G(g), stage(s)
+    {
+        if (G->profile && (a = take_event(G))) (void)hipEventRecord(a, G->ctx->stream);
+    }
+    ~StageTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(G);
+        if (!b) { G->spare.push_back(a); return; }
+        (void)hipEventRecord(b, G->ctx->stream);
+        G->pending.push_back({stage, a, b, launches});
+    }
+};
+
+qbx_status harvest(qbx_geom_s *G)
+{
+    for (auto &r : G->pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        G->acc_ms[r.stage] += ms;
+        G->acc_n[r.stage] += r.launches;
+        G->spare.push_back(r.a);
+        G->spare.push_back(r.b);
+    }
+    G->pending.clear();
+    return QBX_OK;
+}
+
+#define STAGE(id) StageTimer timer_##id(G, id)
+#define LAUNCH(id, n, expr)        \
+    do {                           \
+        if ((n) > 0) timer_##id.launches++; \
+        CHK(expr);                 \
+    } while (0)
+
 qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out)
 {
     const Plan &pl = G->pl;
     const DevGeom &g = G->g;
     hipStream_t st = G->ctx->stream;
-    CHK(launch_charges(g, nd, ss, sd, G->qs, G->qd, st));
-    if (pl.opt.direct) {
-        CHK(launch_p2qbxl_direct(g, nd, G->qs, G->qd, G->coef, st));
-    } else {
-        CHK(launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->mp, st));
-        for (int l = pl.nlev - 2; l >= 2; --l)
-            CHK(launch_m2m(g, nd, l, pl.level_start[l + 1] - pl.level_start[l], pl.P[l + 1], G->mp, st));
-        CHK(launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
-        for (int l = 2; l < pl.nlev; ++l)
-            CHK(launch_m2l(g, nd, l, pl.level_start[l + 1] - pl.level_start[l], pl.P[l], G->mp, G->loc, st));
-        CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
-        for (int l = 2; l + 1 < pl.nlev; ++l)
-            CHK(launch_l2l(g, nd, l, pl.level_start[l + 2] - pl.level_start[l + 1], pl.P[l], G->loc, st));
-        CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
-        CHK(launch_m2qbxl(g, nd, G->wl.d, G->wl.n, G->wl.Pmax, G->mp, G->coef, st));
-        CHK(launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->loc, G->coef, st));
+    {
+        STAGE(QBX_STAGE_CHARGES);
+        LAUNCH(QBX_STAGE_CHARGES, pl.ns, launch_charges(g, nd, ss, sd, G->qs, G->qd, st));
     }
-    CHK(launch_qbx_eval(g, nd, G->coef, u, st));
-    CHK(launch_smooth(g, nd, G->qs, G->qd, u, st));
-    if (coef_out) CHK(launch_coef_out(g, nd, G->coef, coef_out, st));
+    if (pl.opt.direct) {
+        STAGE(QBX_STAGE_DIRECT);
+        LAUNCH(QBX_STAGE_DIRECT, pl.nc, launch_p2qbxl_direct(g, nd, G->qs, G->qd, G->coef, st));
+    } else {
+        {
+            STAGE(QBX_STAGE_P2M);
+            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->mp, st));
+        }
+        {
+            STAGE(QBX_STAGE_M2M);
+            for (int l = pl.nlev - 2; l >= 2; --l) {
+                int nbox = pl.level_start[l + 1] - pl.level_start[l];
+                LAUNCH(QBX_STAGE_M2M, nbox, launch_m2m(g, nd, l, nbox, pl.P[l + 1], G->mp, st));
+            }
+        }
+        {
+            STAGE(QBX_STAGE_M2L);
+            LAUNCH(QBX_STAGE_M2L, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
+            for (int l = 2; l < pl.nlev; ++l) {
+                int nbox = pl.level_start[l + 1] - pl.level_start[l];
+                LAUNCH(QBX_STAGE_M2L, nbox, launch_m2l(g, nd, l, nbox, pl.P[l], G->mp, G->loc, st));
+            }
+        }
+        {
+            STAGE(QBX_STAGE_P2L_X);
+            LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
+        }
+        {
+            STAGE(QBX_STAGE_L2L);
+            for (int l = 2; l + 1 < pl.nlev; ++l) {
+                int nch = pl.level_start[l + 2] - pl.level_start[l + 1];
+                LAUNCH(QBX_STAGE_L2L, nch, launch_l2l(g, nd, l, nch, pl.P[l], G->loc, st));
+            }
+        }
+        {
+            STAGE(QBX_STAGE_P2QBXL);
+            LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
+        }
+        {
+            STAGE(QBX_STAGE_M2QBXL);
+            LAUNCH(QBX_STAGE_M2QBXL, G->wl.n, launch_m2qbxl(g, nd, G->wl.d, G->wl.n, G->wl.Pmax, G->mp, G->coef, st));
+        }
+        {
+            STAGE(QBX_STAGE_L2QBXL);
+            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->loc, G->coef, st));
+        }
+    }
+    {
+        STAGE(QBX_STAGE_EVAL);
+        LAUNCH(QBX_STAGE_EVAL, pl.nt, launch_qbx_eval(g, nd, G->coef, u, st));
+    }
+    {
+        STAGE(QBX_STAGE_SMOOTH);
+        LAUNCH(QBX_STAGE_SMOOTH, G->g.n_smooth, launch_smooth(g, nd, G->qs, G->qd, u, st));
+    }
+    if (coef_out) {
+        STAGE(QBX_STAGE_COEF_OUT);
+        LAUNCH(QBX_STAGE_COEF_OUT, pl.nc, launch_coef_out(g, nd, G->coef, coef_out, st));
+    }
     return QBX_OK;
+}
+
+// Algorithmic flops per stage for nd densities (conventions in qbxfmm.h).
+void stage_work(const qbx_geom_s *G, int nd, double *f)
+{
+    const Plan &pl = G->pl;
+    for (int s = 0; s < QBX_N_STAGES; ++s) f[s] = 0;
+    double cq = 2.0 * pl.p + 1;
+    auto nP = [&](int b) { return 2.0 * pl.P[pl.lev[b]] + 1; };
+    int64_t n_assoc = 0;
+    for (int64_t m = 0; m < pl.nt; ++m) n_assoc += pl.tgt_ctr[m] >= 0;
+    f[QBX_STAGE_EVAL] = 8.0 * cq * n_assoc;
+    f[QBX_STAGE_SMOOTH] = 16.0 * (double)(pl.nt - n_assoc) * pl.ns;
+    if (pl.opt.direct) {
+        f[QBX_STAGE_DIRECT] = 24.0 * cq * (double)pl.nc * pl.ns;
+    } else {
+        for (int b = 0; b < pl.n_boxes(); ++b) {
+            int ns_b = pl.src_end[b] - pl.src_begin[b], nc_b = pl.ctr_end[b] - pl.ctr_begin[b];
+            if (pl.lev[b] >= 2 && pl.leaf[b]) f[QBX_STAGE_P2M] += 24.0 * nP(b) * ns_b;
+            if (pl.lev[b] >= 3) {
+                double t = 8.0 * nP(b) * nP(pl.parent[b]);
+                f[QBX_STAGE_M2M] += t;
+                f[QBX_STAGE_L2L] += t;
+            }
+            f[QBX_STAGE_M2L] += 8.0 * nP(b) * nP(b) * (pl.V_start[b + 1] - pl.V_start[b]);
+            for (int i = pl.X_start[b]; i < pl.X_start[b + 1]; ++i) {
+                int c = pl.X_idx[i];
+                f[QBX_STAGE_P2L_X] += 24.0 * nP(b) * (pl.src_end[c] - pl.src_begin[c]);
+            }
+            if (!pl.leaf[b] || nc_b == 0) continue;
+            for (int i = pl.U_start[b]; i < pl.U_start[b + 1]; ++i) {
+                int c = pl.U_idx[i];
+                f[QBX_STAGE_P2QBXL] += 24.0 * cq * nc_b * (pl.src_end[c] - pl.src_begin[c]);
+            }
+            for (int i = pl.W_start[b]; i < pl.W_start[b + 1]; ++i)
+                f[QBX_STAGE_M2QBXL] += 8.0 * cq * nc_b * nP(pl.W_idx[i]);
+            if (pl.lev[b] >= 2) f[QBX_STAGE_L2QBXL] += 8.0 * cq * nc_b * nP(b);
+        }
+    }
+    for (int s = 0; s < QBX_N_STAGES; ++s) f[s] *= nd;
 }
 
 }  // namespace
@@ -378,6 +532,33 @@ qbx_status qbx_geom_association(qbx_geom G, int32_t *tgt_ctr_out)
 {
     if (!G || (!tgt_ctr_out && G->pl.nt)) return fail(QBX_E_INVAL, "null argument");
     std::copy(G->pl.tgt_ctr.begin(), G->pl.tgt_ctr.end(), tgt_ctr_out);
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_profile(qbx_geom G, int32_t enable)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    G->profile = enable != 0;
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_stage_times(qbx_geom G, double *ms, int64_t *launches, int32_t reset)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    qbx_status st = harvest(G);
+    if (st != QBX_OK) return st;
+    for (int s = 0; s < QBX_N_STAGES; ++s) {
+        if (ms) ms[s] = G->acc_ms[s];
+        if (launches) launches[s] = G->acc_n[s];
+        if (reset) { G->acc_ms[s] = 0; G->acc_n[s] = 0; }
+    }
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_work(qbx_geom G, int32_t n_dens, double *flops)
+{
+    if (!G || !flops || n_dens < 1) return fail(QBX_E_INVAL, "invalid argument");
+    stage_work(G, n_dens, flops);
     return QBX_OK;
 }
 

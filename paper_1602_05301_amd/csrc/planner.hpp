@@ -66,7 +66,7 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
                  const double *cy, const double *cr, int64_t nt, const double *tx,
                  const double *ty, const int32_t *tgt_ctr);
 
-int default_p_add(int p);
+int default_p_add(int p, double eps);
 int fmm_order(double omega, double R, double eps);
 
 // Per-level scale factors W_k = min(1, sigma^k / k!), sigma = omega R_l / sqrt(2),

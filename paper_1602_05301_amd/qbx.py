@@ -26,8 +26,12 @@ EXPORTS = [
     "qbx_plan_create", "qbx_plan_destroy", "qbx_plan_stats", "qbx_plan_boxes",
     "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
     "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
-    "qbx_geom_association", "qbx_eval",
+    "qbx_geom_association", "qbx_geom_profile", "qbx_geom_stage_times", "qbx_geom_work",
+    "qbx_eval",
 ]
+
+STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
+          "eval", "smooth", "direct", "coef_out"]
 
 
 class QbxError(RuntimeError):
@@ -96,6 +100,9 @@ def lib():
     L.qbx_geom_destroy.argtypes = [_vp]
     L.qbx_geom_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     L.qbx_geom_association.argtypes = [_vp, _ip]
+    L.qbx_geom_profile.argtypes = [_vp, i32]
+    L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
+    L.qbx_geom_work.argtypes = [_vp, i32, _dp]
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -228,6 +235,22 @@ class Geometry:
         out = np.empty(max(self.n_tgt, 1), dtype=np.int32)
         _check(lib().qbx_geom_association(self._h, out.ctypes.data_as(_ip)))
         return out[: self.n_tgt]
+
+    def profile(self, enable: bool = True):
+        _check(lib().qbx_geom_profile(self._h, int(bool(enable))))
+
+    def stage_times(self, reset: bool = True) -> dict:
+        ms = np.zeros(len(STAGES))
+        n = np.zeros(len(STAGES), dtype=np.int64)
+        _check(lib().qbx_geom_stage_times(self._h, ms.ctypes.data_as(_dp),
+                                          n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          int(bool(reset))))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def work(self, n_dens: int = 1) -> dict:
+        f = np.zeros(len(STAGES))
+        _check(lib().qbx_geom_work(self._h, int(n_dens), f.ctypes.data_as(_dp)))
+        return {s: float(f[i]) for i, s in enumerate(STAGES)}
 
     def eval(self, sigma_s, sigma_d, u=None, coef=None):
         """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); device complex128 tensors."""

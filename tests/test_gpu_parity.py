@@ -92,6 +92,29 @@ def test_fmm_matches_direct_oracle(ctx, n_panels, omega, eps, p):
     assert err < eps
 
 
+@pytest.mark.parametrize("n_panels,omega,p,p_add,leaf_max", [(64, 20.0, 12, 30, 32),
+                                                             (40, 60.0, 8, 20, 16)])
+def test_fmm_matches_oracle_fmm_stage_by_stage(ctx, n_panels, omega, p, p_add, leaf_max):
+    """Same tree, same orders, same translations: the GPU FMM reproduces the
+    oracle's plain stage-by-stage FMM to rounding (coefficients and
+    potentials), independently of how close either is to direct QBX."""
+    from oracle import fmm as ofmm
+    from oracle import tree as otree
+    g = inputs.star(n_panels, 16, lobes=7)
+    r = np.random.default_rng(21)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    sd = inputs.complex_gaussian(r, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    eps = 1e-10
+    _, u, coef = _eval(ctx, g, omega, eps, g.sx, g.sy, tc, ss, sd, coef=True, p=p,
+                       p_add=p_add, leaf_max=leaf_max)
+    t = otree.build(g.sx, g.sy, g.cx, g.cy, leaf_max)
+    P = ofmm.orders(omega, t["R0"], int(t["level"].max()) + 1, eps, p_add)
+    u_o, alpha_o = ofmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, leaf_max)
+    assert _rel(u, u_o) < 1e-13
+    assert _coef_err(coef, alpha_o, omega, g.cr, p) < 1e-12
+
+
 def test_fmm_full_size_sampled(ctx):
     """2048 panels x 16 nodes = 32768 sources/centres/targets, omega = 50,
     eps = 1e-10, p = 14: potentials at 512 sampled targets against the oracle
