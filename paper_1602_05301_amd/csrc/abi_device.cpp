@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "abi_common.hpp"
@@ -70,6 +71,16 @@ struct qbx_geom_s {
     DeviceArena arena;
     WorkList p2m, xl, qbx, wl, l2q;
     long long total_coef = 0;     // sum over boxes of (2 P_l + 1)
+    // M2L GEMM groups: (level*40 + offset, start in vpair_sorted, pairs)
+    struct Group {
+        int key, start, count;
+    };
+    std::vector<Group> m2l_groups;
+    int m2l_Pmax = 0;
+    long long total_vy = 0;       // sum over V-list positions of (2 P_l + 1)
+    M2LTile *m2l_tiles[kDensChunk + 1] = {};
+    int m2l_ntiles[kDensChunk + 1] = {};
+    cd *vy = nullptr;
     // per-eval scratch, sized for kDensChunk densities
     DeviceArena scratch;
     cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
@@ -179,6 +190,32 @@ qbx_status upload(qbx_geom_s *G)
     std::vector<cd> m2m, l2l, m2l;
     std::vector<long long> m2m_off(4 * (size_t)std::max(pl.nlev, 1), -1),
         l2l_off(4 * (size_t)std::max(pl.nlev, 1), -1), m2l_off(40 * (size_t)std::max(pl.nlev, 1), -1);
+    // V-list positions: target box, grouping by (level, offset), output rows
+    int nv = (int)pl.V_idx.size();
+    std::vector<int> vtgt(nv), vpos(nv);
+    std::vector<long long> vy_off(std::max(nv, 1));
+    long long vy_tot = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int v = pl.V_start[b]; v < pl.V_start[b + 1]; ++v) {
+            vtgt[v] = b;
+            vy_off[v] = vy_tot;
+            vy_tot += 2 * pl.P[pl.lev[b]] + 1;
+        }
+    G->total_vy = vy_tot;
+    std::iota(vpos.begin(), vpos.end(), 0);
+    auto vkey = [&](int v) { return pl.lev[vtgt[v]] * 40 + pl.V_off[v]; };
+    std::stable_sort(vpos.begin(), vpos.end(), [&](int a, int b) { return vkey(a) < vkey(b); });
+    G->m2l_groups.clear();
+    G->m2l_Pmax = 0;
+    for (int i = 0; i < nv;) {
+        int j = i;
+        while (j < nv && vkey(vpos[j]) == vkey(vpos[i])) ++j;
+        G->m2l_groups.push_back({vkey(vpos[i]), i, j - i});
+        G->m2l_Pmax = std::max(G->m2l_Pmax, pl.P[vkey(vpos[i]) / 40]);
+        i = j;
+    }
+    g.vpair_sorted = ar.upload(vpos);
+    g.vy_off = ar.upload(vy_off);
     auto append_T = [](std::vector<cd> &dst, const std::vector<std::complex<double>> &T, int nout,
                        int nin) {
         long long off = (long long)dst.size();
@@ -197,21 +234,29 @@ qbx_status upload(qbx_geom_s *G)
                 m2m_off[l * 4 + q] = append_T(m2m, m2m_matrix(pl, l, q), np, nc);
                 l2l_off[l * 4 + q] = append_T(l2l, l2l_matrix(pl, l, q), nc, np);
             }
-        for (int l = 2; l < pl.nlev; ++l) {
-            std::vector<char> used(40, 0);
-            for (int b = pl.level_start[l]; b < pl.level_start[l + 1]; ++b)
-                for (int v = pl.V_start[b]; v < pl.V_start[b + 1]; ++v) used[pl.V_off[v]] = 1;
-            for (int o = 0; o < 40; ++o) {
-                if (!used[o]) continue;
-                int dx, dy;
-                v_offset_from_id(o, &dx, &dy);
-                int n = 2 * pl.P[l] + 1;
-                m2l_off[l * 40 + o] = append_T(m2l, m2l_matrix(pl, l, dx, dy), n, n);
-            }
+        // M2L matrices in MFMA A-operand order (see k_m2l_mfma)
+        for (const auto &grp : G->m2l_groups) {
+            int l = grp.key / 40, o = grp.key % 40;
+            int dx, dy;
+            v_offset_from_id(o, &dx, &dy);
+            int n = 2 * pl.P[l] + 1, NR = (n + 15) / 16, NK = (n + 3) / 4;
+            auto M = m2l_matrix(pl, l, dx, dy);   // row-major [out][in]
+            long long off = (long long)m2l.size();
+            m2l.resize(m2l.size() + (size_t)NR * NK * 64, mk(0.0, 0.0));
+            for (int rb = 0; rb < NR; ++rb)
+                for (int kb = 0; kb < NK; ++kb)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        int row = rb * 16 + lane % 16, k = kb * 4 + lane / 16;
+                        if (row < n && k < n) {
+                            const auto &v = M[(size_t)row * n + k];
+                            m2l[off + ((size_t)rb * NK + kb) * 64 + lane] = mk(v.real(), v.imag());
+                        }
+                    }
+            m2l_off[grp.key] = off;
         }
     }
-    g.m2m_tab = ar.upload(m2m); g.l2l_tab = ar.upload(l2l); g.m2l_tab = ar.upload(m2l);
-    g.m2m_off = ar.upload(m2m_off); g.l2l_off = ar.upload(l2l_off); g.m2l_off = ar.upload(m2l_off);
+    g.m2m_tab = ar.upload(m2m); g.l2l_tab = ar.upload(l2l); g.m2l_mf = ar.upload(m2l);
+    g.m2m_off = ar.upload(m2m_off); g.l2l_off = ar.upload(l2l_off); g.m2l_mf_off = ar.upload(m2l_off);
 
     auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
     G->p2m = make_list(ar, pl, [&](int b) { return pl.leaf[b] && pl.lev[b] >= 2; });
@@ -243,6 +288,7 @@ qbx_status ensure_scratch(qbx_geom_s *G)
     if (!pl.opt.direct) {
         G->mp = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
         G->loc = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
+        G->vy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_vy, 1));
     }
     if (s.err != hipSuccess) {
         hipError_t e = s.err;
@@ -251,6 +297,27 @@ qbx_status ensure_scratch(qbx_geom_s *G)
         G->qs = G->qd = G->coef = G->mp = G->loc = nullptr;
         return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                     std::string("scratch allocation failed: ") + hipGetErrorString(e));
+    }
+    return QBX_OK;
+}
+
+// M2L GEMM tiles for nd densities: each (level, offset) group's columns are
+// its (pair, density) combinations, cut into tiles of 16.
+qbx_status ensure_tiles(qbx_geom_s *G, int nd)
+{
+    if (G->m2l_tiles[nd] || G->m2l_groups.empty()) return QBX_OK;
+    std::vector<M2LTile> t;
+    for (const auto &grp : G->m2l_groups) {
+        int cols = grp.count * nd;
+        for (int c0 = 0; c0 < cols; c0 += 16) t.push_back({grp.key, grp.start, c0, std::min(16, cols - c0)});
+    }
+    G->m2l_tiles[nd] = G->scratch.upload(t);
+    G->m2l_ntiles[nd] = (int)t.size();
+    if (G->scratch.err != hipSuccess) {
+        hipError_t e = G->scratch.err;
+        G->scratch.err = hipSuccess;
+        G->m2l_tiles[nd] = nullptr;
+        return fail(QBX_E_DEVICE, std::string("tile upload failed: ") + hipGetErrorString(e));
     }
     return QBX_OK;
 }
@@ -342,21 +409,22 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_M2L);
-            LAUNCH(QBX_STAGE_M2L, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
-            for (int l = 2; l < pl.nlev; ++l) {
-                int nbox = pl.level_start[l + 1] - pl.level_start[l];
-                LAUNCH(QBX_STAGE_M2L, nbox, launch_m2l(g, nd, l, nbox, pl.P[l], G->mp, G->loc, st));
-            }
+            qbx_status ts = ensure_tiles(G, nd);
+            if (ts != QBX_OK) return ts;
+            LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
+                   launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->mp, G->vy, st));
         }
         {
             STAGE(QBX_STAGE_P2L_X);
+            LAUNCH(QBX_STAGE_P2L_X, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
             LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
         }
         {
+            // V-list sums in list order, then L2L from the parent, level by level
             STAGE(QBX_STAGE_L2L);
-            for (int l = 2; l + 1 < pl.nlev; ++l) {
-                int nch = pl.level_start[l + 2] - pl.level_start[l + 1];
-                LAUNCH(QBX_STAGE_L2L, nch, launch_l2l(g, nd, l, nch, pl.P[l], G->loc, st));
+            for (int l = 2; l < pl.nlev; ++l) {
+                int nbox = pl.level_start[l + 1] - pl.level_start[l];
+                LAUNCH(QBX_STAGE_L2L, nbox, launch_down(g, nd, l, nbox, pl.P[l - 1], G->vy, G->loc, st));
             }
         }
         {

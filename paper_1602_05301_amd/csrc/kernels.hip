@@ -145,40 +145,114 @@ __global__ void k_m2m(DevGeom g, int nd, int l, cd *mp)
     }
 }
 
-// Stage 4: M2L over the V list of every box of level l (locals must be zeroed).
-__global__ void k_m2l(DevGeom g, int nd, int l, const cd *mp, cd *loc)
+// ---------------------------------------------------------------------------
+// Stage 4 as batched complex GEMM on FP64 MFMA.  For one (level, offset)
+// group the scaled M2L matrix M (n x n, n = 2P+1) multiplies up to 16
+// columns, each the scaled multipole of one V-list source box for one
+// density; column c of the result is that pair's contribution to the target
+// box's local, written to its own output row (vy) and summed in a fixed
+// order by the downward pass.  Complex product with four real MFMAs:
+//   Yr += Mr Xr - Mi Xi,  Yi += Mr Xi + Mi Xr.
+// v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16], B[l/16][l%16];
+// result D[4i + l/16][l%16] in element i.  The matrix is stored in that
+// A-operand order, 16x4 blocks of 64 complex values, block (rb, kb) at
+// (rb * NK + kb) * 64.
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int M2L_KCH = 64;   // k-blocks of 4 staged at once: 256 rows x 16 columns = 64 KiB
+
+__global__ void __launch_bounds__(256) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles,
+                                                  const cd *mp, cd *vy)
+{
+    extern __shared__ double lds_raw[];
+    cd *X = reinterpret_cast<cd *>(lds_raw);    // [min(kpad, M2L_KCH * 4)][16]
+    M2LTile t = tiles[blockIdx.x];
+    int l = t.lo / 40;
+    int P = g.Plev[l], n = 2 * P + 1;
+    int NK = (n + 3) / 4, NR = (n + 15) / 16;
+    const cd *A = g.m2l_mf + g.m2l_mf_off[t.lo];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int bk = lane >> 4, bc = lane & 15;
+    // columns' multipoles, staged in chunks of M2L_KCH k-blocks
+    auto stage = [&](int kb0, int kb1) {
+        int rows = (kb1 - kb0) * 4;
+        for (int i = threadIdx.x; i < rows * 16; i += blockDim.x) {
+            int c = i / rows, k = kb0 * 4 + i % rows;
+            cd v = mk(0.0, 0.0);
+            if (c < t.ncol && k < n) {
+                int col = t.col0 + c;
+                int pos = g.vpair_sorted[t.pair_start + col / nd];
+                int src = g.V_idx[pos];
+                v = mp[g.box_off[src] * nd + (long long)(col % nd) * n + k];
+            }
+            X[(k - kb0 * 4) * 16 + c] = v;
+        }
+    };
+    bool single = NK <= M2L_KCH;
+    if (single) {
+        stage(0, NK);
+        __syncthreads();
+    }
+    for (int rb0 = 0; rb0 < NR; rb0 += 4) {
+        int rb = rb0 + wave;
+        bool active = rb < NR;
+        d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+        const cd *Ab = A + (long long)rb * NK * 64 + lane;
+        for (int kc = 0; kc < NK; kc += M2L_KCH) {
+            int kend = min(NK, kc + M2L_KCH);
+            if (!single) {
+                __syncthreads();
+                stage(kc, kend);
+                __syncthreads();
+            }
+            if (active) {
+                int xoff = single ? 0 : kc;
+                for (int kb = kc; kb < kend; ++kb) {
+                    cd a = Ab[kb * 64];
+                    cd b = X[((kb - xoff) * 4 + bk) * 16 + bc];
+                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, yr, 0, 0, 0);
+                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, yi, 0, 0, 0);
+                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, yr, 0, 0, 0);
+                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, yi, 0, 0, 0);
+                }
+            }
+        }
+        if (active && bc < t.ncol) {
+            int col = t.col0 + bc;
+            int pos = g.vpair_sorted[t.pair_start + col / nd];
+            cd *o = vy + g.vy_off[pos] * nd + (long long)(col % nd) * n;
+            for (int i = 0; i < 4; ++i) {
+                int row = rb * 16 + 4 * i + bk;
+                if (row < n) o[row] = mk(yr[i], yi[i]);
+            }
+        }
+    }
+}
+
+// Downward pass at level l: local of every box = X-list part (already in
+// loc) + its V-list contributions in list order + L2L of the parent's local
+// (Stages 4, 6 and 7 combined).
+__global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
 {
     extern __shared__ double lds_raw[];
     cd *buf = reinterpret_cast<cd *>(lds_raw);
     int b = g.level_start[l] + blockIdx.x;
-    int v0 = g.V_start[b], v1 = g.V_start[b + 1];
-    if (v0 == v1) return;
     int P = g.Plev[l], n = 2 * P + 1;
     cd *out = loc + g.box_off[b] * nd;
-    for (int v = v0; v < v1; ++v) {
-        int s = g.V_idx[v], o = g.V_off[v];
-        const cd *src = mp + g.box_off[s] * nd;
-        for (int i = threadIdx.x; i < nd * n; i += blockDim.x) buf[i] = src[i];
-        __syncthreads();
-        apply_table(g.m2l_tab + g.m2l_off[l * 40 + o], n, n, buf, nd, out, true);
-        __syncthreads();
+    int v0 = g.V_start[b], v1 = g.V_start[b + 1];
+    for (int i = threadIdx.x; i < nd * n; i += blockDim.x) {
+        cd acc = out[i];
+        for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + i];
+        out[i] = acc;
     }
-}
-
-// Stage 7: L2L from the parent (level l) into every box of level l + 1.
-__global__ void k_l2l(DevGeom g, int nd, int l, cd *loc)
-{
-    extern __shared__ double lds_raw[];
-    cd *buf = reinterpret_cast<cd *>(lds_raw);
-    int c = g.level_start[l + 1] + blockIdx.x;
-    int b = g.parent[c];
-    int Pp = g.Plev[l], Pc = g.Plev[l + 1];
-    int np = 2 * Pp + 1, nc = 2 * Pc + 1;
-    int q = (g.bcx[c] > g.bcx[b] ? 1 : 0) | (g.bcy[c] > g.bcy[b] ? 2 : 0);
-    const cd *src = loc + g.box_off[b] * nd;
+    if (l < 3) return;
+    int par = g.parent[b];
+    int Pp = g.Plev[l - 1], np = 2 * Pp + 1;
+    int q = (g.bcx[b] > g.bcx[par] ? 1 : 0) | (g.bcy[b] > g.bcy[par] ? 2 : 0);
+    const cd *src = loc + g.box_off[par] * nd;
     for (int i = threadIdx.x; i < nd * np; i += blockDim.x) buf[i] = src[i];
     __syncthreads();
-    apply_table(g.l2l_tab + g.l2l_off[l * 4 + q], np, nc, buf, nd, loc + g.box_off[c] * nd, true);
+    apply_table(g.l2l_tab + g.l2l_off[(l - 1) * 4 + q], np, n, buf, nd, out, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -678,21 +752,23 @@ hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp,
     return hipSuccess;
 }
 
-hipError_t launch_m2l(const DevGeom &g, int nd, int l, int nbox, int P, const cd *mp, cd *loc,
-                      hipStream_t s)
+hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
+                           const cd *mp, cd *vy, hipStream_t s)
 {
-    if (!nbox) return hipSuccess;
-    size_t lds = sizeof(cd) * nd * (2 * P + 1);
-    k_m2l<<<nbox, 256, lds, s>>>(g, nd, l, mp, loc);
+    if (!ntiles) return hipSuccess;
+    int nk = std::min((2 * Pmax + 1 + 3) / 4, M2L_KCH);
+    size_t lds = sizeof(cd) * nk * 4 * 16;
+    k_m2l_mfma<<<ntiles, 256, lds, s>>>(g, nd, tiles, mp, vy);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_l2l(const DevGeom &g, int nd, int l, int nchild, int Pp, cd *loc, hipStream_t s)
+hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, int Pp, const cd *vy, cd *loc,
+                       hipStream_t s)
 {
-    if (!nchild) return hipSuccess;
+    if (!nbox) return hipSuccess;
     size_t lds = sizeof(cd) * nd * (2 * Pp + 1);
-    k_l2l<<<nchild, 256, lds, s>>>(g, nd, l, loc);
+    k_down<<<nbox, 256, lds, s>>>(g, nd, l, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

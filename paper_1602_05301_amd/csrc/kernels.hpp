@@ -27,8 +27,22 @@ struct DevGeom {
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
     const long long *box_off;                  // per box, in coefficients of one density
-    const cd *m2m_tab, *l2l_tab, *m2l_tab;
-    const long long *m2m_off, *l2l_off, *m2l_off;   // [level*4+q], [level*4+q], [level*40+o]
+    const cd *m2m_tab, *l2l_tab;
+    const long long *m2m_off, *l2l_off;        // [level*4+q]
+    // M2L as batched GEMM: per (level, offset) matrices in MFMA tile order,
+    // V-list positions grouped by (level, offset), per-position output offsets.
+    const cd *m2l_mf;                          // tiled scaled M2L matrices
+    const long long *m2l_mf_off;               // [level*40+o]
+    const int *vpair_sorted;                   // V-list positions sorted by (level, offset)
+    const long long *vy_off;                   // per V-list position: output row offset
+};
+
+// One M2L GEMM tile: up to 16 (pair, density) columns of one (level, offset) group.
+struct M2LTile {
+    int lo;           // level * 40 + offset id
+    int pair_start;   // first position in vpair_sorted of the group
+    int col0;         // first column of the tile within the group
+    int ncol;         // columns in this tile (<= 16)
 };
 
 hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
@@ -37,9 +51,10 @@ hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, 
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                       const cd *qd, cd *mp, hipStream_t s);
 hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp, hipStream_t s);
-hipError_t launch_m2l(const DevGeom &g, int nd, int l, int nbox, int P, const cd *mp, cd *loc,
-                      hipStream_t s);
-hipError_t launch_l2l(const DevGeom &g, int nd, int l, int nchild, int Pp, cd *loc, hipStream_t s);
+hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
+                           const cd *mp, cd *vy, hipStream_t s);
+hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, int Pp, const cd *vy, cd *loc,
+                       hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, hipStream_t s);
 hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
