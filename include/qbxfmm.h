@@ -64,7 +64,12 @@ typedef struct {
     int32_t leaf_max;     /* n_max: split a box holding more sources + centres (Stage 1) */
     int32_t direct;       /* 1 = form QBX coefficients directly over all sources (no FMM) */
     int32_t far_fp32;     /* reserved: FP32 far field; must be 0 in this build */
-    int32_t reserved;
+    int32_t w_direct;     /* W-list boxes (Stage 5) whose sources enter the centre's
+                             coefficients directly, as in P2QBXL, instead of through
+                             M2QBXL: -1 = when cheaper by operation count (default),
+                             0 = never (every W box through M2QBXL, as in Stage 5),
+                             n > 0 = boxes holding at most n sources.  Direct sums
+                             are exact, so the choice only removes truncation. */
     double eps_assoc;     /* association slack epsilon_assoc (Sec. 6.1); default 0.05 */
 } qbx_options;
 

@@ -78,6 +78,14 @@ struct qbx_geom_s {
     std::vector<Group> m2l_groups;
     int m2l_Pmax = 0;
     long long total_vy = 0;       // sum over V-list positions of (2 P_l + 1)
+    std::vector<int32_t> near_start, near_idx, wf_start, wf_idx;   // host copies
+    // M2QBXL work: (leaf, far W) pairs, their output rows and per-leaf ranges
+    int n_wpairs = 0;
+    long long total_wy = 0;
+    int2 *d_wpairs = nullptr;
+    long long *d_wpair_off = nullptr;
+    int *d_wleaf_start = nullptr;
+    cd *wy = nullptr;
     M2LTile *m2l_tiles[kDensChunk + 1] = {};
     int m2l_ntiles[kDensChunk + 1] = {};
     cd *vy = nullptr;
@@ -103,6 +111,20 @@ struct qbx_geom_s {
 };
 
 namespace {
+
+// Whether a W-list box's sources enter the centres' coefficients directly
+// (P2QBXL) rather than through M2QBXL.  Automatic rule: per centre, direct
+// costs about 3(2p+1) + 48 complex multiply-adds per source (coefficient
+// updates plus Bessel values), M2QBXL (2p+1)(2P_w+1).
+bool w_is_direct(const Plan &pl, int w)
+{
+    int ns = pl.src_end[w] - pl.src_begin[w];
+    int wd = pl.opt.w_direct;
+    if (wd == 0) return false;
+    if (wd > 0) return ns <= wd;
+    long long q = 2 * pl.p + 1, Pw = pl.P[pl.lev[w]];
+    return (long long)ns * (3 * q + 48) <= q * (2 * Pw + 1);
+}
 
 template <class F>
 WorkList make_list(DeviceArena &ar, const Plan &pl, F pred)
@@ -263,12 +285,52 @@ qbx_status upload(qbx_geom_s *G)
     G->xl = make_list(ar, pl, [&](int b) { return pl.X_start[b + 1] > pl.X_start[b]; });
     G->qbx = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b); });
     G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
-    G->wl = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.W_start[b + 1] > pl.W_start[b]; });
+    // Split every leaf's W list: boxes summed directly join the near list
+    // (P2QBXL), the others go through M2QBXL.
+    {
+        std::vector<int32_t> ns(nb + 1, 0), nidx, ws(nb + 1, 0), widx;
+        for (int b = 0; b < nb; ++b) {
+            for (int i = pl.U_start[b]; i < pl.U_start[b + 1]; ++i) nidx.push_back(pl.U_idx[i]);
+            for (int i = pl.W_start[b]; i < pl.W_start[b + 1]; ++i) {
+                int w = pl.W_idx[i];
+                if (w_is_direct(pl, w)) nidx.push_back(w);
+                else widx.push_back(w);
+            }
+            ns[b + 1] = (int)nidx.size();
+            ws[b + 1] = (int)widx.size();
+        }
+        G->near_start = ns; G->near_idx = nidx; G->wf_start = ws; G->wf_idx = widx;
+        g.near_start = ar.upload(ns); g.near_idx = ar.upload(nidx);
+        g.wf_start = ar.upload(ws); g.wf_idx = ar.upload(widx);
+    }
+    G->wl = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && G->wf_start[b + 1] > G->wf_start[b]; });
+    // (leaf, far W box) pairs in leaf order, their output rows, per-leaf ranges
+    {
+        std::vector<int2> pairs;
+        std::vector<long long> off;
+        std::vector<int> lstart(1, 0);
+        long long tot = 0;
+        int nq = 2 * pl.p + 1;
+        for (int b = 0; b < nb; ++b) {
+            if (!(pl.leaf[b] && has_ctr(b) && G->wf_start[b + 1] > G->wf_start[b])) continue;
+            for (int i = G->wf_start[b]; i < G->wf_start[b + 1]; ++i) {
+                pairs.push_back(make_int2(b, G->wf_idx[i]));
+                off.push_back(tot);
+                tot += (long long)(pl.ctr_end[b] - pl.ctr_begin[b]) * nq;
+            }
+            lstart.push_back((int)pairs.size());
+        }
+        G->n_wpairs = (int)pairs.size();
+        G->total_wy = tot;
+        G->d_wpairs = ar.upload(pairs);
+        G->d_wpair_off = ar.upload(off);
+        G->d_wleaf_start = ar.upload(lstart);
+    }
     // the W list needs the largest order among W boxes, not among the leaves
     int pw = 0;
     for (int b = 0; b < nb; ++b)
         if (pl.leaf[b] && has_ctr(b))
-            for (int i = pl.W_start[b]; i < pl.W_start[b + 1]; ++i) pw = std::max(pw, pl.P[pl.lev[pl.W_idx[i]]]);
+            for (int i = G->wf_start[b]; i < G->wf_start[b + 1]; ++i) pw = std::max(pw, pl.P[pl.lev[G->wf_idx[i]]]);
     G->wl.Pmax = pw;
 
     if (ar.err != hipSuccess) return fail(ar.err == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
@@ -289,12 +351,13 @@ qbx_status ensure_scratch(qbx_geom_s *G)
         G->mp = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
         G->loc = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
         G->vy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_vy, 1));
+        G->wy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_wy, 1));
     }
     if (s.err != hipSuccess) {
         hipError_t e = s.err;
         s.release();
         s.err = hipSuccess;
-        G->qs = G->qd = G->coef = G->mp = G->loc = nullptr;
+        G->qs = G->qd = G->coef = G->mp = G->loc = G->vy = G->wy = nullptr;
         return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                     std::string("scratch allocation failed: ") + hipGetErrorString(e));
     }
@@ -433,7 +496,9 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_M2QBXL);
-            LAUNCH(QBX_STAGE_M2QBXL, G->wl.n, launch_m2qbxl(g, nd, G->wl.d, G->wl.n, G->wl.Pmax, G->mp, G->coef, st));
+            LAUNCH(QBX_STAGE_M2QBXL, G->n_wpairs,
+                   launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, G->mp,
+                                 G->wy, G->wl.d, G->d_wleaf_start, G->wl.n, G->coef, st));
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
@@ -483,12 +548,12 @@ void stage_work(const qbx_geom_s *G, int nd, double *f)
                 f[QBX_STAGE_P2L_X] += 24.0 * nP(b) * (pl.src_end[c] - pl.src_begin[c]);
             }
             if (!pl.leaf[b] || nc_b == 0) continue;
-            for (int i = pl.U_start[b]; i < pl.U_start[b + 1]; ++i) {
-                int c = pl.U_idx[i];
+            for (int i = G->near_start[b]; i < G->near_start[b + 1]; ++i) {
+                int c = G->near_idx[i];
                 f[QBX_STAGE_P2QBXL] += 24.0 * cq * nc_b * (pl.src_end[c] - pl.src_begin[c]);
             }
-            for (int i = pl.W_start[b]; i < pl.W_start[b + 1]; ++i)
-                f[QBX_STAGE_M2QBXL] += 8.0 * cq * nc_b * nP(pl.W_idx[i]);
+            for (int i = G->wf_start[b]; i < G->wf_start[b + 1]; ++i)
+                f[QBX_STAGE_M2QBXL] += 8.0 * cq * nc_b * nP(G->wf_idx[i]);
             if (pl.lev[b] >= 2) f[QBX_STAGE_L2QBXL] += 8.0 * cq * nc_b * nP(b);
         }
     }

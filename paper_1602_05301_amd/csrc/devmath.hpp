@@ -74,10 +74,53 @@ __device__ inline void besselj_seq(double x, int N, double *out, int stride)
     for (int n = 1; n <= N; ++n) out[n * stride] *= s;
 }
 
-__device__ __forceinline__ void hankel01(double x, cd &h0, cd &h1)
+__device__ __attribute__((noinline)) void hankel01_lib(double x, cd &h0, cd &h1)
 {
     h0 = mk(j0(x), y0(x));
     h1 = mk(j1(x), y1(x));
+}
+
+constexpr double kSeriesMaxX = 4.0;
+
+// J0, J1, Y0, Y1 for 0 < x <= kSeriesMaxX from their ascending series
+// (DLMF 10.2.2 and 10.8.1), t = x^2/4, H_k the harmonic numbers:
+//   J0 = sum_k (-t)^k/(k!)^2,           J1 = (x/2) sum_k (-t)^k/(k!(k+1)!)
+//   Y0 = (2/pi)[(ln(x/2) + gamma) J0 - sum_k H_k (-t)^k/(k!)^2]
+//   Y1 = -2/(pi x) + (2/pi)(ln(x/2) + gamma) J1
+//        - (x/(2 pi)) sum_k (H_k + H_{k+1}) (-t)^k/(k!(k+1)!)
+// 22 terms leave a remainder below 1e-18 at x = 4; the largest term is 4, so
+// at most a few ulps are lost to cancellation.
+__device__ __forceinline__ void hankel01_series(double x, cd &h0, cd &h1)
+{
+    const double t = -0.25 * x * x;
+    double c = 1.0, d = 1.0;                      // (-t)^k/(k!)^2, (-t)^k/(k!(k+1)!)
+    double sj0 = 1.0, sj1 = 1.0, sy0 = 0.0, sy1 = 1.0;
+    double Hk = 0.0;
+#pragma unroll
+    for (int k = 1; k <= 22; ++k) {
+        c *= t * (1.0 / ((double)k * k));
+        d *= t * (1.0 / ((double)k * (k + 1)));
+        Hk += 1.0 / k;
+        double Hk1 = Hk + 1.0 / (k + 1);
+        sj0 += c;
+        sj1 += d;
+        sy0 = fma(Hk, c, sy0);
+        sy1 = fma(Hk + Hk1, d, sy1);
+    }
+    const double two_pi = 0.63661977236758134308;       // 2/pi
+    const double euler_gamma = 0.57721566490153286061;
+    double L = log(0.5 * x) + euler_gamma;
+    double J0 = sj0, J1 = 0.5 * x * sj1;
+    double Y0 = two_pi * (L * J0 - sy0);
+    double Y1 = -two_pi / x + two_pi * L * J1 - (0.5 / 3.14159265358979323846) * x * sy1;
+    h0 = mk(J0, Y0);
+    h1 = mk(J1, Y1);
+}
+
+__device__ __forceinline__ void hankel01(double x, cd &h0, cd &h1)
+{
+    if (x <= kSeriesMaxX) hankel01_series(x, h0, h1);
+    else hankel01_lib(x, h0, h1);
 }
 
 // A_n = tau^n H_n(x), n = 0..N, written to out[n * stride].  With

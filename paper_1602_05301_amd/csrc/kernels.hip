@@ -350,33 +350,36 @@ __device__ __forceinline__ void p2qbxl_pair(double omega, int p, double cx, doub
     cd upow = u;                        // u^1
     cd Op_prev, Op_cur = H0, Op_next = H1 * u;
     cd Om_prev, Om_cur = H0, Om_next = neg(H1 * conj(u));
+    cd mcnub = neg(cnub);
+    double ix2 = 2.0 / x;
     // alpha_0
     {
         cd t = qS * Op_cur;
         cfma(t, cnu, Om_next);
-        cfma(t, neg(cnub), Op_next);
+        cfma(t, mcnub, Op_next);
         acc[PB] = acc[PB] + t;
     }
 #pragma unroll
     for (int n = 1; n <= PB; ++n) {
-        if (n > p) break;
-        // advance to index n + 1
-        cd Hnext = ((2.0 * n / x) * Hcur) - Hprev;
-        Hprev = Hcur;
-        Hcur = Hnext;
-        upow = upow * u;
-        Op_prev = Op_cur; Op_cur = Op_next; Op_next = Hcur * upow;
-        Om_prev = Om_cur; Om_cur = Om_next;
-        Om_next = Hcur * conj(upow);
-        if ((n + 1) & 1) Om_next = neg(Om_next);
-        cd t = qS * Op_cur;
-        cfma(t, cnu, Op_prev);
-        cfma(t, neg(cnub), Op_next);
-        acc[PB + n] = acc[PB + n] + t;
-        cd v = qS * Om_cur;
-        cfma(v, cnu, Om_next);
-        cfma(v, neg(cnub), Om_prev);
-        acc[PB - n] = acc[PB - n] + v;
+        if (n <= p) {
+            // advance to index n + 1
+            cd Hnext = (((double)n * ix2) * Hcur) - Hprev;
+            Hprev = Hcur;
+            Hcur = Hnext;
+            upow = upow * u;
+            Op_prev = Op_cur; Op_cur = Op_next; Op_next = Hcur * upow;
+            Om_prev = Om_cur; Om_cur = Om_next;
+            Om_next = Hcur * conj(upow);
+            if ((n + 1) & 1) Om_next = neg(Om_next);
+            cd t = qS * Op_cur;
+            cfma(t, cnu, Op_prev);
+            cfma(t, mcnub, Op_next);
+            acc[PB + n] = acc[PB + n] + t;
+            cd v = qS * Om_cur;
+            cfma(v, cnu, Om_next);
+            cfma(v, mcnub, Om_prev);
+            acc[PB - n] = acc[PB - n] + v;
+        }
     }
 }
 
@@ -431,8 +434,9 @@ __global__ void __launch_bounds__(64) k_p2qbxl(DevGeom g, int nd, const int *lis
 #pragma unroll
             for (int e = 0; e < 2 * PB + 1; ++e) acc[e] = mk(0.0, 0.0);
             if (active) {
-                for (int ui = g.U_start[b]; ui < g.U_start[b + 1]; ++ui) {
-                    int ub = g.U_idx[ui];
+                for (int ui = g.near_start[b]; ui < g.near_start[b + 1]; ++ui) {
+                    int ub = g.near_idx[ui];
+#pragma unroll 1
                     for (int j = g.src_begin[ub] + part; j < g.src_end[ub]; j += parts)
                         p2qbxl_pair<PB>(g.omega, p, cx, cy, g.sx[j], g.sy[j], g.snx[j], g.sny[j],
                                         qs[(long long)d * g.ns + j], qd[(long long)d * g.ns + j], acc);
@@ -461,6 +465,7 @@ __global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, 
 #pragma unroll
         for (int e = 0; e < 2 * PB + 1; ++e) acc[e] = mk(0.0, 0.0);
         if (active)
+#pragma unroll 1
             for (int j = part; j < g.ns; j += parts)
                 p2qbxl_pair<PB>(g.omega, p, cx, cy, g.sx[j], g.sy[j], g.snx[j], g.sny[j],
                                 qs[(long long)d * g.ns + j], qd[(long long)d * g.ns + j], acc);
@@ -471,92 +476,244 @@ __global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, 
 
 // ---------------------------------------------------------------------------
 // Stage 5 (new): M2QBXL.  beta_l(c) += (-1)^l sum_k a_k O_{k+l}(c - m_w) for
-// every W box w of the leaf holding c.  With B_k = a_k = Ahat_k W_|k|,
-//   beta_l = (-1)^l tau^{-l} S+_l + tau^{l} S-_l,
-//   S+_l = sum_{k >= -l} B_k tau^{-k} A+_{k+l},  A+_n = tau^n H_n e^{+i n theta},
-//   S-_l = sum_{k < -l} B_k (-1)^k tau^{k} A-_{-k-l}, A-_n = tau^n H_n e^{-i n theta}.
+// every W box w of the leaf holding c, |l| <= p.
+// With z = c - m_w = |z| e^{i theta}, u = e^{i theta}, x = omega |z|,
+// tau = min(1, x/2) and the scaled Hankel values Hs_n = tau^n H_n(x), and the
+// stored multipole ahat_k = a_k / W_|k|:
+//   beta_l = u^l [ (-1)^l tau^{-l} S+_l + tau^l S-_l ],
+//   S+_l = sum_{n >= 0} v+_{n-l} Hs_n,  v+_k = ahat_k W_|k| tau^{-k} u^k,
+//   S-_l = sum_{n >= 1} v-_{-n-l} Hs_n, v-_k = ahat_k W_|k| tau^{k} (-u)^k,
+// (v = 0 outside |k| <= P_w).  The weights W_|k| tau^{-+k} stay <= 1 and are
+// carried as running products.  One lane holds 8 consecutive l of one
+// centre; the v values enter a sliding register window, so each step costs
+// one Hs load and one ahat load for 8 complex multiply-adds.
 // ---------------------------------------------------------------------------
-constexpr int QCG_MAX = 16;   // centres per group (upper bound)
 constexpr size_t LDS_BUDGET = 64 * 1024;
+constexpr int QCG_MAX = 16;   // centres per group (upper bound)
+constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p + QBLK
 
-__global__ void k_m2qbxl(DevGeom g, int nd, const int *list, const cd *mp, cd *coef, int QCG)
+size_t m2qbxl_lds_bytes(int nd, int Pw, int p, int cg)
+{
+    (void)nd;
+    int nw = 2 * Pw + 1, N = Pw + p;
+    return sizeof(cd) * ((size_t)nw + (size_t)cg * (N + 1) + cg) +
+           sizeof(double) * (2 * (size_t)nw + 3 * (size_t)cg);
+}
+
+// One workgroup per (leaf, far W box) pair; lanes = (centre, 8-wide l
+// block, quarter of the n range).  The four quarters of an item are adjacent
+// lanes and are summed by shuffles; the pair's coefficients go to its own
+// output rows (wy), summed per leaf in list order by k_wsum.
+constexpr int QSPLIT = 4;
+
+__device__ __forceinline__ void chunk_of(int lo, int hi, int s, int *a, int *b)
+{
+    int len = hi - lo + 1;
+    int cs = (len + QSPLIT - 1) / QSPLIT;
+    *a = lo + s * cs;
+    *b = min(*a + cs - 1, hi);
+}
+
+__global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *pairs,
+                                                const long long *pair_off, const cd *mp, cd *wy,
+                                                int QCG)
 {
     extern __shared__ double lds_raw[];
-    int b = list[blockIdx.x];
-    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    int2 pr = pairs[blockIdx.x];
+    int b = pr.x, w = pr.y;
+    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b], nct = c1 - c0;
     int p = g.p, nq = 2 * p + 1;
-    long long ncoef = nq;
-    for (int wi = g.W_start[b]; wi < g.W_start[b + 1]; ++wi) {
-        int w = g.W_idx[wi];
-        int lw = g.blev[w];
-        int Pw = g.Plev[lw], nw = 2 * Pw + 1;
-        int N = Pw + p;
-        const double *logW = g.logW + g.Woff[lw];
-        // LDS layout
-        cd *Bw = reinterpret_cast<cd *>(lds_raw);                 // [nd][nw] scaled multipole
-        cd *Ap = Bw + nd * nw;                                    // [QCG][N+1]
-        cd *Am = Ap + QCG * (N + 1);                              // [QCG][N+1]
-        double *wp = reinterpret_cast<double *>(Am + QCG * (N + 1));  // [QCG][nw]
-        double *wm = wp + QCG * nw;                               // [QCG][nw]
-        double *ltau = wm + QCG * nw;                             // [QCG]
-        // scaled multipole ahat_k; W_|k| enters through the per-centre weights
-        const cd *src = mp + g.box_off[w] * nd;
-        for (int i = threadIdx.x; i < nd * nw; i += blockDim.x) Bw[i] = src[i];
-        double mx = g.bcx[w], my = g.bcy[w];
-        for (int cg = c0; cg < c1; cg += QCG) {
-            int cnt = min(QCG, c1 - cg);
-            if ((int)threadIdx.x < cnt) {
-                int i = cg + threadIdx.x;
+    int nblk = (nq + QBLK - 1) / QBLK;
+    int tid = threadIdx.x;
+    int lw = g.blev[w];
+    int Pw = g.Plev[lw], nw = 2 * Pw + 1;
+    int N = Pw + p;
+    cd *Aw = reinterpret_cast<cd *>(lds_raw);          // [nw]
+    cd *Hs = Aw + nw;                                  // [QCG][N+1]
+    cd *U = Hs + QCG * (N + 1);                        // [QCG]
+    double *rup = reinterpret_cast<double *>(U + QCG); // [nw], W_|k+1| / W_|k|
+    double *rdn = rup + nw;                            // [nw], W_|k-1| / W_|k|
+    double *TAU = rdn + nw;                            // [QCG]
+    double *LT = TAU + QCG;                            // [QCG]
+    double *TH = LT + QCG;                             // [QCG]
+    const double *Wt = g.Wtab + g.Woff[lw], *iW = g.invW + g.Woff[lw];
+    const double *logW = g.logW + g.Woff[lw];
+    for (int i = tid; i < nw; i += blockDim.x) {
+        int k = i - Pw, ak = k < 0 ? -k : k;
+        int kp = k + 1, km = k - 1;
+        rup[i] = k < Pw ? Wt[kp < 0 ? -kp : kp] * iW[ak] : 0.0;
+        rdn[i] = k > -Pw ? Wt[km < 0 ? -km : km] * iW[ak] : 0.0;
+    }
+    double mx = g.bcx[w], my = g.bcy[w];
+    cd *out_pair = wy + pair_off[blockIdx.x] * nd;
+    for (int d = 0; d < nd; ++d) {
+        const cd *src = mp + g.box_off[w] * nd + (long long)d * nw;
+        for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
+            int cnt = min(QCG, c1 - cg0);
+            __syncthreads();
+            for (int i = tid; i < nw; i += blockDim.x) Aw[i] = src[i];
+            if (tid < cnt) {
+                int i = cg0 + tid;
                 double dx = g.cx[i] - mx, dy = g.cy[i] - my;
-                double x = g.omega * sqrt(dx * dx + dy * dy);
+                double r = sqrt(dx * dx + dy * dy);
+                double x = g.omega * r;
                 double tau = fmin(1.0, 0.5 * x);
-                double th = atan2(dy, dx);
-                cd *ap = Ap + threadIdx.x * (N + 1);
-                cd *am = Am + threadIdx.x * (N + 1);
-                scaled_hankel_seq(x, tau, N, ap, 1);
-                for (int n = 0; n <= N; ++n) {
-                    double sn, cs;
-                    sincos((double)n * th, &sn, &cs);
-                    cd a = ap[n];
-                    ap[n] = a * mk(cs, sn);
-                    am[n] = a * mk(cs, -sn);
+                scaled_hankel_seq(x, tau, N, Hs + tid * (N + 1), 1);
+                U[tid] = mk(dx / r, dy / r);
+                TAU[tid] = tau;
+                LT[tid] = log(tau);
+                TH[tid] = atan2(dy, dx);
+            }
+            __syncthreads();
+            int items = cnt * nblk;
+            for (int it0 = 0; it0 < items; it0 += 256 / QSPLIT) {
+                int it = it0 + tid / QSPLIT, sp = tid % QSPLIT;
+                bool active = it < items;
+                int t = active ? it % cnt : 0;
+                int l0 = active ? -p + QBLK * (it / cnt) : -p;
+                cd beta[QBLK];
+#pragma unroll
+                for (int e = 0; e < QBLK; ++e) beta[e] = mk(0.0, 0.0);
+                const cd *hs = Hs + t * (N + 1);
+                cd u = U[t];
+                double tau = TAU[t], lt = LT[t], th = TH[t], itau = 1.0 / tau;
+                const cd *A = Aw + Pw;
+                const double *ru = rup + Pw, *rd = rdn + Pw;
+                cd acc[QBLK], win[QBLK];
+                if (active) {
+                    // ---- S+ over n in this lane's quarter of [0, nmax] ----
+                    int nmax = min(Pw + l0 + QBLK - 1, N);
+                    int na, nb;
+                    chunk_of(0, nmax, sp, &na, &nb);
+#pragma unroll
+                    for (int e = 0; e < QBLK; ++e) { acc[e] = mk(0.0, 0.0); win[e] = mk(0.0, 0.0); }
+                    if (na <= nb) {
+                        int k = na - QBLK - l0;                   // first element
+                        int ak = k < 0 ? -k : k;
+                        double mag = exp(logW[ak] - k * lt);      // W_|k| tau^{-k}
+                        double sn, cs;
+                        sincos((double)k * th, &sn, &cs);
+                        cd ph = mk(cs, sn);                       // u^k
+                        for (int n0 = na - QBLK; n0 <= nb; n0 += QBLK) {
+#pragma unroll
+                            for (int s = 0; s < QBLK; ++s) {
+                                int n = n0 + s;
+                                int kk = n - l0;
+                                cd v = mk(0.0, 0.0);
+                                if (kk >= -Pw && kk <= Pw) {
+                                    v = (mag * A[kk]) * ph;
+                                    mag *= ru[kk] * itau;
+                                }
+                                ph = ph * u;
+                                win[s] = v;
+                                if (n >= na && n <= nb) {
+                                    cd h = hs[n];
+#pragma unroll
+                                    for (int e = 0; e < QBLK; ++e) cfma(acc[e], win[(s - e + QBLK) % QBLK], h);
+                                }
+                            }
+                        }
+                    }
+                    {
+                        double sn0, cs0;
+                        sincos((double)l0 * th, &sn0, &cs0);
+                        cd ul = mk(cs0, sn0);
+                        double f = exp(-l0 * lt);
+#pragma unroll
+                        for (int e = 0; e < QBLK; ++e) {
+                            double fe = ((l0 + e) & 1) ? -f : f;
+                            beta[e] = beta[e] + fe * (ul * acc[e]);
+                            ul = ul * u;
+                            f *= itau;
+                        }
+                    }
+                    // ---- S- over n in this lane's quarter of [1, nmax] ----
+                    nmax = min(Pw - l0, N);
+                    chunk_of(1, nmax, sp, &na, &nb);
+#pragma unroll
+                    for (int e = 0; e < QBLK; ++e) { acc[e] = mk(0.0, 0.0); win[e] = mk(0.0, 0.0); }
+                    if (na <= nb) {
+                        int k = -na - l0;                         // element m = na
+                        int ak = k < 0 ? -k : k;
+                        double mag = exp(logW[ak] + k * lt);      // W_|k| tau^{k}
+                        double sn, cs;
+                        sincos((double)k * th, &sn, &cs);
+                        cd ph = mk(cs, sn);
+                        if (k & 1) ph = neg(ph);                   // (-u)^k
+                        cd mub = neg(conj(u));                     // (-u)^{-1}
+                        for (int n0 = na - QBLK; n0 <= nb; n0 += QBLK) {
+#pragma unroll
+                            for (int s = 0; s < QBLK; ++s) {
+                                int n = n0 + s;
+                                // use elements m = n .. n+7 first: the new one
+                                // (m = n + 8) takes the slot of m = n
+                                if (n >= na && n <= nb) {
+                                    cd h = hs[n];
+#pragma unroll
+                                    for (int e = 0; e < QBLK; ++e) cfma(acc[e], win[(s + e) % QBLK], h);
+                                }
+                                int kk = -(n + QBLK) - l0;
+                                cd v = mk(0.0, 0.0);
+                                if (kk >= -Pw && kk <= Pw) v = (mag * A[kk]) * ph;
+                                if (kk > -Pw && kk <= Pw) mag *= rd[kk] * itau;
+                                ph = ph * mub;
+                                win[s] = v;
+                            }
+                        }
+                    }
+                    {
+                        double sn0, cs0;
+                        sincos((double)l0 * th, &sn0, &cs0);
+                        cd ul = mk(cs0, sn0);
+                        double f = exp(l0 * lt);
+#pragma unroll
+                        for (int e = 0; e < QBLK; ++e) {
+                            beta[e] = beta[e] + f * (ul * acc[e]);
+                            ul = ul * u;
+                            f *= tau;
+                        }
+                    }
                 }
-                ltau[threadIdx.x] = log(tau);
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < cnt * nw; i += blockDim.x) {
-                int t = i / nw, k = i % nw - Pw;
-                double lt = ltau[t];
-                double lwk = logW[k < 0 ? -k : k];
-                wp[t * nw + k + Pw] = exp(lwk - k * lt);
-                double v = exp(lwk + k * lt);
-                wm[t * nw + k + Pw] = (k & 1) ? -v : v;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < cnt * nq; i += blockDim.x) {
-                int t = i / nq, ell = i % nq - p;
-                const cd *ap = Ap + t * (N + 1);
-                const cd *am = Am + t * (N + 1);
-                const double *wpt = wp + t * nw + Pw;
-                const double *wmt = wm + t * nw + Pw;
-                double lt = ltau[t];
-                double fp = exp(-ell * lt), fm = exp(ell * lt);
-                if (ell & 1) fp = -fp;
-                int ci = cg + t;
-                for (int d = 0; d < nd; ++d) {
-                    const cd *B = Bw + d * nw + Pw;
-                    cd sp = mk(0.0, 0.0), sm = mk(0.0, 0.0);
-                    int klo = max(-Pw, -ell);
-                    for (int k = klo; k <= Pw; ++k) cfma(sp, wpt[k] * B[k], ap[k + ell]);
-                    int khi = min(Pw, -ell - 1);
-                    for (int k = -Pw; k <= khi; ++k) cfma(sm, wmt[k] * B[k], am[-k - ell]);
-                    cd beta = fp * sp + fm * sm;
-                    cd *o = coef + ((long long)d * ncoef + ell + p) * g.nc + ci;
-                    *o = *o + beta;
+                // sum the quarters (adjacent lanes)
+#pragma unroll
+                for (int e = 0; e < QBLK; ++e) {
+                    double re = beta[e].x, im = beta[e].y;
+                    for (int m = 1; m < QSPLIT; m <<= 1) {
+                        re += __shfl_xor(re, m, 64);
+                        im += __shfl_xor(im, m, 64);
+                    }
+                    beta[e] = mk(re, im);
+                }
+                if (active && sp == 0) {
+                    int ci = cg0 - c0 + t;
+                    cd *o = out_pair + ((long long)d * nct + ci) * nq;
+#pragma unroll
+                    for (int e = 0; e < QBLK; ++e) {
+                        int ell = l0 + e;
+                        if (ell <= p) o[ell + p] = beta[e];
+                    }
                 }
             }
-            __syncthreads();
         }
+    }
+}
+
+// coef[d][l][i] += sum over the leaf's far-W pairs (list order) of their rows.
+__global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_pair_start,
+                       const long long *pair_off, const cd *wy, cd *coef)
+{
+    int li = blockIdx.x;
+    int b = leaf_list[li];
+    int c0 = g.ctr_begin[b], nct = g.ctr_end[b] - c0;
+    int p = g.p, nq = 2 * p + 1;
+    int q0 = leaf_pair_start[li], q1 = leaf_pair_start[li + 1];
+    for (int idx = threadIdx.x; idx < nd * nct * nq; idx += blockDim.x) {
+        int d = idx / (nct * nq), rem = idx % (nct * nq);
+        int ci = rem / nq, l = rem % nq;
+        cd acc = mk(0.0, 0.0);
+        for (int q = q0; q < q1; ++q) acc = acc + wy[pair_off[q] * nd + idx];
+        cd *o = coef + ((long long)d * nq + l) * g.nc + c0 + ci;
+        *o = *o + acc;
     }
 }
 
@@ -796,6 +953,8 @@ hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const
 {
     if (!n) return hipSuccess;
     if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 12) return p2qbxl_dispatch<12>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 14) return p2qbxl_dispatch<14>(g, nd, list, n, qs, qd, coef, s);
     if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, list, n, qs, qd, coef, s);
     if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, list, n, qs, qd, coef, s);
     if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, list, n, qs, qd, coef, s);
@@ -817,17 +976,12 @@ hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd
 {
     if (!g.nc) return hipSuccess;
     if (g.p <= 8) return p2qbxl_direct_dispatch<8>(g, nd, qs, qd, coef, s);
+    if (g.p <= 12) return p2qbxl_direct_dispatch<12>(g, nd, qs, qd, coef, s);
+    if (g.p <= 14) return p2qbxl_direct_dispatch<14>(g, nd, qs, qd, coef, s);
     if (g.p <= 16) return p2qbxl_direct_dispatch<16>(g, nd, qs, qd, coef, s);
     if (g.p <= 24) return p2qbxl_direct_dispatch<24>(g, nd, qs, qd, coef, s);
     if (g.p <= 32) return p2qbxl_direct_dispatch<32>(g, nd, qs, qd, coef, s);
     return p2qbxl_direct_dispatch<40>(g, nd, qs, qd, coef, s);
-}
-
-size_t m2qbxl_lds_bytes(int nd, int Pw, int p, int cg)
-{
-    int nw = 2 * Pw + 1, N = Pw + p;
-    return sizeof(cd) * ((size_t)nd * nw + 2 * (size_t)cg * (N + 1)) +
-           sizeof(double) * (2 * (size_t)cg * nw + cg);
 }
 
 static int pick_cg(size_t (*bytes)(int, int, int, int), int nd, int P, int p)
@@ -837,14 +991,18 @@ static int pick_cg(size_t (*bytes)(int, int, int, int), int nd, int P, int p)
     return cg;
 }
 
-hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int *list, int n, int PWmax,
-                         const cd *mp, cd *coef, hipStream_t s)
+hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off,
+                         int npairs, int PWmax, const cd *mp, cd *wy, const int *leaf_list,
+                         const int *leaf_pair_start, int nleaf, cd *coef, hipStream_t s)
 {
-    if (!n) return hipSuccess;
-    int cg = pick_cg(m2qbxl_lds_bytes, nd, PWmax, g.p);
+    if (!npairs) return hipSuccess;
+    int cg = 16;
+    while (cg > 1 && m2qbxl_lds_bytes(nd, PWmax, g.p, cg) > LDS_BUDGET) cg >>= 1;
     size_t lds = m2qbxl_lds_bytes(nd, PWmax, g.p, cg);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-    k_m2qbxl<<<n, 256, lds, s>>>(g, nd, list, mp, coef, cg);
+    k_m2qbxl<<<npairs, 256, lds, s>>>(g, nd, pairs, pair_off, mp, wy, cg);
+    QBX_LAUNCH_CHECK();
+    k_wsum<<<nleaf, 256, 0, s>>>(g, nd, leaf_list, leaf_pair_start, pair_off, wy, coef);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

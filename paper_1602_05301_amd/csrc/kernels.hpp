@@ -23,6 +23,8 @@ struct DevGeom {
     const int *src_begin, *src_end, *ctr_begin, *ctr_end;
     const int *level_start;
     const int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
+    // near list of a leaf = U list + W boxes summed directly; far W = the rest
+    const int *near_start, *near_idx, *wf_start, *wf_idx;
     const int *Plev;                           // FMM order per level
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
@@ -61,8 +63,9 @@ hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const
                          const cd *qd, cd *coef, hipStream_t s);
 hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *coef,
                                 hipStream_t s);
-hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int *list, int n, int PWmax,
-                         const cd *mp, cd *coef, hipStream_t s);
+hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off,
+                         int npairs, int PWmax, const cd *mp, cd *wy, const int *leaf_list,
+                         const int *leaf_pair_start, int nleaf, cd *coef, hipStream_t s);
 hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
                          const cd *loc, cd *coef, hipStream_t s);
 hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s);

@@ -495,6 +495,7 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
     if (opt.far_fp32 != 0) return {QBX_E_UNSUPPORTED, "far_fp32 is not available in this build"};
     if (!(opt.eps_assoc >= 0 && opt.eps_assoc < 1)) return {QBX_E_INVAL, "eps_assoc must lie in [0, 1)"};
     if (opt.p_add < -1 || opt.p_add > 200) return {QBX_E_INVAL, "p_add must be -1 or in 0..200"};
+    if (opt.w_direct < -1) return {QBX_E_INVAL, "w_direct must be -1, 0 or a positive source count"};
     if (ns && (!sx || !sy || !w || !nx || !ny || !sh)) return {QBX_E_INVAL, "null source array"};
     if (nc && (!cx || !cy || !cr)) return {QBX_E_INVAL, "null centre array"};
     if (nt && (!tx || !ty)) return {QBX_E_INVAL, "null target array"};
@@ -531,7 +532,9 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
     pl.pfmm.assign(pl.nlev, 0);
     for (int l = 0; l < pl.nlev; ++l) {
         pl.pfmm[l] = fmm_order(omega, pl.box_radius(l), eps);
-        pl.P[l] = pl.pfmm[l] + pl.p_add;
+        // the M2QBXL kernel's 8-wide l window needs P_l >= p + 8 (more terms
+        // only add accuracy)
+        pl.P[l] = std::max(pl.pfmm[l] + pl.p_add, pl.p + 8);
         if (pl.P[l] > kMaxOrder && l >= 2)
             return {QBX_E_UNSUPPORTED, "FMM order at level " + std::to_string(l) + " exceeds 400 (omega * box size too large)"};
         pl.P[l] = std::min(pl.P[l], kMaxOrder);

@@ -43,7 +43,7 @@ class QbxError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("p_add", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("direct", ctypes.c_int32), ("far_fp32", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("eps_assoc", ctypes.c_double)]
+                ("w_direct", ctypes.c_int32), ("eps_assoc", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -117,10 +117,11 @@ def _check(status):
         raise QbxError(status, lib().qbx_last_error().decode())
 
 
-def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05) -> Options:
+def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05, w_direct=-1) -> Options:
     o = Options()
     lib().qbx_options_default(ctypes.byref(o))
     o.p, o.p_add, o.leaf_max, o.direct, o.eps_assoc = int(p), int(p_add), int(leaf_max), int(bool(direct)), float(eps_assoc)
+    o.w_direct = int(w_direct)
     return o
 
 

@@ -107,12 +107,25 @@ def test_fmm_matches_oracle_fmm_stage_by_stage(ctx, n_panels, omega, p, p_add, l
     tc = np.arange(g.n, dtype=np.int32)
     eps = 1e-10
     _, u, coef = _eval(ctx, g, omega, eps, g.sx, g.sy, tc, ss, sd, coef=True, p=p,
-                       p_add=p_add, leaf_max=leaf_max)
+                       p_add=p_add, leaf_max=leaf_max, w_direct=0)
     t = otree.build(g.sx, g.sy, g.cx, g.cy, leaf_max)
     P = ofmm.orders(omega, t["R0"], int(t["level"].max()) + 1, eps, p_add)
     u_o, alpha_o = ofmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, leaf_max)
     assert _rel(u, u_o) < 1e-13
     assert _coef_err(coef, alpha_o, omega, g.cr, p) < 1e-12
+
+
+@pytest.mark.parametrize("w_direct", [0, 4, -1, 100000])
+def test_w_list_direct_switch(ctx, w_direct):
+    """Every way of splitting the W lists between M2QBXL and direct sums
+    agrees with direct QBX to the tolerance (100000 = every W box direct)."""
+    wl = inputs.fmm_star(n_panels=128, omega=40.0, eps=1e-10, p=12)
+    g = wl.geom
+    _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                 p=wl.p, w_direct=w_direct)
+    ref = oracle.direct_qbx(wl.omega, wl.p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d,
+                            tgt_ctr=wl.tgt_ctr)
+    assert _rel(u, ref) < wl.eps
 
 
 def test_fmm_full_size_sampled(ctx):
