@@ -88,6 +88,11 @@ struct qbx_geom_s {
     cd *wy = nullptr;
     M2LTile *m2l_tiles[kDensChunk + 1] = {};
     int m2l_ntiles[kDensChunk + 1] = {};
+    // M2M parents per level, L2L children per (level, quadrant), and their tiles
+    std::vector<int> par_list, par_lvl, chl_list, chl_lvl;
+    int *d_par_list = nullptr, *d_chl_list = nullptr;
+    TTile *m2m_tiles[kDensChunk + 1] = {}, *l2l_tiles[kDensChunk + 1] = {};
+    std::vector<int> m2m_tstart[kDensChunk + 1], l2l_tstart[kDensChunk + 1];   // per level
     cd *vy = nullptr;
     // per-eval scratch, sized for kDensChunk densities
     DeviceArena scratch;
@@ -238,47 +243,70 @@ qbx_status upload(qbx_geom_s *G)
     }
     g.vpair_sorted = ar.upload(vpos);
     g.vy_off = ar.upload(vy_off);
-    auto append_T = [](std::vector<cd> &dst, const std::vector<std::complex<double>> &T, int nout,
-                       int nin) {
+    // Row-major [out][in] matrix -> v_mfma_f64_16x16x4f64 A-operand order:
+    // 16x4 blocks of 64 values, block (rb, kb) at (rb * NK + kb) * 64, lane l
+    // holding element (rb*16 + l%16, kb*4 + l/16), zero outside the matrix.
+    auto append_tiled = [](std::vector<cd> &dst, const std::vector<std::complex<double>> &M, int nout,
+                           int nin) {
+        int NR = (nout + 15) / 16, NK = (nin + 3) / 4;
         long long off = (long long)dst.size();
-        dst.resize(dst.size() + (size_t)nout * nin);
-        for (int j = 0; j < nout; ++j)
-            for (int k = 0; k < nin; ++k) {
-                const auto &v = T[(size_t)j * nin + k];
-                dst[off + (size_t)k * nout + j] = mk(v.real(), v.imag());
-            }
+        dst.resize(dst.size() + (size_t)NR * NK * 64, mk(0.0, 0.0));
+        for (int rb = 0; rb < NR; ++rb)
+            for (int kb = 0; kb < NK; ++kb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    int row = rb * 16 + lane % 16, k = kb * 4 + lane / 16;
+                    if (row < nout && k < nin) {
+                        const auto &v = M[(size_t)row * nin + k];
+                        dst[off + ((size_t)rb * NK + kb) * 64 + lane] = mk(v.real(), v.imag());
+                    }
+                }
         return off;
     };
     if (!pl.opt.direct) {
         for (int l = 2; l + 1 < pl.nlev; ++l)
             for (int q = 0; q < 4; ++q) {
                 int np = 2 * pl.P[l] + 1, nc = 2 * pl.P[l + 1] + 1;
-                m2m_off[l * 4 + q] = append_T(m2m, m2m_matrix(pl, l, q), np, nc);
-                l2l_off[l * 4 + q] = append_T(l2l, l2l_matrix(pl, l, q), nc, np);
+                m2m_off[l * 4 + q] = append_tiled(m2m, m2m_matrix(pl, l, q), np, nc);
+                l2l_off[l * 4 + q] = append_tiled(l2l, l2l_matrix(pl, l, q), nc, np);
             }
-        // M2L matrices in MFMA A-operand order (see k_m2l_mfma)
         for (const auto &grp : G->m2l_groups) {
             int l = grp.key / 40, o = grp.key % 40;
             int dx, dy;
             v_offset_from_id(o, &dx, &dy);
-            int n = 2 * pl.P[l] + 1, NR = (n + 15) / 16, NK = (n + 3) / 4;
-            auto M = m2l_matrix(pl, l, dx, dy);   // row-major [out][in]
-            long long off = (long long)m2l.size();
-            m2l.resize(m2l.size() + (size_t)NR * NK * 64, mk(0.0, 0.0));
-            for (int rb = 0; rb < NR; ++rb)
-                for (int kb = 0; kb < NK; ++kb)
-                    for (int lane = 0; lane < 64; ++lane) {
-                        int row = rb * 16 + lane % 16, k = kb * 4 + lane / 16;
-                        if (row < n && k < n) {
-                            const auto &v = M[(size_t)row * n + k];
-                            m2l[off + ((size_t)rb * NK + kb) * 64 + lane] = mk(v.real(), v.imag());
-                        }
-                    }
-            m2l_off[grp.key] = off;
+            int n = 2 * pl.P[l] + 1;
+            m2l_off[grp.key] = append_tiled(m2l, m2l_matrix(pl, l, dx, dy), n, n);
         }
     }
-    g.m2m_tab = ar.upload(m2m); g.l2l_tab = ar.upload(l2l); g.m2l_mf = ar.upload(m2l);
-    g.m2m_off = ar.upload(m2m_off); g.l2l_off = ar.upload(l2l_off); g.m2l_mf_off = ar.upload(m2l_off);
+    g.m2m_mf = ar.upload(m2m); g.l2l_mf = ar.upload(l2l); g.m2l_mf = ar.upload(m2l);
+    g.m2m_mf_off = ar.upload(m2m_off); g.l2l_mf_off = ar.upload(l2l_off); g.m2l_mf_off = ar.upload(m2l_off);
+
+    // children by quadrant; M2M parent lists and L2L child lists per level
+    {
+        std::vector<int> child4((size_t)nb * 4, -1);
+        for (int b = 0; b < nb; ++b)
+            for (int c = pl.child_begin[b]; c >= 0 && c < pl.child_begin[b] + pl.child_count[b]; ++c)
+                child4[(size_t)b * 4 + ((pl.bix[c] & 1) | ((pl.biy[c] & 1) << 1))] = c;
+        g.child4 = ar.upload(child4);
+        G->par_list.clear();
+        G->par_lvl.assign(pl.nlev + 1, 0);
+        for (int l = 0; l < pl.nlev; ++l) {
+            G->par_lvl[l] = (int)G->par_list.size();
+            for (int b = pl.level_start[l]; b < pl.level_start[l + 1]; ++b)
+                if (!pl.leaf[b] && l >= 2) G->par_list.push_back(b);
+        }
+        G->par_lvl[pl.nlev] = (int)G->par_list.size();
+        G->chl_list.clear();
+        G->chl_lvl.assign((size_t)(pl.nlev + 1) * 4, 0);
+        for (int L = 0; L < pl.nlev; ++L)
+            for (int q = 0; q < 4; ++q) {
+                G->chl_lvl[L * 4 + q] = (int)G->chl_list.size();
+                for (int c = pl.level_start[L]; c < pl.level_start[L + 1]; ++c)
+                    if (L >= 3 && ((pl.bix[c] & 1) | ((pl.biy[c] & 1) << 1)) == q) G->chl_list.push_back(c);
+            }
+        G->chl_lvl[pl.nlev * 4] = (int)G->chl_list.size();
+        G->d_par_list = ar.upload(G->par_list);
+        G->d_chl_list = ar.upload(G->chl_list);
+    }
 
     auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
     G->p2m = make_list(ar, pl, [&](int b) { return pl.leaf[b] && pl.lev[b] >= 2; });
@@ -368,7 +396,7 @@ qbx_status ensure_scratch(qbx_geom_s *G)
 // its (pair, density) combinations, cut into tiles of 16.
 qbx_status ensure_tiles(qbx_geom_s *G, int nd)
 {
-    if (G->m2l_tiles[nd] || G->m2l_groups.empty()) return QBX_OK;
+    if (G->m2m_tiles[nd]) return QBX_OK;
     std::vector<M2LTile> t;
     for (const auto &grp : G->m2l_groups) {
         int cols = grp.count * nd;
@@ -376,6 +404,28 @@ qbx_status ensure_tiles(qbx_geom_s *G, int nd)
     }
     G->m2l_tiles[nd] = G->scratch.upload(t);
     G->m2l_ntiles[nd] = (int)t.size();
+    // M2M: per parent level, 16-column tiles of (parent, density)
+    int nlev = G->pl.nlev;
+    std::vector<TTile> tm, tl;
+    G->m2m_tstart[nd].assign(nlev + 1, 0);
+    for (int l = 0; l < nlev; ++l) {
+        G->m2m_tstart[nd][l] = (int)tm.size();
+        int s0 = G->par_lvl[l], cols = (G->par_lvl[l + 1] - s0) * nd;
+        for (int c0 = 0; c0 < cols; c0 += 16) tm.push_back({0, s0, c0, std::min(16, cols - c0)});
+    }
+    G->m2m_tstart[nd][nlev] = (int)tm.size();
+    // L2L: per child level, per quadrant, 16-column tiles of (child, density)
+    G->l2l_tstart[nd].assign(nlev + 1, 0);
+    for (int L = 0; L < nlev; ++L) {
+        G->l2l_tstart[nd][L] = (int)tl.size();
+        for (int q = 0; q < 4; ++q) {
+            int s0 = G->chl_lvl[L * 4 + q], cols = (G->chl_lvl[L * 4 + q + 1] - s0) * nd;
+            for (int c0 = 0; c0 < cols; c0 += 16) tl.push_back({q, s0, c0, std::min(16, cols - c0)});
+        }
+    }
+    G->l2l_tstart[nd][nlev] = (int)tl.size();
+    G->m2m_tiles[nd] = G->scratch.upload(tm);
+    G->l2l_tiles[nd] = G->scratch.upload(tl);
     if (G->scratch.err != hipSuccess) {
         hipError_t e = G->scratch.err;
         G->scratch.err = hipSuccess;
@@ -465,15 +515,16 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_M2M);
+            qbx_status ts = ensure_tiles(G, nd);
+            if (ts != QBX_OK) return ts;
             for (int l = pl.nlev - 2; l >= 2; --l) {
-                int nbox = pl.level_start[l + 1] - pl.level_start[l];
-                LAUNCH(QBX_STAGE_M2M, nbox, launch_m2m(g, nd, l, nbox, pl.P[l + 1], G->mp, st));
+                int t0 = G->m2m_tstart[nd][l], nt = G->m2m_tstart[nd][l + 1] - t0;
+                int nrb = (2 * pl.P[l] + 1 + 15) / 16;
+                LAUNCH(QBX_STAGE_M2M, nt, launch_m2m_mfma(g, nd, l, G->m2m_tiles[nd] + t0, nt, nrb, G->d_par_list, G->mp, st));
             }
         }
         {
             STAGE(QBX_STAGE_M2L);
-            qbx_status ts = ensure_tiles(G, nd);
-            if (ts != QBX_OK) return ts;
             LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
                    launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->mp, G->vy, st));
         }
@@ -485,9 +536,14 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         {
             // V-list sums in list order, then L2L from the parent, level by level
             STAGE(QBX_STAGE_L2L);
-            for (int l = 2; l < pl.nlev; ++l) {
-                int nbox = pl.level_start[l + 1] - pl.level_start[l];
-                LAUNCH(QBX_STAGE_L2L, nbox, launch_down(g, nd, l, nbox, pl.P[l - 1], G->vy, G->loc, st));
+            if (pl.nlev > 2) {
+                int nbox = pl.level_start[3] - pl.level_start[2];
+                LAUNCH(QBX_STAGE_L2L, nbox, launch_down(g, nd, 2, nbox, G->vy, G->loc, st));
+            }
+            for (int L = 3; L < pl.nlev; ++L) {
+                int t0 = G->l2l_tstart[nd][L], nt = G->l2l_tstart[nd][L + 1] - t0;
+                int nrb = (2 * pl.P[L] + 1 + 15) / 16;
+                LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, G->vy, G->loc, st));
             }
         }
         {

@@ -108,44 +108,6 @@ __global__ void k_p2m(DevGeom g, int nd, const int *list, const cd *qs, const cd
 }
 
 // ---------------------------------------------------------------------------
-// Dense scaled translation (M2M, L2L, M2L): out[d][j] (+)= sum_k T[k][j] in[d][k].
-// ---------------------------------------------------------------------------
-__device__ inline void apply_table(const cd *T, int nin, int nout, const cd *in_lds, int nd,
-                                   cd *out, bool accumulate)
-{
-    for (int j = threadIdx.x; j < nout; j += blockDim.x) {
-        for (int d = 0; d < nd; ++d) {
-            cd acc = accumulate ? out[d * nout + j] : mk(0.0, 0.0);
-            const cd *x = in_lds + d * nin;
-            for (int k = 0; k < nin; ++k) cfma(acc, T[(long long)k * nout + j], x[k]);
-            out[d * nout + j] = acc;
-        }
-    }
-}
-
-// Stage 2b: M2M into every non-leaf box of level l from its children.
-__global__ void k_m2m(DevGeom g, int nd, int l, cd *mp)
-{
-    extern __shared__ double lds_raw[];
-    cd *buf = reinterpret_cast<cd *>(lds_raw);
-    int b = g.level_start[l] + blockIdx.x;
-    if (g.leaf[b]) return;
-    int Pp = g.Plev[l], Pc = g.Plev[l + 1];
-    int np = 2 * Pp + 1, nc = 2 * Pc + 1;
-    cd *out = mp + g.box_off[b] * nd;
-    bool first = true;
-    for (int c = g.child_begin[b]; c < g.child_begin[b] + g.child_count[b]; ++c) {
-        int q = (g.bcx[c] > g.bcx[b] ? 1 : 0) | (g.bcy[c] > g.bcy[b] ? 2 : 0);
-        const cd *src = mp + g.box_off[c] * nd;
-        for (int i = threadIdx.x; i < nd * nc; i += blockDim.x) buf[i] = src[i];
-        __syncthreads();
-        apply_table(g.m2m_tab + g.m2m_off[l * 4 + q], nc, np, buf, nd, out, !first);
-        first = false;
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Stage 4 as batched complex GEMM on FP64 MFMA.  For one (level, offset)
 // group the scaled M2L matrix M (n x n, n = 2P+1) multiplies up to 16
 // columns, each the scaled multipole of one V-list source box for one
@@ -229,13 +191,10 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(DevGeom g, int nd, const M2LTi
     }
 }
 
-// Downward pass at level l: local of every box = X-list part (already in
-// loc) + its V-list contributions in list order + L2L of the parent's local
-// (Stages 4, 6 and 7 combined).
+// Level-2 part of the downward pass: local = X-list part (already in loc)
+// + the box's V-list contributions in list order (no parent local exists).
 __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
 {
-    extern __shared__ double lds_raw[];
-    cd *buf = reinterpret_cast<cd *>(lds_raw);
     int b = g.level_start[l] + blockIdx.x;
     int P = g.Plev[l], n = 2 * P + 1;
     cd *out = loc + g.box_off[b] * nd;
@@ -245,14 +204,93 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
         for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + i];
         out[i] = acc;
     }
-    if (l < 3) return;
-    int par = g.parent[b];
-    int Pp = g.Plev[l - 1], np = 2 * Pp + 1;
-    int q = (g.bcx[b] > g.bcx[par] ? 1 : 0) | (g.bcy[b] > g.bcy[par] ? 2 : 0);
-    const cd *src = loc + g.box_off[par] * nd;
-    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) buf[i] = src[i];
+}
+
+// One 16x16 output block of a scaled translation on FP64 MFMA: rows
+// rb*16.., the lane's column given by bptr (nin complex inputs, NULL = 0).
+// The table is in A-operand order (see k_m2l_mfma), NK k-blocks per row block.
+__device__ __forceinline__ void trans_block(const cd *Arow, int NK, const cd *bptr, int nin, int lane,
+                                            d4 &yr, d4 &yi)
+{
+    int bk = lane >> 4;
+    for (int kb = 0; kb < NK; ++kb) {
+        cd a = Arow[kb * 64 + lane];
+        int k = kb * 4 + bk;
+        cd b = (bptr && k < nin) ? bptr[k] : mk(0.0, 0.0);
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, yi, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, yi, 0, 0, 0);
+    }
+}
+
+// Stage 2b: M2M into the non-leaf boxes of level l.  Block = (tile of 16
+// (parent, density) columns, row block); wave q applies the child-quadrant-q
+// matrix; the four partial blocks are summed in quadrant order.
+__global__ void __launch_bounds__(256) k_m2m_mfma(DevGeom g, int nd, int l, const TTile *tiles,
+                                                  const int *plist, cd *mp)
+{
+    __shared__ double part[3][64][8];
+    TTile t = tiles[blockIdx.x];
+    int rb = blockIdx.y;
+    int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    int np = 2 * g.Plev[l] + 1, nc = 2 * g.Plev[l + 1] + 1;
+    int NKc = (nc + 3) / 4;
+    int bc = lane & 15, bk = lane >> 4;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    int par = valid ? plist[t.start + col / nd] : 0;
+    int d = col % nd;
+    int child = valid ? g.child4[par * 4 + q] : -1;
+    const cd *bptr = child >= 0 ? mp + g.box_off[child] * nd + (long long)d * nc : nullptr;
+    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    if (__any(child >= 0))
+        trans_block(g.m2m_mf + g.m2m_mf_off[l * 4 + q] + (long long)rb * NKc * 64, NKc, bptr, nc, lane, yr, yi);
+    if (q > 0) {
+        for (int i = 0; i < 4; ++i) { part[q - 1][lane][i] = yr[i]; part[q - 1][lane][4 + i] = yi[i]; }
+    }
     __syncthreads();
-    apply_table(g.l2l_tab + g.l2l_off[(l - 1) * 4 + q], np, n, buf, nd, out, true);
+    if (q == 0 && valid) {
+        for (int w = 0; w < 3; ++w)
+            for (int i = 0; i < 4; ++i) { yr[i] += part[w][lane][i]; yi[i] += part[w][lane][4 + i]; }
+        cd *o = mp + g.box_off[par] * nd + (long long)d * np;
+        for (int i = 0; i < 4; ++i) {
+            int row = rb * 16 + 4 * i + bk;
+            if (row < np) o[row] = mk(yr[i], yi[i]);
+        }
+    }
+}
+
+// Stage 7 (levels >= 3): local of a child = X-list part (already in loc) +
+// its V-list contributions in list order + L2L of the parent's local.
+// Block = one wave = (tile of 16 (child, density) columns of one quadrant, row block).
+__global__ void __launch_bounds__(64) k_l2l_mfma(DevGeom g, int nd, int L, const TTile *tiles,
+                                                 const int *clist, const cd *vy, cd *loc)
+{
+    TTile t = tiles[blockIdx.x];
+    int rb = blockIdx.y;
+    int lane = threadIdx.x;
+    int nc = 2 * g.Plev[L] + 1, np = 2 * g.Plev[L - 1] + 1;
+    int NKp = (np + 3) / 4;
+    int bc = lane & 15, bk = lane >> 4;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    int child = valid ? clist[t.start + col / nd] : 0;
+    int d = col % nd;
+    const cd *bptr = valid ? loc + g.box_off[g.parent[child]] * nd + (long long)d * np : nullptr;
+    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    trans_block(g.l2l_mf + g.l2l_mf_off[(L - 1) * 4 + t.q] + (long long)rb * NKp * 64, NKp, bptr, np,
+                lane, yr, yi);
+    if (!valid) return;
+    long long base = g.box_off[child] * nd + (long long)d * nc;
+    int v0 = g.V_start[child], v1 = g.V_start[child + 1];
+    for (int i = 0; i < 4; ++i) {
+        int row = rb * 16 + 4 * i + bk;
+        if (row >= nc) continue;
+        cd acc = loc[base + row];
+        for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + (long long)d * nc + row];
+        loc[base + row] = acc + mk(yr[i], yi[i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -900,11 +938,20 @@ hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax
     return hipSuccess;
 }
 
-hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp, hipStream_t s)
+hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
+                           int nrb, const int *plist, cd *mp, hipStream_t s)
 {
-    if (!nbox) return hipSuccess;
-    size_t lds = sizeof(cd) * nd * (2 * Pc + 1);
-    k_m2m<<<nbox, 256, lds, s>>>(g, nd, l, mp);
+    if (!ntiles) return hipSuccess;
+    k_m2m_mfma<<<dim3(ntiles, nrb), 256, 0, s>>>(g, nd, l, tiles, plist, mp);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
+                           const int *clist, const cd *vy, cd *loc, hipStream_t s)
+{
+    if (!ntiles) return hipSuccess;
+    k_l2l_mfma<<<dim3(ntiles, nrb), 64, 0, s>>>(g, nd, L, tiles, clist, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -920,12 +967,11 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
     return hipSuccess;
 }
 
-hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, int Pp, const cd *vy, cd *loc,
+hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,
                        hipStream_t s)
 {
     if (!nbox) return hipSuccess;
-    size_t lds = sizeof(cd) * nd * (2 * Pp + 1);
-    k_down<<<nbox, 256, lds, s>>>(g, nd, l, vy, loc);
+    k_down<<<nbox, 256, 0, s>>>(g, nd, l, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

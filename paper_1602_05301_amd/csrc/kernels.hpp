@@ -29,14 +29,26 @@ struct DevGeom {
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
     const long long *box_off;                  // per box, in coefficients of one density
-    const cd *m2m_tab, *l2l_tab;
-    const long long *m2m_off, *l2l_off;        // [level*4+q]
+    // M2M / L2L scaled matrices per (parent level, child quadrant) in MFMA
+    // A-operand order; child4[b*4+q] = child of b in quadrant q or -1
+    const cd *m2m_mf, *l2l_mf;
+    const long long *m2m_mf_off, *l2l_mf_off;  // [level*4+q]
+    const int *child4;
     // M2L as batched GEMM: per (level, offset) matrices in MFMA tile order,
     // V-list positions grouped by (level, offset), per-position output offsets.
     const cd *m2l_mf;                          // tiled scaled M2L matrices
     const long long *m2l_mf_off;               // [level*40+o]
     const int *vpair_sorted;                   // V-list positions sorted by (level, offset)
     const long long *vy_off;                   // per V-list position: output row offset
+};
+
+// One M2M / L2L GEMM tile: up to 16 (box, density) columns taken from a box
+// list (parents of one level, or the children of one level in quadrant q).
+struct TTile {
+    int q;            // child quadrant (L2L)
+    int start;        // first position of the list
+    int col0;         // first column of the tile
+    int ncol;         // columns in this tile (<= 16)
 };
 
 // One M2L GEMM tile: up to 16 (pair, density) columns of one (level, offset) group.
@@ -52,10 +64,13 @@ hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, 
                           hipStream_t s);
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                       const cd *qd, cd *mp, hipStream_t s);
-hipError_t launch_m2m(const DevGeom &g, int nd, int l, int nbox, int Pc, cd *mp, hipStream_t s);
+hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
+                           int nrb, const int *plist, cd *mp, hipStream_t s);
+hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
+                           const int *clist, const cd *vy, cd *loc, hipStream_t s);
 hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
                            const cd *mp, cd *vy, hipStream_t s);
-hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, int Pp, const cd *vy, cd *loc,
+hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,
                        hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, hipStream_t s);
