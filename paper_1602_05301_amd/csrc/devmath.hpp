@@ -1,7 +1,8 @@
 // Complex arithmetic and Bessel/Hankel sequences for the gfx950 kernels.
 //
 // Hankel functions H_n^{(1)}(x) = J_n(x) + i Y_n(x) of real argument: H_0 and
-// H_1 from the HIP device math library (j0, y0, j1, y1), higher orders by the
+// H_1 from their ascending series for x <= 4 and from the HIP device math
+// library (j0, y0, j1, y1) above, higher orders by the
 // upward three-term recurrence H_{n+1} = (2n/x) H_n - H_{n-1}, which is
 // stable because Y_n dominates.  J_n by Miller's backward recurrence,
 // normalised against whichever of J_0(x), J_1(x) is larger in magnitude.
@@ -72,6 +73,13 @@ __device__ inline void besselj_seq(double x, int N, double *out, int stride)
     double s = fabs(jz) >= fabs(jo) ? jz / f : jo / f1;
     out[0] = jz;
     for (int n = 1; n <= N; ++n) out[n * stride] *= s;
+}
+
+// Out-of-line copy for kernels whose hot loop should not share registers with
+// the recurrence.
+__device__ __attribute__((noinline)) void besselj_seq_call(double x, int N, double *out, int stride)
+{
+    besselj_seq(x, N, out, stride);
 }
 
 __device__ __attribute__((noinline)) void hankel01_lib(double x, cd &h0, cd &h1)

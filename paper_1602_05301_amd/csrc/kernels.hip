@@ -756,60 +756,131 @@ __global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_
 }
 
 // ---------------------------------------------------------------------------
-// Stage 8 (new): L2QBXL.  gamma_l(c) += sum_k g_k I_{l-k}(m_b - c), with the
-// box local g_k = ghat_k / W_|k|.
+// L2QBXL: gamma_l(c) += sum_k g_k I_{l-k}(z), z = m_b - c, with the box local
+// g_k = ghat_k / W_|k|.  Writing z = (x/omega) u, |u| = 1, and
+// I_n(z) = J_n(x) u^n with J_{-n} = (-1)^n J_n,
+//   gamma_l = u^l sum_n gt_{l-n} J_n(x),   gt_k = g_k conj(u)^k,
+// a real-by-complex correlation.  One lane holds 8 consecutive l of one
+// centre and a quarter of the n range; gt enters a sliding register window
+// (its phase is a running product), J_n comes from an LDS table filled by
+// Miller's recurrence, one lane per centre.
 // ---------------------------------------------------------------------------
-__global__ void k_l2qbxl(DevGeom g, int nd, const int *list, const cd *loc, cd *coef, int QCG)
+size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
+{
+    int np = 2 * P + 1, N = P + p + QBLK - 1;
+    return sizeof(cd) * ((size_t)nd * np + (size_t)cg) +
+           sizeof(double) * ((size_t)cg * (N + 1) + (size_t)cg);
+}
+
+__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const cd *loc,
+                                                cd *coef, int QCG)
 {
     extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
     int l = g.blev[b];
     int P = g.Plev[l], np = 2 * P + 1;
     int p = g.p, nq = 2 * p + 1;
-    int N = P + p;
+    int nblk = (nq + QBLK - 1) / QBLK;
+    int N = P + p + QBLK - 1;                          // largest |n| any lane reads
     int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    int tid = threadIdx.x;
     cd *Gb = reinterpret_cast<cd *>(lds_raw);          // [nd][np]
-    cd *Iv = Gb + nd * np;                             // [QCG][2N+1]
-    double *Jt = reinterpret_cast<double *>(Iv + QCG * (2 * N + 1));  // [QCG][N+1]
+    cd *U = Gb + nd * np;                              // [QCG]
+    double *Jt = reinterpret_cast<double *>(U + QCG);  // [QCG][N+1]
+    double *TH = Jt + QCG * (N + 1);                   // [QCG]
     const double *iw = g.invW + g.Woff[l];
     const cd *src = loc + g.box_off[b] * nd;
-    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) {
+    for (int i = tid; i < nd * np; i += blockDim.x) {
         int k = i % np - P;
         Gb[i] = iw[k < 0 ? -k : k] * src[i];
     }
     double mx = g.bcx[b], my = g.bcy[b];
-    for (int cg = c0; cg < c1; cg += QCG) {
-        int cnt = min(QCG, c1 - cg);
-        if ((int)threadIdx.x < cnt) {
-            int i = cg + threadIdx.x;
+    for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
+        int cnt = min(QCG, c1 - cg0);
+        __syncthreads();
+        if (tid < cnt) {
+            int i = cg0 + tid;
             double dx = mx - g.cx[i], dy = my - g.cy[i];
-            double x = g.omega * sqrt(dx * dx + dy * dy);
-            double th = atan2(dy, dx);
-            double *jt = Jt + threadIdx.x * (N + 1);
-            besselj_seq(x, N, jt, 1);
-            cd *iv = Iv + threadIdx.x * (2 * N + 1) + N;
-            for (int n = 0; n <= N; ++n) {
-                double sn, cs;
-                sincos((double)n * th, &sn, &cs);
-                iv[n] = jt[n] * mk(cs, sn);
-                double jm = (n & 1) ? -jt[n] : jt[n];
-                iv[-n] = jm * mk(cs, -sn);
-            }
+            double r = sqrt(dx * dx + dy * dy);
+            besselj_seq_call(g.omega * r, N, Jt + tid * (N + 1), 1);
+            U[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
+            TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < cnt * nq; i += blockDim.x) {
-            int t = i / nq, ell = i % nq - p;
-            const cd *iv = Iv + t * (2 * N + 1) + N;
-            int ci = cg + t;
-            for (int d = 0; d < nd; ++d) {
-                const cd *G = Gb + d * np + P;
-                cd acc = mk(0.0, 0.0);
-                for (int k = -P; k <= P; ++k) cfma(acc, G[k], iv[ell - k]);
-                cd *o = coef + ((long long)d * nq + ell + p) * g.nc + ci;
-                *o = *o + acc;
+        int items = nd * cnt * nblk;
+        for (int it0 = 0; it0 < items; it0 += 256 / QSPLIT) {
+            int it = it0 + tid / QSPLIT, sp = tid % QSPLIT;
+            bool active = it < items;
+            int t = active ? it % cnt : 0;
+            int rest = active ? it / cnt : 0;
+            int d = rest / nblk;
+            int l0 = -p + QBLK * (rest % nblk);
+            cd acc[QBLK], win[QBLK];
+#pragma unroll
+            for (int e = 0; e < QBLK; ++e) { acc[e] = mk(0.0, 0.0); win[e] = mk(0.0, 0.0); }
+            const double *jt = Jt + t * (N + 1);
+            const cd *G = Gb + d * np + P;
+            cd u = U[t];
+            double th = TH[t];
+            if (active) {
+                int na, nb;
+                chunk_of(l0 - P, l0 + QBLK - 1 + P, sp, &na, &nb);
+                if (na <= nb) {
+                    int k = l0 - (na - QBLK);                 // element of the first step
+                    double sn, cs;
+                    sincos((double)k * th, &sn, &cs);
+                    cd ph = mk(cs, -sn);                      // conj(u)^k
+#pragma unroll 1
+                    for (int n0 = na - QBLK; n0 <= nb; n0 += QBLK) {
+#pragma unroll
+                        for (int s = 0; s < QBLK; ++s) {
+                            int n = n0 + s;
+                            int kk = l0 - n;
+                            cd v = mk(0.0, 0.0);
+                            if (kk >= -P && kk <= P) v = G[kk] * ph;
+                            ph = ph * u;
+                            win[s] = v;
+                            if (n >= na && n <= nb) {
+                                int an = n < 0 ? -n : n;
+                                double jn = jt[an];
+                                if (n < 0 && (an & 1)) jn = -jn;
+#pragma unroll
+                                for (int e = 0; e < QBLK; ++e) {
+                                    cd w = win[(s - e + QBLK) % QBLK];
+                                    acc[e].x = fma(w.x, jn, acc[e].x);
+                                    acc[e].y = fma(w.y, jn, acc[e].y);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            // sum the quarters (adjacent lanes)
+#pragma unroll
+            for (int e = 0; e < QBLK; ++e) {
+                double re = acc[e].x, im = acc[e].y;
+                for (int m = 1; m < QSPLIT; m <<= 1) {
+                    re += __shfl_xor(re, m, 64);
+                    im += __shfl_xor(im, m, 64);
+                }
+                acc[e] = mk(re, im);
+            }
+            if (active && sp == 0) {
+                double sn0, cs0;
+                sincos((double)l0 * th, &sn0, &cs0);
+                cd ul = mk(cs0, sn0);                         // u^l
+                int ci = cg0 + t;
+#pragma unroll
+                for (int e = 0; e < QBLK; ++e) {
+                    int ell = l0 + e;
+                    if (ell <= p) {
+                        cd *o = coef + ((long long)d * nq + ell + p) * g.nc + ci;
+                        *o = *o + ul * acc[e];
+                    }
+                    ul = ul * u;
+                }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -1051,12 +1122,6 @@ hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long
     k_wsum<<<nleaf, 256, 0, s>>>(g, nd, leaf_list, leaf_pair_start, pair_off, wy, coef);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
-}
-
-size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
-{
-    int np = 2 * P + 1, N = P + p;
-    return sizeof(cd) * ((size_t)nd * np + (size_t)cg * (2 * N + 1)) + sizeof(double) * (size_t)cg * (N + 1);
 }
 
 hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
