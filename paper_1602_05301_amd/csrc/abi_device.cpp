@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -196,6 +197,15 @@ qbx_status upload(qbx_geom_s *G)
     g.W_start = ar.upload(pl.W_start); g.W_idx = ar.upload(pl.W_idx);
     g.X_start = ar.upload(pl.X_start); g.X_idx = ar.upload(pl.X_idx);
     g.Plev = ar.upload(pl.P);
+    {
+        // ln n! for the series form of J_n (orders up to max P_l + p + 8)
+        int nf = pl.p + 10;
+        for (int v : pl.P) nf = std::max(nf, v + pl.p + 10);
+        std::vector<double> lf(nf);
+        for (int n = 0; n < nf; ++n) lf[n] = (double)lgammal((long double)n + 1.0L);
+        g.n_lnfact = nf;
+        g.lnfact = ar.upload(lf);
+    }
 
     std::vector<int> woff(pl.nlev + 1, 0);
     std::vector<double> W, iW, lW;

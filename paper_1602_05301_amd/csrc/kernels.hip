@@ -41,69 +41,161 @@ __global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, c
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2a: P2M at leaves (a_k = q L_k(s - m), dipole via L_{k +- 1}).
-// One block per leaf; sources in chunks of P2M_CH; J sequences in LDS.
+// J_n(x_t), n = 0..N, for the block's arguments x_t (t < cnt), every one at
+// most kSeriesMaxX, written to out[t * ld + n * st].  Block-cooperative, one
+// (t, n) per thread step, from the ascending series (DLMF 10.2.2)
+//   J_n(x) = (x/2)^n / n! * sum_k (-x^2/4)^k / (k! (n+1)_k),
+// prefactor exp(n ln(x/2) - ln n!) with lhx[t] = ln(x_t / 2).  Terms fall
+// off at least like 4^k/(k!)^2 here, so the sum stops once a term drops
+// below 1e-17 of it (40 terms at most).
 // ---------------------------------------------------------------------------
-constexpr int P2M_CH = 8;
-
-__global__ void k_p2m(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *mp)
+__device__ __attribute__((noinline)) void besselj_table_series(const double *X, const double *lhx, int cnt, int N,
+                                     const double *lnfact, double *out, int ld, int st)
 {
-    extern __shared__ double lds[];
+    int tot = cnt * (N + 1);
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+        int t = it / (N + 1), n = it - t * (N + 1);
+        double x = X[t];
+        double v;
+        if (x == 0.0) {
+            v = n == 0 ? 1.0 : 0.0;
+        } else {
+            double q = -0.25 * x * x;
+            double term = 1.0, sum = 1.0;
+            for (int k = 1; k <= 40; ++k) {
+                term *= q / ((double)k * (double)(n + k));
+                sum += term;
+                if (fabs(term) <= 1e-17 * fabs(sum)) break;
+            }
+            v = n == 0 ? sum : exp((double)n * lhx[t] - lnfact[n]) * sum;
+        }
+        out[t * ld + n * st] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shared layout of the per-source expansion tables (P2M, X-list P2L).
+// A pass takes up to CH sources; for each, row t of T holds the 2P+3
+// basis values of orders n = -(P+1)..P+1 at T[t*(2P+3) + P+1 + n], built in
+// two steps: one lane per source runs the radial recurrence into the
+// non-negative half, then lanes (source, run of PT_SEG orders) attach the
+// phases (one sincos per run, running products after it) and fill the
+// negative orders.  Per-source weights of the three terms (charge, and the
+// dipole's two neighbours) sit in Wt[t][d][3].  Each thread then owns output
+// orders tid, tid + 256 and sums over the pass's sources in source order.
+// ---------------------------------------------------------------------------
+constexpr int PT_SEG = 8;
+constexpr int PT_KR = 2;      // output orders per thread: 2P+1 <= 512
+
+size_t ptab_lds_bytes(int nd, int P, int ch)
+{
+    return (size_t)ch * ((2 * (size_t)P + 3) * sizeof(cd) + 3 * (size_t)nd * sizeof(cd) + sizeof(cd) +
+                         3 * sizeof(double));
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2a: P2M at leaves, a_k = sum_j qS_j L_k(s_j - m) +
+// (omega/2) qD_j (conj(nu_j) L_{k-1} - nu_j L_{k+1}), stored as a_k / W_|k|.
+// L_n(z) = J_n(x) conj(v)^n with z = (x/omega) v, |v| = 1, and
+// L_{-n} = (-1)^n J_n v^n.
+// ---------------------------------------------------------------------------
+template <int ND>
+__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd,
+                                             cd *mp, int CH)
+{
+    extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
     int l = g.blev[b];
-    int P = g.Plev[l];
-    int J = P + 2;
-    double *Jb = lds;                    // [P2M_CH][J]
-    double *th = lds + P2M_CH * J;       // [P2M_CH]
-    double mx = g.bcx[b], my = g.bcy[b];
-    int np = 2 * P + 1;
-    cd *out = mp + g.box_off[b] * nd;
-    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) out[i] = mk(0.0, 0.0);
+    int P = g.Plev[l], np = 2 * P + 1, NT = 2 * P + 3;
+    cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT]
+    cd *Wt = T + CH * NT;                              // [CH][ND][3]
+    cd *V = Wt + CH * ND * 3;                          // [CH]
+    double *TH = reinterpret_cast<double *>(V + CH);   // [CH]
+    double *XA = TH + CH;                              // [CH] omega |s - m|
+    double *LH = XA + CH;                              // [CH] ln(x / 2)
+    int tid = threadIdx.x;
+    double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
+    cd acc[PT_KR][ND];
+#pragma unroll
+    for (int r = 0; r < PT_KR; ++r)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[r][d] = mk(0.0, 0.0);
     int s_begin = g.src_begin[b], s_end = g.src_end[b];
-    double hw = 0.5 * g.omega;
-    for (int s0 = s_begin; s0 < s_end; s0 += P2M_CH) {
-        int cnt = min(P2M_CH, s_end - s0);
-        if ((int)threadIdx.x < cnt) {
-            int j = s0 + threadIdx.x;
+    int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
+    for (int s0 = s_begin; s0 < s_end; s0 += CH) {
+        int cnt = min(CH, s_end - s0);
+        __syncthreads();
+        bool big = false;
+        if (tid < cnt) {
+            int j = s0 + tid;
             double dx = g.sx[j] - mx, dy = g.sy[j] - my;
             double r = sqrt(dx * dx + dy * dy);
-            besselj_seq(g.omega * r, P + 1, Jb + threadIdx.x * J, 1);
-            th[threadIdx.x] = atan2(dy, dx);
+            double x = g.omega * r;
+            XA[tid] = x;
+            LH[tid] = log(0.5 * x);
+            big = x > kSeriesMaxX;
+            V[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
+            TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
+            cd nu = mk(g.snx[j], g.sny[j]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                cd c = qd[(long long)d * g.ns + j];
+                cd *w = Wt + (tid * ND + d) * 3;
+                w[0] = qs[(long long)d * g.ns + j];
+                w[1] = hw * (c * conj(nu));
+                w[2] = neg(hw * (c * nu));
+            }
+        }
+        if (__syncthreads_or(big)) {
+            if (tid < cnt) besselj_seq_call(XA[tid], P + 1, &T[tid * NT + P + 1].x, 2);
+        } else {
+            besselj_table_series(XA, LH, cnt, P + 1, g.lnfact, &T[P + 1].x, 2 * NT, 2);
         }
         __syncthreads();
-        for (int kk = threadIdx.x; kk < np; kk += blockDim.x) {
-            int k = kk - P;
-            for (int t = 0; t < cnt; ++t) {
-                int j = s0 + t;
-                const double *Jt = Jb + t * J;
-                double L[3][2];
-                for (int e = 0; e < 3; ++e) {
-                    int n = k - 1 + e;
-                    int an = n < 0 ? -n : n;
-                    double jv = Jt[an];
-                    if (n < 0 && (an & 1)) jv = -jv;
-                    double sn, cs;
-                    sincos(-(double)n * th[t], &sn, &cs);
-                    L[e][0] = jv * cs;
-                    L[e][1] = jv * sn;
-                }
-                cd Lm = mk(L[0][0], L[0][1]), L0 = mk(L[1][0], L[1][1]), Lp = mk(L[2][0], L[2][1]);
-                cd nu = mk(g.snx[j], g.sny[j]);
-                cd dip = hw * (conj(nu) * Lm - nu * Lp);
-                for (int d = 0; d < nd; ++d) {
-                    cd acc = out[d * np + kk];
-                    cfma(acc, qs[(long long)d * g.ns + j], L0);
-                    cfma(acc, qd[(long long)d * g.ns + j], dip);
-                    out[d * np + kk] = acc;
-                }
+        for (int it = tid; it < cnt * nseg; it += blockDim.x) {
+            int t = it % cnt, n0 = (it / cnt) * PT_SEG;
+            cd v = V[t];
+            double sn, cs;
+            sincos((double)n0 * TH[t], &sn, &cs);
+            cd ph = mk(cs, sn);                        // v^n
+            cd *row = T + t * NT + P + 1;
+            for (int n = n0; n < n0 + PT_SEG && n <= P + 1; ++n) {
+                double jn = row[n].x;
+                row[n] = jn * conj(ph);
+                if (n > 0) row[-n] = ((n & 1) ? -jn : jn) * ph;
+                ph = ph * v;
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PT_KR; ++r) {
+            int kk = tid + 256 * r;
+            if (kk < np) {
+                for (int t = 0; t < cnt; ++t) {
+                    const cd *row = T + t * NT + kk + 1;   // order k = kk - P at row[0]
+                    cd lm = row[-1], l0 = row[0], lp = row[1];
+                    const cd *w = Wt + t * ND * 3;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        cfma(acc[r][d], w[3 * d], l0);
+                        cfma(acc[r][d], w[3 * d + 1], lm);
+                        cfma(acc[r][d], w[3 * d + 2], lp);
+                    }
+                }
+            }
+        }
     }
     const double *iw = g.invW + g.Woff[l];
-    for (int i = threadIdx.x; i < nd * np; i += blockDim.x) {
-        int k = i % np - P;
-        out[i] = iw[k < 0 ? -k : k] * out[i];
+    cd *out = mp + g.box_off[b] * ND;
+#pragma unroll
+    for (int r = 0; r < PT_KR; ++r) {
+        int kk = tid + 256 * r;
+        if (kk < np) {
+            int k = kk - P;
+            double f = iw[k < 0 ? -k : k];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) out[d * np + kk] = f * acc[r][d];
+        }
     }
 }
 
@@ -121,6 +213,7 @@ __global__ void k_p2m(DevGeom g, int nd, const int *list, const cd *qs, const cd
 // (rb * NK + kb) * 64.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TB_U = 4;      // k-blocks whose table operands are loaded ahead
 constexpr int M2L_KCH = 64;   // k-blocks of 4 staged at once: 256 rows x 16 columns = 64 KiB
 
 __global__ void __launch_bounds__(256) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles,
@@ -169,13 +262,28 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(DevGeom g, int nd, const M2LTi
             }
             if (active) {
                 int xoff = single ? 0 : kc;
-                for (int kb = kc; kb < kend; ++kb) {
-                    cd a = Ab[kb * 64];
-                    cd b = X[((kb - xoff) * 4 + bk) * 16 + bc];
-                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, yr, 0, 0, 0);
-                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, yi, 0, 0, 0);
-                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, yr, 0, 0, 0);
-                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, yi, 0, 0, 0);
+                // table operands of the next TB_U k-blocks load during the current ones
+                cd a[TB_U];
+#pragma unroll
+                for (int u = 0; u < TB_U; ++u) a[u] = kc + u < kend ? Ab[(kc + u) * 64] : mk(0.0, 0.0);
+                for (int kb = kc; kb < kend; kb += TB_U) {
+                    cd an[TB_U];
+#pragma unroll
+                    for (int u = 0; u < TB_U; ++u) {
+                        int kn = kb + TB_U + u;
+                        an[u] = kn < kend ? Ab[kn * 64] : mk(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < TB_U; ++u) {
+                        int kk = min(kb + u, kend - 1);
+                        cd b = X[((kk - xoff) * 4 + bk) * 16 + bc];
+                        if (kb + u >= kend) b = mk(0.0, 0.0);
+                        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b.x, yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b.y, yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b.y, yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b.x, yi, 0, 0, 0);
+                        a[u] = an[u];
+                    }
                 }
             }
         }
@@ -206,37 +314,84 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
     }
 }
 
-// One 16x16 output block of a scaled translation on FP64 MFMA: rows
-// rb*16.., the lane's column given by bptr (nin complex inputs, NULL = 0).
-// The table is in A-operand order (see k_m2l_mfma), NK k-blocks per row block.
-__device__ __forceinline__ void trans_block(const cd *Arow, int NK, const cd *bptr, int nin, int lane,
-                                            d4 &yr, d4 &yi)
+// Part of one 16x16 output block of a scaled translation on FP64 MFMA: rows
+// rb*16.. (Arow points at the row block), k-blocks [kb0, kb1), the lane's
+// column given by bptr (nin complex inputs, NULL = 0).  The table is in
+// A-operand order (see k_m2l_mfma).  Operands of the next TB_U k-blocks are
+// loaded while the current ones go through the matrix core.
+__device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const cd *bptr, int nin,
+                                        int lane, cd *a, cd *b)
 {
     int bk = lane >> 4;
-    for (int kb = 0; kb < NK; ++kb) {
-        cd a = Arow[kb * 64 + lane];
-        int k = kb * 4 + bk;
-        cd b = (bptr && k < nin) ? bptr[k] : mk(0.0, 0.0);
-        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, yi, 0, 0, 0);
-        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, yi, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < TB_U; ++u) {
+        int kbu = kb + u, k = kbu * 4 + bk;
+        a[u] = kbu < kb1 ? Arow[kbu * 64 + lane] : mk(0.0, 0.0);
+        b[u] = (kbu < kb1 && bptr && k < nin) ? bptr[k] : mk(0.0, 0.0);
     }
 }
 
-// Stage 2b: M2M into the non-leaf boxes of level l.  Block = (tile of 16
-// (parent, density) columns, row block); wave q applies the child-quadrant-q
-// matrix; the four partial blocks are summed in quadrant order.
-__global__ void __launch_bounds__(256) k_m2m_mfma(DevGeom g, int nd, int l, const TTile *tiles,
-                                                  const int *plist, cd *mp)
+__device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, const cd *bptr, int nin,
+                                            int lane, d4 &yr, d4 &yi)
 {
-    __shared__ double part[3][64][8];
+    cd a[TB_U], b[TB_U];
+    tb_load(Arow, kb0, kb1, bptr, nin, lane, a, b);
+    for (int kb = kb0; kb < kb1; kb += TB_U) {
+        cd an[TB_U], bn[TB_U];
+        tb_load(Arow, kb + TB_U, kb1, bptr, nin, lane, an, bn);
+#pragma unroll
+        for (int u = 0; u < TB_U; ++u) {
+            yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, yi, 0, 0, 0);
+            yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, yi, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < TB_U; ++u) { a[u] = an[u]; b[u] = bn[u]; }
+    }
+}
+
+// k-block range of part h of NK split in KS near-equal parts
+__device__ __forceinline__ void ksplit(int NK, int KS, int h, int *kb0, int *kb1)
+{
+    int c = (NK + KS - 1) / KS;
+    *kb0 = min(NK, h * c);
+    *kb1 = min(NK, *kb0 + c);
+}
+
+// Partial 16x16 blocks of the waves of one workgroup: element i of lane l is
+// D[4i + l/16][l%16]; padded to 9 doubles per lane against bank conflicts.
+__device__ __forceinline__ void tb_store(double (*part)[9], int lane, const d4 &yr, const d4 &yi)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { part[lane][i] = yr[i]; part[lane][4 + i] = yi[i]; }
+}
+
+// Sum of the nw partial blocks (in wave order) at output row r, column c.
+__device__ __forceinline__ cd tb_sum(const double (*part)[64][9], int nw, int r, int c)
+{
+    int ln = (r & 3) * 16 + c, i = r >> 2;
+    cd y = mk(0.0, 0.0);
+    for (int w = 0; w < nw; ++w) y = y + mk(part[w][ln][i], part[w][ln][4 + i]);
+    return y;
+}
+
+// Stage 2b: M2M into the non-leaf boxes of level l.  Block = (tile of 16
+// (parent, density) columns, row block); wave w applies the child-quadrant
+// (w % 4) matrix over half (w / 4) of its k-blocks; the eight partial blocks
+// are summed in wave order.
+constexpr int M2M_KS = 2;
+
+__global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, int l, const TTile *tiles,
+                                                           const int *plist, cd *mp)
+{
+    __shared__ double part[4 * M2M_KS][64][9];
     TTile t = tiles[blockIdx.x];
     int rb = blockIdx.y;
-    int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = w & 3, h = w >> 2;
     int np = 2 * g.Plev[l] + 1, nc = 2 * g.Plev[l + 1] + 1;
     int NKc = (nc + 3) / 4;
-    int bc = lane & 15, bk = lane >> 4;
+    int bc = lane & 15;
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
     int par = valid ? plist[t.start + col / nd] : 0;
@@ -244,123 +399,182 @@ __global__ void __launch_bounds__(256) k_m2m_mfma(DevGeom g, int nd, int l, cons
     int child = valid ? g.child4[par * 4 + q] : -1;
     const cd *bptr = child >= 0 ? mp + g.box_off[child] * nd + (long long)d * nc : nullptr;
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    int kb0, kb1;
+    ksplit(NKc, M2M_KS, h, &kb0, &kb1);
     if (__any(child >= 0))
-        trans_block(g.m2m_mf + g.m2m_mf_off[l * 4 + q] + (long long)rb * NKc * 64, NKc, bptr, nc, lane, yr, yi);
-    if (q > 0) {
-        for (int i = 0; i < 4; ++i) { part[q - 1][lane][i] = yr[i]; part[q - 1][lane][4 + i] = yi[i]; }
-    }
+        trans_block(g.m2m_mf + g.m2m_mf_off[l * 4 + q] + (long long)rb * NKc * 64, kb0, kb1, bptr, nc,
+                    lane, yr, yi);
+    tb_store(part[w], lane, yr, yi);
     __syncthreads();
-    if (q == 0 && valid) {
-        for (int w = 0; w < 3; ++w)
-            for (int i = 0; i < 4; ++i) { yr[i] += part[w][lane][i]; yi[i] += part[w][lane][4 + i]; }
-        cd *o = mp + g.box_off[par] * nd + (long long)d * np;
-        for (int i = 0; i < 4; ++i) {
-            int row = rb * 16 + 4 * i + bk;
-            if (row < np) o[row] = mk(yr[i], yi[i]);
+    int tid = threadIdx.x;
+    if (tid < 256) {
+        int r = tid >> 4, c = tid & 15;
+        int row = rb * 16 + r;
+        if (c < t.ncol && row < np) {
+            int oc = t.col0 + c;
+            int op = plist[t.start + oc / nd];
+            mp[g.box_off[op] * nd + (long long)(oc % nd) * np + row] = tb_sum(part, 4 * M2M_KS, r, c);
         }
     }
 }
 
 // Stage 7 (levels >= 3): local of a child = X-list part (already in loc) +
 // its V-list contributions in list order + L2L of the parent's local.
-// Block = one wave = (tile of 16 (child, density) columns of one quadrant, row block).
-__global__ void __launch_bounds__(64) k_l2l_mfma(DevGeom g, int nd, int L, const TTile *tiles,
-                                                 const int *clist, const cd *vy, cd *loc)
+// Block = (tile of 16 (child, density) columns of one quadrant, row block);
+// the four waves take a quarter of the k-blocks each.
+constexpr int L2L_KS = 4;
+
+__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int L, const TTile *tiles,
+                                                          const int *clist, const cd *vy, cd *loc)
 {
+    __shared__ double part[L2L_KS][64][9];
     TTile t = tiles[blockIdx.x];
     int rb = blockIdx.y;
-    int lane = threadIdx.x;
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int nc = 2 * g.Plev[L] + 1, np = 2 * g.Plev[L - 1] + 1;
     int NKp = (np + 3) / 4;
-    int bc = lane & 15, bk = lane >> 4;
+    int bc = lane & 15;
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
     int child = valid ? clist[t.start + col / nd] : 0;
     int d = col % nd;
     const cd *bptr = valid ? loc + g.box_off[g.parent[child]] * nd + (long long)d * np : nullptr;
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
-    trans_block(g.l2l_mf + g.l2l_mf_off[(L - 1) * 4 + t.q] + (long long)rb * NKp * 64, NKp, bptr, np,
-                lane, yr, yi);
-    if (!valid) return;
-    long long base = g.box_off[child] * nd + (long long)d * nc;
-    int v0 = g.V_start[child], v1 = g.V_start[child + 1];
-    for (int i = 0; i < 4; ++i) {
-        int row = rb * 16 + 4 * i + bk;
-        if (row >= nc) continue;
-        cd acc = loc[base + row];
-        for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + (long long)d * nc + row];
-        loc[base + row] = acc + mk(yr[i], yi[i]);
-    }
+    int kb0, kb1;
+    ksplit(NKp, L2L_KS, w, &kb0, &kb1);
+    trans_block(g.l2l_mf + g.l2l_mf_off[(L - 1) * 4 + t.q] + (long long)rb * NKp * 64, kb0, kb1, bptr,
+                np, lane, yr, yi);
+    tb_store(part[w], lane, yr, yi);
+    __syncthreads();
+    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    int row = rb * 16 + r;
+    if (c >= t.ncol || row >= nc) return;
+    int oc = t.col0 + c;
+    int ch = clist[t.start + oc / nd];
+    long long base = g.box_off[ch] * nd + (long long)(oc % nd) * nc;
+    int v0 = g.V_start[ch], v1 = g.V_start[ch + 1];
+    cd acc = loc[base + row];
+    for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + (long long)(oc % nd) * nc + row];
+    loc[base + row] = acc + tb_sum(part, L2L_KS, r, c);
 }
 
 // ---------------------------------------------------------------------------
-// Stage 6: X-list P2L, g_l += q O_l(s - m_b) (+ dipole), stored as W_l g_l.
-// O_n = s_n tau^{-|n|} A_|n| e^{i n theta}, A_n = tau^n H_n(x), tau = min(1, x/2),
-// s_n = (-1)^n for n < 0.
+// Stage 6: X-list P2L, g_l += qS O_l(s - m_b) + (omega/2) qD (nu O_{l-1} -
+// conj(nu) O_{l+1}), stored as W_|l| g_l.  O_n = H_n(x) v^n and
+// O_{-n} = (-1)^n H_n(x) conj(v)^n.  Row entry n holds S_n O_n with
+// S_n = W_min(|n|,P), built from A_n = tau^n H_n (tau = min(1, x/2)) and
+// S_n tau^{-n} (one exp per run of orders, ratios of the W table after it);
+// the two dipole sums are rescaled by W_|l| / S_{l-+1} at the end.  The
+// sources of all X-list boxes of b are taken in list order.
 // ---------------------------------------------------------------------------
-constexpr int X_CH = 8;
-
-__global__ void k_p2l_x(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *loc)
+template <int ND>
+__global__ void __launch_bounds__(256) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd,
+                                               cd *loc, int CH)
 {
     extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
     int l = g.blev[b];
-    int P = g.Plev[l];
-    int NA = P + 2;
-    cd *Ab = reinterpret_cast<cd *>(lds_raw);            // [X_CH][NA]
-    double *th = reinterpret_cast<double *>(Ab + X_CH * NA);
-    double *ltau = th + X_CH;
-    double mx = g.bcx[b], my = g.bcy[b];
-    int np = 2 * P + 1;
-    cd *out = loc + g.box_off[b] * nd;
-    const double *lw = g.logW + g.Woff[l];
-    double hw = 0.5 * g.omega;
-    for (int xi = g.X_start[b]; xi < g.X_start[b + 1]; ++xi) {
-        int c = g.X_idx[xi];
-        int s_begin = g.src_begin[c], s_end = g.src_end[c];
-        for (int s0 = s_begin; s0 < s_end; s0 += X_CH) {
-            int cnt = min(X_CH, s_end - s0);
-            if ((int)threadIdx.x < cnt) {
-                int j = s0 + threadIdx.x;
-                double dx = g.sx[j] - mx, dy = g.sy[j] - my;
-                double x = g.omega * sqrt(dx * dx + dy * dy);
-                double tau = fmin(1.0, 0.5 * x);
-                scaled_hankel_seq(x, tau, P + 1, Ab + threadIdx.x * NA, 1);
-                th[threadIdx.x] = atan2(dy, dx);
-                ltau[threadIdx.x] = log(tau);
+    int P = g.Plev[l], np = 2 * P + 1, NT = 2 * P + 3;
+    cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT]
+    cd *Wt = T + CH * NT;                              // [CH][ND][3]
+    cd *V = Wt + CH * ND * 3;                          // [CH]
+    double *TH = reinterpret_cast<double *>(V + CH);   // [CH]
+    double *LT = TH + CH;                              // [CH] log tau
+    double *TAU = LT + CH;                             // [CH]
+    const double *Wl = g.Wtab + g.Woff[l], *iWl = g.invW + g.Woff[l], *lWl = g.logW + g.Woff[l];
+    int tid = threadIdx.x;
+    double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
+    cd acc[PT_KR][3][ND];
+#pragma unroll
+    for (int r = 0; r < PT_KR; ++r)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) acc[r][e][d] = mk(0.0, 0.0);
+    int x0 = g.X_start[b], x1 = g.X_start[b + 1];
+    int total = 0;
+    for (int xi = x0; xi < x1; ++xi) total += g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]];
+    int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
+    for (int f0 = 0; f0 < total; f0 += CH) {
+        int cnt = min(CH, total - f0);
+        __syncthreads();
+        if (tid < cnt) {
+            int f = f0 + tid, xi = x0;
+            while (f >= g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]]) {
+                f -= g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]];
+                ++xi;
             }
-            __syncthreads();
-            for (int jj = threadIdx.x; jj < np; jj += blockDim.x) {
-                int ell = jj - P;
-                int al = ell < 0 ? -ell : ell;
+            int j = g.src_begin[g.X_idx[xi]] + f;
+            double dx = g.sx[j] - mx, dy = g.sy[j] - my;
+            double r = sqrt(dx * dx + dy * dy);
+            double x = g.omega * r;
+            double tau = fmin(1.0, 0.5 * x);
+            scaled_hankel_seq(x, tau, P + 1, T + tid * NT + P + 1, 1);
+            V[tid] = mk(dx / r, dy / r);
+            TH[tid] = atan2(dy, dx);
+            LT[tid] = log(tau);
+            TAU[tid] = tau;
+            cd nu = mk(g.snx[j], g.sny[j]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                cd c = qd[(long long)d * g.ns + j];
+                cd *w = Wt + (tid * ND + d) * 3;
+                w[0] = qs[(long long)d * g.ns + j];
+                w[1] = hw * (c * nu);
+                w[2] = neg(hw * (c * conj(nu)));
+            }
+        }
+        __syncthreads();
+        for (int it = tid; it < cnt * nseg; it += blockDim.x) {
+            int t = it % cnt, n0 = (it / cnt) * PT_SEG;
+            cd v = V[t];
+            double itau = 1.0 / TAU[t];
+            double sn, cs;
+            sincos((double)n0 * TH[t], &sn, &cs);
+            cd ph = mk(cs, sn);                        // v^n
+            double sc = exp(lWl[min(n0, P)] - n0 * LT[t]);   // S_n tau^{-n}
+            cd *row = T + t * NT + P + 1;
+            for (int n = n0; n < n0 + PT_SEG && n <= P + 1; ++n) {
+                cd e = sc * row[n];
+                row[n] = e * ph;
+                if (n > 0) {
+                    cd m = e * conj(ph);
+                    row[-n] = (n & 1) ? neg(m) : m;
+                }
+                ph = ph * v;
+                sc *= Wl[min(n + 1, P)] * iWl[min(n, P)] * itau;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PT_KR; ++r) {
+            int kk = tid + 256 * r;
+            if (kk < np) {
                 for (int t = 0; t < cnt; ++t) {
-                    int j = s0 + t;
-                    const cd *A = Ab + t * NA;
-                    double base = exp(lw[al] - al * ltau[t]);   // W_|l| tau^{-|l|}
-                    double tau = exp(ltau[t]);
-                    cd O[3];
-                    for (int e = 0; e < 3; ++e) {
-                        int n = ell - 1 + e;
-                        int an = n < 0 ? -n : n;
-                        double f = base;
-                        if (an > al) f /= tau;
-                        else if (an < al) f *= tau;
-                        if (n < 0 && (an & 1)) f = -f;
-                        double sn, cs;
-                        sincos((double)n * th[t], &sn, &cs);
-                        O[e] = f * (A[an] * mk(cs, sn));
-                    }
-                    cd nu = mk(g.snx[j], g.sny[j]);
-                    cd dip = hw * (nu * O[0] - conj(nu) * O[2]);
-                    for (int d = 0; d < nd; ++d) {
-                        cd acc = out[d * np + jj];
-                        cfma(acc, qs[(long long)d * g.ns + j], O[1]);
-                        cfma(acc, qd[(long long)d * g.ns + j], dip);
-                        out[d * np + jj] = acc;
+                    const cd *row = T + t * NT + kk + 1;   // order l = kk - P at row[0]
+                    cd om = row[-1], o0 = row[0], op = row[1];
+                    const cd *w = Wt + t * ND * 3;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        cfma(acc[r][0][d], w[3 * d], o0);
+                        cfma(acc[r][1][d], w[3 * d + 1], om);
+                        cfma(acc[r][2][d], w[3 * d + 2], op);
                     }
                 }
             }
-            __syncthreads();
+        }
+    }
+    cd *out = loc + g.box_off[b] * ND;
+#pragma unroll
+    for (int r = 0; r < PT_KR; ++r) {
+        int kk = tid + 256 * r;
+        if (kk < np) {
+            int ell = kk - P, al = ell < 0 ? -ell : ell;
+            int am = ell - 1 < 0 ? 1 - ell : ell - 1, ap = ell + 1 < 0 ? -ell - 1 : ell + 1;
+            double rm = Wl[al] * iWl[min(am, P)], rp = Wl[al] * iWl[min(ap, P)];
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                out[d * np + kk] = acc[r][0][d] + rm * acc[r][1][d] + rp * acc[r][2][d];
         }
     }
 }
@@ -769,7 +983,7 @@ size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
 {
     int np = 2 * P + 1, N = P + p + QBLK - 1;
     return sizeof(cd) * ((size_t)nd * np + (size_t)cg) +
-           sizeof(double) * ((size_t)cg * (N + 1) + (size_t)cg);
+           sizeof(double) * ((size_t)cg * (N + 1) + 3 * (size_t)cg);
 }
 
 __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const cd *loc,
@@ -788,6 +1002,8 @@ __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *li
     cd *U = Gb + nd * np;                              // [QCG]
     double *Jt = reinterpret_cast<double *>(U + QCG);  // [QCG][N+1]
     double *TH = Jt + QCG * (N + 1);                   // [QCG]
+    double *XA = TH + QCG;                             // [QCG] omega |m_b - c|
+    double *LH = XA + QCG;                             // [QCG] ln(x / 2)
     const double *iw = g.invW + g.Woff[l];
     const cd *src = loc + g.box_off[b] * nd;
     for (int i = tid; i < nd * np; i += blockDim.x) {
@@ -798,13 +1014,22 @@ __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *li
     for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
         int cnt = min(QCG, c1 - cg0);
         __syncthreads();
+        bool big = false;
         if (tid < cnt) {
             int i = cg0 + tid;
             double dx = mx - g.cx[i], dy = my - g.cy[i];
             double r = sqrt(dx * dx + dy * dy);
-            besselj_seq_call(g.omega * r, N, Jt + tid * (N + 1), 1);
+            double x = g.omega * r;
+            XA[tid] = x;
+            LH[tid] = log(0.5 * x);
+            big = x > kSeriesMaxX;
             U[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
             TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
+        }
+        if (__syncthreads_or(big)) {
+            if (tid < cnt) besselj_seq_call(XA[tid], N, Jt + tid * (N + 1), 1);
+        } else {
+            besselj_table_series(XA, LH, cnt, N, g.lnfact, Jt, N + 1, 1);
         }
         __syncthreads();
         int items = nd * cnt * nblk;
@@ -999,12 +1224,27 @@ hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, 
     return hipSuccess;
 }
 
+static int pick_ch(int nd, int Pmax)
+{
+    int ch = 32;
+    while (ch > 1 && ptab_lds_bytes(nd, Pmax, ch) > LDS_BUDGET) ch >>= 1;
+    return ch;
+}
+
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                       const cd *qd, cd *mp, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    size_t lds = sizeof(double) * (P2M_CH * (Pmax + 2) + P2M_CH);
-    k_p2m<<<n, 256, lds, s>>>(g, nd, list, qs, qd, mp);
+    if (2 * Pmax + 1 > 256 * PT_KR || nd < 1 || nd > 4) return hipErrorInvalidValue;
+    int ch = pick_ch(nd, Pmax);
+    size_t lds = ptab_lds_bytes(nd, Pmax, ch);
+    if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+    switch (nd) {
+    case 1: k_p2m<1><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
+    case 2: k_p2m<2><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
+    case 3: k_p2m<3><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
+    default: k_p2m<4><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
+    }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1013,7 +1253,7 @@ hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, 
                            int nrb, const int *plist, cd *mp, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
-    k_m2m_mfma<<<dim3(ntiles, nrb), 256, 0, s>>>(g, nd, l, tiles, plist, mp);
+    k_m2m_mfma<<<dim3(ntiles, nrb), 256 * M2M_KS, 0, s>>>(g, nd, l, tiles, plist, mp);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1022,7 +1262,7 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
                            const int *clist, const cd *vy, cd *loc, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
-    k_l2l_mfma<<<dim3(ntiles, nrb), 64, 0, s>>>(g, nd, L, tiles, clist, vy, loc);
+    k_l2l_mfma<<<dim3(ntiles, nrb), 64 * L2L_KS, 0, s>>>(g, nd, L, tiles, clist, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1051,8 +1291,16 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
                         const cd *qd, cd *loc, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    size_t lds = sizeof(cd) * X_CH * (Pmax + 2) + sizeof(double) * 2 * X_CH;
-    k_p2l_x<<<n, 256, lds, s>>>(g, nd, list, qs, qd, loc);
+    if (2 * Pmax + 1 > 256 * PT_KR || nd < 1 || nd > 4) return hipErrorInvalidValue;
+    int ch = pick_ch(nd, Pmax);
+    size_t lds = ptab_lds_bytes(nd, Pmax, ch);
+    if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+    switch (nd) {
+    case 1: k_p2l_x<1><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    case 2: k_p2l_x<2><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    case 3: k_p2l_x<3><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    default: k_p2l_x<4><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -28,6 +28,8 @@ struct DevGeom {
     const int *Plev;                           // FMM order per level
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
+    const double *lnfact;                      // ln n!, n < n_lnfact
+    int n_lnfact;
     const long long *box_off;                  // per box, in coefficients of one density
     // M2M / L2L scaled matrices per (parent level, child quadrant) in MFMA
     // A-operand order; child4[b*4+q] = child of b in quadrant q or -1
