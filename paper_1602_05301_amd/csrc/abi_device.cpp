@@ -340,6 +340,16 @@ qbx_status upload(qbx_geom_s *G)
         G->near_start = ns; G->near_idx = nidx; G->wf_start = ws; G->wf_idx = widx;
         g.near_start = ar.upload(ns); g.near_idx = ar.upload(nidx);
         g.wf_start = ar.upload(ws); g.wf_idx = ar.upload(widx);
+        // near-list sources of every leaf of the P2QBXL list, in list order
+        std::vector<int32_t> qs0(1, 0), qidx;
+        for (int b = 0; b < nb; ++b) {
+            if (!(pl.leaf[b] && has_ctr(b))) continue;
+            for (int i = ns[b]; i < ns[b + 1]; ++i)
+                for (int j = pl.src_begin[nidx[i]]; j < pl.src_end[nidx[i]]; ++j) qidx.push_back(j);
+            qs0.push_back((int32_t)qidx.size());
+        }
+        g.qsrc_start = ar.upload(qs0);
+        g.qsrc_idx = ar.upload(qidx);
     }
     G->wl = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && G->wf_start[b + 1] > G->wf_start[b]; });
     // (leaf, far W box) pairs in leaf order, their output rows, per-leaf ranges

@@ -580,8 +580,15 @@ __global__ void __launch_bounds__(256) k_p2l_x(DevGeom g, const int *list, const
 }
 
 // ---------------------------------------------------------------------------
-// Stage 3 (new): P2QBXL.  alpha_l(c) += qS O_l(s-c) + qD (w/2)(nu O_{l-1} - conj(nu) O_{l+1}).
-// One wave per centre group; lanes split the sources; wave shuffles reduce.
+// Stage 3: P2QBXL.  alpha_l(c) += qS O_l(s-c) + qD (w/2)(nu O_{l-1} - conj(nu) O_{l+1}).
+// With z = s - c = (x/omega) u, |u| = 1, O_{+-m} = (+-1)^m H_m u^{+-m} and the
+// recurrence H_{m+1} = (2m/x) H_m - H_{m-1}, the dipole pair folds into two
+// terms per order.  Writing c = (w/2) qD, v = nu conj(u), A = 2 Re(v) c,
+// B = (2/x) c conj(v), B' = (2/x) c v:
+//   alpha_0  += qS H_0 - A H_1,
+//   alpha_m  += u^m [(qS - m B) H_m + A H_{m-1}],
+//   alpha_-m += (-1)^m conj(u)^m [(qS - m B') H_m + A H_{m-1}],   m >= 1,
+// so only H_0..H_p are needed.
 // ---------------------------------------------------------------------------
 template <int PB>
 __device__ __forceinline__ void p2qbxl_pair(double omega, int p, double cx, double cy, double sx,
@@ -595,42 +602,35 @@ __device__ __forceinline__ void p2qbxl_pair(double omega, int p, double cx, doub
     cd H0, H1;
     hankel01(x, H0, H1);
     cd c = (0.5 * omega) * qD;
-    cd cnu = c * mk(nx, ny);            // c nu
-    cd cnub = c * mk(nx, -ny);          // c conj(nu)
-    // window: O_{n-1}, O_n, O_{n+1} and O_{-(n-1)}, O_{-n}, O_{-(n+1)}
-    cd Hprev = H0, Hcur = H1;
-    cd upow = u;                        // u^1
-    cd Op_prev, Op_cur = H0, Op_next = H1 * u;
-    cd Om_prev, Om_cur = H0, Om_next = neg(H1 * conj(u));
-    cd mcnub = neg(cnub);
+    cd v = mk(nx, ny) * conj(u);
+    cd A = (2.0 * v.x) * c;
     double ix2 = 2.0 / x;
-    // alpha_0
+    cd B = ix2 * (c * conj(v));
+    cd Bp = ix2 * (c * v);
     {
-        cd t = qS * Op_cur;
-        cfma(t, cnu, Om_next);
-        cfma(t, mcnub, Op_next);
+        cd t = qS * H0;
+        cfma(t, neg(A), H1);
         acc[PB] = acc[PB] + t;
     }
+    cd Hprev = H0, Hcur = H1;           // H_{m-1}, H_m
+    cd cp = qS - B, cm = qS - Bp;       // qS - m B, qS - m B'
+    cd up = u;                          // u^m
+    // all PB orders, without branches; orders above p are discarded by the caller
 #pragma unroll
-    for (int n = 1; n <= PB; ++n) {
-        if (n <= p) {
-            // advance to index n + 1
-            cd Hnext = (((double)n * ix2) * Hcur) - Hprev;
+    for (int m = 1; m <= PB; ++m) {
+        cd AH = A * Hprev;
+        cd P = AH, M = AH;
+        cfma(P, cp, Hcur);
+        cfma(M, cm, Hcur);
+        cfma(acc[PB + m], up, P);
+        cfma(acc[PB - m], (m & 1) ? neg(conj(up)) : conj(up), M);
+        if (m < PB) {
+            cp = cp - B;
+            cm = cm - Bp;
+            up = up * u;
+            cd Hn = (((double)m * ix2) * Hcur) - Hprev;
             Hprev = Hcur;
-            Hcur = Hnext;
-            upow = upow * u;
-            Op_prev = Op_cur; Op_cur = Op_next; Op_next = Hcur * upow;
-            Om_prev = Om_cur; Om_cur = Om_next;
-            Om_next = Hcur * conj(upow);
-            if ((n + 1) & 1) Om_next = neg(Om_next);
-            cd t = qS * Op_cur;
-            cfma(t, cnu, Op_prev);
-            cfma(t, mcnub, Op_next);
-            acc[PB + n] = acc[PB + n] + t;
-            cd v = qS * Om_cur;
-            cfma(v, cnu, Om_next);
-            cfma(v, mcnub, Om_prev);
-            acc[PB - n] = acc[PB - n] + v;
+            Hcur = Hn;
         }
     }
 }
@@ -664,38 +664,94 @@ __device__ void p2qbxl_finish(cd *acc, int G, int p, bool write, cd *dst, long l
     }
 }
 
+// One workgroup of 256 lanes per leaf: lane = (centre slot, part) with CG
+// centre slots (a power of two, at most 32) and 256 / CG parts.  The leaf's
+// near-list sources (flattened on the host, in list order) are staged in LDS
+// P2Q_SCH at a time and go round-robin to the parts.  Parts are summed by
+// shuffles inside a wave, then wave by wave in order through LDS.
+constexpr int P2Q_SCH = 256;
+
 template <int PB>
-__global__ void __launch_bounds__(64) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
-                                                const cd *qd, cd *coef)
+__global__ void __launch_bounds__(256) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
+                                                 const cd *qd, cd *coef)
 {
+    extern __shared__ double lds_raw[];
+    constexpr int NE = 2 * PB + 1;
+    cd *red = reinterpret_cast<cd *>(lds_raw);          // [32][NE]
+    cd *QS = red + 32 * NE;                             // [P2Q_SCH]
+    cd *QD = QS + P2Q_SCH;                              // [P2Q_SCH]
+    double *SX = reinterpret_cast<double *>(QD + P2Q_SCH);
+    double *SY = SX + P2Q_SCH, *NX = SY + P2Q_SCH, *NY = NX + P2Q_SCH;
     int b = list[blockIdx.x];
     int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
     int nct = c1 - c0;
-    int G = 1;
-    while (G < nct && G < 64) G <<= 1;
-    int parts = 64 / G;
-    int lane = threadIdx.x, gi = lane % G, part = lane / G;
+    int CG = 1;
+    while (CG < nct && CG < 32) CG <<= 1;
+    int parts = 256 / CG;
+    int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int gi = tid % CG, part = tid / CG;
     int p = g.p;
     long long ncoef = 2 * p + 1;
-    for (int cg = c0; cg < c1; cg += G) {
+    int q0 = g.qsrc_start[blockIdx.x], total = g.qsrc_start[blockIdx.x + 1] - q0;
+    for (int cg = c0; cg < c1; cg += CG) {
         int i = cg + gi;
         bool active = i < c1;
         double cx = active ? g.cx[i] : 0.0, cy = active ? g.cy[i] : 0.0;
         for (int d = 0; d < nd; ++d) {
-            cd acc[2 * PB + 1];
+            cd acc[NE];
 #pragma unroll
-            for (int e = 0; e < 2 * PB + 1; ++e) acc[e] = mk(0.0, 0.0);
-            if (active) {
-                for (int ui = g.near_start[b]; ui < g.near_start[b + 1]; ++ui) {
-                    int ub = g.near_idx[ui];
+            for (int e = 0; e < NE; ++e) acc[e] = mk(0.0, 0.0);
+            for (int f0 = 0; f0 < total; f0 += P2Q_SCH) {
+                int cnt = min(P2Q_SCH, total - f0);
+                __syncthreads();
+                for (int f = tid; f < cnt; f += blockDim.x) {
+                    int j = g.qsrc_idx[q0 + f0 + f];
+                    SX[f] = g.sx[j];
+                    SY[f] = g.sy[j];
+                    NX[f] = g.snx[j];
+                    NY[f] = g.sny[j];
+                    QS[f] = qs[(long long)d * g.ns + j];
+                    QD[f] = qd[(long long)d * g.ns + j];
+                }
+                __syncthreads();
+                if (active) {
 #pragma unroll 1
-                    for (int j = g.src_begin[ub] + part; j < g.src_end[ub]; j += parts)
-                        p2qbxl_pair<PB>(g.omega, p, cx, cy, g.sx[j], g.sy[j], g.snx[j], g.sny[j],
-                                        qs[(long long)d * g.ns + j], qd[(long long)d * g.ns + j], acc);
+                    for (int f = part; f < cnt; f += parts)
+                        p2qbxl_pair<PB>(g.omega, p, cx, cy, SX[f], SY[f], NX[f], NY[f], QS[f], QD[f], acc);
                 }
             }
-            p2qbxl_finish<PB>(acc, G, p, active && part == 0,
-                              coef + (long long)d * ncoef * g.nc + i, g.nc, false);
+            // parts inside the wave (lane bits >= log2 CG)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                double re = acc[e].x, im = acc[e].y;
+                for (int m = CG; m < 64; m <<= 1) {
+                    re += shfl_xor_d(re, m);
+                    im += shfl_xor_d(im, m);
+                }
+                acc[e] = mk(re, im);
+            }
+            // waves in order: wave w hands its sums to wave 0 through LDS
+            for (int w = 1; w < 4; ++w) {
+                __syncthreads();
+                if (wave == w && lane < CG) {
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) red[lane * NE + e] = acc[e];
+                }
+                __syncthreads();
+                if (wave == 0 && lane < CG) {
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) acc[e] = acc[e] + red[lane * NE + e];
+                }
+            }
+            if (wave == 0 && lane < CG && active) {
+                cd *dst = coef + (long long)d * ncoef * g.nc + i;
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    int ell = e - PB;
+                    if (ell < -p || ell > p) continue;
+                    dst[(long long)(ell + p) * g.nc] = acc[e];
+                }
+            }
         }
     }
 }
@@ -1309,7 +1365,8 @@ template <int PB>
 static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
                                   const cd *qd, cd *coef, hipStream_t s)
 {
-    k_p2qbxl<PB><<<n, 64, 0, s>>>(g, nd, list, qs, qd, coef);
+    size_t lds = sizeof(cd) * (32 * (2 * PB + 1) + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
+    k_p2qbxl<PB><<<n, 256, lds, s>>>(g, nd, list, qs, qd, coef);
     return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ struct DevGeom {
     const int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
     // near list of a leaf = U list + W boxes summed directly; far W = the rest
     const int *near_start, *near_idx, *wf_start, *wf_idx;
+    // near-list sources of the i-th leaf of the P2QBXL list: qsrc_idx[qsrc_start[i]..]
+    const int *qsrc_start, *qsrc_idx;
     const int *Plev;                           // FMM order per level
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
