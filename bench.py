@@ -79,6 +79,9 @@ def main(argv=None):
     ap.add_argument("--latency-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before warm-up, copy a buffer of this many MiB once on the device: "
+                         "a kernel of known traffic for calibrating HBM byte counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -100,6 +103,14 @@ def main(argv=None):
     ss = torch.from_numpy(wl.sigma_s).cuda()
     sd = torch.from_numpy(wl.sigma_d).cuda()
     u = torch.empty((wl.n_dens, g.n), dtype=torch.complex128, device="cuda")
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         geo.eval(ss, sd, u=u)
     torch.cuda.synchronize()
@@ -131,7 +142,9 @@ def main(argv=None):
     dom = max(stages, key=lambda s: stages[s][0])
     dom_ms = stages[dom][0] / args.steps
     achieved = work[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+    # translations on the FP64 matrix cores; everything else on the FP64 vector ALUs
+    bound = "mfma" if dom in ("m2m", "m2l", "l2l") else "alu"
+    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
             "algorithmic_flops_per_step": work[dom], "ms_per_step": dom_ms,
             "launches_per_step": stages[dom][1] / args.steps}
@@ -160,6 +173,8 @@ def main(argv=None):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "stages_tflops": {k: work[k] / (v[0] / args.steps * 1e-3) / 1e12
+                          for k, v in stages.items() if v[1] and v[0] > 0 and work.get(k)},
         "setup_s": setup_s,
         "rel_err_vs_oracle_sampled": err,
     }

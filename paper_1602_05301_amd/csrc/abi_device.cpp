@@ -21,6 +21,7 @@ struct qbx_ctx_s {
 namespace {
 
 constexpr int kDensChunk = 4;   // densities per pass through the pipeline
+constexpr int kM2LTileCols = 16; // columns per M2L tile (one MFMA column block)
 
 struct DeviceArena {
     std::vector<void *> ptrs;
@@ -91,6 +92,7 @@ struct qbx_geom_s {
     int m2l_ntiles[kDensChunk + 1] = {};
     // M2M parents per level, L2L children per (level, quadrant), and their tiles
     std::vector<int> par_list, par_lvl, chl_list, chl_lvl;
+    std::vector<long long> box_off_h, vy_off_h;   // host copies of box_off, vy_off
     int *d_par_list = nullptr, *d_chl_list = nullptr;
     TTile *m2m_tiles[kDensChunk + 1] = {}, *l2l_tiles[kDensChunk + 1] = {};
     std::vector<int> m2m_tstart[kDensChunk + 1], l2l_tstart[kDensChunk + 1];   // per level
@@ -222,6 +224,7 @@ qbx_status upload(qbx_geom_s *G)
     for (int b = 0; b < nb; ++b) { boff[b] = tot; tot += 2 * pl.P[pl.lev[b]] + 1; }
     G->total_coef = tot;
     g.box_off = ar.upload(boff);
+    G->box_off_h = boff;
 
     // translation tables, [in][out] (column of the scaled matrix per input index)
     std::vector<cd> m2m, l2l, m2l;
@@ -253,6 +256,17 @@ qbx_status upload(qbx_geom_s *G)
     }
     g.vpair_sorted = ar.upload(vpos);
     g.vy_off = ar.upload(vy_off);
+    G->vy_off_h = vy_off;
+    {
+        // per sorted position: source box multipole offset, output row offset
+        std::vector<long long> src(std::max(nv, 1)), dst(std::max(nv, 1));
+        for (int i = 0; i < nv; ++i) {
+            src[i] = boff[pl.V_idx[vpos[i]]];
+            dst[i] = vy_off[vpos[i]];
+        }
+        g.m2l_src = ar.upload(src);
+        g.m2l_dst = ar.upload(dst);
+    }
     // Row-major [out][in] matrix -> v_mfma_f64_16x16x4f64 A-operand order:
     // 16x4 blocks of 64 values, block (rb, kb) at (rb * NK + kb) * 64, lane l
     // holding element (rb*16 + l%16, kb*4 + l/16), zero outside the matrix.
@@ -316,6 +330,34 @@ qbx_status upload(qbx_geom_s *G)
         G->chl_lvl[pl.nlev * 4] = (int)G->chl_list.size();
         G->d_par_list = ar.upload(G->par_list);
         G->d_chl_list = ar.upload(G->chl_list);
+        // per list position, the offsets the translation kernels need, so that
+        // they start with one load instead of a chain of dependent ones
+        std::vector<long long> mc(std::max<size_t>(G->par_list.size() * 4, 1)),
+            mpo(std::max<size_t>(G->par_list.size(), 1));
+        for (size_t i = 0; i < G->par_list.size(); ++i) {
+            int b = G->par_list[i];
+            mpo[i] = G->box_off_h[b];
+            for (int q = 0; q < 4; ++q) mc[i * 4 + q] = -1;
+            for (int c = pl.child_begin[b]; c < pl.child_begin[b] + pl.child_count[b]; ++c)
+                mc[i * 4 + ((pl.bix[c] & 1) | ((pl.biy[c] & 1) << 1))] = G->box_off_h[c];
+        }
+        size_t nch = std::max<size_t>(G->chl_list.size(), 1);
+        std::vector<long long> lpo(nch), lco(nch), lvy(nch);
+        std::vector<int> lnv(nch);
+        for (size_t i = 0; i < G->chl_list.size(); ++i) {
+            int c = G->chl_list[i];
+            lpo[i] = G->box_off_h[pl.parent[c]];
+            lco[i] = G->box_off_h[c];
+            int v0 = pl.V_start[c], v1 = pl.V_start[c + 1];
+            lvy[i] = v1 > v0 ? G->vy_off_h[v0] : 0;
+            lnv[i] = v1 - v0;
+        }
+        g.m2m_coff = ar.upload(mc);
+        g.m2m_poff = ar.upload(mpo);
+        g.l2l_poff = ar.upload(lpo);
+        g.l2l_coff = ar.upload(lco);
+        g.l2l_vy0 = ar.upload(lvy);
+        g.l2l_nv = ar.upload(lnv);
     }
 
     auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
@@ -420,7 +462,8 @@ qbx_status ensure_tiles(qbx_geom_s *G, int nd)
     std::vector<M2LTile> t;
     for (const auto &grp : G->m2l_groups) {
         int cols = grp.count * nd;
-        for (int c0 = 0; c0 < cols; c0 += 16) t.push_back({grp.key, grp.start, c0, std::min(16, cols - c0)});
+        for (int c0 = 0; c0 < cols; c0 += kM2LTileCols)
+            t.push_back({grp.key, grp.start, c0, std::min(kM2LTileCols, cols - c0)});
     }
     G->m2l_tiles[nd] = G->scratch.upload(t);
     G->m2l_ntiles[nd] = (int)t.size();

@@ -214,89 +214,18 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const int *list, const c
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TB_U = 4;      // k-blocks whose table operands are loaded ahead
-constexpr int M2L_KCH = 64;   // k-blocks of 4 staged at once: 256 rows x 16 columns = 64 KiB
 
-__global__ void __launch_bounds__(256) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles,
-                                                  const cd *mp, cd *vy)
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8).
+// Map them so that XCD x works through its own contiguous range of tiles:
+// the tiles of one (level, offset) group then share that XCD's L2 copy of
+// the group's matrix instead of every XCD fetching every matrix.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int b, int n)
 {
-    extern __shared__ double lds_raw[];
-    cd *X = reinterpret_cast<cd *>(lds_raw);    // [min(kpad, M2L_KCH * 4)][16]
-    M2LTile t = tiles[blockIdx.x];
-    int l = t.lo / 40;
-    int P = g.Plev[l], n = 2 * P + 1;
-    int NK = (n + 3) / 4, NR = (n + 15) / 16;
-    const cd *A = g.m2l_mf + g.m2l_mf_off[t.lo];
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int bk = lane >> 4, bc = lane & 15;
-    // columns' multipoles, staged in chunks of M2L_KCH k-blocks
-    auto stage = [&](int kb0, int kb1) {
-        int rows = (kb1 - kb0) * 4;
-        for (int i = threadIdx.x; i < rows * 16; i += blockDim.x) {
-            int c = i / rows, k = kb0 * 4 + i % rows;
-            cd v = mk(0.0, 0.0);
-            if (c < t.ncol && k < n) {
-                int col = t.col0 + c;
-                int pos = g.vpair_sorted[t.pair_start + col / nd];
-                int src = g.V_idx[pos];
-                v = mp[g.box_off[src] * nd + (long long)(col % nd) * n + k];
-            }
-            X[(k - kb0 * 4) * 16 + c] = v;
-        }
-    };
-    bool single = NK <= M2L_KCH;
-    if (single) {
-        stage(0, NK);
-        __syncthreads();
-    }
-    for (int rb0 = 0; rb0 < NR; rb0 += 4) {
-        int rb = rb0 + wave;
-        bool active = rb < NR;
-        d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
-        const cd *Ab = A + (long long)rb * NK * 64 + lane;
-        for (int kc = 0; kc < NK; kc += M2L_KCH) {
-            int kend = min(NK, kc + M2L_KCH);
-            if (!single) {
-                __syncthreads();
-                stage(kc, kend);
-                __syncthreads();
-            }
-            if (active) {
-                int xoff = single ? 0 : kc;
-                // table operands of the next TB_U k-blocks load during the current ones
-                cd a[TB_U];
-#pragma unroll
-                for (int u = 0; u < TB_U; ++u) a[u] = kc + u < kend ? Ab[(kc + u) * 64] : mk(0.0, 0.0);
-                for (int kb = kc; kb < kend; kb += TB_U) {
-                    cd an[TB_U];
-#pragma unroll
-                    for (int u = 0; u < TB_U; ++u) {
-                        int kn = kb + TB_U + u;
-                        an[u] = kn < kend ? Ab[kn * 64] : mk(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int u = 0; u < TB_U; ++u) {
-                        int kk = min(kb + u, kend - 1);
-                        cd b = X[((kk - xoff) * 4 + bk) * 16 + bc];
-                        if (kb + u >= kend) b = mk(0.0, 0.0);
-                        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b.x, yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b.y, yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b.y, yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b.x, yi, 0, 0, 0);
-                        a[u] = an[u];
-                    }
-                }
-            }
-        }
-        if (active && bc < t.ncol) {
-            int col = t.col0 + bc;
-            int pos = g.vpair_sorted[t.pair_start + col / nd];
-            cd *o = vy + g.vy_off[pos] * nd + (long long)(col % nd) * n;
-            for (int i = 0; i < 4; ++i) {
-                int row = rb * 16 + 4 * i + bk;
-                if (row < n) o[row] = mk(yr[i], yi[i]);
-            }
-        }
-    }
+    int per = n / kNumXcd, rem = n % kNumXcd;
+    int x = b % kNumXcd, i = b / kNumXcd;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
 }
 
 // Level-2 part of the downward pass: local = X-list part (already in loc)
@@ -306,10 +235,15 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
     int b = g.level_start[l] + blockIdx.x;
     int P = g.Plev[l], n = 2 * P + 1;
     cd *out = loc + g.box_off[b] * nd;
-    int v0 = g.V_start[b], v1 = g.V_start[b + 1];
+    int v0 = g.V_start[b], nv = g.V_start[b + 1] - v0;
+    if (nv == 0) return;
+    // the box's V-list rows follow each other, n * nd apart
+    const cd *vr = vy + g.vy_off[v0] * nd;
+    long long vs = (long long)n * nd;
     for (int i = threadIdx.x; i < nd * n; i += blockDim.x) {
         cd acc = out[i];
-        for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + i];
+#pragma unroll 4
+        for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs + i];
         out[i] = acc;
     }
 }
@@ -319,35 +253,79 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
 // column given by bptr (nin complex inputs, NULL = 0).  The table is in
 // A-operand order (see k_m2l_mfma).  Operands of the next TB_U k-blocks are
 // loaded while the current ones go through the matrix core.
-__device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const cd *bptr, int nin,
-                                        int lane, cd *a, cd *b)
+__device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const cd *bs, bool bvalid,
+                                        int nin, int lane, cd *a, cd *b)
 {
+    // unconditional loads at clamped addresses, out-of-range operands
+    // replaced by zero afterwards: no branches, so the loads stay in flight
     int bk = lane >> 4;
 #pragma unroll
     for (int u = 0; u < TB_U; ++u) {
-        int kbu = kb + u, k = kbu * 4 + bk;
-        a[u] = kbu < kb1 ? Arow[kbu * 64 + lane] : mk(0.0, 0.0);
-        b[u] = (kbu < kb1 && bptr && k < nin) ? bptr[k] : mk(0.0, 0.0);
+        int kbu = kb + u;
+        bool ok = kbu < kb1;
+        int kbc = ok ? kbu : kb1 - 1;
+        int k = kbc * 4 + bk;
+        a[u] = Arow[kbc * 64 + lane];
+        cd v = bs[min(k, nin - 1)];
+        b[u] = (ok && bvalid && k < nin) ? v : mk(0.0, 0.0);
     }
 }
 
+__device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, d4 &yr, d4 &yi)
+{
+#pragma unroll
+    for (int u = 0; u < TB_U; ++u) {
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, yi, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, yi, 0, 0, 0);
+    }
+}
+
+// Two register sets alternate: one is multiplied while the other loads.
 __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, const cd *bptr, int nin,
                                             int lane, d4 &yr, d4 &yi)
 {
-    cd a[TB_U], b[TB_U];
-    tb_load(Arow, kb0, kb1, bptr, nin, lane, a, b);
-    for (int kb = kb0; kb < kb1; kb += TB_U) {
-        cd an[TB_U], bn[TB_U];
-        tb_load(Arow, kb + TB_U, kb1, bptr, nin, lane, an, bn);
-#pragma unroll
-        for (int u = 0; u < TB_U; ++u) {
-            yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, yr, 0, 0, 0);
-            yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, yi, 0, 0, 0);
-            yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, yr, 0, 0, 0);
-            yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, yi, 0, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < TB_U; ++u) { a[u] = an[u]; b[u] = bn[u]; }
+    if (kb0 >= kb1) return;
+    const cd *bs = bptr ? bptr : Arow;          // any readable address when the column is empty
+    bool bvalid = bptr != nullptr;
+    cd a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
+    tb_load(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
+    for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
+        tb_load(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_mfma(a0, b0, yr, yi);
+        tb_load(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        if (kb + TB_U < kb1) tb_mfma(a1, b1, yr, yi);
+    }
+}
+
+// One wave per (tile, row block), operands straight from memory with the
+// loads of the next TB_U k-blocks in flight (trans_block).  1-D grid of
+// ntiles * nrmax waves in XCD-contiguous order, the row blocks of a tile
+// consecutive, so that a tile's columns and a group's matrix are fetched
+// into one XCD's L2; waves past the tile's row count exit at once.
+__global__ void __launch_bounds__(64) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
+                                                 const cd *mp, cd *vy)
+{
+    int c = xcd_contiguous(blockIdx.x, gridDim.x);
+    M2LTile t = tiles[c / nrmax];
+    int rb = c % nrmax;
+    int l = t.lo / 40;
+    int P = g.Plev[l], n = 2 * P + 1;
+    int NK = (n + 3) / 4, NR = (n + 15) / 16;
+    if (rb >= NR) return;
+    int lane = threadIdx.x;
+    int bk = lane >> 4, bc = lane & 15;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
+    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    trans_block(g.m2l_mf + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
+    if (!valid) return;
+    cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
+    for (int i = 0; i < 4; ++i) {
+        int row = rb * 16 + 4 * i + bk;
+        if (row < n) o[row] = mk(yr[i], yi[i]);
     }
 }
 
@@ -394,14 +372,13 @@ __global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, in
     int bc = lane & 15;
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
-    int par = valid ? plist[t.start + col / nd] : 0;
     int d = col % nd;
-    int child = valid ? g.child4[par * 4 + q] : -1;
-    const cd *bptr = child >= 0 ? mp + g.box_off[child] * nd + (long long)d * nc : nullptr;
+    long long coff = valid ? g.m2m_coff[(long long)(t.start + col / nd) * 4 + q] : -1;
+    const cd *bptr = coff >= 0 ? mp + coff * nd + (long long)d * nc : nullptr;
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
     int kb0, kb1;
     ksplit(NKc, M2M_KS, h, &kb0, &kb1);
-    if (__any(child >= 0))
+    if (__any(coff >= 0))
         trans_block(g.m2m_mf + g.m2m_mf_off[l * 4 + q] + (long long)rb * NKc * 64, kb0, kb1, bptr, nc,
                     lane, yr, yi);
     tb_store(part[w], lane, yr, yi);
@@ -412,8 +389,8 @@ __global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, in
         int row = rb * 16 + r;
         if (c < t.ncol && row < np) {
             int oc = t.col0 + c;
-            int op = plist[t.start + oc / nd];
-            mp[g.box_off[op] * nd + (long long)(oc % nd) * np + row] = tb_sum(part, 4 * M2M_KS, r, c);
+            mp[g.m2m_poff[t.start + oc / nd] * nd + (long long)(oc % nd) * np + row] =
+                tb_sum(part, 4 * M2M_KS, r, c);
         }
     }
 }
@@ -436,9 +413,8 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int
     int bc = lane & 15;
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
-    int child = valid ? clist[t.start + col / nd] : 0;
     int d = col % nd;
-    const cd *bptr = valid ? loc + g.box_off[g.parent[child]] * nd + (long long)d * np : nullptr;
+    const cd *bptr = valid ? loc + g.l2l_poff[t.start + col / nd] * nd + (long long)d * np : nullptr;
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
     int kb0, kb1;
     ksplit(NKp, L2L_KS, w, &kb0, &kb1);
@@ -450,12 +426,17 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int
     int row = rb * 16 + r;
     if (c >= t.ncol || row >= nc) return;
     int oc = t.col0 + c;
-    int ch = clist[t.start + oc / nd];
-    long long base = g.box_off[ch] * nd + (long long)(oc % nd) * nc;
-    int v0 = g.V_start[ch], v1 = g.V_start[ch + 1];
-    cd acc = loc[base + row];
-    for (int v = v0; v < v1; ++v) acc = acc + vy[g.vy_off[v] * nd + (long long)(oc % nd) * nc + row];
-    loc[base + row] = acc + tb_sum(part, L2L_KS, r, c);
+    int pos = t.start + oc / nd;
+    long long dr = (long long)(oc % nd) * nc + row;
+    long long base = g.l2l_coff[pos] * nd + dr;
+    // V-list rows of the child follow each other, nc * nd apart
+    const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
+    int nv = g.l2l_nv[pos];
+    long long vs = (long long)nc * nd;
+    cd acc = loc[base];
+#pragma unroll 4
+    for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs];
+    loc[base] = acc + tb_sum(part, L2L_KS, r, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,12 +995,16 @@ __global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_
     int b = leaf_list[li];
     int c0 = g.ctr_begin[b], nct = g.ctr_end[b] - c0;
     int p = g.p, nq = 2 * p + 1;
-    int q0 = leaf_pair_start[li], q1 = leaf_pair_start[li + 1];
+    int q0 = leaf_pair_start[li], np_ = leaf_pair_start[li + 1] - q0;
+    // the leaf's pair rows follow each other, nct * nq * nd apart
+    const cd *wr = wy + pair_off[q0] * nd;
+    long long ws = (long long)nct * nq * nd;
     for (int idx = threadIdx.x; idx < nd * nct * nq; idx += blockDim.x) {
         int d = idx / (nct * nq), rem = idx % (nct * nq);
         int ci = rem / nq, l = rem % nq;
         cd acc = mk(0.0, 0.0);
-        for (int q = q0; q < q1; ++q) acc = acc + wy[pair_off[q] * nd + idx];
+#pragma unroll 4
+        for (int q = 0; q < np_; ++q) acc = acc + wr[q * ws + idx];
         cd *o = coef + ((long long)d * nq + l) * g.nc + c0 + ci;
         *o = *o + acc;
     }
@@ -1327,9 +1312,10 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
                            const cd *mp, cd *vy, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
-    int nk = std::min((2 * Pmax + 1 + 3) / 4, M2L_KCH);
-    size_t lds = sizeof(cd) * nk * 4 * 16;
-    k_m2l_mfma<<<ntiles, 256, lds, s>>>(g, nd, tiles, mp, vy);
+    int nrmax = (2 * Pmax + 1 + 15) / 16;
+    long long nblk = (long long)ntiles * nrmax;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    k_m2l_mfma<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

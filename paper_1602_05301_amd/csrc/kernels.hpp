@@ -38,12 +38,20 @@ struct DevGeom {
     const cd *m2m_mf, *l2l_mf;
     const long long *m2m_mf_off, *l2l_mf_off;  // [level*4+q]
     const int *child4;
+    // per position of the M2M parent list: children's box_off by quadrant
+    // (-1 = none) and the parent's; per position of the L2L child list: the
+    // parent's and the child's box_off, the vy row of its first V-list entry
+    // and the entry count (the entries' rows follow each other)
+    const long long *m2m_coff, *m2m_poff;
+    const long long *l2l_poff, *l2l_coff, *l2l_vy0;
+    const int *l2l_nv;
     // M2L as batched GEMM: per (level, offset) matrices in MFMA tile order,
     // V-list positions grouped by (level, offset), per-position output offsets.
     const cd *m2l_mf;                          // tiled scaled M2L matrices
     const long long *m2l_mf_off;               // [level*40+o]
     const int *vpair_sorted;                   // V-list positions sorted by (level, offset)
     const long long *vy_off;                   // per V-list position: output row offset
+    const long long *m2l_src, *m2l_dst;        // per sorted position: box_off of the source, vy_off
 };
 
 // One M2M / L2L GEMM tile: up to 16 (box, density) columns taken from a box
