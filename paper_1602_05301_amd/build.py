@@ -20,9 +20,12 @@ HIP_SRC = ["kernels.hip", "abi_device.cpp"]
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions stay disabled for every HIP translation unit.
+# No automatic FMA contraction: the kernels write their fused multiply-adds
+# explicitly, so a result does not depend on how a template instance (the
+# number of densities per launch, say) happens to be scheduled.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-result"]
+             "-ffp-contract=off", "-Wno-unused-result"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
               "-I/opt/rocm/include"]
 

@@ -100,6 +100,10 @@ struct qbx_geom_s {
     // per-eval scratch, sized for kDensChunk densities
     DeviceArena scratch;
     cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
+    // radial sequences, recomputed on every evaluation: J_n per P2M source
+    // and per L2QBXL centre (n-major)
+    int srad_rows = 0, crad_rows = 0;
+    double *srad = nullptr, *crad = nullptr;
     // per-stage HIP-event timing (qbx_geom_profile)
     struct StageRec {
         int stage;
@@ -157,6 +161,9 @@ qbx_status upload(qbx_geom_s *G)
     int nb = pl.n_boxes();
     g.ns = (int)pl.ns; g.nc = (int)pl.nc; g.nt = (int)pl.nt; g.nb = nb; g.nlev = pl.nlev;
     g.p = pl.p; g.omega = pl.omega;
+    g.max_leaf_ctr = 1;
+    for (int b = 0; b < nb; ++b)
+        if (pl.leaf[b]) g.max_leaf_ctr = std::max(g.max_leaf_ctr, pl.ctr_end[b] - pl.ctr_begin[b]);
 
     std::vector<double> a(pl.ns), bq(pl.ns), c(pl.ns), d(pl.ns), e(pl.ns);
     std::vector<int> perm(pl.ns);
@@ -199,15 +206,6 @@ qbx_status upload(qbx_geom_s *G)
     g.W_start = ar.upload(pl.W_start); g.W_idx = ar.upload(pl.W_idx);
     g.X_start = ar.upload(pl.X_start); g.X_idx = ar.upload(pl.X_idx);
     g.Plev = ar.upload(pl.P);
-    {
-        // ln n! for the series form of J_n (orders up to max P_l + p + 8)
-        int nf = pl.p + 10;
-        for (int v : pl.P) nf = std::max(nf, v + pl.p + 10);
-        std::vector<double> lf(nf);
-        for (int n = 0; n < nf; ++n) lf[n] = (double)lgammal((long double)n + 1.0L);
-        g.n_lnfact = nf;
-        g.lnfact = ar.upload(lf);
-    }
 
     std::vector<int> woff(pl.nlev + 1, 0);
     std::vector<double> W, iW, lW;
@@ -392,6 +390,25 @@ qbx_status upload(qbx_geom_s *G)
         }
         g.qsrc_start = ar.upload(qs0);
         g.qsrc_idx = ar.upload(qidx);
+        // sources of all X-list boxes of every box of the X-list P2L list, in list order
+        std::vector<int32_t> xs0(1, 0), xidx;
+        for (int b = 0; b < nb; ++b) {
+            if (pl.X_start[b + 1] <= pl.X_start[b]) continue;
+            for (int i = pl.X_start[b]; i < pl.X_start[b + 1]; ++i)
+                for (int j = pl.src_begin[pl.X_idx[i]]; j < pl.src_end[pl.X_idx[i]]; ++j) xidx.push_back(j);
+            xs0.push_back((int32_t)xidx.size());
+        }
+        g.xsrc_start = ar.upload(xs0);
+        g.xsrc_idx = ar.upload(xidx);
+        // the leaf (level >= 2) of every source and of every centre, else -1
+        std::vector<int32_t> sbox(std::max<int64_t>(pl.ns, 1), -1), cbox(std::max<int64_t>(pl.nc, 1), -1);
+        for (int b = 0; b < nb; ++b) {
+            if (!pl.leaf[b] || pl.lev[b] < 2) continue;
+            for (int j = pl.src_begin[b]; j < pl.src_end[b]; ++j) sbox[j] = b;
+            for (int c = pl.ctr_begin[b]; c < pl.ctr_end[b]; ++c) cbox[c] = b;
+        }
+        g.src_box = ar.upload(sbox);
+        g.ctr_box = ar.upload(cbox);
     }
     G->wl = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && G->wf_start[b + 1] > G->wf_start[b]; });
     // (leaf, far W box) pairs in leaf order, their output rows, per-leaf ranges
@@ -442,12 +459,17 @@ qbx_status ensure_scratch(qbx_geom_s *G)
         G->loc = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
         G->vy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_vy, 1));
         G->wy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_wy, 1));
+        G->srad_rows = G->p2m.Pmax + 2;
+        G->crad_rows = G->l2q.Pmax + pl.p + 8;
+        G->srad = (double *)s.alloc(sizeof(double) * G->srad_rows * std::max<int64_t>(pl.ns, 1));
+        G->crad = (double *)s.alloc(sizeof(double) * G->crad_rows * std::max<int64_t>(pl.nc, 1));
     }
     if (s.err != hipSuccess) {
         hipError_t e = s.err;
         s.release();
         s.err = hipSuccess;
         G->qs = G->qd = G->coef = G->mp = G->loc = G->vy = G->wy = nullptr;
+        G->srad = G->crad = nullptr;
         return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                     std::string("scratch allocation failed: ") + hipGetErrorString(e));
     }
@@ -574,7 +596,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
     } else {
         {
             STAGE(QBX_STAGE_P2M);
-            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->mp, st));
+            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->srad, G->srad_rows, G->mp, st));
         }
         {
             STAGE(QBX_STAGE_M2M);
@@ -621,7 +643,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
-            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->loc, G->coef, st));
+            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, G->loc, G->coef, st));
         }
     }
     {

@@ -19,7 +19,13 @@ struct cd {
 __host__ __device__ __forceinline__ cd mk(double a, double b) { return {a, b}; }
 __host__ __device__ __forceinline__ cd operator+(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
 __host__ __device__ __forceinline__ cd operator-(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }
-__host__ __device__ __forceinline__ cd operator*(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// Complex product with explicit fused multiply-adds: the library is built
+// without automatic contraction, so every rounding is written in the source
+// and results do not depend on how the compiler schedules a kernel.
+__host__ __device__ __forceinline__ cd operator*(cd a, cd b)
+{
+    return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
 __host__ __device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.x, s * a.y}; }
 __host__ __device__ __forceinline__ cd operator*(cd a, double s) { return {s * a.x, s * a.y}; }
 __host__ __device__ __forceinline__ cd conj(cd a) { return {a.x, -a.y}; }
@@ -46,7 +52,7 @@ __host__ __device__ __forceinline__ int miller_start(double x, int N)
 }
 
 // J_n(x), n = 0..N, written to out[n * stride].  x >= 0.
-__device__ inline void besselj_seq(double x, int N, double *out, int stride)
+__device__ inline void besselj_seq(double x, int N, double *out, long long stride)
 {
     if (x == 0.0) {
         out[0] = 1.0;
@@ -73,13 +79,6 @@ __device__ inline void besselj_seq(double x, int N, double *out, int stride)
     double s = fabs(jz) >= fabs(jo) ? jz / f : jo / f1;
     out[0] = jz;
     for (int n = 1; n <= N; ++n) out[n * stride] *= s;
-}
-
-// Out-of-line copy for kernels whose hot loop should not share registers with
-// the recurrence.
-__device__ __attribute__((noinline)) void besselj_seq_call(double x, int N, double *out, int stride)
-{
-    besselj_seq(x, N, out, stride);
 }
 
 __device__ __attribute__((noinline)) void hankel01_lib(double x, cd &h0, cd &h1)
@@ -133,7 +132,7 @@ __device__ __forceinline__ void hankel01(double x, cd &h0, cd &h1)
 
 // A_n = tau^n H_n(x), n = 0..N, written to out[n * stride].  With
 // tau = min(1, x/2) the sequence stays below (n-1)! in magnitude.
-__device__ inline void scaled_hankel_seq(double x, double tau, int N, cd *out, int stride)
+__device__ inline void scaled_hankel_seq(double x, double tau, int N, cd *out, long long stride)
 {
     cd h0, h1;
     hankel01(x, h0, h1);
@@ -141,8 +140,9 @@ __device__ inline void scaled_hankel_seq(double x, double tau, int N, cd *out, i
     out[0] = a0;
     if (N >= 1) out[stride] = a1;
     double t2 = tau * tau;
+    double c = 2.0 * tau / x;                 // one division, outside the recurrence
     for (int n = 1; n < N; ++n) {
-        cd a2 = ((2.0 * n * tau / x) * a1) - (t2 * a0);
+        cd a2 = (((double)n * c) * a1) - (t2 * a0);
         out[(n + 1) * stride] = a2;
         a0 = a1;
         a1 = a2;

@@ -40,57 +40,83 @@ __global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, c
     qd[idx] = mk(-s * b.y, s * b.x);
 }
 
+constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p + QBLK
+
 // ---------------------------------------------------------------------------
-// J_n(x_t), n = 0..N, for the block's arguments x_t (t < cnt), every one at
-// most kSeriesMaxX, written to out[t * ld + n * st].  Block-cooperative, one
-// (t, n) per thread step, from the ascending series (DLMF 10.2.2)
-//   J_n(x) = (x/2)^n / n! * sum_k (-x^2/4)^k / (k! (n+1)_k),
-// prefactor exp(n ln(x/2) - ln n!) with lhx[t] = ln(x_t / 2).  Terms fall
-// off at least like 4^k/(k!)^2 here, so the sum stops once a term drops
-// below 1e-17 of it (40 terms at most).
+// Radial sequences, one lane per source / centre (so every lane does a
+// whole recurrence), written n-major: element n of item i at rad[n * count + i].
+//   k_src_rad: J_n(omega |s - m_b|), n = 0..P_b+1, s in a leaf b of level >= 2
+//   k_ctr_rad: J_n(omega |m_b - c|), n = 0..P_b+p+7, c in such a leaf
+// Miller's recurrence rewrites earlier values when it rescales and
+// normalises at the end, so it runs in LDS ([rows][lanes]) and each lane
+// then copies its own column out.
 // ---------------------------------------------------------------------------
-__device__ __attribute__((noinline)) void besselj_table_series(const double *X, const double *lhx, int cnt, int N,
-                                     const double *lnfact, double *out, int ld, int st)
+__global__ void k_src_rad(DevGeom g, int rows, double *rad)
 {
-    int tot = cnt * (N + 1);
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-        int t = it / (N + 1), n = it - t * (N + 1);
-        double x = X[t];
-        double v;
-        if (x == 0.0) {
-            v = n == 0 ? 1.0 : 0.0;
-        } else {
-            double q = -0.25 * x * x;
-            double term = 1.0, sum = 1.0;
-            for (int k = 1; k <= 40; ++k) {
-                term *= q / ((double)k * (double)(n + k));
-                sum += term;
-                if (fabs(term) <= 1e-17 * fabs(sum)) break;
-            }
-            v = n == 0 ? sum : exp((double)n * lhx[t] - lnfact[n]) * sum;
+    extern __shared__ double lds_raw[];
+    int lanes = blockDim.x;
+    int s = blockIdx.x * lanes + threadIdx.x;
+    int N = -1;
+    if (s < g.ns) {
+        int b = g.src_box[s];
+        if (b >= 0) {
+            N = g.Plev[g.blev[b]] + 1;
+            double dx = g.sx[s] - g.bcx[b], dy = g.sy[s] - g.bcy[b];
+            besselj_seq(g.omega * sqrt(dx * dx + dy * dy), N, lds_raw + threadIdx.x, lanes);
         }
-        out[t * ld + n * st] = v;
     }
+    (void)rows;
+    for (int n = 0; n <= N; ++n) rad[(long long)n * g.ns + s] = lds_raw[n * lanes + threadIdx.x];
+}
+
+__global__ void k_ctr_rad(DevGeom g, int rows, double *rad)
+{
+    extern __shared__ double lds_raw[];
+    int lanes = blockDim.x;
+    int c = blockIdx.x * lanes + threadIdx.x;
+    int N = -1;
+    if (c < g.nc) {
+        int b = g.ctr_box[c];
+        if (b >= 0) {
+            N = g.Plev[g.blev[b]] + g.p + QBLK - 1;
+            double dx = g.bcx[b] - g.cx[c], dy = g.bcy[b] - g.cy[c];
+            besselj_seq(g.omega * sqrt(dx * dx + dy * dy), N, lds_raw + threadIdx.x, lanes);
+        }
+    }
+    (void)rows;
+    for (int n = 0; n <= N; ++n) rad[(long long)n * g.nc + c] = lds_raw[n * lanes + threadIdx.x];
+}
+
+// lanes per block of a Miller kernel: [rows][lanes] doubles within 64 KiB
+static int rad_lanes(int rows)
+{
+    int lanes = 64;
+    while (lanes > 1 && (size_t)rows * lanes * sizeof(double) > 64 * 1024) lanes >>= 1;
+    return lanes;
 }
 
 // ---------------------------------------------------------------------------
 // Shared layout of the per-source expansion tables (P2M, X-list P2L).
-// A pass takes up to CH sources; for each, row t of T holds the 2P+3
-// basis values of orders n = -(P+1)..P+1 at T[t*(2P+3) + P+1 + n], built in
-// two steps: one lane per source runs the radial recurrence into the
-// non-negative half, then lanes (source, run of PT_SEG orders) attach the
-// phases (one sincos per run, running products after it) and fill the
-// negative orders.  Per-source weights of the three terms (charge, and the
-// dipole's two neighbours) sit in Wt[t][d][3].  Each thread then owns output
-// orders tid, tid + 256 and sums over the pass's sources in source order.
+// One wave per box.  A pass takes up to CH sources; for each, row t of T
+// holds the 2P+3 basis values of orders n = -(P+1)..P+1 at
+// T[t*(2P+3) + P+1 + n], built in two steps: one lane per source runs the
+// radial recurrence into the non-negative half, then lanes (source, run of
+// PT_SEG orders) attach the phases (one sincos per run, running products
+// after it) and fill the negative orders.  Per-source weights of the three
+// terms (charge, and the dipole's two neighbours) sit in Wt[t][d][3].  Each
+// lane then owns output orders lane, lane + 64, ..., sums the pass's sources
+// in source order and adds the result to the box's expansion (the first pass
+// writes it).  One wave per box keeps many boxes in flight per CU, so the
+// serial recurrences of some overlap the sums of others.
 // ---------------------------------------------------------------------------
 constexpr int PT_SEG = 8;
-constexpr int PT_KR = 2;      // output orders per thread: 2P+1 <= 512
+constexpr size_t PT_LDS = 24 * 1024;   // LDS per box: several boxes per CU
 
 size_t ptab_lds_bytes(int nd, int P, int ch)
 {
     return (size_t)ch * ((2 * (size_t)P + 3) * sizeof(cd) + 3 * (size_t)nd * sizeof(cd) + sizeof(cd) +
-                         3 * sizeof(double));
+                         3 * sizeof(double)) +
+           ((size_t)P + 2) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -99,41 +125,50 @@ size_t ptab_lds_bytes(int nd, int P, int ch)
 // L_n(z) = J_n(x) conj(v)^n with z = (x/omega) v, |v| = 1, and
 // L_{-n} = (-1)^n J_n v^n.
 // ---------------------------------------------------------------------------
+// P2M keeps only the orders n = 0..P+1 of a row (J_n is real, so
+// L_{-n} = (-1)^n conj(L_n)): rows of P+2 entries, twice the sources per pass.
+size_t p2m_lds_bytes(int nd, int P, int ch)
+{
+    return (size_t)ch * (((size_t)P + 2) * sizeof(cd) + 3 * (size_t)nd * sizeof(cd) + sizeof(cd) +
+                         3 * sizeof(double));
+}
+
+__device__ __forceinline__ cd p2m_basis(const cd *row, int m)
+{
+    if (m >= 0) return row[m];
+    cd c = conj(row[-m]);
+    return (m & 1) ? neg(c) : c;
+}
+
 template <int ND>
-__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd,
-                                             cd *mp, int CH)
+__global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd,
+                                            const double *srad, cd *mp, int CH)
 {
     extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
     int l = g.blev[b];
-    int P = g.Plev[l], np = 2 * P + 1, NT = 2 * P + 3;
-    cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT]
+    int P = g.Plev[l], np = 2 * P + 1, NT = P + 2;
+    cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT], order n at row[n]
     cd *Wt = T + CH * NT;                              // [CH][ND][3]
     cd *V = Wt + CH * ND * 3;                          // [CH]
     double *TH = reinterpret_cast<double *>(V + CH);   // [CH]
-    double *XA = TH + CH;                              // [CH] omega |s - m|
-    double *LH = XA + CH;                              // [CH] ln(x / 2)
     int tid = threadIdx.x;
     double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
-    cd acc[PT_KR][ND];
-#pragma unroll
-    for (int r = 0; r < PT_KR; ++r)
-#pragma unroll
-        for (int d = 0; d < ND; ++d) acc[r][d] = mk(0.0, 0.0);
+    const double *iw = g.invW + g.Woff[l];
+    cd *out = mp + g.box_off[b] * ND;
     int s_begin = g.src_begin[b], s_end = g.src_end[b];
+    if (s_begin == s_end) {                             // leaf without sources
+        for (int i = tid; i < ND * np; i += blockDim.x) out[i] = mk(0.0, 0.0);
+        return;
+    }
     int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
     for (int s0 = s_begin; s0 < s_end; s0 += CH) {
         int cnt = min(CH, s_end - s0);
         __syncthreads();
-        bool big = false;
         if (tid < cnt) {
             int j = s0 + tid;
             double dx = g.sx[j] - mx, dy = g.sy[j] - my;
             double r = sqrt(dx * dx + dy * dy);
-            double x = g.omega * r;
-            XA[tid] = x;
-            LH[tid] = log(0.5 * x);
-            big = x > kSeriesMaxX;
             V[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
             TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
             cd nu = mk(g.snx[j], g.sny[j]);
@@ -146,55 +181,45 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const int *list, const c
                 w[2] = neg(hw * (c * nu));
             }
         }
-        if (__syncthreads_or(big)) {
-            if (tid < cnt) besselj_seq_call(XA[tid], P + 1, &T[tid * NT + P + 1].x, 2);
-        } else {
-            besselj_table_series(XA, LH, cnt, P + 1, g.lnfact, &T[P + 1].x, 2 * NT, 2);
-        }
         __syncthreads();
         for (int it = tid; it < cnt * nseg; it += blockDim.x) {
             int t = it % cnt, n0 = (it / cnt) * PT_SEG;
             cd v = V[t];
             double sn, cs;
             sincos((double)n0 * TH[t], &sn, &cs);
-            cd ph = mk(cs, sn);                        // v^n
-            cd *row = T + t * NT + P + 1;
+            cd ph = mk(cs, -sn);                       // conj(v)^n
+            cd *row = T + t * NT;
+            const double *jr = srad + s0 + t;
             for (int n = n0; n < n0 + PT_SEG && n <= P + 1; ++n) {
-                double jn = row[n].x;
-                row[n] = jn * conj(ph);
-                if (n > 0) row[-n] = ((n & 1) ? -jn : jn) * ph;
-                ph = ph * v;
+                row[n] = jr[(long long)n * g.ns] * ph;
+                ph = ph * conj(v);
             }
         }
         __syncthreads();
+        bool first = s0 == s_begin;
+        for (int kk = tid; kk < np; kk += blockDim.x) {
+            int k = kk - P;
+            cd acc[ND];
 #pragma unroll
-        for (int r = 0; r < PT_KR; ++r) {
-            int kk = tid + 256 * r;
-            if (kk < np) {
-                for (int t = 0; t < cnt; ++t) {
-                    const cd *row = T + t * NT + kk + 1;   // order k = kk - P at row[0]
-                    cd lm = row[-1], l0 = row[0], lp = row[1];
-                    const cd *w = Wt + t * ND * 3;
+            for (int d = 0; d < ND; ++d) acc[d] = mk(0.0, 0.0);
+            for (int t = 0; t < cnt; ++t) {
+                const cd *row = T + t * NT;
+                cd lm = p2m_basis(row, k - 1), l0 = p2m_basis(row, k), lp = p2m_basis(row, k + 1);
+                const cd *w = Wt + t * ND * 3;
 #pragma unroll
-                    for (int d = 0; d < ND; ++d) {
-                        cfma(acc[r][d], w[3 * d], l0);
-                        cfma(acc[r][d], w[3 * d + 1], lm);
-                        cfma(acc[r][d], w[3 * d + 2], lp);
-                    }
+                for (int d = 0; d < ND; ++d) {
+                    cfma(acc[d], w[3 * d], l0);
+                    cfma(acc[d], w[3 * d + 1], lm);
+                    cfma(acc[d], w[3 * d + 2], lp);
                 }
             }
-        }
-    }
-    const double *iw = g.invW + g.Woff[l];
-    cd *out = mp + g.box_off[b] * ND;
-#pragma unroll
-    for (int r = 0; r < PT_KR; ++r) {
-        int kk = tid + 256 * r;
-        if (kk < np) {
-            int k = kk - P;
             double f = iw[k < 0 ? -k : k];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) out[d * np + kk] = f * acc[r][d];
+            for (int d = 0; d < ND; ++d) {
+                cd v = mk(f * acc[d].x, f * acc[d].y);
+                if (!first) v = out[d * np + kk] + v;
+                out[d * np + kk] = v;
+            }
         }
     }
 }
@@ -446,11 +471,12 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int
 // S_n = W_min(|n|,P), built from A_n = tau^n H_n (tau = min(1, x/2)) and
 // S_n tau^{-n} (one exp per run of orders, ratios of the W table after it);
 // the two dipole sums are rescaled by W_|l| / S_{l-+1} at the end.  The
-// sources of all X-list boxes of b are taken in list order.
+// sources of all X-list boxes of b are taken in list order (flattened on
+// the host).
 // ---------------------------------------------------------------------------
 template <int ND>
-__global__ void __launch_bounds__(256) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd,
-                                               cd *loc, int CH)
+__global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd,
+                                              cd *loc, int CH)
 {
     extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
@@ -462,30 +488,19 @@ __global__ void __launch_bounds__(256) k_p2l_x(DevGeom g, const int *list, const
     double *TH = reinterpret_cast<double *>(V + CH);   // [CH]
     double *LT = TH + CH;                              // [CH] log tau
     double *TAU = LT + CH;                             // [CH]
+    double *RW = TAU + CH;                             // [P+2] S_{n+1} / S_n
     const double *Wl = g.Wtab + g.Woff[l], *iWl = g.invW + g.Woff[l], *lWl = g.logW + g.Woff[l];
     int tid = threadIdx.x;
+    for (int n = tid; n <= P + 1; n += blockDim.x) RW[n] = Wl[min(n + 1, P)] * iWl[min(n, P)];
     double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
-    cd acc[PT_KR][3][ND];
-#pragma unroll
-    for (int r = 0; r < PT_KR; ++r)
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-#pragma unroll
-            for (int d = 0; d < ND; ++d) acc[r][e][d] = mk(0.0, 0.0);
-    int x0 = g.X_start[b], x1 = g.X_start[b + 1];
-    int total = 0;
-    for (int xi = x0; xi < x1; ++xi) total += g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]];
+    cd *out = loc + g.box_off[b] * ND;
+    int q0 = g.xsrc_start[blockIdx.x], total = g.xsrc_start[blockIdx.x + 1] - q0;
     int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
     for (int f0 = 0; f0 < total; f0 += CH) {
         int cnt = min(CH, total - f0);
         __syncthreads();
         if (tid < cnt) {
-            int f = f0 + tid, xi = x0;
-            while (f >= g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]]) {
-                f -= g.src_end[g.X_idx[xi]] - g.src_begin[g.X_idx[xi]];
-                ++xi;
-            }
-            int j = g.src_begin[g.X_idx[xi]] + f;
+            int j = g.xsrc_idx[q0 + f0 + tid];
             double dx = g.sx[j] - mx, dy = g.sy[j] - my;
             double r = sqrt(dx * dx + dy * dy);
             double x = g.omega * r;
@@ -523,39 +538,38 @@ __global__ void __launch_bounds__(256) k_p2l_x(DevGeom g, const int *list, const
                     row[-n] = (n & 1) ? neg(m) : m;
                 }
                 ph = ph * v;
-                sc *= Wl[min(n + 1, P)] * iWl[min(n, P)] * itau;
+                sc *= RW[n] * itau;
             }
         }
         __syncthreads();
+        bool first = f0 == 0;
+        for (int kk = tid; kk < np; kk += blockDim.x) {
+            cd acc[3][ND];
 #pragma unroll
-        for (int r = 0; r < PT_KR; ++r) {
-            int kk = tid + 256 * r;
-            if (kk < np) {
-                for (int t = 0; t < cnt; ++t) {
-                    const cd *row = T + t * NT + kk + 1;   // order l = kk - P at row[0]
-                    cd om = row[-1], o0 = row[0], op = row[1];
-                    const cd *w = Wt + t * ND * 3;
+            for (int e = 0; e < 3; ++e)
 #pragma unroll
-                    for (int d = 0; d < ND; ++d) {
-                        cfma(acc[r][0][d], w[3 * d], o0);
-                        cfma(acc[r][1][d], w[3 * d + 1], om);
-                        cfma(acc[r][2][d], w[3 * d + 2], op);
-                    }
+                for (int d = 0; d < ND; ++d) acc[e][d] = mk(0.0, 0.0);
+            for (int t = 0; t < cnt; ++t) {
+                const cd *row = T + t * NT + kk + 1;   // order l = kk - P at row[0]
+                cd om = row[-1], o0 = row[0], op = row[1];
+                const cd *w = Wt + t * ND * 3;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    cfma(acc[0][d], w[3 * d], o0);
+                    cfma(acc[1][d], w[3 * d + 1], om);
+                    cfma(acc[2][d], w[3 * d + 2], op);
                 }
             }
-        }
-    }
-    cd *out = loc + g.box_off[b] * ND;
-#pragma unroll
-    for (int r = 0; r < PT_KR; ++r) {
-        int kk = tid + 256 * r;
-        if (kk < np) {
             int ell = kk - P, al = ell < 0 ? -ell : ell;
             int am = ell - 1 < 0 ? 1 - ell : ell - 1, ap = ell + 1 < 0 ? -ell - 1 : ell + 1;
             double rm = Wl[al] * iWl[min(am, P)], rp = Wl[al] * iWl[min(ap, P)];
 #pragma unroll
-            for (int d = 0; d < ND; ++d)
-                out[d * np + kk] = acc[r][0][d] + rm * acc[r][1][d] + rp * acc[r][2][d];
+            for (int d = 0; d < ND; ++d) {
+                cd v = mk(fma(rp, acc[2][d].x, fma(rm, acc[1][d].x, acc[0][d].x)),
+                          fma(rp, acc[2][d].y, fma(rm, acc[1][d].y, acc[0][d].y)));
+                if (!first) v = out[d * np + kk] + v;
+                out[d * np + kk] = v;
+            }
         }
     }
 }
@@ -779,7 +793,6 @@ __global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, 
 // ---------------------------------------------------------------------------
 constexpr size_t LDS_BUDGET = 64 * 1024;
 constexpr int QCG_MAX = 16;   // centres per group (upper bound)
-constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p + QBLK
 
 size_t m2qbxl_lds_bytes(int nd, int Pw, int p, int cg)
 {
@@ -835,24 +848,28 @@ __global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *p
     }
     double mx = g.bcx[w], my = g.bcy[w];
     cd *out_pair = wy + pair_off[blockIdx.x] * nd;
+    // this workgroup's group of centres (blockIdx.y); the Hankel sequences
+    // depend on the geometry only and serve every density
+    int cg0 = c0 + blockIdx.y * QCG;
+    if (cg0 >= c1) return;
+    int cnt = min(QCG, c1 - cg0);
+    if (tid < cnt) {
+        int i = cg0 + tid;
+        double dx = g.cx[i] - mx, dy = g.cy[i] - my;
+        double r = sqrt(dx * dx + dy * dy);
+        double x = g.omega * r;
+        double tau = fmin(1.0, 0.5 * x);
+        scaled_hankel_seq(x, tau, N, Hs + tid * (N + 1), 1);
+        U[tid] = mk(dx / r, dy / r);
+        TAU[tid] = tau;
+        LT[tid] = log(tau);
+        TH[tid] = atan2(dy, dx);
+    }
     for (int d = 0; d < nd; ++d) {
         const cd *src = mp + g.box_off[w] * nd + (long long)d * nw;
-        for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
-            int cnt = min(QCG, c1 - cg0);
+        {
             __syncthreads();
             for (int i = tid; i < nw; i += blockDim.x) Aw[i] = src[i];
-            if (tid < cnt) {
-                int i = cg0 + tid;
-                double dx = g.cx[i] - mx, dy = g.cy[i] - my;
-                double r = sqrt(dx * dx + dy * dy);
-                double x = g.omega * r;
-                double tau = fmin(1.0, 0.5 * x);
-                scaled_hankel_seq(x, tau, N, Hs + tid * (N + 1), 1);
-                U[tid] = mk(dx / r, dy / r);
-                TAU[tid] = tau;
-                LT[tid] = log(tau);
-                TH[tid] = atan2(dy, dx);
-            }
             __syncthreads();
             int items = cnt * nblk;
             for (int it0 = 0; it0 < items; it0 += 256 / QSPLIT) {
@@ -1027,8 +1044,8 @@ size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
            sizeof(double) * ((size_t)cg * (N + 1) + 3 * (size_t)cg);
 }
 
-__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const cd *loc,
-                                                cd *coef, int QCG)
+__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad,
+                                                const cd *loc, cd *coef, int QCG)
 {
     extern __shared__ double lds_raw[];
     int b = list[blockIdx.x];
@@ -1043,8 +1060,6 @@ __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *li
     cd *U = Gb + nd * np;                              // [QCG]
     double *Jt = reinterpret_cast<double *>(U + QCG);  // [QCG][N+1]
     double *TH = Jt + QCG * (N + 1);                   // [QCG]
-    double *XA = TH + QCG;                             // [QCG] omega |m_b - c|
-    double *LH = XA + QCG;                             // [QCG] ln(x / 2)
     const double *iw = g.invW + g.Woff[l];
     const cd *src = loc + g.box_off[b] * nd;
     for (int i = tid; i < nd * np; i += blockDim.x) {
@@ -1055,22 +1070,16 @@ __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *li
     for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
         int cnt = min(QCG, c1 - cg0);
         __syncthreads();
-        bool big = false;
         if (tid < cnt) {
             int i = cg0 + tid;
             double dx = mx - g.cx[i], dy = my - g.cy[i];
             double r = sqrt(dx * dx + dy * dy);
-            double x = g.omega * r;
-            XA[tid] = x;
-            LH[tid] = log(0.5 * x);
-            big = x > kSeriesMaxX;
             U[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
             TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
         }
-        if (__syncthreads_or(big)) {
-            if (tid < cnt) besselj_seq_call(XA[tid], N, Jt + tid * (N + 1), 1);
-        } else {
-            besselj_table_series(XA, LH, cnt, N, g.lnfact, Jt, N + 1, 1);
+        for (int i = tid; i < cnt * (N + 1); i += blockDim.x) {
+            int n = i / cnt, t = i - n * cnt;
+            Jt[t * (N + 1) + n] = crad[(long long)n * g.nc + cg0 + t];
         }
         __syncthreads();
         int items = nd * cnt * nblk;
@@ -1265,26 +1274,36 @@ hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, 
     return hipSuccess;
 }
 
-static int pick_ch(int nd, int Pmax)
+// Sources per pass, sized for the largest density count so that the order
+// of the sums (and so every bit of the result) does not depend on how many
+// densities share a launch.
+static int pick_ch(int Pmax)
 {
-    int ch = 32;
-    while (ch > 1 && ptab_lds_bytes(nd, Pmax, ch) > LDS_BUDGET) ch >>= 1;
+    int ch = 64;
+    while (ch > 1 && ptab_lds_bytes(4, Pmax, ch) > PT_LDS) --ch;
     return ch;
 }
 
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, cd *mp, hipStream_t s)
+                      const cd *qd, double *srad, int srad_rows, cd *mp, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    if (2 * Pmax + 1 > 256 * PT_KR || nd < 1 || nd > 4) return hipErrorInvalidValue;
-    int ch = pick_ch(nd, Pmax);
-    size_t lds = ptab_lds_bytes(nd, Pmax, ch);
-    if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+    if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+    {
+        int lanes = rad_lanes(srad_rows);
+        k_src_rad<<<(g.ns + lanes - 1) / lanes, lanes, (size_t)srad_rows * lanes * sizeof(double), s>>>(
+            g, srad_rows, srad);
+        QBX_LAUNCH_CHECK();
+    }
+    // sources per pass sized for four densities: the same passes for every nd
+    int ch = 64;
+    while (ch > 1 && p2m_lds_bytes(4, Pmax, ch) > PT_LDS) --ch;
+    size_t lds = p2m_lds_bytes(nd, Pmax, ch);
     switch (nd) {
-    case 1: k_p2m<1><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
-    case 2: k_p2m<2><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
-    case 3: k_p2m<3><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
-    default: k_p2m<4><<<n, 256, lds, s>>>(g, list, qs, qd, mp, ch); break;
+    case 1: k_p2m<1><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
+    case 2: k_p2m<2><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
+    case 3: k_p2m<3><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
+    default: k_p2m<4><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
@@ -1333,15 +1352,15 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
                         const cd *qd, cd *loc, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    if (2 * Pmax + 1 > 256 * PT_KR || nd < 1 || nd > 4) return hipErrorInvalidValue;
-    int ch = pick_ch(nd, Pmax);
+    if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+    int ch = pick_ch(Pmax);
     size_t lds = ptab_lds_bytes(nd, Pmax, ch);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
     switch (nd) {
-    case 1: k_p2l_x<1><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
-    case 2: k_p2l_x<2><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
-    case 3: k_p2l_x<3><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
-    default: k_p2l_x<4><<<n, 256, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    case 1: k_p2l_x<1><<<n, 64, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    case 2: k_p2l_x<2><<<n, 64, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    case 3: k_p2l_x<3><<<n, 64, lds, s>>>(g, list, qs, qd, loc, ch); break;
+    default: k_p2l_x<4><<<n, 64, lds, s>>>(g, list, qs, qd, loc, ch); break;
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
@@ -1408,21 +1427,29 @@ hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long
     while (cg > 1 && m2qbxl_lds_bytes(nd, PWmax, g.p, cg) > LDS_BUDGET) cg >>= 1;
     size_t lds = m2qbxl_lds_bytes(nd, PWmax, g.p, cg);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-    k_m2qbxl<<<npairs, 256, lds, s>>>(g, nd, pairs, pair_off, mp, wy, cg);
+    // centre groups per leaf: at most ceil(max centres per leaf / cg)
+    k_m2qbxl<<<dim3(npairs, (g.max_leaf_ctr + cg - 1) / cg), 256, lds, s>>>(g, nd, pairs, pair_off, mp, wy, cg);
     QBX_LAUNCH_CHECK();
     k_wsum<<<nleaf, 256, 0, s>>>(g, nd, leaf_list, leaf_pair_start, pair_off, wy, coef);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
-                         const cd *loc, cd *coef, hipStream_t s)
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
+                         int crad_rows, const cd *loc, cd *coef, hipStream_t s)
 {
     if (!n) return hipSuccess;
+    if (Pmax + g.p + QBLK > crad_rows) return hipErrorInvalidValue;
+    {
+        int lanes = rad_lanes(crad_rows);
+        k_ctr_rad<<<(g.nc + lanes - 1) / lanes, lanes, (size_t)crad_rows * lanes * sizeof(double), s>>>(
+            g, crad_rows, crad);
+        QBX_LAUNCH_CHECK();
+    }
     int cg = pick_cg(l2qbxl_lds_bytes, nd, Pmax, g.p);
     size_t lds = l2qbxl_lds_bytes(nd, Pmax, g.p, cg);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-    k_l2qbxl<<<n, 256, lds, s>>>(g, nd, list, loc, coef, cg);
+    k_l2qbxl<<<n, 256, lds, s>>>(g, nd, list, crad, loc, coef, cg);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -10,6 +10,7 @@ namespace qbx {
 // All pointers are device pointers.  Points are in tree (Morton) order.
 struct DevGeom {
     int ns, nc, nt, nb, nlev, p, n_smooth;
+    int max_leaf_ctr;                          // most centres in one leaf
     double omega;
     const double *sx, *sy, *sw, *snx, *sny;   // sorted sources
     const int *src_perm;                       // sorted -> user source index
@@ -27,11 +28,12 @@ struct DevGeom {
     const int *near_start, *near_idx, *wf_start, *wf_idx;
     // near-list sources of the i-th leaf of the P2QBXL list: qsrc_idx[qsrc_start[i]..]
     const int *qsrc_start, *qsrc_idx;
+    // X-list sources of the i-th box of the X-list P2L list: xsrc_idx[xsrc_start[i]..]
+    const int *xsrc_start, *xsrc_idx;
+    const int *src_box, *ctr_box;              // leaf (level >= 2) of each source / centre, or -1
     const int *Plev;                           // FMM order per level
     const int *Woff;                           // per level offset into Wtab/invW/logW
     const double *Wtab, *invW, *logW;
-    const double *lnfact;                      // ln n!, n < n_lnfact
-    int n_lnfact;
     const long long *box_off;                  // per box, in coefficients of one density
     // M2M / L2L scaled matrices per (parent level, child quadrant) in MFMA
     // A-operand order; child4[b*4+q] = child of b in quadrant q or -1
@@ -75,7 +77,7 @@ hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
 hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,
                           hipStream_t s);
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, cd *mp, hipStream_t s);
+                      const cd *qd, double *srad, int srad_rows, cd *mp, hipStream_t s);
 hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
                            int nrb, const int *plist, cd *mp, hipStream_t s);
 hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
@@ -93,8 +95,8 @@ hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd
 hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off,
                          int npairs, int PWmax, const cd *mp, cd *wy, const int *leaf_list,
                          const int *leaf_pair_start, int nleaf, cd *coef, hipStream_t s);
-hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax,
-                         const cd *loc, cd *coef, hipStream_t s);
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
+                         int crad_rows, const cd *loc, cd *coef, hipStream_t s);
 hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s);
 hipError_t launch_smooth(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, hipStream_t s);
 hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hipStream_t s);
