@@ -16,6 +16,11 @@ using namespace qbx;
 struct qbx_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    // a second stream for the near field and the X-list P2L, which depend on
+    // the charges only and overlap the latency-bound upward/downward passes;
+    // events fork it from and join it back to the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr;
 };
 
 namespace {
@@ -594,14 +599,30 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         STAGE(QBX_STAGE_DIRECT);
         LAUNCH(QBX_STAGE_DIRECT, pl.nc, launch_p2qbxl_direct(g, nd, G->qs, G->qd, G->coef, st));
     } else {
+        qbx_status ts = ensure_tiles(G, nd);
+        if (ts != QBX_OK) return ts;
+        // Fork: the side stream takes the centre J sequences, the X-list P2L
+        // and the near field while this stream runs P2M, M2M and M2L.  With
+        // stage profiling on everything stays on one stream, in order.
+        const qbx_ctx_s *C = G->ctx;
+        bool conc = !G->profile && C->side;
+        hipStream_t s1 = conc ? C->side : st;
+        if (conc) {
+            CHK(hipEventRecord(C->ev_fork, st));
+            CHK(hipStreamWaitEvent(s1, C->ev_fork, 0));
+            CHK(launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, s1));
+            CHK(launch_fill_zero(G->loc, (long long)nd * G->total_coef, s1));
+            CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, s1));
+            CHK(hipEventRecord(C->ev_x, s1));
+            CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, s1));
+            CHK(hipEventRecord(C->ev_q, s1));
+        }
         {
             STAGE(QBX_STAGE_P2M);
             LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->srad, G->srad_rows, G->mp, st));
         }
         {
             STAGE(QBX_STAGE_M2M);
-            qbx_status ts = ensure_tiles(G, nd);
-            if (ts != QBX_OK) return ts;
             for (int l = pl.nlev - 2; l >= 2; --l) {
                 int t0 = G->m2m_tstart[nd][l], nt = G->m2m_tstart[nd][l + 1] - t0;
                 int nrb = (2 * pl.P[l] + 1 + 15) / 16;
@@ -613,7 +634,9 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
                    launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->mp, G->vy, st));
         }
-        {
+        if (conc) {
+            CHK(hipStreamWaitEvent(st, C->ev_x, 0));
+        } else {
             STAGE(QBX_STAGE_P2L_X);
             LAUNCH(QBX_STAGE_P2L_X, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
             LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
@@ -631,7 +654,9 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
                 LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, G->vy, G->loc, st));
             }
         }
-        {
+        if (conc) {
+            CHK(hipStreamWaitEvent(st, C->ev_q, 0));
+        } else {
             STAGE(QBX_STAGE_P2QBXL);
             LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
         }
@@ -643,6 +668,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
+            if (!conc) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
             LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, G->loc, G->coef, st));
         }
     }
@@ -721,6 +747,19 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     if (!c) return fail(QBX_E_NOMEM, "host allocation failed");
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
+    // default priority on purpose; without the stream the pipeline runs in order
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_x, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_q, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_x) (void)hipEventDestroy(c->ev_x);
+        if (c->ev_q) (void)hipEventDestroy(c->ev_q);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        c->side = nullptr;
+        c->ev_fork = c->ev_x = c->ev_q = nullptr;
+    }
     *out = c;
     return QBX_OK;
 }
@@ -734,6 +773,15 @@ qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream)
 
 qbx_status qbx_ctx_destroy(qbx_ctx ctx)
 {
+    if (!ctx) return QBX_OK;
+    if (ctx->side) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipEventDestroy(ctx->ev_fork);
+        (void)hipEventDestroy(ctx->ev_x);
+        (void)hipEventDestroy(ctx->ev_q);
+        (void)hipStreamDestroy(ctx->side);
+    }
     delete ctx;
     return QBX_OK;
 }

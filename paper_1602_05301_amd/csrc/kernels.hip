@@ -1435,17 +1435,21 @@ hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long
     return hipSuccess;
 }
 
+hipError_t launch_ctr_rad(const DevGeom &g, int nleaf, double *crad, int crad_rows, hipStream_t s)
+{
+    if (!nleaf || !g.nc) return hipSuccess;
+    int lanes = rad_lanes(crad_rows);
+    k_ctr_rad<<<(g.nc + lanes - 1) / lanes, lanes, (size_t)crad_rows * lanes * sizeof(double), s>>>(
+        g, crad_rows, crad);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
 hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
                          int crad_rows, const cd *loc, cd *coef, hipStream_t s)
 {
     if (!n) return hipSuccess;
     if (Pmax + g.p + QBLK > crad_rows) return hipErrorInvalidValue;
-    {
-        int lanes = rad_lanes(crad_rows);
-        k_ctr_rad<<<(g.nc + lanes - 1) / lanes, lanes, (size_t)crad_rows * lanes * sizeof(double), s>>>(
-            g, crad_rows, crad);
-        QBX_LAUNCH_CHECK();
-    }
     int cg = pick_cg(l2qbxl_lds_bytes, nd, Pmax, g.p);
     size_t lds = l2qbxl_lds_bytes(nd, Pmax, g.p, cg);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;

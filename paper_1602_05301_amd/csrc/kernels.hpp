@@ -95,6 +95,8 @@ hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd
 hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off,
                          int npairs, int PWmax, const cd *mp, cd *wy, const int *leaf_list,
                          const int *leaf_pair_start, int nleaf, cd *coef, hipStream_t s);
+// J_n sequences of the L2QBXL centres (leaves of level >= 2), into crad
+hipError_t launch_ctr_rad(const DevGeom &g, int nleaf, double *crad, int crad_rows, hipStream_t s);
 hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
                          int crad_rows, const cd *loc, cd *coef, hipStream_t s);
 hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s);

@@ -188,3 +188,21 @@ def test_no_targets(ctx):
     u = geo.eval(s, None)
     torch.cuda.synchronize()
     assert u.shape == (1, 0)
+
+
+def test_side_stream_matches_in_order_run(ctx):
+    """The near field and the X-list P2L run on a second stream unless stage
+    profiling is on; both schedules compute the same numbers, bit for bit,
+    over several evaluations in a row."""
+    from paper_1602_05301_amd import qbx
+    wl = inputs.fmm_star(n_panels=256, omega=50.0, eps=1e-10, p=14)
+    g = wl.geom
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    ss, sd = _dev(wl.sigma_s), _dev(wl.sigma_d)
+    geo.profile(True)
+    ref = geo.eval(ss, sd).cpu().numpy()
+    geo.profile(False)
+    for _ in range(3):
+        u = geo.eval(ss, sd)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref)
