@@ -20,7 +20,7 @@ struct qbx_ctx_s {
     // the charges only and overlap the latency-bound upward/downward passes;
     // events fork it from and join it back to the caller's stream
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr, ev_m = nullptr;
 };
 
 namespace {
@@ -601,9 +601,10 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
     } else {
         qbx_status ts = ensure_tiles(G, nd);
         if (ts != QBX_OK) return ts;
-        // Fork: the side stream takes the centre J sequences, the X-list P2L
-        // and the near field while this stream runs P2M, M2M and M2L.  With
-        // stage profiling on everything stays on one stream, in order.
+        // Fork: the side stream takes the centre J sequences, the X-list P2L,
+        // the near field and (once M2M is done) M2QBXL while this stream runs
+        // P2M, M2M, M2L and L2L.  With stage profiling on everything stays on
+        // one stream, in order.
         const qbx_ctx_s *C = G->ctx;
         bool conc = !G->profile && C->side;
         hipStream_t s1 = conc ? C->side : st;
@@ -615,7 +616,6 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, s1));
             CHK(hipEventRecord(C->ev_x, s1));
             CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, s1));
-            CHK(hipEventRecord(C->ev_q, s1));
         }
         {
             STAGE(QBX_STAGE_P2M);
@@ -628,6 +628,14 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
                 int nrb = (2 * pl.P[l] + 1 + 15) / 16;
                 LAUNCH(QBX_STAGE_M2M, nt, launch_m2m_mfma(g, nd, l, G->m2m_tiles[nd] + t0, nt, nrb, G->d_par_list, G->mp, st));
             }
+        }
+        if (conc) {
+            // multipoles complete: M2QBXL joins the side stream after the near field
+            CHK(hipEventRecord(C->ev_m, st));
+            CHK(hipStreamWaitEvent(s1, C->ev_m, 0));
+            CHK(launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, G->mp, G->wy,
+                              G->wl.d, G->d_wleaf_start, G->wl.n, G->coef, s1));
+            CHK(hipEventRecord(C->ev_q, s1));
         }
         {
             STAGE(QBX_STAGE_M2L);
@@ -657,10 +665,10 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         if (conc) {
             CHK(hipStreamWaitEvent(st, C->ev_q, 0));
         } else {
-            STAGE(QBX_STAGE_P2QBXL);
-            LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
-        }
-        {
+            {
+                STAGE(QBX_STAGE_P2QBXL);
+                LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
+            }
             STAGE(QBX_STAGE_M2QBXL);
             LAUNCH(QBX_STAGE_M2QBXL, G->n_wpairs,
                    launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, G->mp,
@@ -751,14 +759,16 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_x, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_q, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_q, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_m, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_x) (void)hipEventDestroy(c->ev_x);
         if (c->ev_q) (void)hipEventDestroy(c->ev_q);
+        if (c->ev_m) (void)hipEventDestroy(c->ev_m);
         if (c->side) (void)hipStreamDestroy(c->side);
         c->side = nullptr;
-        c->ev_fork = c->ev_x = c->ev_q = nullptr;
+        c->ev_fork = c->ev_x = c->ev_q = c->ev_m = nullptr;
     }
     *out = c;
     return QBX_OK;
@@ -780,6 +790,7 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx)
         (void)hipEventDestroy(ctx->ev_fork);
         (void)hipEventDestroy(ctx->ev_x);
         (void)hipEventDestroy(ctx->ev_q);
+        (void)hipEventDestroy(ctx->ev_m);
         (void)hipStreamDestroy(ctx->side);
     }
     delete ctx;
