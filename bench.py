@@ -71,6 +71,33 @@ def cpu_baseline(wl, target_seconds=12.0):
                       f"threads of {cpu}"}
 
 
+# stage -> its main kernel, as rocprofv3 names it
+STAGE_KERNEL = {"p2m": "k_p2m", "m2m": "k_m2m_mfma", "m2l": "k_m2l_mfma", "p2l_x": "k_p2l_x",
+                "l2l": "k_l2l_mfma", "p2qbxl": "k_p2qbxl", "m2qbxl": "k_m2qbxl",
+                "l2qbxl": "k_l2qbxl", "eval": "k_qbx_eval"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qbx_fmm_star7_32768_traffic.json")
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (copy-calibrated), or None when there is
+    none or the kernel source has changed since the counters were taken."""
+    import hashlib
+    kname = STAGE_KERNEL.get(stage)
+    if not kname or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        doc = json.load(f)
+    src = os.path.join(ROOT, "paper_1602_05301_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != doc.get("kernels_source_sha256"):
+            return None
+    for k, v in doc.get("kernels", {}).items():
+        if k == kname or k.startswith(kname + "<"):
+            return v["hbm_bytes_per_dispatch"]
+    return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,8 +183,9 @@ def main(argv=None):
     achieved = work[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
     # translations on the FP64 matrix cores; everything else on the FP64 vector ALUs
     bound = "mfma" if dom in ("m2m", "m2l", "l2l") else "alu"
+    traffic = measured_traffic(dom)
     roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
             "algorithmic_flops_per_step": work[dom], "ms_per_step": dom_ms,
             "launches_per_step": stages[dom][1] / args.steps}
 
