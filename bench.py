@@ -107,6 +107,9 @@ def main(argv=None):
     ap.add_argument("--latency-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay a captured HIP graph per evaluation instead of enqueueing every "
+                         "kernel (measured slower here: the eager two-stream schedule overlaps more)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warm-up, copy a buffer of this many MiB once on the device: "
                          "a kernel of known traffic for calibrating HBM byte counters")
@@ -139,6 +142,7 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    geo.graph(args.graph)
     for _ in range(args.warmup):
         geo.eval(ss, sd, u=u)
     torch.cuda.synchronize()
@@ -214,6 +218,7 @@ def main(argv=None):
         "roofline": roof,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
         "ms_per_step_stages_in_order": serial_ms,
+        "graph_replay": args.graph,
         "stages_tflops": {k: work[k] / (v[0] / args.steps * 1e-3) / 1e12
                           for k, v in stages.items() if v[1] and v[0] > 0 and work.get(k)},
         "setup_s": setup_s,

@@ -188,8 +188,22 @@ enum {
 
 /* qbx_geom_profile: enable (1) or disable (0) HIP-event timing of every
  * stage of later qbx_eval calls on this geometry (events are recorded on
- * the context's stream around each stage's launches). */
+ * the context's stream around each stage's launches).  While profiling is
+ * on, every stage runs in order on the context's stream (no second stream,
+ * no graph), so each stage's time is its own. */
 qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
+/* qbx_geom_graph: enable (1) or disable (0) graph replay of later qbx_eval
+ * calls on this geometry (the "execution modes" of a served matvec loop,
+ * where the same evaluation repeats with new density values in the same
+ * buffers).  The first call with a given (n_dens, sigma_s, sigma_d, u, coef)
+ * captures the whole evaluation into a HIP graph on a stream of the
+ * library's own; later calls with the same pointers replay it.  The graph
+ * stream waits for the context's stream and the context's stream waits for
+ * the graph, so ordering against the caller is unchanged.  Up to 8 argument
+ * sets are kept per geometry (least recently used evicted).  Results are
+ * identical to the plain path.  QBX_E_UNSUPPORTED if the context could not
+ * create its streams. */
+qbx_status qbx_geom_graph(qbx_geom geom, int32_t enable);
 /* Accumulated milliseconds and launch counts per stage since the last reset
  * (synchronises the stream).  ms and launches hold QBX_N_STAGES entries
  * (either may be NULL); reset != 0 clears the accumulators. */

@@ -21,6 +21,11 @@ struct qbx_ctx_s {
     // events fork it from and join it back to the caller's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr, ev_m = nullptr;
+    // captured evaluations run on a stream of the library's own (the caller's
+    // may be the null stream, which cannot be captured), joined to the
+    // caller's stream by events
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -109,6 +114,17 @@ struct qbx_geom_s {
     // and per L2QBXL centre (n-major)
     int srad_rows = 0, crad_rows = 0;
     double *srad = nullptr, *crad = nullptr;
+    // captured evaluations (qbx_geom_graph), keyed by their arguments
+    struct GraphRec {
+        int n_dens;
+        const void *ss, *sd;
+        void *u, *coef;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    bool graph_on = false;
+    std::vector<GraphRec> graphs;
+    uint64_t graph_clock = 0;
     // per-stage HIP-event timing (qbx_geom_profile)
     struct StageRec {
         int stage;
@@ -124,6 +140,7 @@ struct qbx_geom_s {
     {
         for (auto &r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : spare) (void)hipEventDestroy(e);
+        for (auto &r : graphs) (void)hipGraphExecDestroy(r.exec);
     }
 };
 
@@ -586,11 +603,11 @@ qbx_status harvest(qbx_geom_s *G)
         CHK(expr);                 \
     } while (0)
 
-qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out)
+qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out,
+                        hipStream_t st)
 {
     const Plan &pl = G->pl;
     const DevGeom &g = G->g;
-    hipStream_t st = G->ctx->stream;
     {
         STAGE(QBX_STAGE_CHARGES);
         LAUNCH(QBX_STAGE_CHARGES, pl.ns, launch_charges(g, nd, ss, sd, G->qs, G->qd, st));
@@ -760,15 +777,21 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_x, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_q, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_m, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_m, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_x) (void)hipEventDestroy(c->ev_x);
         if (c->ev_q) (void)hipEventDestroy(c->ev_q);
         if (c->ev_m) (void)hipEventDestroy(c->ev_m);
+        if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+        if (c->ev_out) (void)hipEventDestroy(c->ev_out);
         if (c->side) (void)hipStreamDestroy(c->side);
-        c->side = nullptr;
-        c->ev_fork = c->ev_x = c->ev_q = c->ev_m = nullptr;
+        if (c->gstream) (void)hipStreamDestroy(c->gstream);
+        c->side = c->gstream = nullptr;
+        c->ev_fork = c->ev_x = c->ev_q = c->ev_m = c->ev_in = c->ev_out = nullptr;
     }
     *out = c;
     return QBX_OK;
@@ -787,11 +810,15 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx)
     if (ctx->side) {
         (void)hipSetDevice(ctx->device);
         (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamSynchronize(ctx->gstream);
         (void)hipEventDestroy(ctx->ev_fork);
         (void)hipEventDestroy(ctx->ev_x);
         (void)hipEventDestroy(ctx->ev_q);
         (void)hipEventDestroy(ctx->ev_m);
+        (void)hipEventDestroy(ctx->ev_in);
+        (void)hipEventDestroy(ctx->ev_out);
         (void)hipStreamDestroy(ctx->side);
+        (void)hipStreamDestroy(ctx->gstream);
     }
     delete ctx;
     return QBX_OK;
@@ -847,6 +874,8 @@ qbx_status qbx_geom_destroy(qbx_geom G)
     (void)hipSetDevice(G->ctx->device);
     if (G->ctx->stream) (void)hipStreamSynchronize(G->ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (G->ctx->gstream) (void)hipStreamSynchronize(G->ctx->gstream);
+    if (G->ctx->side) (void)hipStreamSynchronize(G->ctx->side);
     G->scratch.release();
     G->arena.release();
     delete G;
@@ -895,6 +924,70 @@ qbx_status qbx_geom_work(qbx_geom G, int32_t n_dens, double *flops)
     return QBX_OK;
 }
 
+// All chunks of one evaluation, enqueued on stream st.
+qbx_status eval_chunks(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
+                       void *coef, hipStream_t st)
+{
+    const Plan &pl = G->pl;
+    long long nq = 2 * pl.p + 1;
+    for (int d0 = 0; d0 < n_dens; d0 += kDensChunk) {
+        int nd = std::min(kDensChunk, n_dens - d0);
+        const cd *ss = sigma_s ? static_cast<const cd *>(sigma_s) + (long long)d0 * pl.ns : nullptr;
+        const cd *sd = sigma_d ? static_cast<const cd *>(sigma_d) + (long long)d0 * pl.ns : nullptr;
+        cd *uu = static_cast<cd *>(u) + (long long)d0 * pl.nt;
+        cd *co = coef ? static_cast<cd *>(coef) + (long long)d0 * nq * pl.nc : nullptr;
+        qbx_status q = run_pipeline(G, nd, ss, sd, uu, co, st);
+        if (q != QBX_OK) return q;
+    }
+    return QBX_OK;
+}
+
+constexpr size_t kMaxGraphs = 8;   // captured argument sets kept per geometry
+
+// The captured evaluation for these arguments, capturing it on first use.
+qbx_status graph_for(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
+                     void *coef, hipGraphExec_t *out)
+{
+    for (auto &r : G->graphs)
+        if (r.n_dens == n_dens && r.ss == sigma_s && r.sd == sigma_d && r.u == u && r.coef == coef) {
+            r.used = ++G->graph_clock;
+            *out = r.exec;
+            return QBX_OK;
+        }
+    // everything that allocates happens before the capture
+    for (int d0 = 0; d0 < n_dens; d0 += kDensChunk) {
+        qbx_status q = ensure_tiles(G, std::min(kDensChunk, n_dens - d0));
+        if (q != QBX_OK) return q;
+    }
+    hipStream_t gs = G->ctx->gstream;
+    hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    qbx_status q = eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, gs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(gs, &graph);
+    if (q != QBX_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return q;
+    }
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    if (G->graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < G->graphs.size(); ++i)
+            if (G->graphs[i].used < G->graphs[lru].used) lru = i;
+        // the evicted graph may still run: wait for the library's stream
+        (void)hipStreamSynchronize(gs);
+        (void)hipGraphExecDestroy(G->graphs[lru].exec);
+        G->graphs.erase(G->graphs.begin() + lru);
+    }
+    G->graphs.push_back({n_dens, sigma_s, sigma_d, u, coef, exec, ++G->graph_clock});
+    *out = exec;
+    return QBX_OK;
+}
+
 qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
                     void *coef)
 {
@@ -906,17 +999,26 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     qbx_status st = ensure_scratch(G);
     if (st != QBX_OK) return st;
-    const Plan &pl = G->pl;
-    long long nq = 2 * pl.p + 1;
-    for (int d0 = 0; d0 < n_dens; d0 += kDensChunk) {
-        int nd = std::min(kDensChunk, n_dens - d0);
-        const cd *ss = sigma_s ? static_cast<const cd *>(sigma_s) + (long long)d0 * pl.ns : nullptr;
-        const cd *sd = sigma_d ? static_cast<const cd *>(sigma_d) + (long long)d0 * pl.ns : nullptr;
-        cd *uu = static_cast<cd *>(u) + (long long)d0 * pl.nt;
-        cd *co = coef ? static_cast<cd *>(coef) + (long long)d0 * nq * pl.nc : nullptr;
-        st = run_pipeline(G, nd, ss, sd, uu, co);
+    const qbx_ctx_s *C = G->ctx;
+    if (G->graph_on && !G->profile && C->gstream) {
+        hipGraphExec_t exec = nullptr;
+        st = graph_for(G, n_dens, sigma_s, sigma_d, u, coef, &exec);
         if (st != QBX_OK) return st;
+        CHK(hipEventRecord(C->ev_in, C->stream));
+        CHK(hipStreamWaitEvent(C->gstream, C->ev_in, 0));
+        CHK(hipGraphLaunch(exec, C->gstream));
+        CHK(hipEventRecord(C->ev_out, C->gstream));
+        CHK(hipStreamWaitEvent(C->stream, C->ev_out, 0));
+        return QBX_OK;
     }
+    return eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, C->stream);
+}
+
+qbx_status qbx_geom_graph(qbx_geom G, int32_t enable)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    if (!G->ctx->gstream) return fail(QBX_E_UNSUPPORTED, "graph stream unavailable");
+    G->graph_on = enable != 0;
     return QBX_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "qbx_plan_create", "qbx_plan_destroy", "qbx_plan_stats", "qbx_plan_boxes",
     "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
     "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
-    "qbx_geom_association", "qbx_geom_profile", "qbx_geom_stage_times", "qbx_geom_work",
+    "qbx_geom_association", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times", "qbx_geom_work",
     "qbx_eval",
 ]
 
@@ -101,6 +101,7 @@ def lib():
     L.qbx_geom_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     L.qbx_geom_association.argtypes = [_vp, _ip]
     L.qbx_geom_profile.argtypes = [_vp, i32]
+    L.qbx_geom_graph.argtypes = [_vp, i32]
     L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
     L.qbx_geom_work.argtypes = [_vp, i32, _dp]
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
@@ -239,6 +240,10 @@ class Geometry:
 
     def profile(self, enable: bool = True):
         _check(lib().qbx_geom_profile(self._h, int(bool(enable))))
+
+    def graph(self, enable: bool = True):
+        """Replay evaluations from captured HIP graphs (keyed by the buffers)."""
+        _check(lib().qbx_geom_graph(self._h, int(bool(enable))))
 
     def stage_times(self, reset: bool = True) -> dict:
         ms = np.zeros(len(STAGES))

@@ -206,3 +206,30 @@ def test_side_stream_matches_in_order_run(ctx):
         u = geo.eval(ss, sd)
         torch.cuda.synchronize()
         assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Captured evaluations replayed several times, with eager work and
+    synchronisations in between and new density values in the same buffers,
+    equal the eager results bit for bit (one and five densities)."""
+    from paper_1602_05301_amd import qbx
+    wl = inputs.fmm_star(n_panels=256, omega=50.0, eps=1e-10, p=14)
+    g = wl.geom
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    r = np.random.default_rng(11)
+    for nd in (1, 5):
+        ss = torch.empty((nd, g.n), dtype=torch.complex128, device="cuda:0")
+        sd = torch.empty_like(ss)
+        u = torch.empty((nd, g.n), dtype=torch.complex128, device="cuda:0")
+        for rep in range(3):
+            a = inputs.complex_gaussian(r, (nd, g.n))
+            b = inputs.complex_gaussian(r, (nd, g.n))
+            ss.copy_(_dev(a))
+            sd.copy_(_dev(b))
+            geo.graph(False)
+            ref = geo.eval(ss, sd).cpu().numpy()          # eager, fresh output
+            geo.graph(True)
+            geo.eval(ss, sd, u=u)                          # captured on rep 0, replayed after
+            torch.cuda.synchronize()
+            assert np.array_equal(u.cpu().numpy(), ref), (nd, rep)
+    geo.graph(False)
