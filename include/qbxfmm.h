@@ -63,7 +63,9 @@ typedef struct {
     int32_t p_add;        /* FMM order increment (Sec. 7.1, Table p_add); -1 = default rule */
     int32_t leaf_max;     /* n_max: split a box holding more sources + centres (Stage 1) */
     int32_t direct;       /* 1 = form QBX coefficients directly over all sources (no FMM) */
-    int32_t far_fp32;     /* reserved: FP32 far field; must be 0 in this build */
+    int32_t far_fp32;     /* 1 = M2L and L2L on FP32 matrix cores with complex-float
+                             tables (the scaled entries are bounded by one); allowed
+                             only when eps >= 1e-6.  Everything else stays FP64. */
     int32_t w_direct;     /* W-list boxes (Stage 5) whose sources enter the centre's
                              coefficients directly, as in P2QBXL, instead of through
                              M2QBXL: -1 = when cheaper by operation count (default),
@@ -123,7 +125,7 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx);
  * centres may be different point sets (oversampled sources, Sec. 2.2).
  * Errors: QBX_E_INVAL (n < 0, non-finite input, cr <= 0, w < 0, |n| not 1
  * within 1e-6, omega <= 0, eps outside [1e-15, 1e-2], p outside 0..40,
- * leaf_max < 1, far_fp32 != 0), QBX_E_ASSOC, QBX_E_NOMEM. */
+ * leaf_max < 1, far_fp32 with eps < 1e-6), QBX_E_ASSOC, QBX_E_NOMEM. */
 qbx_status qbx_plan_create(double omega, double eps, const qbx_options *opt,
                            int64_t n_src, const double *sx, const double *sy,
                            const double *w, const double *nx, const double *ny,

@@ -322,6 +322,18 @@ qbx_status upload(qbx_geom_s *G)
         }
     }
     g.m2m_mf = ar.upload(m2m); g.l2l_mf = ar.upload(l2l); g.m2l_mf = ar.upload(m2l);
+    g.far32 = pl.opt.far_fp32 ? 1 : 0;
+    g.m2l_mf32 = g.l2l_mf32 = nullptr;
+    if (g.far32) {
+        // the scaled entries are bounded by one, so complex float holds them
+        auto to32 = [](const std::vector<cd> &v) {
+            std::vector<cf> o(v.size());
+            for (size_t i = 0; i < v.size(); ++i) o[i] = cf{(float)v[i].x, (float)v[i].y};
+            return o;
+        };
+        g.m2l_mf32 = ar.upload(to32(m2l));
+        g.l2l_mf32 = ar.upload(to32(l2l));
+    }
     g.m2m_mf_off = ar.upload(m2m_off); g.l2l_mf_off = ar.upload(l2l_off); g.m2l_mf_off = ar.upload(m2l_off);
 
     // children by quadrant; M2M parent lists and L2L child lists per level

@@ -16,6 +16,11 @@ struct cd {
     double x, y;
 };
 
+// complex float, for the translation tables of the FP32 far field
+struct cf {
+    float x, y;
+};
+
 __host__ __device__ __forceinline__ cd mk(double a, double b) { return {a, b}; }
 __host__ __device__ __forceinline__ cd operator+(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
 __host__ __device__ __forceinline__ cd operator-(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }

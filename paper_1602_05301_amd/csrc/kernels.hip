@@ -354,6 +354,83 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(DevGeom g, int nd, const M2LTil
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 far field (eps >= 1e-6): the same translations on v_mfma_f32_16x16x4f32
+// with complex-float tables.  Inputs are rounded to float as they load and
+// results return to the FP64 expansion arrays.  Operand layout as in the FP64
+// instruction; the result layout differs: element i of lane l is
+// D[4 (l/16) + i][l%16].
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const cd *bs, bool bvalid,
+                                          int nin, int lane, cf *a, cf *b)
+{
+    int bk = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < TB_U; ++u) {
+        int kbu = kb + u;
+        bool ok = kbu < kb1;
+        int kbc = ok ? kbu : kb1 - 1;
+        int k = kbc * 4 + bk;
+        a[u] = Arow[kbc * 64 + lane];
+        cd v = bs[min(k, nin - 1)];
+        b[u] = (ok && bvalid && k < nin) ? cf{(float)v.x, (float)v.y} : cf{0.f, 0.f};
+    }
+}
+
+__device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, f4 &yr, f4 &yi)
+{
+#pragma unroll
+    for (int u = 0; u < TB_U; ++u) {
+        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].x, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].y, yi, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[u].y, b[u].y, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, b[u].x, yi, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, const cd *bptr, int nin,
+                                              int lane, f4 &yr, f4 &yi)
+{
+    if (kb0 >= kb1) return;
+    const cd *bs = bptr ? bptr : reinterpret_cast<const cd *>(Arow);
+    bool bvalid = bptr != nullptr;
+    cf a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
+    tb_load32(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
+    for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
+        tb_load32(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_mfma32(a0, b0, yr, yi);
+        tb_load32(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        if (kb + TB_U < kb1) tb_mfma32(a1, b1, yr, yi);
+    }
+}
+
+__global__ void __launch_bounds__(64) k_m2l_mfma32(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
+                                                   const cd *mp, cd *vy)
+{
+    int c = xcd_contiguous(blockIdx.x, gridDim.x);
+    M2LTile t = tiles[c / nrmax];
+    int rb = c % nrmax;
+    int l = t.lo / 40;
+    int P = g.Plev[l], n = 2 * P + 1;
+    int NK = (n + 3) / 4, NR = (n + 15) / 16;
+    if (rb >= NR) return;
+    int lane = threadIdx.x;
+    int bk = lane >> 4, bc = lane & 15;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
+    f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    trans_block32(g.m2l_mf32 + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
+    if (!valid) return;
+    cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
+    for (int i = 0; i < 4; ++i) {
+        int row = rb * 16 + 4 * bk + i;
+        if (row < n) o[row] = mk((double)yr[i], (double)yi[i]);
+    }
+}
+
 // k-block range of part h of NK split in KS near-equal parts
 __device__ __forceinline__ void ksplit(int NK, int KS, int h, int *kb0, int *kb1)
 {
@@ -462,6 +539,54 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int
 #pragma unroll 4
     for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs];
     loc[base] = acc + tb_sum(part, L2L_KS, r, c);
+}
+
+// FP32 variant of k_l2l_mfma (FP32 far field): same work split; the partial
+// blocks are stored in double in the FP32 result layout.
+__device__ __forceinline__ cd tb_sum32(const double (*part)[64][9], int nw, int r, int c)
+{
+    int ln = (r >> 2) * 16 + c, i = r & 3;
+    cd y = mk(0.0, 0.0);
+    for (int w = 0; w < nw; ++w) y = y + mk(part[w][ln][i], part[w][ln][4 + i]);
+    return y;
+}
+
+__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, int L, const TTile *tiles,
+                                                            const cd *vy, cd *loc)
+{
+    __shared__ double part[L2L_KS][64][9];
+    TTile t = tiles[blockIdx.x];
+    int rb = blockIdx.y;
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int nc = 2 * g.Plev[L] + 1, np = 2 * g.Plev[L - 1] + 1;
+    int NKp = (np + 3) / 4;
+    int bc = lane & 15;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    int d = col % nd;
+    const cd *bptr = valid ? loc + g.l2l_poff[t.start + col / nd] * nd + (long long)d * np : nullptr;
+    f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    int kb0, kb1;
+    ksplit(NKp, L2L_KS, w, &kb0, &kb1);
+    trans_block32(g.l2l_mf32 + g.l2l_mf_off[(L - 1) * 4 + t.q] + (long long)rb * NKp * 64, kb0, kb1, bptr,
+                  np, lane, yr, yi);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { part[w][lane][i] = (double)yr[i]; part[w][lane][4 + i] = (double)yi[i]; }
+    __syncthreads();
+    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    int row = rb * 16 + r;
+    if (c >= t.ncol || row >= nc) return;
+    int oc = t.col0 + c;
+    int pos = t.start + oc / nd;
+    long long dr = (long long)(oc % nd) * nc + row;
+    long long base = g.l2l_coff[pos] * nd + dr;
+    const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
+    int nv = g.l2l_nv[pos];
+    long long vs = (long long)nc * nd;
+    cd acc = loc[base];
+#pragma unroll 4
+    for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs];
+    loc[base] = acc + tb_sum32(part, L2L_KS, r, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1322,7 +1447,8 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
                            const int *clist, const cd *vy, cd *loc, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
-    k_l2l_mfma<<<dim3(ntiles, nrb), 64 * L2L_KS, 0, s>>>(g, nd, L, tiles, clist, vy, loc);
+    if (g.far32) k_l2l_mfma32<<<dim3(ntiles, nrb), 64 * L2L_KS, 0, s>>>(g, nd, L, tiles, vy, loc);
+    else k_l2l_mfma<<<dim3(ntiles, nrb), 64 * L2L_KS, 0, s>>>(g, nd, L, tiles, clist, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1334,7 +1460,8 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
     int nrmax = (2 * Pmax + 1 + 15) / 16;
     long long nblk = (long long)ntiles * nrmax;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    k_m2l_mfma<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+    if (g.far32) k_m2l_mfma32<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+    else k_m2l_mfma<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

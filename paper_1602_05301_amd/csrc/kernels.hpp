@@ -50,6 +50,10 @@ struct DevGeom {
     // M2L as batched GEMM: per (level, offset) matrices in MFMA tile order,
     // V-list positions grouped by (level, offset), per-position output offsets.
     const cd *m2l_mf;                          // tiled scaled M2L matrices
+    // FP32 far field (eps >= 1e-6): M2L and L2L tables in complex float, same
+    // tile order and offsets as the FP64 ones; null when off
+    int far32;
+    const cf *m2l_mf32, *l2l_mf32;
     const long long *m2l_mf_off;               // [level*40+o]
     const int *vpair_sorted;                   // V-list positions sorted by (level, offset)
     const long long *vy_off;                   // per V-list position: output row offset

@@ -492,7 +492,8 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
     if (!(eps >= 1e-15 && eps <= 1e-2)) return {QBX_E_INVAL, "eps must lie in [1e-15, 1e-2]"};
     if (opt.p < 0 || opt.p > kMaxP) return {QBX_E_INVAL, "p must lie in 0..40"};
     if (opt.leaf_max < 1) return {QBX_E_INVAL, "leaf_max must be >= 1"};
-    if (opt.far_fp32 != 0) return {QBX_E_UNSUPPORTED, "far_fp32 is not available in this build"};
+    if (opt.far_fp32 != 0 && opt.far_fp32 != 1) return {QBX_E_INVAL, "far_fp32 must be 0 or 1"};
+    if (opt.far_fp32 && eps < 1e-6) return {QBX_E_INVAL, "far_fp32 needs eps >= 1e-6"};
     if (!(opt.eps_assoc >= 0 && opt.eps_assoc < 1)) return {QBX_E_INVAL, "eps_assoc must lie in [0, 1)"};
     if (opt.p_add < -1 || opt.p_add > 200) return {QBX_E_INVAL, "p_add must be -1 or in 0..200"};
     if (opt.w_direct < -1) return {QBX_E_INVAL, "w_direct must be -1, 0 or a positive source count"};

@@ -118,11 +118,13 @@ def _check(status):
         raise QbxError(status, lib().qbx_last_error().decode())
 
 
-def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05, w_direct=-1) -> Options:
+def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05, w_direct=-1,
+            far_fp32=False) -> Options:
     o = Options()
     lib().qbx_options_default(ctypes.byref(o))
     o.p, o.p_add, o.leaf_max, o.direct, o.eps_assoc = int(p), int(p_add), int(leaf_max), int(bool(direct)), float(eps_assoc)
     o.w_direct = int(w_direct)
+    o.far_fp32 = int(bool(far_fp32))
     return o
 
 

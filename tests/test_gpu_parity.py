@@ -233,3 +233,17 @@ def test_graph_replay_matches_eager(ctx):
             torch.cuda.synchronize()
             assert np.array_equal(u.cpu().numpy(), ref), (nd, rep)
     geo.graph(False)
+
+
+@pytest.mark.parametrize("n_panels,omega,eps,p", [(256, 50.0, 1e-6, 9), (128, 80.0, 1e-5, 8),
+                                                  (512, 30.0, 1e-6, 9)])
+def test_fp32_far_field_matches_direct_oracle(ctx, n_panels, omega, eps, p):
+    """FP32 M2L/L2L (eps >= 1e-6) still agrees with direct QBX to eps."""
+    wl = inputs.fmm_star(n_panels=n_panels, omega=omega, eps=eps, p=p)
+    g = wl.geom
+    _, u = _eval(ctx, g, omega, eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                 p=p, far_fp32=True)
+    ref = oracle.direct_qbx(omega, p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d, tgt_ctr=wl.tgt_ctr)
+    err = _rel(u, ref)
+    print(f"fp32 far field n={g.n} omega={omega} eps={eps}: rel_l2={err:.3e}", flush=True)
+    assert err < eps

@@ -122,7 +122,7 @@ def test_orders_follow_the_criterion(omega, eps):
             assert _criterion(omega, R, np.array([pf]))[0] > eps, lev
 
 
-@pytest.mark.parametrize("bad", ["omega", "eps", "p", "normal", "radius", "nan", "tgt_ctr"])
+@pytest.mark.parametrize("bad", ["omega", "eps", "p", "normal", "radius", "nan", "tgt_ctr", "fp32_eps"])
 def test_invalid_arguments_are_rejected(bad):
     g = inputs.star(8, 8, lobes=3)
     omega, eps, opts, tc = 10.0, 1e-8, qbx.options(p=8), np.arange(g.n)
@@ -140,9 +140,17 @@ def test_invalid_arguments_are_rejected(bad):
         g.sx[5] = np.nan
     elif bad == "tgt_ctr":
         tc = tc.copy(); tc[0] = g.n + 5
+    elif bad == "fp32_eps":
+        eps, opts = 1e-8, qbx.options(p=8, far_fp32=True)   # FP32 far field needs eps >= 1e-6
     with pytest.raises(qbx.QbxError) as ei:
         qbx.Plan(g, omega, eps, g.sx, g.sy, tc, opts)
     assert ei.value.status == qbx.QBX_E_INVAL
+
+
+def test_fp32_far_field_accepted_at_loose_tolerance():
+    g = inputs.star(8, 8, lobes=3)
+    pl = qbx.Plan(g, 10.0, 1e-6, g.sx, g.sy, np.arange(g.n), qbx.options(p=8, far_fp32=True))
+    assert pl.stats()["n_levels"] >= 1
 
 
 def test_context_without_gpu_reports_device_error():
