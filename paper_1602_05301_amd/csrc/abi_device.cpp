@@ -89,6 +89,7 @@ struct qbx_geom_s {
     };
     std::vector<Group> m2l_groups;
     int m2l_Pmax = 0;
+    int m2l_nw = 1;                                // waves per M2L tile
     long long total_vy = 0;       // sum over V-list positions of (2 P_l + 1)
     std::vector<int32_t> near_start, near_idx, wf_start, wf_idx;   // host copies
     // M2QBXL work: (leaf, far W) pairs, their output rows and per-leaf ranges
@@ -267,12 +268,24 @@ qbx_status upload(qbx_geom_s *G)
     std::stable_sort(vpos.begin(), vpos.end(), [&](int a, int b) { return vkey(a) < vkey(b); });
     G->m2l_groups.clear();
     G->m2l_Pmax = 0;
+    G->m2l_nw = 1;
     for (int i = 0; i < nv;) {
         int j = i;
         while (j < nv && vkey(vpos[j]) == vkey(vpos[i])) ++j;
         G->m2l_groups.push_back({vkey(vpos[i]), i, j - i});
         G->m2l_Pmax = std::max(G->m2l_Pmax, pl.P[vkey(vpos[i]) / 40]);
         i = j;
+    }
+    {
+        // waves per M2L tile: the row-block count of most V pairs, so that
+        // those tiles have one row block per wave
+        std::vector<long long> cnt(64, 0);
+        for (const auto &grp : G->m2l_groups) {
+            int nr = (2 * pl.P[grp.key / 40] + 1 + 15) / 16;
+            cnt[std::min(nr, 63)] += grp.count;
+        }
+        G->m2l_nw = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
+        G->m2l_nw = std::max(1, std::min(G->m2l_nw, 16));
     }
     g.vpair_sorted = ar.upload(vpos);
     g.vy_off = ar.upload(vy_off);
@@ -669,7 +682,8 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         {
             STAGE(QBX_STAGE_M2L);
             LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
-                   launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->mp, G->vy, st));
+                   launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->m2l_nw,
+                                   G->mp, G->vy, st));
         }
         if (conc) {
             CHK(hipStreamWaitEvent(st, C->ev_x, 0));

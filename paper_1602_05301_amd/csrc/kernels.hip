@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd
 // (rb * NK + kb) * 64.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int TB_U = 4;      // k-blocks whose table operands are loaded ahead
+constexpr int TB_U = 2;      // k-blocks whose table operands are loaded ahead
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8).
 // Map them so that XCD x works through its own contiguous range of tiles:
@@ -324,33 +324,81 @@ __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, co
     }
 }
 
-// One wave per (tile, row block), operands straight from memory with the
-// loads of the next TB_U k-blocks in flight (trans_block).  1-D grid of
-// ntiles * nrmax waves in XCD-contiguous order, the row blocks of a tile
-// consecutive, so that a tile's columns and a group's matrix are fetched
-// into one XCD's L2; waves past the tile's row count exit at once.
-__global__ void __launch_bounds__(64) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
-                                                 const cd *mp, cd *vy)
+// M2L: one workgroup per 16-column tile, nw waves over its row blocks
+// (rb = wave, wave + nw, ...).  The tile's columns (the source boxes'
+// multipoles) are staged once in LDS through host-precomputed offsets and
+// serve every row block; table fragments stream from memory with the next
+// TB_U k-blocks in flight.  Workgroups run in XCD-contiguous order so that the
+// tiles of one (level, offset) group share an XCD's L2 copy of its matrix.
+constexpr int M2L_XS = 17;    // LDS row stride of the staged columns (padded)
+
+__global__ void __launch_bounds__(1024) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles,
+                                                   const cd *mp, cd *vy)
 {
-    int c = xcd_contiguous(blockIdx.x, gridDim.x);
-    M2LTile t = tiles[c / nrmax];
-    int rb = c % nrmax;
+    extern __shared__ double lds_raw[];
+    cd *X = reinterpret_cast<cd *>(lds_raw);    // [4 NK][M2L_XS]
+    M2LTile t = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
     int l = t.lo / 40;
     int P = g.Plev[l], n = 2 * P + 1;
     int NK = (n + 3) / 4, NR = (n + 15) / 16;
-    if (rb >= NR) return;
-    int lane = threadIdx.x;
+    int nw = blockDim.x >> 6;
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int bk = lane >> 4, bc = lane & 15;
-    int col = t.col0 + bc;
-    bool valid = bc < t.ncol;
-    const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
-    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
-    trans_block(g.m2l_mf + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
-    if (!valid) return;
-    cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
-    for (int i = 0; i < 4; ++i) {
-        int row = rb * 16 + 4 * i + bk;
-        if (row < n) o[row] = mk(yr[i], yi[i]);
+    {
+        // blockDim/16 threads per column, consecutive k per column
+        int tpc = blockDim.x >> 4;
+        int sc = threadIdx.x / tpc, sr = threadIdx.x - sc * tpc;
+        const cd *col = nullptr;
+        if (sc < t.ncol) {
+            int cc = t.col0 + sc;
+            col = mp + g.m2l_src[t.pair_start + cc / nd] * nd + (long long)(cc % nd) * n;
+        }
+        for (int k = sr; k < 4 * NK; k += tpc) X[k * M2L_XS + sc] = (col && k < n) ? col[k] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    const cd *A = g.m2l_mf + g.m2l_mf_off[t.lo];
+    for (int rb = wave; rb < NR; rb += nw) {
+        const cd *Ab = A + (long long)rb * NK * 64 + lane;
+        d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+        cd a0[TB_U], a1[TB_U];
+#pragma unroll
+        for (int u = 0; u < TB_U; ++u) a0[u] = Ab[min(u, NK - 1) * 64];
+        for (int kb = 0; kb < NK; kb += 2 * TB_U) {
+#pragma unroll
+            for (int u = 0; u < TB_U; ++u) a1[u] = Ab[min(kb + TB_U + u, NK - 1) * 64];
+#pragma unroll
+            for (int u = 0; u < TB_U; ++u) {
+                int kk = kb + u;
+                cd bv = X[(min(kk, NK - 1) * 4 + bk) * M2L_XS + bc];
+                if (kk >= NK) bv = mk(0.0, 0.0);
+                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, bv.x, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, bv.y, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0[u].y, bv.y, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].y, bv.x, yi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < TB_U; ++u) a0[u] = Ab[min(kb + 2 * TB_U + u, NK - 1) * 64];
+            if (kb + TB_U < NK) {
+#pragma unroll
+                for (int u = 0; u < TB_U; ++u) {
+                    int kk = kb + TB_U + u;
+                    cd bv = X[(min(kk, NK - 1) * 4 + bk) * M2L_XS + bc];
+                    if (kk >= NK) bv = mk(0.0, 0.0);
+                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, bv.x, yr, 0, 0, 0);
+                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, bv.y, yi, 0, 0, 0);
+                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1[u].y, bv.y, yr, 0, 0, 0);
+                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].y, bv.x, yi, 0, 0, 0);
+                }
+            }
+        }
+        if (bc < t.ncol) {
+            int col = t.col0 + bc;
+            cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
+            for (int i = 0; i < 4; ++i) {
+                int row = rb * 16 + 4 * i + bk;
+                if (row < n) o[row] = mk(yr[i], yi[i]);
+            }
+        }
     }
 }
 
@@ -1454,14 +1502,20 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
 }
 
 hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
-                           const cd *mp, cd *vy, hipStream_t s)
+                           int nw, const cd *mp, cd *vy, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
     int nrmax = (2 * Pmax + 1 + 15) / 16;
-    long long nblk = (long long)ntiles * nrmax;
-    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (g.far32) k_m2l_mfma32<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
-    else k_m2l_mfma<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+    if (g.far32) {
+        long long nblk = (long long)ntiles * nrmax;
+        if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+        k_m2l_mfma32<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+    } else {
+        nw = std::max(1, std::min(nw, 16));
+        size_t lds = sizeof(cd) * 4 * ((2 * Pmax + 1 + 3) / 4) * M2L_XS;
+        if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+        k_m2l_mfma<<<ntiles, 64 * nw, lds, s>>>(g, nd, tiles, mp, vy);
+    }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
