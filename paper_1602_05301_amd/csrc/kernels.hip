@@ -832,15 +832,16 @@ __device__ void p2qbxl_finish(cd *acc, int G, int p, bool write, cd *dst, long l
     }
 }
 
-// One workgroup of 256 lanes per leaf: lane = (centre slot, part) with CG
-// centre slots (a power of two, at most 32) and 256 / CG parts.  The leaf's
+// One workgroup of P2Q_THREADS lanes per leaf: lane = (centre slot, part)
+// with CG centre slots (a power of two, at most 32) and P2Q_THREADS / CG parts.  The leaf's
 // near-list sources (flattened on the host, in list order) are staged in LDS
 // P2Q_SCH at a time and go round-robin to the parts.  Parts are summed by
 // shuffles inside a wave, then wave by wave in order through LDS.
 constexpr int P2Q_SCH = 256;
+constexpr int P2Q_THREADS = 128;   // lanes per leaf
 
 template <int PB>
-__global__ void __launch_bounds__(256) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
                                                  const cd *qd, cd *coef)
 {
     extern __shared__ double lds_raw[];
@@ -855,7 +856,7 @@ __global__ void __launch_bounds__(256) k_p2qbxl(DevGeom g, int nd, const int *li
     int nct = c1 - c0;
     int CG = 1;
     while (CG < nct && CG < 32) CG <<= 1;
-    int parts = 256 / CG;
+    int parts = P2Q_THREADS / CG;
     int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int gi = tid % CG, part = tid / CG;
     int p = g.p;
@@ -899,7 +900,7 @@ __global__ void __launch_bounds__(256) k_p2qbxl(DevGeom g, int nd, const int *li
                 acc[e] = mk(re, im);
             }
             // waves in order: wave w hands its sums to wave 0 through LDS
-            for (int w = 1; w < 4; ++w) {
+            for (int w = 1; w < P2Q_THREADS / 64; ++w) {
                 __syncthreads();
                 if (wave == w && lane < CG) {
 #pragma unroll
@@ -1552,7 +1553,7 @@ static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *list, int
                                   const cd *qd, cd *coef, hipStream_t s)
 {
     size_t lds = sizeof(cd) * (32 * (2 * PB + 1) + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
-    k_p2qbxl<PB><<<n, 256, lds, s>>>(g, nd, list, qs, qd, coef);
+    k_p2qbxl<PB><<<n, P2Q_THREADS, lds, s>>>(g, nd, list, qs, qd, coef);
     return hipGetLastError();
 }
 
