@@ -194,6 +194,21 @@ enum {
  * on, every stage runs in order on the context's stream (no second stream,
  * no graph), so each stage's time is its own. */
 qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
+/* qbx_eval_batch: evaluate several resident geometries at once (one matvec
+ * each), as a serving loop or a multi-geometry solve does.  Geometry i takes
+ * n_dens[i] densities sigma_s[i] / sigma_d[i] (arrays of device pointers;
+ * either array, or an entry of it, may be NULL as in qbx_eval) and writes
+ * u[i]; no coefficient export.  The geometries are spread over four stream
+ * slots of the context (each with its own side stream), which start after
+ * the context's stream and which the context's stream waits for, so their
+ * work overlaps on the device.  A geometry listed twice runs twice, in list
+ * order, on one slot.  Each result is bitwise the same as from qbx_eval alone.
+ * If stage profiling or graph replay is on for any of them, the evaluations
+ * run one after another through qbx_eval.  Errors: QBX_E_INVAL (null or
+ * foreign geometry, n_dens outside 1..64, missing u or densities),
+ * QBX_E_DEVICE, QBX_E_NOMEM. */
+qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
+                          const void *const *sigma_s, const void *const *sigma_d, void *const *u);
 /* qbx_geom_graph: enable (1) or disable (0) graph replay of later qbx_eval
  * calls on this geometry (the "execution modes" of a served matvec loop,
  * where the same evaluation repeats with new density values in the same

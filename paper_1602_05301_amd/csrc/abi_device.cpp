@@ -13,14 +13,29 @@
 
 using namespace qbx;
 
+// A side stream and the events that fork it from, and join it back to, the
+// stream an evaluation is enqueued on.
+struct QbxLane {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr, ev_m = nullptr;
+};
+
+// one batch slot: its own main stream plus a lane
+struct QbxSlot {
+    hipStream_t main = nullptr;
+    hipEvent_t ev_done = nullptr;
+    QbxLane lane;
+};
+
 struct qbx_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    // a second stream for the near field and the X-list P2L, which depend on
-    // the charges only and overlap the latency-bound upward/downward passes;
-    // events fork it from and join it back to the caller's stream
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr, ev_m = nullptr;
+    std::vector<QbxSlot> slots;   // created on the first qbx_eval_batch
+    // the side stream of plain evaluations: the near field and the X-list
+    // P2L depend on the charges only and overlap the latency-bound
+    // upward/downward passes; events fork it from and join it back to the
+    // caller's stream
+    QbxLane lane;
     // captured evaluations run on a stream of the library's own (the caller's
     // may be the null stream, which cannot be captured), joined to the
     // caller's stream by events
@@ -29,6 +44,23 @@ struct qbx_ctx_s {
 };
 
 namespace {
+
+bool lane_create(QbxLane &L)
+{
+    if (hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking) != hipSuccess) { L.side = nullptr; return false; }
+    for (hipEvent_t *e : {&L.ev_fork, &L.ev_x, &L.ev_q, &L.ev_m})
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { *e = nullptr; return false; }
+    return true;
+}
+
+void lane_destroy(QbxLane &L)
+{
+    if (L.side) (void)hipStreamSynchronize(L.side);
+    for (hipEvent_t e : {L.ev_fork, L.ev_x, L.ev_q, L.ev_m})
+        if (e) (void)hipEventDestroy(e);
+    if (L.side) (void)hipStreamDestroy(L.side);
+    L = QbxLane{};
+}
 
 constexpr int kDensChunk = 4;   // densities per pass through the pipeline
 constexpr int kM2LTileCols = 16; // columns per M2L tile (one MFMA column block)
@@ -629,7 +661,7 @@ qbx_status harvest(qbx_geom_s *G)
     } while (0)
 
 qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out,
-                        hipStream_t st)
+                        hipStream_t st, const QbxLane &lane)
 {
     const Plan &pl = G->pl;
     const DevGeom &g = G->g;
@@ -647,7 +679,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         // the near field and (once M2M is done) M2QBXL while this stream runs
         // P2M, M2M, M2L and L2L.  With stage profiling on everything stays on
         // one stream, in order.
-        const qbx_ctx_s *C = G->ctx;
+        const QbxLane *C = &lane;
         bool conc = !G->profile && C->side;
         hipStream_t s1 = conc ? C->side : st;
         if (conc) {
@@ -798,26 +830,18 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     if (!c) return fail(QBX_E_NOMEM, "host allocation failed");
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
-    // default priority on purpose; without the stream the pipeline runs in order
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_x, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_q, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_m, hipEventDisableTiming) != hipSuccess ||
+    // default priority on purpose; without the streams the pipeline runs in order
+    if (!lane_create(c->lane) ||
         hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        if (c->ev_x) (void)hipEventDestroy(c->ev_x);
-        if (c->ev_q) (void)hipEventDestroy(c->ev_q);
-        if (c->ev_m) (void)hipEventDestroy(c->ev_m);
+        lane_destroy(c->lane);
         if (c->ev_in) (void)hipEventDestroy(c->ev_in);
         if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-        if (c->side) (void)hipStreamDestroy(c->side);
         if (c->gstream) (void)hipStreamDestroy(c->gstream);
-        c->side = c->gstream = nullptr;
-        c->ev_fork = c->ev_x = c->ev_q = c->ev_m = c->ev_in = c->ev_out = nullptr;
+        c->gstream = nullptr;
+        c->ev_in = c->ev_out = nullptr;
     }
     *out = c;
     return QBX_OK;
@@ -833,19 +857,20 @@ qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream)
 qbx_status qbx_ctx_destroy(qbx_ctx ctx)
 {
     if (!ctx) return QBX_OK;
-    if (ctx->side) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipStreamSynchronize(ctx->side);
+    (void)hipSetDevice(ctx->device);
+    lane_destroy(ctx->lane);
+    for (auto &sl : ctx->slots) {
+        if (sl.main) (void)hipStreamSynchronize(sl.main);
+        lane_destroy(sl.lane);
+        if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
+        if (sl.main) (void)hipStreamDestroy(sl.main);
+    }
+    if (ctx->gstream) {
         (void)hipStreamSynchronize(ctx->gstream);
-        (void)hipEventDestroy(ctx->ev_fork);
-        (void)hipEventDestroy(ctx->ev_x);
-        (void)hipEventDestroy(ctx->ev_q);
-        (void)hipEventDestroy(ctx->ev_m);
-        (void)hipEventDestroy(ctx->ev_in);
-        (void)hipEventDestroy(ctx->ev_out);
-        (void)hipStreamDestroy(ctx->side);
         (void)hipStreamDestroy(ctx->gstream);
     }
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     delete ctx;
     return QBX_OK;
 }
@@ -901,7 +926,8 @@ qbx_status qbx_geom_destroy(qbx_geom G)
     if (G->ctx->stream) (void)hipStreamSynchronize(G->ctx->stream);
     else (void)hipDeviceSynchronize();
     if (G->ctx->gstream) (void)hipStreamSynchronize(G->ctx->gstream);
-    if (G->ctx->side) (void)hipStreamSynchronize(G->ctx->side);
+    if (G->ctx->lane.side) (void)hipStreamSynchronize(G->ctx->lane.side);
+    for (auto &sl : G->ctx->slots) (void)hipStreamSynchronize(sl.main), (void)hipStreamSynchronize(sl.lane.side);
     G->scratch.release();
     G->arena.release();
     delete G;
@@ -952,7 +978,7 @@ qbx_status qbx_geom_work(qbx_geom G, int32_t n_dens, double *flops)
 
 // All chunks of one evaluation, enqueued on stream st.
 qbx_status eval_chunks(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
-                       void *coef, hipStream_t st)
+                       void *coef, hipStream_t st, const QbxLane &lane)
 {
     const Plan &pl = G->pl;
     long long nq = 2 * pl.p + 1;
@@ -962,7 +988,7 @@ qbx_status eval_chunks(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const
         const cd *sd = sigma_d ? static_cast<const cd *>(sigma_d) + (long long)d0 * pl.ns : nullptr;
         cd *uu = static_cast<cd *>(u) + (long long)d0 * pl.nt;
         cd *co = coef ? static_cast<cd *>(coef) + (long long)d0 * nq * pl.nc : nullptr;
-        qbx_status q = run_pipeline(G, nd, ss, sd, uu, co, st);
+        qbx_status q = run_pipeline(G, nd, ss, sd, uu, co, st, lane);
         if (q != QBX_OK) return q;
     }
     return QBX_OK;
@@ -988,7 +1014,7 @@ qbx_status graph_for(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const v
     hipStream_t gs = G->ctx->gstream;
     hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
-    qbx_status q = eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, gs);
+    qbx_status q = eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, gs, G->ctx->lane);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(gs, &graph);
     if (q != QBX_OK) {
@@ -1037,7 +1063,71 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
         CHK(hipStreamWaitEvent(C->stream, C->ev_out, 0));
         return QBX_OK;
     }
-    return eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, C->stream);
+    return eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, C->stream, C->lane);
+}
+
+constexpr int kBatchSlots = 4;   // stream slots of qbx_eval_batch
+
+qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
+                          const void *const *sigma_s, const void *const *sigma_d, void *const *u)
+{
+    if (!ctx || n_geom < 0 || (n_geom && (!geoms || !n_dens || !u))) return fail(QBX_E_INVAL, "invalid argument");
+    if (n_geom == 0) return QBX_OK;
+    for (int i = 0; i < n_geom; ++i) {
+        qbx_geom G = geoms[i];
+        if (!G || G->ctx != ctx) return fail(QBX_E_INVAL, "geometry missing or from another context");
+        if (n_dens[i] < 1 || n_dens[i] > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
+        if (!u[i] && G->pl.nt) return fail(QBX_E_INVAL, "u is NULL");
+        if ((!sigma_s || !sigma_s[i]) && (!sigma_d || !sigma_d[i])) return fail(QBX_E_INVAL, "both densities are NULL");
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    bool serial = !ctx->lane.side;
+    for (int i = 0; i < n_geom; ++i) serial = serial || geoms[i]->profile || geoms[i]->graph_on;
+    if (!serial && ctx->slots.empty()) {
+        ctx->slots.resize(kBatchSlots);
+        for (auto &sl : ctx->slots)
+            if (hipStreamCreateWithFlags(&sl.main, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming) != hipSuccess || !lane_create(sl.lane)) {
+                (void)hipGetLastError();
+                serial = true;
+                break;
+            }
+    }
+    for (int i = 0; i < n_geom; ++i) {
+        qbx_status q = ensure_scratch(geoms[i]);
+        if (q != QBX_OK) return q;
+    }
+    auto dens = [&](const void *const *a, int i) { return a ? a[i] : nullptr; };
+    if (serial) {
+        // profiling or graph replay on some geometry: one after another
+        for (int i = 0; i < n_geom; ++i) {
+            qbx_status q = qbx_eval(geoms[i], n_dens[i], dens(sigma_s, i), dens(sigma_d, i), u[i], nullptr);
+            if (q != QBX_OK) return q;
+        }
+        return QBX_OK;
+    }
+    // slots start after the caller's stream; a geometry listed twice stays
+    // on the slot of its first occurrence, since its scratch is shared
+    CHK(hipEventRecord(ctx->ev_in, ctx->stream));
+    for (auto &sl : ctx->slots) CHK(hipStreamWaitEvent(sl.main, ctx->ev_in, 0));
+    std::vector<int> slot_of(n_geom);
+    int next = 0;
+    for (int i = 0; i < n_geom; ++i) {
+        slot_of[i] = -1;
+        for (int j = 0; j < i; ++j)
+            if (geoms[j] == geoms[i]) { slot_of[i] = slot_of[j]; break; }
+        if (slot_of[i] < 0) slot_of[i] = next++ % kBatchSlots;
+        QbxSlot &sl = ctx->slots[slot_of[i]];
+        qbx_status q = eval_chunks(geoms[i], n_dens[i], dens(sigma_s, i), dens(sigma_d, i), u[i], nullptr,
+                                   sl.main, sl.lane);
+        if (q != QBX_OK) return q;
+    }
+    for (auto &sl : ctx->slots) {
+        CHK(hipEventRecord(sl.ev_done, sl.main));
+        CHK(hipStreamWaitEvent(ctx->stream, sl.ev_done, 0));
+    }
+    return QBX_OK;
 }
 
 qbx_status qbx_geom_graph(qbx_geom G, int32_t enable)

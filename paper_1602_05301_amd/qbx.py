@@ -27,6 +27,7 @@ EXPORTS = [
     "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
     "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
     "qbx_geom_association", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times", "qbx_geom_work",
+    "qbx_eval_batch",
     "qbx_eval",
 ]
 
@@ -102,6 +103,8 @@ def lib():
     L.qbx_geom_association.argtypes = [_vp, _ip]
     L.qbx_geom_profile.argtypes = [_vp, i32]
     L.qbx_geom_graph.argtypes = [_vp, i32]
+    L.qbx_eval_batch.argtypes = [_vp, i32, ctypes.POINTER(_vp), ctypes.POINTER(i32),
+                                 ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
     L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
     L.qbx_geom_work.argtypes = [_vp, i32, _dp]
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
@@ -206,6 +209,20 @@ class Context:
         if getattr(self, "_h", None):
             lib().qbx_ctx_destroy(self._h)
             self._h = None
+
+    def eval_batch(self, geoms, sigmas_s, sigmas_d, us):
+        """One evaluation per geometry, overlapped on the device (qbx_eval_batch).
+        sigmas_s[i] / sigmas_d[i]: [n_dens_i, n_src_i] complex128 CUDA tensors or
+        None; us[i]: [n_dens_i, n_tgt_i] outputs."""
+        n = len(geoms)
+        ptr = lambda t: None if t is None else t.data_ptr()
+        G = (_vp * n)(*[g._h for g in geoms])
+        ND = (ctypes.c_int32 * n)(*[int((s if s is not None else d).shape[0]) for s, d in zip(sigmas_s, sigmas_d)])
+        S = (_vp * n)(*[ptr(s) for s in sigmas_s])
+        D = (_vp * n)(*[ptr(d) for d in sigmas_d])
+        U = (_vp * n)(*[u.data_ptr() for u in us])
+        _check(lib().qbx_eval_batch(self._h, n, G, ND, S, D, U))
+        return us
 
 
 class Geometry:
