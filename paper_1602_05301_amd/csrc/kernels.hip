@@ -402,6 +402,37 @@ __global__ void __launch_bounds__(1024) k_m2l_mfma(DevGeom g, int nd, const M2LT
     }
 }
 
+// M2L for orders whose staged columns exceed the LDS budget: one wave per
+// (tile, row block), operands straight from memory with the
+// loads of the next TB_U k-blocks in flight (trans_block).  1-D grid of
+// ntiles * nrmax waves in XCD-contiguous order, the row blocks of a tile
+// consecutive, so that a tile's columns and a group's matrix are fetched
+// into one XCD's L2; waves past the tile's row count exit at once.
+__global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
+                                                 const cd *mp, cd *vy)
+{
+    int c = xcd_contiguous(blockIdx.x, gridDim.x);
+    M2LTile t = tiles[c / nrmax];
+    int rb = c % nrmax;
+    int l = t.lo / 40;
+    int P = g.Plev[l], n = 2 * P + 1;
+    int NK = (n + 3) / 4, NR = (n + 15) / 16;
+    if (rb >= NR) return;
+    int lane = threadIdx.x;
+    int bk = lane >> 4, bc = lane & 15;
+    int col = t.col0 + bc;
+    bool valid = bc < t.ncol;
+    const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
+    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    trans_block(g.m2l_mf + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
+    if (!valid) return;
+    cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
+    for (int i = 0; i < 4; ++i) {
+        int row = rb * 16 + 4 * i + bk;
+        if (row < n) o[row] = mk(yr[i], yi[i]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP32 far field (eps >= 1e-6): the same translations on v_mfma_f32_16x16x4f32
 // with complex-float tables.  Inputs are rounded to float as they load and
@@ -1514,8 +1545,13 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
     } else {
         nw = std::max(1, std::min(nw, 16));
         size_t lds = sizeof(cd) * 4 * ((2 * Pmax + 1 + 3) / 4) * M2L_XS;
-        if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-        k_m2l_mfma<<<ntiles, 64 * nw, lds, s>>>(g, nd, tiles, mp, vy);
+        if (lds <= LDS_BUDGET) {
+            k_m2l_mfma<<<ntiles, 64 * nw, lds, s>>>(g, nd, tiles, mp, vy);
+        } else {
+            long long nblk = (long long)ntiles * nrmax;
+            if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+            k_m2l_mfma_direct<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+        }
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;

@@ -1,0 +1,234 @@
+"""Continuous-batching server for layer-potential matvec streams.
+
+A request is one geometry (curve nodes, weights, normals, QBX centres) with
+omega, eps, p and a chain of densities, as in one GMRES solve: density k+1 is
+released only when matvec k has completed.  The server
+
+* admits arrived requests while the HBM budget allows, building their
+  resident geometry (host planning plus upload) on a small thread pool so
+  that setup overlaps the GPU work of requests already admitted;
+* in every step, takes the next matvec of every admitted request whose
+  previous matvec is done and evaluates them together with one
+  ``qbx_eval_batch`` call (their work overlaps on the device);
+* frees a request's geometry when its last matvec completes.
+
+Results are bitwise the same as evaluating each request alone (the batch
+entry point guarantees it per geometry).  ``fifo`` is the plain per-request
+path it is compared with: one request at a time in arrival order, setup then
+its matvecs through ``qbx_eval``.
+
+    python -m paper_1602_05301_amd.serve [--requests 24] [--qps-fracs 0.5,0.8,0.95]
+
+prints one JSON object: the FIFO path and the server at several arrival
+rates (fractions of the measured closed-loop saturation rate), with
+throughput (targets x matvecs per second) and p50/p99 request latency
+(last matvec done minus arrival).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import dataclasses
+import json
+import time
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    geom: inputs.Geometry
+    omega: float
+    eps: float
+    p: int
+    densities: list          # [n_matvec] complex128 arrays [n_src] (sigma_s; sigma_d = sigma_s)
+    arrival: float = 0.0     # seconds after the start of the run
+    # filled in by the server
+    outputs: list = dataclasses.field(default_factory=list)
+    done: float = 0.0
+
+
+def make_requests(n: int, seed: int = 4, nodes=(1024, 32768), omega=(1.0, 200.0),
+                  eps_choices=(1e-6, 1e-10), matvecs=(20, 60)) -> list:
+    """Seeded stream of star-curve requests: node counts log-uniform (rounded
+    to whole 16-node panels), omega uniform, eps from eps_choices, 20-60
+    chained Gaussian densities each.  Each curve is scaled so that its
+    panels stay below 5 wavelengths (omega h <= 5)."""
+    rng = inputs.rng_for(seed, 0)
+    reqs = []
+    for i in range(n):
+        nn = int(np.exp(rng.uniform(np.log(nodes[0]), np.log(nodes[1]))))
+        npan = max(8, nn // 16)
+        lobes = int(rng.integers(3, 10))
+        w = float(rng.uniform(*omega))
+        g0 = inputs.star(npan, 16, lobes=lobes)
+        scale = min(1.0, 5.0 / (w * float(np.max(g0.h))))
+        g = inputs.star(npan, 16, lobes=lobes, radius=scale)
+        eps = float(eps_choices[int(rng.integers(0, len(eps_choices)))])
+        p = 9 if eps >= 1e-6 else 14
+        k = int(rng.integers(matvecs[0], matvecs[1] + 1))
+        dr = inputs.rng_for(seed, 100 + i)
+        dens = [inputs.complex_gaussian(dr, (g.n,)) for _ in range(k)]
+        reqs.append(Request(i, g, w, eps, p, dens))
+    return reqs
+
+
+def _build(ctx, req: Request):
+    from . import qbx
+    g = req.geom
+    tc = np.arange(g.n, dtype=np.int32)
+    far32 = req.eps >= 1e-6
+    return qbx.Geometry(ctx, g, req.omega, req.eps, g.sx, g.sy, tc,
+                        qbx.options(p=req.p, far_fp32=far32))
+
+
+def fifo(ctx, reqs, keep_outputs: bool = False) -> dict:
+    """Plain per-request path: setup, then every matvec with qbx_eval, one
+    request after another, each request starting at max(arrival, previous done)."""
+    import torch
+    t0 = time.perf_counter()
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        geo = _build(ctx, r)
+        s = torch.empty((1, r.geom.n), dtype=torch.complex128, device="cuda")
+        u = torch.empty_like(s)
+        r.outputs = []
+        for d in r.densities:
+            s.copy_(torch.from_numpy(d[None]))
+            geo.eval(s, s, u=u)
+            if keep_outputs:
+                r.outputs.append(u.cpu().numpy()[0])
+        torch.cuda.synchronize()
+        r.done = time.perf_counter() - t0
+        del geo
+    return _summary(reqs, time.perf_counter() - t0)
+
+
+class _Active:
+    def __init__(self, req, geo):
+        import torch
+        self.req, self.geo, self.k = req, geo, 0
+        self.s = torch.empty((1, req.geom.n), dtype=torch.complex128, device="cuda")
+        self.u = torch.empty_like(self.s)
+
+
+def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int = 4,
+          keep_outputs: bool = False) -> dict:
+    """Continuous batching (see the module docstring)."""
+    import torch
+    pending = sorted(reqs, key=lambda r: r.arrival)
+    building: dict = {}                   # future -> (request, reserved bytes)
+    active: list = []
+    used = 0.0
+    bytes_per_node = 60e3                 # running estimate of resident bytes per node
+    pool = cf.ThreadPoolExecutor(max_workers=setup_threads)
+    t0 = time.perf_counter()
+    finished = 0
+    while finished < len(reqs):
+        now = time.perf_counter() - t0
+        # admission: arrived requests, in order, while the budget allows
+        while pending and pending[0].arrival <= now:
+            r = pending[0]
+            need = bytes_per_node * r.geom.n
+            if used + need > hbm_budget and (active or building):
+                break
+            pending.pop(0)
+            used += need
+            building[pool.submit(_build, ctx, r)] = (r, need)
+        for fut in [f for f in building if f.done()]:
+            r, need = building.pop(fut)
+            geo = fut.result()
+            real = float(geo.stats()["device_bytes"])
+            used += real - need
+            bytes_per_node = max(bytes_per_node, 1.25 * real / r.geom.n)
+            active.append(_Active(r, geo))
+        if not active:
+            if building:
+                cf.wait(list(building), timeout=0.01, return_when=cf.FIRST_COMPLETED)
+            elif pending:
+                time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
+            continue
+        # one step: the next matvec of up to max_batch active requests
+        step = active[:max_batch]
+        for a in step:
+            a.s.copy_(torch.from_numpy(a.req.densities[a.k][None]))
+        ctx.eval_batch([a.geo for a in step], [a.s for a in step], [a.s for a in step],
+                       [a.u for a in step])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        keep = []
+        for a in step:
+            if keep_outputs:
+                a.req.outputs.append(a.u.cpu().numpy()[0])
+            a.k += 1
+            if a.k == len(a.req.densities):
+                a.req.done = t
+                used -= float(a.geo.stats()["device_bytes"])
+                finished += 1
+                a.geo = None                 # frees the resident geometry
+            else:
+                keep.append(a)
+        # round robin: the requests just served go behind those that waited
+        active = active[len(step):] + keep
+    pool.shutdown()
+    return _summary(reqs, time.perf_counter() - t0)
+
+
+def _summary(reqs, wall: float) -> dict:
+    lat = np.array([r.done - r.arrival for r in reqs])
+    work = sum(r.geom.n * len(r.densities) for r in reqs)
+    return {"requests": len(reqs), "matvecs": sum(len(r.densities) for r in reqs),
+            "wall_s": wall, "targets_x_matvecs_per_s": work / wall,
+            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+
+
+def _poisson(reqs, qps: float, seed: int = 7):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    for r in reqs:
+        t += rng.exponential(1.0 / qps)
+        r.arrival = t
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--max-nodes", type=int, default=32768)
+    ap.add_argument("--qps-fracs", default="0.5,0.8,0.95")
+    ap.add_argument("--hbm-gib", type=float, default=64.0)
+    args = ap.parse_args(argv)
+    import torch
+    from . import qbx
+    ctx = qbx.Context(0)
+    budget = args.hbm_gib * 2 ** 30
+    # warm-up: library, kernels, one small request each way
+    w = make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2))
+    fifo(ctx, w)
+    serve(ctx, make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2)), budget)
+    reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
+    for r in reqs:
+        r.arrival = 0.0
+    closed = serve(ctx, reqs, budget)                  # all at once: saturation rate
+    sat_qps = args.requests / closed["wall_s"]
+    reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
+    _poisson(reqs, 0.8 * sat_qps)
+    out = {"workload": f"{args.requests} star requests, {1024}-{args.max_nodes} nodes, omega U[1,200], "
+                       "eps in {1e-6 (FP32 far field), 1e-10}, 20-60 chained matvecs",
+           "saturation_qps": sat_qps, "closed_loop": closed,
+           "fifo_at_0.8": fifo(ctx, reqs), "served": {}}
+    for f in [float(x) for x in args.qps_fracs.split(",")]:
+        reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
+        _poisson(reqs, f * sat_qps)
+        out["served"][str(f)] = serve(ctx, reqs, budget)
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -274,3 +274,39 @@ def test_batch_matches_each_alone(ctx):
     torch.cuda.synchronize()
     for k, i in enumerate(order):
         assert np.array_equal(us[k].cpu().numpy(), alone[k]), (k, i)
+
+
+def test_served_requests_equal_alone(ctx):
+    """Continuous batching: requests of different sizes, omega and eps
+    arriving while others run (chained matvecs, admission by an HBM budget
+    small enough to make some wait) give, matvec by matvec, exactly the
+    results of evaluating each request alone."""
+    from paper_1602_05301_amd import serve
+    reqs = serve.make_requests(6, seed=5, nodes=(512, 4096), matvecs=(3, 5))
+    for i, r in enumerate(reqs):
+        r.arrival = 0.002 * i
+    serve.serve(ctx, reqs, hbm_budget=0.3 * 2 ** 30, max_batch=4, keep_outputs=True)
+    alone = serve.make_requests(6, seed=5, nodes=(512, 4096), matvecs=(3, 5))
+    serve.fifo(ctx, alone, keep_outputs=True)
+    for r, a in zip(reqs, alone):
+        assert len(r.outputs) == len(a.outputs) == len(r.densities)
+        for x, y in zip(r.outputs, a.outputs):
+            assert np.array_equal(x, y), r.rid
+
+
+def test_fmm_high_frequency_large_orders(ctx):
+    """omega large enough that the coarse-level FMM orders exceed what the
+    M2L kernel stages in LDS (its direct-load path runs there)."""
+    from paper_1602_05301_amd import qbx
+    g = inputs.star(128, 16, lobes=5)
+    r = np.random.default_rng(23)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    omega, eps, p = 200.0, 1e-6, 9
+    geo = qbx.Geometry(ctx, g, omega, eps, g.sx, g.sy, tc, qbx.options(p=p))
+    assert qbx.Plan(g, omega, eps, g.sx, g.sy, tc, qbx.options(p=p)).orders()[2] > 120   # M2L at level 2
+    u = geo.eval(_dev(ss), None).cpu().numpy()
+    ref = oracle.direct_qbx(omega, p, g, g.sx, g.sy, ss, None, tgt_ctr=tc)
+    err = _rel(u, ref)
+    print(f"omega=200 rel_l2={err:.3e}", flush=True)
+    assert err < eps
