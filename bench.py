@@ -149,6 +149,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
     geo.graph(args.graph)
+    m2l_choice = geo.autotune(wl.n_dens)      # M2L configuration timed on this geometry
     for _ in range(args.warmup):
         geo.eval(ss, sd, u=u)
     torch.cuda.synchronize()
@@ -228,6 +229,7 @@ def main(argv=None):
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
         "ms_per_step_stages_in_order": serial_ms,
         "graph_replay": args.graph,
+        "m2l_waves_per_tile": m2l_choice,
         "stages_tflops": {k: work[k] / (v[0] / args.steps * 1e-3) / 1e12
                           for k, v in stages.items() if v[1] and v[0] > 0 and work.get(k)},
         "setup_s": setup_s,

@@ -121,7 +121,8 @@ struct qbx_geom_s {
     };
     std::vector<Group> m2l_groups;
     int m2l_Pmax = 0;
-    int m2l_nw = 1;                                // waves per M2L tile
+    int m2l_nw = 1;                                // waves per M2L tile (0 = direct kernel)
+    int m2l_nw_default = 1;                        // the common row-block count
     long long total_vy = 0;       // sum over V-list positions of (2 P_l + 1)
     std::vector<int32_t> near_start, near_idx, wf_start, wf_idx;   // host copies
     // M2QBXL work: (leaf, far W) pairs, their output rows and per-leaf ranges
@@ -318,6 +319,7 @@ qbx_status upload(qbx_geom_s *G)
         }
         G->m2l_nw = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
         G->m2l_nw = std::max(1, std::min(G->m2l_nw, 16));
+        G->m2l_nw_default = G->m2l_nw;
     }
     g.vpair_sorted = ar.upload(vpos);
     g.vy_off = ar.upload(vy_off);
@@ -1127,6 +1129,71 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
         CHK(hipEventRecord(sl.ev_done, sl.main));
         CHK(hipStreamWaitEvent(ctx->stream, sl.ev_done, 0));
     }
+    return QBX_OK;
+}
+
+qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
+    hipError_t e = hipSetDevice(G->ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    if (G->pl.opt.direct || G->g.far32 || G->m2l_groups.empty()) {
+        if (choice_out) *choice_out = G->m2l_nw;
+        return QBX_OK;
+    }
+    qbx_status st = ensure_scratch(G);
+    if (st != QBX_OK) return st;
+    // Whole evaluations with zero densities, timed with HIP events on the
+    // context's stream: the M2L configuration that makes the evaluation
+    // fastest in context (caches and the overlapped side stream included).
+    // Candidates: the common row-block count, about half of it, and the
+    // direct-load kernel (0).  They compute the same sums in the same order.
+    const Plan &pl = G->pl;
+    size_t ns = sizeof(cd) * (size_t)n_dens * std::max<int64_t>(pl.ns, 1);
+    size_t nu = sizeof(cd) * (size_t)n_dens * std::max<int64_t>(pl.nt, 1);
+    void *dsig = nullptr, *du = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s = G->ctx->stream;
+    auto cleanup = [&]() {
+        if (dsig) (void)hipFree(dsig);
+        if (du) (void)hipFree(du);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    };
+    if (hipMalloc(&dsig, ns) != hipSuccess || hipMalloc(&du, nu) != hipSuccess ||
+        hipMemsetAsync(dsig, 0, ns, s) != hipSuccess || hipEventCreate(&a) != hipSuccess ||
+        hipEventCreate(&b) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(QBX_E_NOMEM, "autotune buffers");
+    }
+    int nr = G->m2l_nw_default;
+    std::vector<int> cand = {nr, (nr + 1) / 2, 0};
+    bool prof = G->profile, graph = G->graph_on;
+    G->profile = false;
+    G->graph_on = false;
+    double best = 1e300;
+    int pick = nr;
+    for (int c : cand) {
+        G->m2l_nw = c;
+        float tot = 0.f;
+        bool ok = true;
+        for (int rep = 0; rep < 4 && ok; ++rep) {
+            ok = hipEventRecord(a, s) == hipSuccess &&
+                 eval_chunks(G, n_dens, dsig, nullptr, du, nullptr, s, G->ctx->lane) == QBX_OK &&
+                 hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+            float ms = 0.f;
+            if (ok && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) tot += ms;   // rep 0 warms up
+        }
+        if (ok && tot < best) { best = tot; pick = c; }
+    }
+    G->profile = prof;
+    G->graph_on = graph;
+    G->m2l_nw = pick;
+    (void)hipStreamSynchronize(s);
+    cleanup();
+    if (choice_out) *choice_out = pick;
     return QBX_OK;
 }
 

@@ -1543,9 +1543,9 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
         if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
         k_m2l_mfma32<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
     } else {
-        nw = std::max(1, std::min(nw, 16));
+        nw = std::min(nw, 16);
         size_t lds = sizeof(cd) * 4 * ((2 * Pmax + 1 + 3) / 4) * M2L_XS;
-        if (lds <= LDS_BUDGET) {
+        if (nw > 0 && lds <= LDS_BUDGET) {
             k_m2l_mfma<<<ntiles, 64 * nw, lds, s>>>(g, nd, tiles, mp, vy);
         } else {
             long long nblk = (long long)ntiles * nrmax;

@@ -86,7 +86,9 @@ hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, 
                            int nrb, const int *plist, cd *mp, hipStream_t s);
 hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
                            const int *clist, const cd *vy, cd *loc, hipStream_t s);
-// nw: waves per tile (row blocks are spread over them)
+// nw > 0: columns staged in LDS, nw waves per tile (row blocks spread over
+// them); nw = 0 (or staging beyond the LDS budget): one wave per (tile, row
+// block) with operands straight from memory.  Same sums, same order.
 hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
                            int nw, const cd *mp, cd *vy, hipStream_t s);
 hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,

@@ -27,7 +27,7 @@ EXPORTS = [
     "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
     "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
     "qbx_geom_association", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times", "qbx_geom_work",
-    "qbx_eval_batch",
+    "qbx_eval_batch", "qbx_geom_autotune",
     "qbx_eval",
 ]
 
@@ -103,6 +103,7 @@ def lib():
     L.qbx_geom_association.argtypes = [_vp, _ip]
     L.qbx_geom_profile.argtypes = [_vp, i32]
     L.qbx_geom_graph.argtypes = [_vp, i32]
+    L.qbx_geom_autotune.argtypes = [_vp, i32, ctypes.POINTER(i32)]
     L.qbx_eval_batch.argtypes = [_vp, i32, ctypes.POINTER(_vp), ctypes.POINTER(i32),
                                  ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
     L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
@@ -259,6 +260,13 @@ class Geometry:
 
     def profile(self, enable: bool = True):
         _check(lib().qbx_geom_profile(self._h, int(bool(enable))))
+
+    def autotune(self, n_dens: int = 1) -> int:
+        """Pick the fastest M2L configuration on this geometry; returns the
+        waves per tile chosen (0 = direct-load kernel)."""
+        c = ctypes.c_int32(-1)
+        _check(lib().qbx_geom_autotune(self._h, int(n_dens), ctypes.byref(c)))
+        return int(c.value)
 
     def graph(self, enable: bool = True):
         """Replay evaluations from captured HIP graphs (keyed by the buffers)."""

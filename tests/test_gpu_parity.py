@@ -310,3 +310,19 @@ def test_fmm_high_frequency_large_orders(ctx):
     err = _rel(u, ref)
     print(f"omega=200 rel_l2={err:.3e}", flush=True)
     assert err < eps
+
+
+def test_autotune_keeps_results(ctx):
+    """The M2L autotuner picks among kernels that compute the same sums in the
+    same order: results before and after tuning are bitwise equal."""
+    from paper_1602_05301_amd import qbx
+    wl = inputs.fmm_star(n_panels=256, omega=50.0, eps=1e-10, p=14)
+    g = wl.geom
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    ss, sd = _dev(wl.sigma_s), _dev(wl.sigma_d)
+    before = geo.eval(ss, sd).cpu().numpy()
+    choice = geo.autotune(1)
+    after = geo.eval(ss, sd).cpu().numpy()
+    print(f"autotune choice: {choice}", flush=True)
+    assert choice >= 0
+    assert np.array_equal(before, after)
