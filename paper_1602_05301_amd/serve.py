@@ -187,6 +187,35 @@ def _summary(reqs, wall: float) -> dict:
             "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
 
 
+def batch_vs_sequential(ctx, n_geom: int = 16, rounds: int = 10, max_nodes: int = 16384) -> dict:
+    """One matvec on each of n_geom resident geometries (uneven sizes, omega,
+    eps; 4 densities each): qbx_eval_batch against qbx_eval one after another."""
+    import torch
+    reqs = make_requests(n_geom, seed=11, nodes=(512, max_nodes), matvecs=(4, 4))
+    geos = [_build(ctx, r) for r in reqs]
+    s = [torch.from_numpy(np.stack(r.densities)).cuda() for r in reqs]
+    u = [torch.empty_like(x) for x in s]
+    for g, x, y in zip(geos, s, u):                  # warm-up (scratch, tiles)
+        g.eval(x, x, u=y)
+    ctx.eval_batch(geos, s, s, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        for g, x, y in zip(geos, s, u):
+            g.eval(x, x, u=y)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) / rounds
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        ctx.eval_batch(geos, s, s, u)
+    torch.cuda.synchronize()
+    bat = (time.perf_counter() - t0) / rounds
+    work = sum(r.geom.n * 4 for r in reqs)
+    return {"geometries": n_geom, "densities_each": 4, "nodes": [r.geom.n for r in reqs],
+            "sequential_ms": seq * 1e3, "batched_ms": bat * 1e3,
+            "batched_targets_x_densities_per_s": work / bat}
+
+
 def _poisson(reqs, qps: float, seed: int = 7):
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -219,6 +248,7 @@ def main(argv=None) -> int:
     _poisson(reqs, 0.8 * sat_qps)
     out = {"workload": f"{args.requests} star requests, {1024}-{args.max_nodes} nodes, omega U[1,200], "
                        "eps in {1e-6 (FP32 far field), 1e-10}, 20-60 chained matvecs",
+           "batch": batch_vs_sequential(ctx),
            "saturation_qps": sat_qps, "closed_loop": closed,
            "fifo_at_0.8": fifo(ctx, reqs), "served": {}}
     for f in [float(x) for x in args.qps_fracs.split(",")]:
