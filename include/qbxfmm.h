@@ -198,14 +198,19 @@ qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
  * each), as a serving loop or a multi-geometry solve does.  Geometry i takes
  * n_dens[i] densities sigma_s[i] / sigma_d[i] (arrays of device pointers;
  * either array, or an entry of it, may be NULL as in qbx_eval) and writes
- * u[i]; no coefficient export.  The geometries are spread over four stream
- * slots of the context (each with its own side stream), which start after
- * the context's stream and which the context's stream waits for, so their
- * work overlaps on the device.  A geometry listed twice runs twice, in list
- * order, on one slot.  Each result is bitwise the same as from qbx_eval alone.
- * If stage profiling or graph replay is on for any of them, the evaluations
- * run one after another through qbx_eval.  Errors: QBX_E_INVAL (null or
- * foreign geometry, n_dens outside 1..64, missing u or densities),
+ * u[i]; no coefficient export.  Every FMM stage is one launch over all the
+ * geometries (per kernel variant the geometries need): the grid is the
+ * concatenation of each geometry's own grid for the stage, and a per-block
+ * map names the geometry whose arguments a block takes.  The geometries go
+ * through the pipeline together in passes of up to 4 densities each; a
+ * geometry listed twice, or with more than 4 densities, takes several
+ * passes.  The launches run on the context's stream (and its side stream,
+ * forked from and joined back to it).  Each result is bitwise the same as
+ * from qbx_eval alone.  The launch records are built on the host and copied
+ * to the device once per call; the call waits for the previous call's copy
+ * to finish.  If stage profiling or graph replay is on for any geometry, the
+ * evaluations run one after another through qbx_eval.  Errors: QBX_E_INVAL
+ * (null or foreign geometry, n_dens outside 1..64, missing u or densities),
  * QBX_E_DEVICE, QBX_E_NOMEM. */
 qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
                           const void *const *sigma_s, const void *const *sigma_d, void *const *u);

@@ -20,17 +20,9 @@ struct QbxLane {
     hipEvent_t ev_fork = nullptr, ev_x = nullptr, ev_q = nullptr, ev_m = nullptr;
 };
 
-// one batch slot: its own main stream plus a lane
-struct QbxSlot {
-    hipStream_t main = nullptr;
-    hipEvent_t ev_done = nullptr;
-    QbxLane lane;
-};
-
 struct qbx_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    std::vector<QbxSlot> slots;   // created on the first qbx_eval_batch
     // the side stream of plain evaluations: the near field and the X-list
     // P2L depend on the charges only and overlap the latency-bound
     // upward/downward passes; events fork it from and join it back to the
@@ -41,6 +33,13 @@ struct qbx_ctx_s {
     // caller's stream by events
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // fused batch launches: records and block maps, staged in pinned host
+    // memory and copied to the device once per qbx_eval_batch call
+    unsigned char *fz_host = nullptr, *fz_dev = nullptr;
+    size_t fz_cap = 0;
+    hipEvent_t fz_copied = nullptr;   // the last copy out of fz_host
+    hipEvent_t fz_done = nullptr;     // the last launch reading fz_dev was enqueued before this
+    bool fz_used = false;
 };
 
 namespace {
@@ -112,6 +111,7 @@ struct qbx_geom_s {
     qbx_ctx ctx = nullptr;
     Plan pl;
     DevGeom g{};
+    const DevGeom *d_self = nullptr;   // device copy of g (fused launches)
     DeviceArena arena;
     WorkList p2m, xl, qbx, wl, l2q;
     long long total_coef = 0;     // sum over boxes of (2 P_l + 1)
@@ -521,6 +521,7 @@ qbx_status upload(qbx_geom_s *G)
             for (int i = G->wf_start[b]; i < G->wf_start[b + 1]; ++i) pw = std::max(pw, pl.P[pl.lev[G->wf_idx[i]]]);
     G->wl.Pmax = pw;
 
+    G->d_self = ar.upload(std::vector<DevGeom>{g});
     if (ar.err != hipSuccess) return fail(ar.err == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                                           std::string("device upload failed: ") + hipGetErrorString(ar.err));
     return QBX_OK;
@@ -812,6 +813,269 @@ void stage_work(const qbx_geom_s *G, int nd, double *f)
     for (int s = 0; s < QBX_N_STAGES; ++s) f[s] *= nd;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched evaluation: one fused launch per stage over all geometries of a
+// pass (see FRec).  A pass holds each geometry at most once (its scratch is
+// per geometry) with one chunk of up to kDensChunk densities; the stages run
+// in the order and on the streams of run_pipeline.
+// ---------------------------------------------------------------------------
+struct BItem {
+    qbx_geom_s *G;
+    int nd;
+    const cd *ss, *sd;
+    cd *u;
+};
+
+// one step of a planned batch: a fused launch, an event record or a wait,
+// on the caller's stream (0) or the side stream (1)
+struct FOp {
+    enum { LAUNCH, RECORD, WAIT } type;
+    int launch;
+    int stream;
+    hipEvent_t ev;
+};
+
+qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, FBuf &fb, std::vector<FOp> &ops)
+{
+    auto item = [](const BItem &b) {
+        FItem it{};
+        it.h = &b.G->g;
+        it.r.g = b.G->d_self;
+        it.r.nd = b.nd;
+        return it;
+    };
+    auto stage = [&](int kind, const std::vector<FItem> &v, int stream) -> qbx_status {
+        if (v.empty()) return QBX_OK;
+        std::vector<int> ids;
+        hipError_t e = fused_plan(fb, kind, v, ids);
+        if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("fused launch plan: ") + hipGetErrorString(e));
+        for (int id : ids) ops.push_back({FOp::LAUNCH, id, stream, nullptr});
+        return QBX_OK;
+    };
+    auto record = [&](hipEvent_t e, int stream) { ops.push_back({FOp::RECORD, -1, stream, e}); };
+    auto wait = [&](int stream, hipEvent_t e) { ops.push_back({FOp::WAIT, -1, stream, e}); };
+#define QQ(expr)                          \
+    do {                                  \
+        qbx_status q_ = (expr);           \
+        if (q_ != QBX_OK) return q_;      \
+    } while (0)
+    std::vector<FItem> v;
+    for (const auto &b : B) {
+        FItem it = item(b);
+        it.r.in0 = b.ss;
+        it.r.in1 = b.sd;
+        it.r.out0 = b.G->qs;
+        it.r.out1 = b.G->qd;
+        v.push_back(it);
+    }
+    QQ(stage(FK_CHARGES, v, 0));
+    v.clear();
+    for (const auto &b : B)
+        if (b.G->pl.opt.direct) {
+            FItem it = item(b);
+            it.r.in0 = b.G->qs;
+            it.r.in1 = b.G->qd;
+            it.r.out0 = b.G->coef;
+            v.push_back(it);
+        }
+    QQ(stage(FK_P2QBXL_DIRECT, v, 0));
+    std::vector<const BItem *> F;
+    int maxlev = 0;
+    for (const auto &b : B)
+        if (!b.G->pl.opt.direct) {
+            F.push_back(&b);
+            maxlev = std::max(maxlev, b.G->pl.nlev);
+        }
+    auto over = [&](auto fill) {
+        std::vector<FItem> w;
+        for (const BItem *b : F) {
+            FItem it = item(*b);
+            if (fill(*b, it)) w.push_back(it);
+        }
+        return w;
+    };
+    auto v_ctr_rad = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            it.r.i0 = b.G->crad_rows; it.r.out0 = b.G->crad; it.n = b.G->l2q.n;
+            return it.n > 0;
+        });
+    };
+    auto v_fill = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            it.r.out0 = b.G->loc; it.n = (long long)b.nd * b.G->total_coef;
+            return true;
+        });
+    };
+    auto v_p2l_x = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            const qbx_geom_s *G = b.G;
+            it.r.in0 = G->xl.d; it.r.in1 = G->qs; it.r.in2 = G->qd; it.r.out0 = G->loc;
+            it.n = G->xl.n; it.P = G->xl.Pmax;
+            return it.n > 0;
+        });
+    };
+    auto v_p2qbxl = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            const qbx_geom_s *G = b.G;
+            it.r.in0 = G->qbx.d; it.r.in1 = G->qs; it.r.in2 = G->qd; it.r.out0 = G->coef;
+            it.n = G->qbx.n;
+            return it.n > 0;
+        });
+    };
+    auto v_m2qbxl = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            const qbx_geom_s *G = b.G;
+            it.r.in0 = G->d_wpairs; it.r.in1 = G->d_wpair_off; it.r.in2 = G->mp; it.r.out0 = G->wy;
+            it.n = G->n_wpairs; it.P = G->wl.Pmax;
+            return it.n > 0;
+        });
+    };
+    auto v_wsum = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            const qbx_geom_s *G = b.G;
+            it.r.in0 = G->wl.d; it.r.in1 = G->d_wleaf_start; it.r.in2 = G->d_wpair_off; it.r.in3 = G->wy;
+            it.r.out0 = G->coef; it.n = G->wl.n;
+            return G->n_wpairs > 0 && it.n > 0;
+        });
+    };
+    if (!F.empty()) {
+        int s1 = conc ? 1 : 0;
+        if (conc) {
+            record(L.ev_fork, 0);
+            wait(1, L.ev_fork);
+            QQ(stage(FK_CTR_RAD, v_ctr_rad(), 1));
+            QQ(stage(FK_FILL, v_fill(), 1));
+            QQ(stage(FK_P2L_X, v_p2l_x(), 1));
+            record(L.ev_x, 1);
+            QQ(stage(FK_P2QBXL, v_p2qbxl(), 1));
+        }
+        QQ(stage(FK_SRC_RAD, over([](const BItem &b, FItem &it) {
+                     it.r.i0 = b.G->srad_rows; it.r.out0 = b.G->srad; it.n = b.G->p2m.n;
+                     return it.n > 0;
+                 }), 0));
+        QQ(stage(FK_P2M, over([](const BItem &b, FItem &it) {
+                     const qbx_geom_s *G = b.G;
+                     it.r.in0 = G->p2m.d; it.r.in1 = G->qs; it.r.in2 = G->qd; it.r.in3 = G->srad; it.r.out0 = G->mp;
+                     it.n = G->p2m.n; it.P = G->p2m.Pmax;
+                     return it.n > 0;
+                 }), 0));
+        for (int l = maxlev - 2; l >= 2; --l)
+            QQ(stage(FK_M2M, over([l](const BItem &b, FItem &it) {
+                         const qbx_geom_s *G = b.G;
+                         if (l > G->pl.nlev - 2) return false;
+                         int t0 = G->m2m_tstart[b.nd][l], nt = G->m2m_tstart[b.nd][l + 1] - t0;
+                         it.r.i0 = l; it.r.in0 = G->m2m_tiles[b.nd] + t0; it.r.in1 = G->d_par_list; it.r.out0 = G->mp;
+                         it.n = nt; it.aux = (2 * G->pl.P[l] + 1 + 15) / 16;
+                         return nt > 0;
+                     }), 0));
+        if (conc) {
+            record(L.ev_m, 0);
+            wait(1, L.ev_m);
+            QQ(stage(FK_M2QBXL, v_m2qbxl(), 1));
+            QQ(stage(FK_WSUM, v_wsum(), 1));
+            record(L.ev_q, 1);
+        }
+        QQ(stage(FK_M2L, over([](const BItem &b, FItem &it) {
+                     const qbx_geom_s *G = b.G;
+                     it.r.in0 = G->m2l_tiles[b.nd]; it.r.in1 = G->mp; it.r.out0 = G->vy;
+                     it.n = G->m2l_ntiles[b.nd]; it.P = G->m2l_Pmax; it.aux = G->m2l_nw;
+                     return it.n > 0;
+                 }), 0));
+        if (conc) {
+            wait(0, L.ev_x);
+        } else {
+            QQ(stage(FK_FILL, v_fill(), 0));
+            QQ(stage(FK_P2L_X, v_p2l_x(), 0));
+        }
+        QQ(stage(FK_DOWN, over([](const BItem &b, FItem &it) {
+                     const Plan &pl = b.G->pl;
+                     if (pl.nlev <= 2) return false;
+                     it.r.i0 = 2; it.r.in0 = b.G->vy; it.r.out0 = b.G->loc;
+                     it.n = pl.level_start[3] - pl.level_start[2];
+                     return it.n > 0;
+                 }), 0));
+        for (int Lv = 3; Lv < maxlev; ++Lv)
+            QQ(stage(FK_L2L, over([Lv](const BItem &b, FItem &it) {
+                         const qbx_geom_s *G = b.G;
+                         if (Lv >= G->pl.nlev) return false;
+                         int t0 = G->l2l_tstart[b.nd][Lv], nt = G->l2l_tstart[b.nd][Lv + 1] - t0;
+                         it.r.i0 = Lv; it.r.in0 = G->l2l_tiles[b.nd] + t0; it.r.in1 = G->d_chl_list;
+                         it.r.in2 = G->vy; it.r.out0 = G->loc;
+                         it.n = nt; it.aux = (2 * G->pl.P[Lv] + 1 + 15) / 16;
+                         return nt > 0;
+                     }), 0));
+        if (conc) {
+            wait(0, L.ev_q);
+        } else {
+            QQ(stage(FK_P2QBXL, v_p2qbxl(), 0));
+            QQ(stage(FK_M2QBXL, v_m2qbxl(), 0));
+            QQ(stage(FK_WSUM, v_wsum(), 0));
+            QQ(stage(FK_CTR_RAD, v_ctr_rad(), 0));
+        }
+        (void)s1;
+        QQ(stage(FK_L2QBXL, over([](const BItem &b, FItem &it) {
+                     const qbx_geom_s *G = b.G;
+                     it.r.in0 = G->l2q.d; it.r.in1 = G->crad; it.r.in2 = G->loc; it.r.out0 = G->coef;
+                     it.n = G->l2q.n; it.P = G->l2q.Pmax; it.aux = G->crad_rows;
+                     return it.n > 0;
+                 }), 0));
+    }
+    v.clear();
+    for (const auto &b : B) {
+        FItem it = item(b);
+        it.r.in0 = b.G->coef;
+        it.r.out0 = b.u;
+        v.push_back(it);
+    }
+    QQ(stage(FK_EVAL, v, 0));
+    v.clear();
+    for (const auto &b : B) {
+        FItem it = item(b);
+        it.r.in0 = b.G->qs;
+        it.r.in1 = b.G->qd;
+        it.r.out0 = b.u;
+        v.push_back(it);
+    }
+    QQ(stage(FK_SMOOTH, v, 0));
+#undef QQ
+    return QBX_OK;
+}
+
+// Copies the planned records and maps to the device (one copy on st).
+qbx_status fused_upload(qbx_ctx_s *C, const FBuf &fb, hipStream_t st)
+{
+    size_t n = fb.bytes.size();
+    // the staging buffer is free once the previous copy out of it is done,
+    // the device buffer once the launches of the previous batch have run
+    if (C->fz_used) {
+        CHK(hipEventSynchronize(C->fz_copied));
+        CHK(hipStreamWaitEvent(st, C->fz_done, 0));
+    }
+    if (n > C->fz_cap) {
+        if (C->fz_used) CHK(hipEventSynchronize(C->fz_done));
+        if (C->fz_host) (void)hipHostFree(C->fz_host);
+        if (C->fz_dev) (void)hipFree(C->fz_dev);
+        C->fz_host = C->fz_dev = nullptr;
+        C->fz_cap = 0;
+        size_t cap = std::max<size_t>(n + n / 2, 1 << 20);
+        hipError_t e = hipHostMalloc((void **)&C->fz_host, cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void **)&C->fz_dev, cap);
+        if (e != hipSuccess) {
+            if (C->fz_host) (void)hipHostFree(C->fz_host);
+            C->fz_host = nullptr;
+            return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
+                        std::string("batch launch records: ") + hipGetErrorString(e));
+        }
+        C->fz_cap = cap;
+    }
+    std::memcpy(C->fz_host, fb.bytes.data(), n);
+    CHK(hipMemcpyAsync(C->fz_dev, C->fz_host, n, hipMemcpyHostToDevice, st));
+    CHK(hipEventRecord(C->fz_copied, st));
+    C->fz_used = true;
+    return QBX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -836,14 +1100,18 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     if (!lane_create(c->lane) ||
         hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fz_copied, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fz_done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         lane_destroy(c->lane);
         if (c->ev_in) (void)hipEventDestroy(c->ev_in);
         if (c->ev_out) (void)hipEventDestroy(c->ev_out);
         if (c->gstream) (void)hipStreamDestroy(c->gstream);
+        if (c->fz_copied) (void)hipEventDestroy(c->fz_copied);
+        if (c->fz_done) (void)hipEventDestroy(c->fz_done);
         c->gstream = nullptr;
-        c->ev_in = c->ev_out = nullptr;
+        c->ev_in = c->ev_out = c->fz_copied = c->fz_done = nullptr;
     }
     *out = c;
     return QBX_OK;
@@ -861,12 +1129,12 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx)
     if (!ctx) return QBX_OK;
     (void)hipSetDevice(ctx->device);
     lane_destroy(ctx->lane);
-    for (auto &sl : ctx->slots) {
-        if (sl.main) (void)hipStreamSynchronize(sl.main);
-        lane_destroy(sl.lane);
-        if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
-        if (sl.main) (void)hipStreamDestroy(sl.main);
-    }
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->fz_copied) (void)hipEventDestroy(ctx->fz_copied);
+    if (ctx->fz_done) (void)hipEventDestroy(ctx->fz_done);
+    if (ctx->fz_host) (void)hipHostFree(ctx->fz_host);
+    if (ctx->fz_dev) (void)hipFree(ctx->fz_dev);
     if (ctx->gstream) {
         (void)hipStreamSynchronize(ctx->gstream);
         (void)hipStreamDestroy(ctx->gstream);
@@ -929,7 +1197,6 @@ qbx_status qbx_geom_destroy(qbx_geom G)
     else (void)hipDeviceSynchronize();
     if (G->ctx->gstream) (void)hipStreamSynchronize(G->ctx->gstream);
     if (G->ctx->lane.side) (void)hipStreamSynchronize(G->ctx->lane.side);
-    for (auto &sl : G->ctx->slots) (void)hipStreamSynchronize(sl.main), (void)hipStreamSynchronize(sl.lane.side);
     G->scratch.release();
     G->arena.release();
     delete G;
@@ -1068,8 +1335,6 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
     return eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, C->stream, C->lane);
 }
 
-constexpr int kBatchSlots = 4;   // stream slots of qbx_eval_batch
-
 qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
                           const void *const *sigma_s, const void *const *sigma_d, void *const *u)
 {
@@ -1084,51 +1349,63 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
     }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
-    bool serial = !ctx->lane.side;
-    for (int i = 0; i < n_geom; ++i) serial = serial || geoms[i]->profile || geoms[i]->graph_on;
-    if (!serial && ctx->slots.empty()) {
-        ctx->slots.resize(kBatchSlots);
-        for (auto &sl : ctx->slots)
-            if (hipStreamCreateWithFlags(&sl.main, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming) != hipSuccess || !lane_create(sl.lane)) {
-                (void)hipGetLastError();
-                serial = true;
-                break;
-            }
-    }
-    for (int i = 0; i < n_geom; ++i) {
-        qbx_status q = ensure_scratch(geoms[i]);
-        if (q != QBX_OK) return q;
-    }
     auto dens = [&](const void *const *a, int i) { return a ? a[i] : nullptr; };
+    bool serial = !ctx->fz_copied;
+    for (int i = 0; i < n_geom; ++i) serial = serial || geoms[i]->profile || geoms[i]->graph_on;
     if (serial) {
-        // profiling or graph replay on some geometry: one after another
+        // stage profiling or graph replay on some geometry: one after another
         for (int i = 0; i < n_geom; ++i) {
             qbx_status q = qbx_eval(geoms[i], n_dens[i], dens(sigma_s, i), dens(sigma_d, i), u[i], nullptr);
             if (q != QBX_OK) return q;
         }
         return QBX_OK;
     }
-    // slots start after the caller's stream; a geometry listed twice stays
-    // on the slot of its first occurrence, since its scratch is shared
-    CHK(hipEventRecord(ctx->ev_in, ctx->stream));
-    for (auto &sl : ctx->slots) CHK(hipStreamWaitEvent(sl.main, ctx->ev_in, 0));
-    std::vector<int> slot_of(n_geom);
-    int next = 0;
-    for (int i = 0; i < n_geom; ++i) {
-        slot_of[i] = -1;
-        for (int j = 0; j < i; ++j)
-            if (geoms[j] == geoms[i]) { slot_of[i] = slot_of[j]; break; }
-        if (slot_of[i] < 0) slot_of[i] = next++ % kBatchSlots;
-        QbxSlot &sl = ctx->slots[slot_of[i]];
-        qbx_status q = eval_chunks(geoms[i], n_dens[i], dens(sigma_s, i), dens(sigma_d, i), u[i], nullptr,
-                                   sl.main, sl.lane);
+    // passes: the k-th chunk that names a geometry goes to pass k (a
+    // geometry's scratch serves one chunk at a time)
+    std::vector<std::vector<BItem>> passes;
+    std::vector<std::pair<qbx_geom_s *, int>> seen;
+    for (int d0 = 0;; d0 += kDensChunk) {
+        bool any = false;
+        for (int i = 0; i < n_geom; ++i) {
+            if (n_dens[i] <= d0) continue;
+            any = true;
+            qbx_geom_s *G = geoms[i];
+            qbx_status q = ensure_scratch(G);
+            if (q != QBX_OK) return q;
+            int nd = std::min(kDensChunk, n_dens[i] - d0);
+            if (!G->pl.opt.direct && (q = ensure_tiles(G, nd)) != QBX_OK) return q;
+            int k = 0;
+            for (auto &sv : seen)
+                if (sv.first == G) k = ++sv.second;
+            if (k == 0) seen.push_back({G, 0});
+            if ((int)passes.size() <= k) passes.resize(k + 1);
+            const Plan &pl = G->pl;
+            const void *ss = dens(sigma_s, i), *sd = dens(sigma_d, i);
+            passes[k].push_back({G, nd, ss ? static_cast<const cd *>(ss) + (long long)d0 * pl.ns : nullptr,
+                                 sd ? static_cast<const cd *>(sd) + (long long)d0 * pl.ns : nullptr,
+                                 static_cast<cd *>(u[i]) + (long long)d0 * pl.nt});
+        }
+        if (!any) break;
+    }
+    FBuf fb;
+    std::vector<FOp> ops;
+    bool conc = ctx->lane.side != nullptr;
+    for (const auto &B : passes) {
+        qbx_status q = plan_pass(B, ctx->lane, conc, fb, ops);
         if (q != QBX_OK) return q;
     }
-    for (auto &sl : ctx->slots) {
-        CHK(hipEventRecord(sl.ev_done, sl.main));
-        CHK(hipStreamWaitEvent(ctx->stream, sl.ev_done, 0));
+    hipStream_t st = ctx->stream;
+    qbx_status q = fused_upload(ctx, fb, st);
+    if (q != QBX_OK) return q;
+    for (const FOp &op : ops) {
+        hipStream_t s = op.stream ? ctx->lane.side : st;
+        switch (op.type) {
+        case FOp::LAUNCH: CHK(fused_launch(fb.launches[op.launch], ctx->fz_dev, s)); break;
+        case FOp::RECORD: CHK(hipEventRecord(op.ev, s)); break;
+        case FOp::WAIT: CHK(hipStreamWaitEvent(s, op.ev, 0)); break;
+        }
     }
+    CHK(hipEventRecord(ctx->fz_done, st));
     return QBX_OK;
 }
 

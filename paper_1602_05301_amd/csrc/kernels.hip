@@ -9,6 +9,11 @@
 // with the per-level W_k = min(1, s^k/k!), s = w R_l / sqrt(2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#define QBX_KERNELS_TU
 #include "devmath.hpp"
 #include "kernels.hpp"
 
@@ -18,17 +23,22 @@ namespace qbx {
 // Utilities
 // ---------------------------------------------------------------------------
 
-__global__ void k_fill_zero(cd *p, long long n)
+__device__ __forceinline__ void fill_zero_body(cd *p, long long n, BlockId bid)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long step = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)bid.x * blockDim.x + threadIdx.x;
+    long long step = (long long)bid.nx * blockDim.x;
     for (; i < n; i += step) p[i] = mk(0.0, 0.0);
 }
 
-// qS[d][j] = (i/4) w_j sigma_S[d][perm[j]] (sorted source order); same for qD.
-__global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, cd *qs, cd *qd)
+__global__ void k_fill_zero(cd *p, long long n)
 {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    fill_zero_body(p, n, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+// qS[d][j] = (i/4) w_j sigma_S[d][perm[j]] (sorted source order); same for qD.
+__device__ __forceinline__ void charges_body(const DevGeom &g, int nd, const cd *sig_s, const cd *sig_d, cd *qs, cd *qd, BlockId bid)
+{
+    long long idx = (long long)bid.x * blockDim.x + threadIdx.x;
     long long n = (long long)nd * g.ns;
     if (idx >= n) return;
     int d = (int)(idx / g.ns), j = (int)(idx % g.ns);
@@ -38,6 +48,11 @@ __global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, c
     cd b = sig_d ? sig_d[(long long)d * g.ns + u] : mk(0.0, 0.0);
     qs[idx] = mk(-s * a.y, s * a.x);
     qd[idx] = mk(-s * b.y, s * b.x);
+}
+
+__global__ void k_charges(DevGeom g, int nd, const cd *sig_s, const cd *sig_d, cd *qs, cd *qd)
+{
+    charges_body(g, nd, sig_s, sig_d, qs, qd, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p + QBLK
@@ -51,11 +66,11 @@ constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p +
 // normalises at the end, so it runs in LDS ([rows][lanes]) and each lane
 // then copies its own column out.
 // ---------------------------------------------------------------------------
-__global__ void k_src_rad(DevGeom g, int rows, double *rad)
+__device__ __forceinline__ void src_rad_body(const DevGeom &g, int rows, double *rad, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     int lanes = blockDim.x;
-    int s = blockIdx.x * lanes + threadIdx.x;
+    int s = bid.x * lanes + threadIdx.x;
     int N = -1;
     if (s < g.ns) {
         int b = g.src_box[s];
@@ -69,11 +84,16 @@ __global__ void k_src_rad(DevGeom g, int rows, double *rad)
     for (int n = 0; n <= N; ++n) rad[(long long)n * g.ns + s] = lds_raw[n * lanes + threadIdx.x];
 }
 
-__global__ void k_ctr_rad(DevGeom g, int rows, double *rad)
+__global__ void k_src_rad(DevGeom g, int rows, double *rad)
+{
+    src_rad_body(g, rows, rad, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+__device__ __forceinline__ void ctr_rad_body(const DevGeom &g, int rows, double *rad, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     int lanes = blockDim.x;
-    int c = blockIdx.x * lanes + threadIdx.x;
+    int c = bid.x * lanes + threadIdx.x;
     int N = -1;
     if (c < g.nc) {
         int b = g.ctr_box[c];
@@ -85,6 +105,11 @@ __global__ void k_ctr_rad(DevGeom g, int rows, double *rad)
     }
     (void)rows;
     for (int n = 0; n <= N; ++n) rad[(long long)n * g.nc + c] = lds_raw[n * lanes + threadIdx.x];
+}
+
+__global__ void k_ctr_rad(DevGeom g, int rows, double *rad)
+{
+    ctr_rad_body(g, rows, rad, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // lanes per block of a Miller kernel: [rows][lanes] doubles within 64 KiB
@@ -141,11 +166,10 @@ __device__ __forceinline__ cd p2m_basis(const cd *row, int m)
 }
 
 template <int ND>
-__global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd,
-                                            const double *srad, cd *mp, int CH)
+__device__ __forceinline__ void p2m_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, const double *srad, cd *mp, int CH, BlockId bid)
 {
     extern __shared__ double lds_raw[];
-    int b = list[blockIdx.x];
+    int b = list[bid.x];
     int l = g.blev[b];
     int P = g.Plev[l], np = 2 * P + 1, NT = P + 2;
     cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT], order n at row[n]
@@ -224,6 +248,12 @@ __global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd
     }
 }
 
+template <int ND>
+__global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd, const double *srad, cd *mp, int CH)
+{
+    p2m_body<ND>(g, list, qs, qd, srad, mp, CH, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // ---------------------------------------------------------------------------
 // Stage 4 as batched complex GEMM on FP64 MFMA.  For one (level, offset)
 // group the scaled M2L matrix M (n x n, n = 2P+1) multiplies up to 16
@@ -255,9 +285,9 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n)
 
 // Level-2 part of the downward pass: local = X-list part (already in loc)
 // + the box's V-list contributions in list order (no parent local exists).
-__global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
+__device__ __forceinline__ void down_body(const DevGeom &g, int nd, int l, const cd *vy, cd *loc, BlockId bid)
 {
-    int b = g.level_start[l] + blockIdx.x;
+    int b = g.level_start[l] + bid.x;
     int P = g.Plev[l], n = 2 * P + 1;
     cd *out = loc + g.box_off[b] * nd;
     int v0 = g.V_start[b], nv = g.V_start[b + 1] - v0;
@@ -271,6 +301,11 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
         for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs + i];
         out[i] = acc;
     }
+}
+
+__global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
+{
+    down_body(g, nd, l, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // Part of one 16x16 output block of a scaled translation on FP64 MFMA: rows
@@ -332,12 +367,11 @@ __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, co
 // tiles of one (level, offset) group share an XCD's L2 copy of its matrix.
 constexpr int M2L_XS = 17;    // LDS row stride of the staged columns (padded)
 
-__global__ void __launch_bounds__(1024) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles,
-                                                   const cd *mp, cd *vy)
+__device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2LTile *tiles, const cd *mp, cd *vy, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     cd *X = reinterpret_cast<cd *>(lds_raw);    // [4 NK][M2L_XS]
-    M2LTile t = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
+    M2LTile t = tiles[xcd_contiguous(bid.x, bid.nx)];
     int l = t.lo / 40;
     int P = g.Plev[l], n = 2 * P + 1;
     int NK = (n + 3) / 4, NR = (n + 15) / 16;
@@ -402,16 +436,20 @@ __global__ void __launch_bounds__(1024) k_m2l_mfma(DevGeom g, int nd, const M2LT
     }
 }
 
+__global__ void __launch_bounds__(1024) k_m2l_mfma(DevGeom g, int nd, const M2LTile *tiles, const cd *mp, cd *vy)
+{
+    m2l_mfma_body(g, nd, tiles, mp, vy, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // M2L for orders whose staged columns exceed the LDS budget: one wave per
 // (tile, row block), operands straight from memory with the
 // loads of the next TB_U k-blocks in flight (trans_block).  1-D grid of
 // ntiles * nrmax waves in XCD-contiguous order, the row blocks of a tile
 // consecutive, so that a tile's columns and a group's matrix are fetched
 // into one XCD's L2; waves past the tile's row count exit at once.
-__global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
-                                                 const cd *mp, cd *vy)
+__device__ __forceinline__ void m2l_mfma_direct_body(const DevGeom &g, int nd, const M2LTile *tiles, int nrmax, const cd *mp, cd *vy, BlockId bid)
 {
-    int c = xcd_contiguous(blockIdx.x, gridDim.x);
+    int c = xcd_contiguous(bid.x, bid.nx);
     M2LTile t = tiles[c / nrmax];
     int rb = c % nrmax;
     int l = t.lo / 40;
@@ -431,6 +469,11 @@ __global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const
         int row = rb * 16 + 4 * i + bk;
         if (row < n) o[row] = mk(yr[i], yi[i]);
     }
+}
+
+__global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const M2LTile *tiles, int nrmax, const cd *mp, cd *vy)
+{
+    m2l_mfma_direct_body(g, nd, tiles, nrmax, mp, vy, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -485,10 +528,9 @@ __device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, 
     }
 }
 
-__global__ void __launch_bounds__(64) k_m2l_mfma32(DevGeom g, int nd, const M2LTile *tiles, int nrmax,
-                                                   const cd *mp, cd *vy)
+__device__ __forceinline__ void m2l_mfma32_body(const DevGeom &g, int nd, const M2LTile *tiles, int nrmax, const cd *mp, cd *vy, BlockId bid)
 {
-    int c = xcd_contiguous(blockIdx.x, gridDim.x);
+    int c = xcd_contiguous(bid.x, bid.nx);
     M2LTile t = tiles[c / nrmax];
     int rb = c % nrmax;
     int l = t.lo / 40;
@@ -508,6 +550,11 @@ __global__ void __launch_bounds__(64) k_m2l_mfma32(DevGeom g, int nd, const M2LT
         int row = rb * 16 + 4 * bk + i;
         if (row < n) o[row] = mk((double)yr[i], (double)yi[i]);
     }
+}
+
+__global__ void __launch_bounds__(64) k_m2l_mfma32(DevGeom g, int nd, const M2LTile *tiles, int nrmax, const cd *mp, cd *vy)
+{
+    m2l_mfma32_body(g, nd, tiles, nrmax, mp, vy, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // k-block range of part h of NK split in KS near-equal parts
@@ -541,12 +588,11 @@ __device__ __forceinline__ cd tb_sum(const double (*part)[64][9], int nw, int r,
 // are summed in wave order.
 constexpr int M2M_KS = 2;
 
-__global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, int l, const TTile *tiles,
-                                                           const int *plist, cd *mp)
+__device__ __forceinline__ void m2m_mfma_body(const DevGeom &g, int nd, int l, const TTile *tiles, const int *plist, cd *mp, BlockId bid)
 {
     __shared__ double part[4 * M2M_KS][64][9];
-    TTile t = tiles[blockIdx.x];
-    int rb = blockIdx.y;
+    TTile t = tiles[bid.x];
+    int rb = bid.y;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = w & 3, h = w >> 2;
     int np = 2 * g.Plev[l] + 1, nc = 2 * g.Plev[l + 1] + 1;
     int NKc = (nc + 3) / 4;
@@ -576,18 +622,22 @@ __global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, in
     }
 }
 
+__global__ void __launch_bounds__(256 * M2M_KS) k_m2m_mfma(DevGeom g, int nd, int l, const TTile *tiles, const int *plist, cd *mp)
+{
+    m2m_mfma_body(g, nd, l, tiles, plist, mp, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // Stage 7 (levels >= 3): local of a child = X-list part (already in loc) +
 // its V-list contributions in list order + L2L of the parent's local.
 // Block = (tile of 16 (child, density) columns of one quadrant, row block);
 // the four waves take a quarter of the k-blocks each.
 constexpr int L2L_KS = 4;
 
-__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int L, const TTile *tiles,
-                                                          const int *clist, const cd *vy, cd *loc)
+__device__ __forceinline__ void l2l_mfma_body(const DevGeom &g, int nd, int L, const TTile *tiles, const int *clist, const cd *vy, cd *loc, BlockId bid)
 {
     __shared__ double part[L2L_KS][64][9];
-    TTile t = tiles[blockIdx.x];
-    int rb = blockIdx.y;
+    TTile t = tiles[bid.x];
+    int rb = bid.y;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int nc = 2 * g.Plev[L] + 1, np = 2 * g.Plev[L - 1] + 1;
     int NKp = (np + 3) / 4;
@@ -620,6 +670,11 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int
     loc[base] = acc + tb_sum(part, L2L_KS, r, c);
 }
 
+__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma(DevGeom g, int nd, int L, const TTile *tiles, const int *clist, const cd *vy, cd *loc)
+{
+    l2l_mfma_body(g, nd, L, tiles, clist, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // FP32 variant of k_l2l_mfma (FP32 far field): same work split; the partial
 // blocks are stored in double in the FP32 result layout.
 __device__ __forceinline__ cd tb_sum32(const double (*part)[64][9], int nw, int r, int c)
@@ -630,12 +685,11 @@ __device__ __forceinline__ cd tb_sum32(const double (*part)[64][9], int nw, int 
     return y;
 }
 
-__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, int L, const TTile *tiles,
-                                                            const cd *vy, cd *loc)
+__device__ __forceinline__ void l2l_mfma32_body(const DevGeom &g, int nd, int L, const TTile *tiles, const cd *vy, cd *loc, BlockId bid)
 {
     __shared__ double part[L2L_KS][64][9];
-    TTile t = tiles[blockIdx.x];
-    int rb = blockIdx.y;
+    TTile t = tiles[bid.x];
+    int rb = bid.y;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int nc = 2 * g.Plev[L] + 1, np = 2 * g.Plev[L - 1] + 1;
     int NKp = (np + 3) / 4;
@@ -668,6 +722,11 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, i
     loc[base] = acc + tb_sum32(part, L2L_KS, r, c);
 }
 
+__global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, int L, const TTile *tiles, const cd *vy, cd *loc)
+{
+    l2l_mfma32_body(g, nd, L, tiles, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // ---------------------------------------------------------------------------
 // Stage 6: X-list P2L, g_l += qS O_l(s - m_b) + (omega/2) qD (nu O_{l-1} -
 // conj(nu) O_{l+1}), stored as W_|l| g_l.  O_n = H_n(x) v^n and
@@ -679,11 +738,10 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, i
 // the host).
 // ---------------------------------------------------------------------------
 template <int ND>
-__global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd,
-                                              cd *loc, int CH)
+__device__ __forceinline__ void p2l_x_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, cd *loc, int CH, BlockId bid)
 {
     extern __shared__ double lds_raw[];
-    int b = list[blockIdx.x];
+    int b = list[bid.x];
     int l = g.blev[b];
     int P = g.Plev[l], np = 2 * P + 1, NT = 2 * P + 3;
     cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT]
@@ -698,7 +756,7 @@ __global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const 
     for (int n = tid; n <= P + 1; n += blockDim.x) RW[n] = Wl[min(n + 1, P)] * iWl[min(n, P)];
     double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
     cd *out = loc + g.box_off[b] * ND;
-    int q0 = g.xsrc_start[blockIdx.x], total = g.xsrc_start[blockIdx.x + 1] - q0;
+    int q0 = g.xsrc_start[bid.x], total = g.xsrc_start[bid.x + 1] - q0;
     int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
     for (int f0 = 0; f0 < total; f0 += CH) {
         int cnt = min(CH, total - f0);
@@ -776,6 +834,12 @@ __global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const 
             }
         }
     }
+}
+
+template <int ND>
+__global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd, cd *loc, int CH)
+{
+    p2l_x_body<ND>(g, list, qs, qd, loc, CH, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -872,8 +936,7 @@ constexpr int P2Q_SCH = 256;
 constexpr int P2Q_THREADS = 128;   // lanes per leaf
 
 template <int PB>
-__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs,
-                                                 const cd *qd, cd *coef)
+__device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int *list, const cd *qs, const cd *qd, cd *coef, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     constexpr int NE = 2 * PB + 1;
@@ -882,7 +945,7 @@ __global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const
     cd *QD = QS + P2Q_SCH;                              // [P2Q_SCH]
     double *SX = reinterpret_cast<double *>(QD + P2Q_SCH);
     double *SY = SX + P2Q_SCH, *NX = SY + P2Q_SCH, *NY = NX + P2Q_SCH;
-    int b = list[blockIdx.x];
+    int b = list[bid.x];
     int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
     int nct = c1 - c0;
     int CG = 1;
@@ -892,7 +955,7 @@ __global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const
     int gi = tid % CG, part = tid / CG;
     int p = g.p;
     long long ncoef = 2 * p + 1;
-    int q0 = g.qsrc_start[blockIdx.x], total = g.qsrc_start[blockIdx.x + 1] - q0;
+    int q0 = g.qsrc_start[bid.x], total = g.qsrc_start[bid.x + 1] - q0;
     for (int cg = c0; cg < c1; cg += CG) {
         int i = cg + gi;
         bool active = i < c1;
@@ -956,14 +1019,19 @@ __global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const
     }
 }
 
+template <int PB>
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *coef)
+{
+    p2qbxl_body<PB>(g, nd, list, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // Direct mode: all sources to every centre (Sec. 3.2, oversampled coefficient sum).
 template <int PB>
-__global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, const cd *qs,
-                                                       const cd *qd, cd *coef)
+__device__ __forceinline__ void p2qbxl_direct_body(const DevGeom &g, int nd, int G, const cd *qs, const cd *qd, cd *coef, BlockId bid)
 {
     int parts = 64 / G;
     int lane = threadIdx.x, gi = lane % G, part = lane / G;
-    int i = blockIdx.x * G + gi;
+    int i = bid.x * G + gi;
     bool active = i < g.nc;
     int p = g.p;
     long long ncoef = 2 * p + 1;
@@ -980,6 +1048,12 @@ __global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, 
         p2qbxl_finish<PB>(acc, G, p, active && part == 0,
                           coef + (long long)d * ncoef * g.nc + (active ? i : 0), g.nc, false);
     }
+}
+
+template <int PB>
+__global__ void __launch_bounds__(64) k_p2qbxl_direct(DevGeom g, int nd, int G, const cd *qs, const cd *qd, cd *coef)
+{
+    p2qbxl_direct_body<PB>(g, nd, G, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,12 +1095,10 @@ __device__ __forceinline__ void chunk_of(int lo, int hi, int s, int *a, int *b)
     *b = min(*a + cs - 1, hi);
 }
 
-__global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *pairs,
-                                                const long long *pair_off, const cd *mp, cd *wy,
-                                                int QCG)
+__device__ __forceinline__ void m2qbxl_body(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off, const cd *mp, cd *wy, int QCG, BlockId bid)
 {
     extern __shared__ double lds_raw[];
-    int2 pr = pairs[blockIdx.x];
+    int2 pr = pairs[bid.x];
     int b = pr.x, w = pr.y;
     int c0 = g.ctr_begin[b], c1 = g.ctr_end[b], nct = c1 - c0;
     int p = g.p, nq = 2 * p + 1;
@@ -1052,10 +1124,10 @@ __global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *p
         rdn[i] = k > -Pw ? Wt[km < 0 ? -km : km] * iW[ak] : 0.0;
     }
     double mx = g.bcx[w], my = g.bcy[w];
-    cd *out_pair = wy + pair_off[blockIdx.x] * nd;
-    // this workgroup's group of centres (blockIdx.y); the Hankel sequences
+    cd *out_pair = wy + pair_off[bid.x] * nd;
+    // this workgroup's group of centres (bid.y); the Hankel sequences
     // depend on the geometry only and serve every density
-    int cg0 = c0 + blockIdx.y * QCG;
+    int cg0 = c0 + bid.y * QCG;
     if (cg0 >= c1) return;
     int cnt = min(QCG, c1 - cg0);
     if (tid < cnt) {
@@ -1209,11 +1281,15 @@ __global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *p
     }
 }
 
-// coef[d][l][i] += sum over the leaf's far-W pairs (list order) of their rows.
-__global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_pair_start,
-                       const long long *pair_off, const cd *wy, cd *coef)
+__global__ void __launch_bounds__(256) k_m2qbxl(DevGeom g, int nd, const int2 *pairs, const long long *pair_off, const cd *mp, cd *wy, int QCG)
 {
-    int li = blockIdx.x;
+    m2qbxl_body(g, nd, pairs, pair_off, mp, wy, QCG, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+// coef[d][l][i] += sum over the leaf's far-W pairs (list order) of their rows.
+__device__ __forceinline__ void wsum_body(const DevGeom &g, int nd, const int *leaf_list, const int *leaf_pair_start, const long long *pair_off, const cd *wy, cd *coef, BlockId bid)
+{
+    int li = bid.x;
     int b = leaf_list[li];
     int c0 = g.ctr_begin[b], nct = g.ctr_end[b] - c0;
     int p = g.p, nq = 2 * p + 1;
@@ -1230,6 +1306,11 @@ __global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_
         cd *o = coef + ((long long)d * nq + l) * g.nc + c0 + ci;
         *o = *o + acc;
     }
+}
+
+__global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_pair_start, const long long *pair_off, const cd *wy, cd *coef)
+{
+    wsum_body(g, nd, leaf_list, leaf_pair_start, pair_off, wy, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -1249,11 +1330,10 @@ size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
            sizeof(double) * ((size_t)cg * (N + 1) + 3 * (size_t)cg);
 }
 
-__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad,
-                                                const cd *loc, cd *coef, int QCG)
+__device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG, BlockId bid)
 {
     extern __shared__ double lds_raw[];
-    int b = list[blockIdx.x];
+    int b = list[bid.x];
     int l = g.blev[b];
     int P = g.Plev[l], np = 2 * P + 1;
     int p = g.p, nq = 2 * p + 1;
@@ -1364,13 +1444,18 @@ __global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *li
     }
 }
 
+__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG)
+{
+    l2qbxl_body(g, nd, list, crad, loc, coef, QCG, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // ---------------------------------------------------------------------------
 // QBX evaluation at associated targets: u = sum_{|l|<=p} alpha_l J_l(w rho) e^{-i l theta}.
 // Miller's recurrence runs downward and the series is summed on the fly.
 // ---------------------------------------------------------------------------
-__global__ void k_qbx_eval(DevGeom g, int nd, const cd *coef, cd *u)
+__device__ __forceinline__ void qbx_eval_body(const DevGeom &g, int nd, const cd *coef, cd *u, BlockId bid)
 {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    int m = bid.x * blockDim.x + threadIdx.x;
     if (m >= g.nt) return;
     int i = g.tgt_cs[m];
     if (i < 0) return;
@@ -1416,10 +1501,15 @@ __global__ void k_qbx_eval(DevGeom g, int nd, const cd *coef, cd *u)
     }
 }
 
-// Smooth (unmodified Gauss) rule at unassociated targets, over all sources.
-__global__ void k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
+__global__ void k_qbx_eval(DevGeom g, int nd, const cd *coef, cd *u)
 {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    qbx_eval_body(g, nd, coef, u, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+// Smooth (unmodified Gauss) rule at unassociated targets, over all sources.
+__device__ __forceinline__ void smooth_body(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, BlockId bid)
+{
+    int idx = bid.x * blockDim.x + threadIdx.x;
     if (idx >= g.n_smooth) return;
     int m = g.smooth_list[idx];
     double tx = g.tx[m], ty = g.ty[m];
@@ -1439,10 +1529,15 @@ __global__ void k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
     }
 }
 
-// coef_user[d][l][user(i)] = coef[d][l][i]
-__global__ void k_coef_out(DevGeom g, int nd, const cd *coef, cd *out)
+__global__ void k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
 {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    smooth_body(g, nd, qs, qd, u, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+// coef_user[d][l][user(i)] = coef[d][l][i]
+__device__ __forceinline__ void coef_out_body(const DevGeom &g, int nd, const cd *coef, cd *out, BlockId bid)
+{
+    long long idx = (long long)bid.x * blockDim.x + threadIdx.x;
     long long nq = 2 * g.p + 1;
     long long n = nd * nq * g.nc;
     if (idx >= n) return;
@@ -1450,6 +1545,177 @@ __global__ void k_coef_out(DevGeom g, int nd, const cd *coef, cd *out)
     int i = (int)(idx % g.nc);
     out[row * g.nc + g.ctr_perm[i]] = coef[idx];
 }
+
+__global__ void k_coef_out(DevGeom g, int nd, const cd *coef, cd *out)
+{
+    coef_out_body(g, nd, coef, out, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+
+// ---------------------------------------------------------------------------
+// Fused launches (one grid per stage over several geometries)
+// ---------------------------------------------------------------------------
+// Records, maps and geometry views are read through the constant address
+// space: they are never written while a launch runs, so the loads are
+// scalar and the values stay in scalar registers, as kernel arguments do.
+#ifdef __HIP_DEVICE_COMPILE__
+#define QBX_CONST __attribute__((address_space(4)))
+#else
+#define QBX_CONST
+#endif
+
+__device__ __forceinline__ FRec fused_rec(const FRec *recs, const int *map, BlockId &bid)
+{
+    int gi = __builtin_amdgcn_readfirstlane(((const QBX_CONST int *)map)[blockIdx.x]);
+    FRec r = ((const QBX_CONST FRec *)recs)[gi];
+    int loc = (int)blockIdx.x - r.first;
+    bid.x = loc % r.nx;
+    bid.y = loc / r.nx;
+    bid.nx = r.nx;
+    return r;
+}
+
+// The geometry's view is copied at the top, before any store, so its fields
+// load once like kernel arguments.
+#define FUSED_BEGIN                                     \
+    BlockId bid;                                        \
+    const FRec r = fused_rec(recs, map, bid);           \
+    const DevGeom g = *(const QBX_CONST DevGeom *)r.g;
+
+#define CP(T, x) ((T)(r.x))
+
+__global__ void kf_fill(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    (void)g;
+    fill_zero_body(CP(cd *, out0), r.n64, bid);
+}
+
+__global__ void kf_charges(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    charges_body(g, r.nd, CP(const cd *, in0), CP(const cd *, in1), CP(cd *, out0), CP(cd *, out1), bid);
+}
+
+__global__ void kf_src_rad(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    src_rad_body(g, r.i0, CP(double *, out0), bid);
+}
+
+__global__ void kf_ctr_rad(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    ctr_rad_body(g, r.i0, CP(double *, out0), bid);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(64) kf_p2m(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    p2m_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(const double *, in3),
+                 CP(cd *, out0), r.i0, bid);
+}
+
+__global__ void __launch_bounds__(256 * M2M_KS) kf_m2m(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    m2m_mfma_body(g, r.nd, r.i0, CP(const TTile *, in0), CP(const int *, in1), CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(1024) kf_m2l(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    m2l_mfma_body(g, r.nd, CP(const M2LTile *, in0), CP(const cd *, in1), CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(64) kf_m2l_direct(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    m2l_mfma_direct_body(g, r.nd, CP(const M2LTile *, in0), r.i0, CP(const cd *, in1), CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(64) kf_m2l32(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    m2l_mfma32_body(g, r.nd, CP(const M2LTile *, in0), r.i0, CP(const cd *, in1), CP(cd *, out0), bid);
+}
+
+__global__ void kf_down(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    down_body(g, r.nd, r.i0, CP(const cd *, in0), CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(64 * L2L_KS) kf_l2l(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    l2l_mfma_body(g, r.nd, r.i0, CP(const TTile *, in0), CP(const int *, in1), CP(const cd *, in2),
+                  CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(64 * L2L_KS) kf_l2l32(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    l2l_mfma32_body(g, r.nd, r.i0, CP(const TTile *, in0), CP(const cd *, in2), CP(cd *, out0), bid);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(64) kf_p2l_x(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    p2l_x_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(cd *, out0), r.i0, bid);
+}
+
+template <int PB>
+__global__ void __launch_bounds__(P2Q_THREADS) kf_p2qbxl(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    p2qbxl_body<PB>(g, r.nd, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(cd *, out0), bid);
+}
+
+template <int PB>
+__global__ void __launch_bounds__(64) kf_p2qbxl_direct(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    p2qbxl_direct_body<PB>(g, r.nd, r.i0, CP(const cd *, in0), CP(const cd *, in1), CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(256) kf_m2qbxl(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    m2qbxl_body(g, r.nd, CP(const int2 *, in0), CP(const long long *, in1), CP(const cd *, in2), CP(cd *, out0),
+                r.i0, bid);
+}
+
+__global__ void kf_wsum(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    wsum_body(g, r.nd, CP(const int *, in0), CP(const int *, in1), CP(const long long *, in2), CP(const cd *, in3),
+              CP(cd *, out0), bid);
+}
+
+__global__ void __launch_bounds__(256) kf_l2qbxl(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    l2qbxl_body(g, r.nd, CP(const int *, in0), CP(const double *, in1), CP(const cd *, in2), CP(cd *, out0), r.i0,
+                bid);
+}
+
+__global__ void kf_eval(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    qbx_eval_body(g, r.nd, CP(const cd *, in0), CP(cd *, out0), bid);
+}
+
+__global__ void kf_smooth(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    smooth_body(g, r.nd, CP(const cd *, in0), CP(const cd *, in1), CP(cd *, out0), bid);
+}
+
+#undef CP
+#undef FUSED_BEGIN
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -1699,6 +1965,311 @@ hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hi
     k_coef_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, nd, coef, out);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
+}
+
+
+// ---------------------------------------------------------------------------
+// Fused-launch planning.  Record fields per stage, besides g and nd (item
+// sizes n, P, aux in brackets):
+//   FILL           out0 = array, n64 = elements                      [n = elements]
+//   CHARGES        in0 = sigma_S, in1 = sigma_D, out0 = qS, out1 = qD
+//   SRC_RAD        i0 = rows, out0 = J table                         [n = P2M leaves]
+//   CTR_RAD        i0 = rows, out0 = J table                         [n = L2QBXL leaves]
+//   P2M            in0 = leaf list, in1 = qS, in2 = qD, in3 = J table, out0 = multipoles  [n, P]
+//   M2M            i0 = level, in0 = its tiles, in1 = parent list, out0 = multipoles   [n = tiles, aux = row blocks]
+//   M2L            in0 = tiles, in1 = multipoles, out0 = pair rows  [n = tiles, P, aux = waves per tile]
+//   DOWN           i0 = level, in0 = pair rows, out0 = locals        [n = boxes of the level]
+//   L2L            i0 = level, in0 = its tiles, in1 = child list, in2 = pair rows, out0 = locals  [n, aux = row blocks]
+//   P2L_X          in0 = box list, in1 = qS, in2 = qD, out0 = locals [n, P]
+//   P2QBXL         in0 = leaf list, in1 = qS, in2 = qD, out0 = coefficients  [n]
+//   P2QBXL_DIRECT  in0 = qS, in1 = qD, out0 = coefficients
+//   M2QBXL         in0 = pairs, in1 = pair row offsets, in2 = multipoles, out0 = pair rows  [n = pairs, P = largest W order]
+//   WSUM           in0 = leaf list, in1 = per-leaf first pair, in2 = pair row offsets, in3 = pair rows,
+//                  out0 = coefficients                               [n = leaves]
+//   L2QBXL         in0 = leaf list, in1 = J table, in2 = locals, out0 = coefficients  [n, P, aux = J table rows]
+//   EVAL           in0 = coefficients, out0 = u
+//   SMOOTH         in0 = qS, in1 = qD, out0 = u
+// Per geometry, pass sizes, centre groups and tile shapes are those of its
+// own launch; block size and LDS are the largest any geometry needs.
+// ---------------------------------------------------------------------------
+namespace {
+
+int p2q_bucket(int p)
+{
+    return p <= 8 ? 8 : p <= 12 ? 12 : p <= 14 ? 14 : p <= 16 ? 16 : p <= 24 ? 24 : p <= 32 ? 32 : 40;
+}
+
+size_t p2qbxl_lds(int PB)
+{
+    return sizeof(cd) * (32 * (2 * (size_t)PB + 1) + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
+}
+
+// Appends one launch: records (first block filled in) and the block map.
+// Returns its index, -1 without blocks, -2 when the grid is too large.
+int fb_add(FBuf &fb, int kind, int variant, int threads, size_t lds, std::vector<FRec> recs,
+           const std::vector<long long> &blocks)
+{
+    long long total = 0;
+    for (size_t i = 0; i < recs.size(); ++i) {
+        recs[i].first = (int)total;
+        total += blocks[i];
+        if (total > 0x7fffffffLL) return -2;
+    }
+    if (total == 0) return -1;
+    auto align = [&](size_t a) { fb.bytes.resize((fb.bytes.size() + a - 1) / a * a, 0); };
+    align(256);
+    FLaunch L{kind, variant, threads, (int)total, lds, fb.bytes.size(), 0};
+    size_t rb = recs.size() * sizeof(FRec);
+    fb.bytes.resize(L.rec_off + rb);
+    std::memcpy(fb.bytes.data() + L.rec_off, recs.data(), rb);
+    align(256);
+    L.map_off = fb.bytes.size();
+    fb.bytes.resize(L.map_off + (size_t)total * sizeof(int));
+    int *m = reinterpret_cast<int *>(fb.bytes.data() + L.map_off);
+    for (size_t i = 0; i < recs.size(); ++i)
+        for (long long b = 0; b < blocks[i]; ++b) *m++ = (int)i;
+    fb.launches.push_back(L);
+    return (int)fb.launches.size() - 1;
+}
+
+}  // namespace
+
+hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::vector<int> &ids)
+{
+    struct Row {
+        int kind, variant, threads;
+        FRec r;
+        long long blocks;
+        size_t lds;
+    };
+    std::vector<Row> rows;
+    auto add = [&](int k, int v, FRec r, long long blocks, long long nx, size_t lds, int threads) {
+        if (blocks <= 0) return;
+        r.nx = (int)std::max<long long>(nx, 1);
+        rows.push_back({k, v, threads, r, blocks, lds});
+    };
+    switch (kind) {
+    case FK_FILL:
+        for (const auto &it : items) {
+            FRec r = it.r;
+            r.n64 = it.n;
+            long long b = std::min<long long>((it.n + 255) / 256, 1024);
+            add(kind, 0, r, b, b, 0, 256);
+        }
+        break;
+    case FK_CHARGES:
+        for (const auto &it : items) {
+            long long b = ((long long)it.r.nd * it.h->ns + 255) / 256;
+            add(kind, 0, it.r, b, b, 0, 256);
+        }
+        break;
+    case FK_SRC_RAD:
+    case FK_CTR_RAD: {
+        int rmax = 1;
+        for (const auto &it : items) rmax = std::max(rmax, it.r.i0);
+        int lanes = rad_lanes(rmax);
+        size_t lds = (size_t)rmax * lanes * sizeof(double);
+        for (const auto &it : items) {
+            long long cnt = it.n > 0 ? (kind == FK_SRC_RAD ? it.h->ns : it.h->nc) : 0;
+            long long b = (cnt + lanes - 1) / lanes;
+            add(kind, 0, it.r, b, b, lds, lanes);
+        }
+        break;
+    }
+    case FK_P2M:
+        for (const auto &it : items) {
+            int nd = it.r.nd;
+            if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+            int ch = 64;
+            while (ch > 1 && p2m_lds_bytes(4, it.P, ch) > PT_LDS) --ch;
+            FRec r = it.r;
+            r.i0 = ch;
+            add(kind, nd, r, it.n, it.n, p2m_lds_bytes(nd, it.P, ch), 64);
+        }
+        break;
+    case FK_M2M:
+        for (const auto &it : items) add(kind, 0, it.r, it.n * it.aux, it.n, 0, 256 * M2M_KS);
+        break;
+    case FK_M2L: {
+        int nw = 0;
+        size_t lmax = 0;
+        for (const auto &it : items)
+            if (!it.h->far32) {
+                nw = std::max(nw, std::min(it.aux, 16));
+                lmax = std::max(lmax, sizeof(cd) * 4 * ((2 * (size_t)it.P + 1 + 3) / 4) * M2L_XS);
+            }
+        bool staged = nw > 0 && lmax <= LDS_BUDGET;
+        for (const auto &it : items) {
+            int nrmax = (2 * it.P + 1 + 15) / 16;
+            FRec r = it.r;
+            r.i0 = nrmax;
+            if (it.h->far32) add(FK_M2L32, 0, r, it.n * nrmax, it.n * nrmax, 0, 64);
+            else if (staged) add(FK_M2L, 0, r, it.n, it.n, lmax, 64 * nw);
+            else add(FK_M2L_DIRECT, 0, r, it.n * nrmax, it.n * nrmax, 0, 64);
+        }
+        break;
+    }
+    case FK_DOWN:
+        for (const auto &it : items) add(kind, 0, it.r, it.n, it.n, 0, 256);
+        break;
+    case FK_L2L:
+        for (const auto &it : items)
+            add(it.h->far32 ? FK_L2L32 : FK_L2L, 0, it.r, it.n * it.aux, it.n, 0, 64 * L2L_KS);
+        break;
+    case FK_P2L_X:
+        for (const auto &it : items) {
+            int nd = it.r.nd;
+            if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+            int ch = pick_ch(it.P);
+            size_t lds = ptab_lds_bytes(nd, it.P, ch);
+            if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+            FRec r = it.r;
+            r.i0 = ch;
+            add(kind, nd, r, it.n, it.n, lds, 64);
+        }
+        break;
+    case FK_P2QBXL:
+        for (const auto &it : items) {
+            int pb = p2q_bucket(it.h->p);
+            add(kind, pb, it.r, it.n, it.n, p2qbxl_lds(pb), P2Q_THREADS);
+        }
+        break;
+    case FK_P2QBXL_DIRECT:
+        for (const auto &it : items) {
+            FRec r = it.r;
+            r.i0 = 4;
+            long long b = (it.h->nc + 3) / 4;
+            add(kind, p2q_bucket(it.h->p), r, b, b, 0, 64);
+        }
+        break;
+    case FK_M2QBXL:
+        for (const auto &it : items) {
+            int cg = QCG_MAX;
+            while (cg > 1 && m2qbxl_lds_bytes(it.r.nd, it.P, it.h->p, cg) > LDS_BUDGET) cg >>= 1;
+            size_t lds = m2qbxl_lds_bytes(it.r.nd, it.P, it.h->p, cg);
+            if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+            FRec r = it.r;
+            r.i0 = cg;
+            long long ny = (it.h->max_leaf_ctr + cg - 1) / cg;
+            add(kind, 0, r, it.n * ny, it.n, lds, 256);
+        }
+        break;
+    case FK_WSUM:
+        for (const auto &it : items) add(kind, 0, it.r, it.n, it.n, 0, 256);
+        break;
+    case FK_L2QBXL:
+        for (const auto &it : items) {
+            if (it.P + it.h->p + QBLK > it.aux) return hipErrorInvalidValue;
+            int cg = pick_cg(l2qbxl_lds_bytes, it.r.nd, it.P, it.h->p);
+            size_t lds = l2qbxl_lds_bytes(it.r.nd, it.P, it.h->p, cg);
+            if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+            FRec r = it.r;
+            r.i0 = cg;
+            add(kind, 0, r, it.n, it.n, lds, 256);
+        }
+        break;
+    case FK_EVAL:
+        for (const auto &it : items) {
+            long long b = ((long long)it.h->nt + 255) / 256;
+            add(kind, 0, it.r, b, b, 0, 256);
+        }
+        break;
+    case FK_SMOOTH:
+        for (const auto &it : items) {
+            long long b = ((long long)it.h->n_smooth + 127) / 128;
+            add(kind, 0, it.r, b, b, 0, 128);
+        }
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    // one launch per (kernel, variant), in order of first appearance
+    std::vector<char> done(rows.size(), 0);
+    for (size_t i = 0; i < rows.size(); ++i) {
+        if (done[i]) continue;
+        std::vector<FRec> recs;
+        std::vector<long long> blocks;
+        size_t lds = 0;
+        for (size_t j = i; j < rows.size(); ++j)
+            if (!done[j] && rows[j].kind == rows[i].kind && rows[j].variant == rows[i].variant) {
+                done[j] = 1;
+                recs.push_back(rows[j].r);
+                blocks.push_back(rows[j].blocks);
+                lds = std::max(lds, rows[j].lds);
+            }
+        int id = fb_add(fb, rows[i].kind, rows[i].variant, rows[i].threads, lds, recs, blocks);
+        if (id == -2) return hipErrorInvalidValue;
+        if (id >= 0) ids.push_back(id);
+    }
+    return hipSuccess;
+}
+
+hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t s)
+{
+    const FRec *recs = reinterpret_cast<const FRec *>(dev + L.rec_off);
+    const int *map = reinterpret_cast<const int *>(dev + L.map_off);
+    dim3 grid((unsigned)L.nblocks), block((unsigned)L.threads);
+    size_t lds = L.lds;
+#define FL(...) __VA_ARGS__<<<grid, block, lds, s>>>(recs, map)
+    switch (L.kind) {
+    case FK_FILL: FL(kf_fill); break;
+    case FK_CHARGES: FL(kf_charges); break;
+    case FK_SRC_RAD: FL(kf_src_rad); break;
+    case FK_CTR_RAD: FL(kf_ctr_rad); break;
+    case FK_P2M:
+        switch (L.variant) {
+        case 1: FL(kf_p2m<1>); break;
+        case 2: FL(kf_p2m<2>); break;
+        case 3: FL(kf_p2m<3>); break;
+        default: FL(kf_p2m<4>); break;
+        }
+        break;
+    case FK_M2M: FL(kf_m2m); break;
+    case FK_M2L: FL(kf_m2l); break;
+    case FK_M2L_DIRECT: FL(kf_m2l_direct); break;
+    case FK_M2L32: FL(kf_m2l32); break;
+    case FK_DOWN: FL(kf_down); break;
+    case FK_L2L: FL(kf_l2l); break;
+    case FK_L2L32: FL(kf_l2l32); break;
+    case FK_P2L_X:
+        switch (L.variant) {
+        case 1: FL(kf_p2l_x<1>); break;
+        case 2: FL(kf_p2l_x<2>); break;
+        case 3: FL(kf_p2l_x<3>); break;
+        default: FL(kf_p2l_x<4>); break;
+        }
+        break;
+    case FK_P2QBXL:
+        switch (L.variant) {
+        case 8: FL(kf_p2qbxl<8>); break;
+        case 12: FL(kf_p2qbxl<12>); break;
+        case 14: FL(kf_p2qbxl<14>); break;
+        case 16: FL(kf_p2qbxl<16>); break;
+        case 24: FL(kf_p2qbxl<24>); break;
+        case 32: FL(kf_p2qbxl<32>); break;
+        default: FL(kf_p2qbxl<40>); break;
+        }
+        break;
+    case FK_P2QBXL_DIRECT:
+        switch (L.variant) {
+        case 8: FL(kf_p2qbxl_direct<8>); break;
+        case 12: FL(kf_p2qbxl_direct<12>); break;
+        case 14: FL(kf_p2qbxl_direct<14>); break;
+        case 16: FL(kf_p2qbxl_direct<16>); break;
+        case 24: FL(kf_p2qbxl_direct<24>); break;
+        case 32: FL(kf_p2qbxl_direct<32>); break;
+        default: FL(kf_p2qbxl_direct<40>); break;
+        }
+        break;
+    case FK_M2QBXL: FL(kf_m2qbxl); break;
+    case FK_WSUM: FL(kf_wsum); break;
+    case FK_L2QBXL: FL(kf_l2qbxl); break;
+    case FK_EVAL: FL(kf_eval); break;
+    case FK_SMOOTH: FL(kf_smooth); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FL
+    return hipGetLastError();
 }
 
 }  // namespace qbx

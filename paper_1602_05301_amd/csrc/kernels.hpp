@@ -3,61 +3,81 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "devmath.hpp"
 
 namespace qbx {
+
+// Pointers into device memory.  In the kernels' device code they carry the
+// global address space, as a kernel's own pointer arguments do, also when
+// the view is read from memory (fused launches): loads through them stay
+// scalar or global, never flat.  Host code sees plain pointers; the layout
+// is the same.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(QBX_KERNELS_TU)
+#define QBX_G __attribute__((address_space(1)))
+#else
+#define QBX_G
+#endif
 
 // All pointers are device pointers.  Points are in tree (Morton) order.
 struct DevGeom {
     int ns, nc, nt, nb, nlev, p, n_smooth;
     int max_leaf_ctr;                          // most centres in one leaf
     double omega;
-    const double *sx, *sy, *sw, *snx, *sny;   // sorted sources
-    const int *src_perm;                       // sorted -> user source index
-    const double *cx, *cy;                     // sorted centres
-    const int *ctr_perm;                       // sorted -> user centre index
-    const double *tx, *ty;                     // targets, user order
-    const int *tgt_cs;                         // per target: sorted centre or -1
-    const int *smooth_list;                    // targets served by the smooth rule
-    const double *bcx, *bcy;                   // box centres
-    const int *blev, *leaf, *parent, *child_begin, *child_count;
-    const int *src_begin, *src_end, *ctr_begin, *ctr_end;
-    const int *level_start;
-    const int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
+    const QBX_G double *sx, *sy, *sw, *snx, *sny;   // sorted sources
+    const QBX_G int *src_perm;                       // sorted -> user source index
+    const QBX_G double *cx, *cy;                     // sorted centres
+    const QBX_G int *ctr_perm;                       // sorted -> user centre index
+    const QBX_G double *tx, *ty;                     // targets, user order
+    const QBX_G int *tgt_cs;                         // per target: sorted centre or -1
+    const QBX_G int *smooth_list;                    // targets served by the smooth rule
+    const QBX_G double *bcx, *bcy;                   // box centres
+    const QBX_G int *blev, *leaf, *parent, *child_begin, *child_count;
+    const QBX_G int *src_begin, *src_end, *ctr_begin, *ctr_end;
+    const QBX_G int *level_start;
+    const QBX_G int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
     // near list of a leaf = U list + W boxes summed directly; far W = the rest
-    const int *near_start, *near_idx, *wf_start, *wf_idx;
+    const QBX_G int *near_start, *near_idx, *wf_start, *wf_idx;
     // near-list sources of the i-th leaf of the P2QBXL list: qsrc_idx[qsrc_start[i]..]
-    const int *qsrc_start, *qsrc_idx;
+    const QBX_G int *qsrc_start, *qsrc_idx;
     // X-list sources of the i-th box of the X-list P2L list: xsrc_idx[xsrc_start[i]..]
-    const int *xsrc_start, *xsrc_idx;
-    const int *src_box, *ctr_box;              // leaf (level >= 2) of each source / centre, or -1
-    const int *Plev;                           // FMM order per level
-    const int *Woff;                           // per level offset into Wtab/invW/logW
-    const double *Wtab, *invW, *logW;
-    const long long *box_off;                  // per box, in coefficients of one density
+    const QBX_G int *xsrc_start, *xsrc_idx;
+    const QBX_G int *src_box, *ctr_box;              // leaf (level >= 2) of each source / centre, or -1
+    const QBX_G int *Plev;                           // FMM order per level
+    const QBX_G int *Woff;                           // per level offset into Wtab/invW/logW
+    const QBX_G double *Wtab, *invW, *logW;
+    const QBX_G long long *box_off;                  // per box, in coefficients of one density
     // M2M / L2L scaled matrices per (parent level, child quadrant) in MFMA
     // A-operand order; child4[b*4+q] = child of b in quadrant q or -1
-    const cd *m2m_mf, *l2l_mf;
-    const long long *m2m_mf_off, *l2l_mf_off;  // [level*4+q]
-    const int *child4;
+    const QBX_G cd *m2m_mf, *l2l_mf;
+    const QBX_G long long *m2m_mf_off, *l2l_mf_off;  // [level*4+q]
+    const QBX_G int *child4;
     // per position of the M2M parent list: children's box_off by quadrant
     // (-1 = none) and the parent's; per position of the L2L child list: the
     // parent's and the child's box_off, the vy row of its first V-list entry
     // and the entry count (the entries' rows follow each other)
-    const long long *m2m_coff, *m2m_poff;
-    const long long *l2l_poff, *l2l_coff, *l2l_vy0;
-    const int *l2l_nv;
+    const QBX_G long long *m2m_coff, *m2m_poff;
+    const QBX_G long long *l2l_poff, *l2l_coff, *l2l_vy0;
+    const QBX_G int *l2l_nv;
     // M2L as batched GEMM: per (level, offset) matrices in MFMA tile order,
     // V-list positions grouped by (level, offset), per-position output offsets.
-    const cd *m2l_mf;                          // tiled scaled M2L matrices
+    const QBX_G cd *m2l_mf;                          // tiled scaled M2L matrices
     // FP32 far field (eps >= 1e-6): M2L and L2L tables in complex float, same
     // tile order and offsets as the FP64 ones; null when off
     int far32;
-    const cf *m2l_mf32, *l2l_mf32;
-    const long long *m2l_mf_off;               // [level*40+o]
-    const int *vpair_sorted;                   // V-list positions sorted by (level, offset)
-    const long long *vy_off;                   // per V-list position: output row offset
-    const long long *m2l_src, *m2l_dst;        // per sorted position: box_off of the source, vy_off
+    const QBX_G cf *m2l_mf32, *l2l_mf32;
+    const QBX_G long long *m2l_mf_off;               // [level*40+o]
+    const QBX_G int *vpair_sorted;                   // V-list positions sorted by (level, offset)
+    const QBX_G long long *vy_off;                   // per V-list position: output row offset
+    const QBX_G long long *m2l_src, *m2l_dst;        // per sorted position: box_off of the source, vy_off
+};
+
+// Block index of a workgroup within one geometry's part of a launch: x
+// fastest, y above it, nx = blocks along x.  A single-geometry launch passes
+// (blockIdx.x, blockIdx.y, gridDim.x).
+struct BlockId {
+    int x, y, nx;
 };
 
 // One M2M / L2L GEMM tile: up to 16 (box, density) columns taken from a box
@@ -76,6 +96,58 @@ struct M2LTile {
     int col0;         // first column of the tile within the group
     int ncol;         // columns in this tile (<= 16)
 };
+
+// ---------------------------------------------------------------------------
+// Fused launches: one grid per stage over several geometries.  The grid is
+// the concatenation of each geometry's own grid for the stage; map[block]
+// names the record of the geometry a block belongs to, and the record holds
+// that geometry's arguments and its first block.  A block then runs the same
+// body as in the geometry's own launch, with its local block index, so each
+// geometry's results are bitwise those of its own launch.
+// ---------------------------------------------------------------------------
+struct FRec {
+    const DevGeom *g;          // device copy of the geometry's view
+    int first, nx;             // first block of the geometry in the grid; its blocks along x
+    int nd, i0;                // densities per column; a stage integer (level, pass size, ...)
+    long long n64;             // a count (fill)
+    const QBX_G void *in0, *in1, *in2, *in3;
+    QBX_G void *out0, *out1;
+};
+
+enum FKind {
+    FK_FILL, FK_CHARGES, FK_SRC_RAD, FK_CTR_RAD, FK_P2M, FK_M2M, FK_M2L, FK_DOWN, FK_L2L, FK_P2L_X,
+    FK_P2QBXL, FK_P2QBXL_DIRECT, FK_M2QBXL, FK_WSUM, FK_L2QBXL, FK_EVAL, FK_SMOOTH,
+    // chosen by the planner
+    FK_M2L_DIRECT, FK_M2L32, FK_L2L32
+};
+
+// One geometry's part of a stage, as the host describes it.  The record's
+// g, nd, i0, in*, out* are the stage's arguments (their meaning per stage is
+// listed at fused_plan); n, P and aux size the geometry's grid.
+struct FItem {
+    const DevGeom *h;          // host copy of the geometry's view
+    FRec r;
+    long long n;               // work items (boxes, tiles, pairs, elements)
+    int P;                     // largest expansion order involved
+    int aux;                   // row blocks (M2M, L2L), waves per tile (M2L), rows (L2QBXL check)
+};
+
+struct FLaunch {
+    int kind, variant, threads, nblocks;
+    size_t lds, rec_off, map_off;
+};
+
+// Records and block maps of a set of fused launches, uploaded in one copy.
+struct FBuf {
+    std::vector<unsigned char> bytes;
+    std::vector<FLaunch> launches;
+};
+
+// Appends the launches of one stage (one per kernel variant the items need,
+// none if they have no work) and their indices to ids.
+hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::vector<int> &ids);
+// Launches fb.launches[i] with its records at dev (the device copy of fb.bytes).
+hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t s);
 
 hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
 hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,

@@ -148,6 +148,32 @@ def concat(geoms) -> Geometry:
                     meta=dict(kind="multi", parts=[g.meta for g in geoms]))
 
 
+def batched_geometries(n: int = 256, workload_id: int = 3, nodes=(512, 16384),
+                       omega=(5.0, 150.0)):
+    """Independent curves of uneven size for batched evaluation: even
+    indices stars (3-9 lobes, amplitude 0.3), odd indices ellipses (aspect
+    ratio uniform in [1, 10]); node counts log-uniform in `nodes`, rounded
+    to whole 16-node panels; omega uniform in `omega`.  Each curve is scaled
+    by min(1, 5 n_panels / (omega L_1)), L_1 its perimeter at unit scale, so
+    that omega times the mean panel length stays at most 5.  Returns a list
+    of (Geometry, omega)."""
+    rng = rng_for(workload_id, 0)
+    out = []
+    for i in range(n):
+        nn = float(np.exp(rng.uniform(np.log(nodes[0]), np.log(nodes[1]))))
+        npan = max(2, int(round(nn / 16)))
+        w = float(rng.uniform(*omega))
+        if i % 2 == 0:
+            lobes = int(rng.integers(3, 10))
+            make = lambda sc: star(npan, 16, lobes=lobes, amp=0.3, radius=sc)
+        else:
+            ar = float(rng.uniform(1.0, 10.0))
+            make = lambda sc: ellipse(npan, 16, a=sc, b=sc / ar)
+        L1 = float(np.sum(make(1.0).w))
+        out.append((make(min(1.0, 5.0 * npan / (w * L1))), w))
+    return out
+
+
 def annulus_targets(rng: np.random.Generator, n: int, r_in: float, r_out: float):
     """Area-uniform points in r_in < |x| < r_out."""
     rho = np.sqrt(rng.uniform(r_in ** 2, r_out ** 2, size=n))

@@ -212,7 +212,7 @@ class Context:
             self._h = None
 
     def eval_batch(self, geoms, sigmas_s, sigmas_d, us):
-        """One evaluation per geometry, overlapped on the device (qbx_eval_batch).
+        """One evaluation per geometry, every stage one launch over all of them (qbx_eval_batch).
         sigmas_s[i] / sigmas_d[i]: [n_dens_i, n_src_i] complex128 CUDA tensors or
         None; us[i]: [n_dens_i, n_tgt_i] outputs."""
         n = len(geoms)

@@ -9,7 +9,7 @@ released only when matvec k has completed.  The server
   that setup overlaps the GPU work of requests already admitted;
 * in every step, takes the next matvec of every admitted request whose
   previous matvec is done and evaluates them together with one
-  ``qbx_eval_batch`` call (their work overlaps on the device);
+  ``qbx_eval_batch`` call (each FMM stage one launch over all of them);
 * frees a request's geometry when its last matvec completes.
 
 Results are bitwise the same as evaluating each request alone (the batch
@@ -216,6 +216,59 @@ def batch_vs_sequential(ctx, n_geom: int = 16, rounds: int = 10, max_nodes: int 
             "batched_targets_x_densities_per_s": work / bat}
 
 
+def batched_workload(ctx, n_geom: int = 256, eps: float = 1e-10, n_dens: int = 4, rounds: int = 3,
+                     setup_threads: int = 8) -> dict:
+    """The batched workload: n_geom independent star and ellipse curves of
+    512-16384 nodes (inputs.batched_geometries), n_dens seeded Gaussian
+    densities each, all geometries resident.  Times one qbx_eval_batch over
+    all of them against qbx_eval on each in turn (the plain per-request
+    path), both with inputs already in HBM.  eps >= 1e-6 runs the FP32 far
+    field (p = 9), else FP64 throughout (p = 14)."""
+    import torch
+    from . import qbx
+    far32 = eps >= 1e-6
+    p = 9 if far32 else 14
+    curves = inputs.batched_geometries(n_geom)
+    dr = inputs.rng_for(3, 2)
+    dens = [inputs.complex_gaussian(dr, (n_dens, g.n)) for g, _ in curves]
+
+    def build(item):
+        g, w = item
+        return qbx.Geometry(ctx, g, w, eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32),
+                            qbx.options(p=p, far_fp32=far32))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=setup_threads) as pool:
+        geos = list(pool.map(build, curves))
+    setup = time.perf_counter() - t0
+    s = [torch.from_numpy(d).cuda() for d in dens]
+    u = [torch.empty_like(x) for x in s]
+    ub = [torch.empty_like(x) for x in s]
+    for g, x, y in zip(geos, s, u):                  # warm-up: scratch, tiles, kernels
+        g.eval(x, x, u=y)
+    ctx.eval_batch(geos, s, s, ub)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(u, ub))
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        for g, x, y in zip(geos, s, u):
+            g.eval(x, x, u=y)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) / rounds
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        ctx.eval_batch(geos, s, s, ub)
+    torch.cuda.synchronize()
+    bat = (time.perf_counter() - t0) / rounds
+    work = sum(g.n * n_dens for g, _ in curves)
+    nodes = np.array([g.n for g, _ in curves])
+    return {"geometries": n_geom, "densities_each": n_dens, "eps": eps, "far_fp32": far32, "p": p,
+            "nodes_total": int(nodes.sum()), "nodes_min": int(nodes.min()), "nodes_max": int(nodes.max()),
+            "setup_s": setup, "batched_ms": bat * 1e3, "one_by_one_ms": seq * 1e3,
+            "batched_targets_x_densities_per_s": work / bat,
+            "one_by_one_targets_x_densities_per_s": work / seq,
+            "batched_equals_alone": bool(same)}
+
+
 def _poisson(reqs, qps: float, seed: int = 7):
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -230,10 +283,16 @@ def main(argv=None) -> int:
     ap.add_argument("--max-nodes", type=int, default=32768)
     ap.add_argument("--qps-fracs", default="0.5,0.8,0.95")
     ap.add_argument("--hbm-gib", type=float, default=64.0)
+    ap.add_argument("--batched", action="store_true",
+                    help="only the batched workload (256 geometries, 4 densities, eps 1e-10 and 1e-6)")
     args = ap.parse_args(argv)
     import torch
     from . import qbx
     ctx = qbx.Context(0)
+    if args.batched:
+        out = {"batched": [batched_workload(ctx, eps=e) for e in (1e-10, 1e-6)]}
+        print(json.dumps(out), flush=True)
+        return 0
     budget = args.hbm_gib * 2 ** 30
     # warm-up: library, kernels, one small request each way
     w = make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2))

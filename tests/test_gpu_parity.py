@@ -276,6 +276,45 @@ def test_batch_matches_each_alone(ctx):
         assert np.array_equal(us[k].cpu().numpy(), alone[k]), (k, i)
 
 
+def test_batch_mixed_modes_match_alone(ctx):
+    """Geometries that need different kernel variants in one batch: FP32 and
+    FP64 far fields, different p, a direct-mode geometry whose off-curve
+    targets partly use the smooth rule, and six densities (two passes).
+    Each result equals the geometry evaluated alone, bit for bit."""
+    from paper_1602_05301_amd import qbx
+    r = np.random.default_rng(23)
+    geos, ss, sd = [], [], []
+
+    def add(g, omega, eps, nd, tx=None, ty=None, tc="own", **opt):
+        if tx is None:
+            tx, ty = g.sx, g.sy
+        tgt = np.arange(g.n, dtype=np.int32) if isinstance(tc, str) else tc
+        geos.append(qbx.Geometry(ctx, g, omega, eps, tx, ty, tgt, qbx.options(**opt)))
+        ss.append(_dev(inputs.complex_gaussian(r, (nd, g.n))))
+        sd.append(_dev(inputs.complex_gaussian(r, (nd, g.n))))
+
+    add(inputs.star(80, 16, lobes=4), 70.0, 1e-6, 2, p=9, far_fp32=True)
+    add(inputs.star(48, 16, lobes=6), 25.0, 1e-10, 6, p=14)
+    add(inputs.ellipse(64, 16, a=1.0, b=0.4), 40.0, 1e-6, 3, p=9)
+    gd = inputs.star(24, 16, lobes=5)
+    tx_a, ty_a = inputs.annulus_targets(r, 150, 1.4, 2.0)
+    j = r.integers(0, gd.n, 100)
+    s = r.uniform(0.05, 0.6, j.size) * gd.h[j]
+    add(gd, 10.0, 1e-10, 1, np.concatenate([gd.sx[j] + s * gd.nx[j], tx_a]),
+        np.concatenate([gd.sy[j] + s * gd.ny[j], ty_a]), None, p=12, direct=1)
+    add(inputs.star(160, 16, lobes=8), 120.0, 1e-6, 4, p=9, far_fp32=True)
+    alone = [g.eval(a, b).cpu().numpy() for g, a, b in zip(geos, ss, sd)]
+    us = [torch.empty((a.shape[0], g.n_tgt), dtype=torch.complex128, device="cuda:0")
+          for g, a in zip(geos, ss)]
+    for rep in range(2):
+        for u in us:
+            u.zero_()
+        ctx.eval_batch(geos, ss, sd, us)
+        torch.cuda.synchronize()
+        for k in range(len(geos)):
+            assert np.array_equal(us[k].cpu().numpy(), alone[k]), (rep, k)
+
+
 def test_served_requests_equal_alone(ctx):
     """Continuous batching: requests of different sizes, omega and eps
     arriving while others run (chained matvecs, admission by an HBM budget
