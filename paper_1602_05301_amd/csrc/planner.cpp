@@ -537,7 +537,7 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
         // only add accuracy)
         pl.P[l] = std::max(pl.pfmm[l] + pl.p_add, pl.p + 8);
         if (pl.P[l] > kMaxOrder && l >= 2)
-            return {QBX_E_UNSUPPORTED, "FMM order at level " + std::to_string(l) + " exceeds 400 (omega * box size too large)"};
+            return {QBX_E_UNSUPPORTED, "FMM order at level " + std::to_string(l) + " exceeds 1024 (omega * box size too large)"};
         pl.P[l] = std::min(pl.P[l], kMaxOrder);
     }
     return {QBX_OK, ""};

@@ -14,7 +14,7 @@ namespace qbx {
 
 constexpr int kMaxLevel = 30;     // Morton coordinates carry 30 bits per axis
 constexpr int kMaxP = 40;         // QBX order limit
-constexpr int kMaxOrder = 400;    // FMM order limit
+constexpr int kMaxOrder = 1024;   // FMM order limit
 constexpr int kNumV = 40;         // V-list offsets: [-3,3]^2 minus [-1,1]^2
 
 struct Error {

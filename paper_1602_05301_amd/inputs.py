@@ -174,6 +174,142 @@ def batched_geometries(n: int = 256, workload_id: int = 3, nodes=(512, 16384),
     return out
 
 
+def _shape(kind, rad, par, rot, center):
+    """Position, first and second theta-derivatives of a star (par = lobes,
+    amplitude 0.3, r = rad (1 + 0.3 cos(par t))) or an ellipse (par = aspect
+    ratio, semi-axes rad and rad / par), rotated and moved to center."""
+    c0, s0 = np.cos(rot), np.sin(rot)
+
+    def place(x, y, shift):
+        return (shift * center[0] + c0 * x - s0 * y, shift * center[1] + s0 * x + c0 * y)
+
+    if kind == "star":
+        k, a = par, 0.3
+
+        def f(t, d):
+            r = rad * (1 + a * np.cos(k * t))
+            r1 = -rad * a * k * np.sin(k * t)
+            r2 = -rad * a * k * k * np.cos(k * t)
+            c, sn = np.cos(t), np.sin(t)
+            if d == 0:
+                return place(r * c, r * sn, 1.0)
+            if d == 1:
+                return place(r1 * c - r * sn, r1 * sn + r * c, 0.0)
+            return place(r2 * c - 2 * r1 * sn - r * c, r2 * sn + 2 * r1 * c - r * sn, 0.0)
+    else:
+        A, B = rad, rad / par
+
+        def f(t, d):
+            c, sn = np.cos(t), np.sin(t)
+            if d == 0:
+                return place(A * c, B * sn, 1.0)
+            if d == 1:
+                return place(-A * sn, B * c, 0.0)
+            return place(-A * c, -B * sn, 0.0)
+    return f
+
+
+def _adaptive_edges(f, omega, c_curv, q=16, start=8):
+    """Theta panels of one closed curve, bisected until every panel has
+    omega h <= 5 and h kappa_max <= c_curv (h its arclength, kappa_max the
+    largest curvature at its nodes and ends), then until neighbouring panels
+    differ in length by at most a factor 2."""
+    x, wq = _gl(q)
+    xs = np.concatenate([[-1.0], x, [1.0]])
+
+    def measure(e):
+        a, b = e[:-1, None], e[1:, None]
+        half = 0.5 * (b - a)
+        t = 0.5 * (a + b) + half * xs[None, :]
+        dx, dy = f(t, 1)
+        ddx, ddy = f(t, 2)
+        sp = np.hypot(dx, dy)
+        h = (half[:, 0] * (wq[None, :] * sp[:, 1:-1]).sum(axis=1))
+        kap = np.abs(dx * ddy - dy * ddx) / sp ** 3
+        return h, kap.max(axis=1)
+
+    e = np.linspace(0.0, 2.0 * np.pi, start + 1)
+    while True:
+        h, km = measure(e)
+        split = (omega * h > 5.0) | (h * km > c_curv)
+        if not split.any():
+            break
+        mid = 0.5 * (e[:-1] + e[1:])[split]
+        e = np.sort(np.concatenate([e, mid]))
+    while True:
+        h, _ = measure(e)
+        hn = np.roll(h, -1)
+        hp = np.roll(h, 1)
+        split = (h > 2.0 * hn) | (h > 2.0 * hp)
+        if not split.any():
+            break
+        mid = 0.5 * (e[:-1] + e[1:])[split]
+        e = np.sort(np.concatenate([e, mid]))
+    return e
+
+
+def multiscale_curves(n_curves: int = 64, omega: float = 100.0, workload_id: int = 2,
+                      nodes=(570_000, 630_000), box: float = 10.0, gap: float = 0.5, q: int = 16):
+    """Many disjoint curves of different sizes and curvatures in
+    [-box, box]^2, as one discretisation: half ellipses (aspect ratio uniform
+    in [1, 10]), half stars (3-9 lobes, amplitude 0.3), circumradius uniform
+    in [0.5, 1.5], random rotation, placed largest first by rejection so that
+    each curve stays at least `gap` from the others (distance between 128
+    sample points per curve).  Panels are adaptive in theta (_adaptive_edges);
+    the curvature bound c is bisected until the total node count lies in
+    `nodes`.  Returns (Geometry, c)."""
+    rng = rng_for(workload_id, 0)
+    draws = []
+    for i in range(n_curves):
+        R = float(rng.uniform(0.5, 1.5))
+        if i % 2 == 0:
+            draws.append(("star", R / 1.3, int(rng.integers(3, 10)), R))
+        else:
+            draws.append(("ellipse", R, float(rng.uniform(1.0, 10.0)), R))
+    # largest first: later, smaller curves fill the gaps
+    draws.sort(key=lambda d: -d[3])
+    t = np.linspace(0.0, 2.0 * np.pi, 128, endpoint=False)
+    specs, placed = [], []          # placed: (centre, circumradius, sample points)
+    for i, (kind, rad, par, R) in enumerate(draws):
+        for _ in range(200000):
+            rot = float(rng.uniform(0.0, 2.0 * np.pi))
+            cen = rng.uniform(-box + R, box - R, size=2)
+            close = [q for c2, R2, q in placed if np.hypot(*(cen - c2)) < R + R2 + gap]
+            if not close:
+                break
+            px, py = _shape(kind, rad, par, rot, cen)(t, 0)
+            pts = np.stack([px, py], axis=1)
+            near = np.concatenate(close)
+            if ((pts[:, None, :] - near[None, :, :]) ** 2).sum(axis=2).min() >= gap * gap:
+                break
+        else:
+            raise RuntimeError("multiscale_curves: could not place curve %d" % i)
+        px, py = _shape(kind, rad, par, rot, cen)(t, 0)
+        placed.append((cen, R, np.stack([px, py], axis=1)))
+        specs.append((kind, rad, par, rot, (float(cen[0]), float(cen[1]))))
+
+    def build(c_curv):
+        parts = []
+        for kind, rad, par, rot, cen in specs:
+            f = _shape(kind, rad, par, rot, cen)
+            e = _adaptive_edges(f, omega, c_curv, q)
+            out = _panelize(e, q, lambda th: f(th, 0), lambda th: f(th, 1))
+            parts.append(_finish(*out, q, dict(kind=kind, rad=rad, par=par, n_panels=e.size - 1)))
+        return concat(parts)
+
+    lo, hi = 1e-3, 10.0          # curvature bounds giving too many / too few nodes
+    for _ in range(60):
+        c = float(np.sqrt(lo * hi))
+        g = build(c)
+        if g.n > nodes[1]:
+            lo = c
+        elif g.n < nodes[0]:
+            hi = c
+        else:
+            return g, c
+    raise RuntimeError("multiscale_curves: node target not reached")
+
+
 def annulus_targets(rng: np.random.Generator, n: int, r_in: float, r_out: float):
     """Area-uniform points in r_in < |x| < r_out."""
     rho = np.sqrt(rng.uniform(r_in ** 2, r_out ** 2, size=n))

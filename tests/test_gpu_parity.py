@@ -146,6 +146,29 @@ def test_fmm_full_size_sampled(ctx):
     assert err < wl.eps
 
 
+def test_fmm_multiscale_sampled(ctx):
+    """64 curves of different sizes and curvatures in [-10, 10]^2 with
+    adaptive panels, about 600k nodes = centres = targets, omega = 100,
+    eps = 1e-8, p = 12, leaves of up to 64 points: orders run from 54 at the
+    leaves to 425 at level 2.  Potentials at 128 sampled targets against the
+    oracle evaluated for exactly those targets' centres."""
+    g, _ = inputs.multiscale_curves()
+    r = inputs.rng_for(2, 2)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    sd = inputs.complex_gaussian(r, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    omega, eps, p = 100.0, 1e-8, 12
+    print(f"multiscale n={g.n}", flush=True)
+    _, u = _eval(ctx, g, omega, eps, g.sx, g.sy, tc, ss, sd, p=p, leaf_max=64)
+    pick = np.sort(np.random.default_rng(1).choice(g.n, 128, replace=False))
+    alpha = oracle.qbx_coefficients(omega, p, g.sx, g.sy, g.w, g.nx, g.ny, ss, sd, g.cx[pick], g.cy[pick])
+    ref = oracle.qbx_eval(omega, p, g.cx[pick], g.cy[pick], alpha, g.sx[pick], g.sy[pick],
+                          np.arange(pick.size, dtype=np.int32))
+    err = _rel(u[:, pick], ref)
+    print(f"multiscale sampled rel_l2={err:.3e}", flush=True)
+    assert err < eps
+
+
 def test_multi_density_chunks_and_determinism(ctx):
     g = inputs.star(64, 16, lobes=7)
     r = np.random.default_rng(5)
