@@ -1450,21 +1450,24 @@ qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
     bool prof = G->profile, graph = G->graph_on;
     G->profile = false;
     G->graph_on = false;
-    double best = 1e300;
-    int pick = nr;
-    for (int c : cand) {
-        G->m2l_nw = c;
-        float tot = 0.f;
-        bool ok = true;
-        for (int rep = 0; rep < 4 && ok; ++rep) {
-            ok = hipEventRecord(a, s) == hipSuccess &&
-                 eval_chunks(G, n_dens, dsig, nullptr, du, nullptr, s, G->ctx->lane) == QBX_OK &&
-                 hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    // rounds over the candidates in turn (drift of clocks and caches hits
+    // them alike); each keeps its fastest evaluation; round 0 warms up
+    constexpr int kRounds = 7;
+    std::vector<double> best_of(cand.size(), 1e300);
+    for (int rep = 0; rep < kRounds; ++rep)
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+            G->m2l_nw = cand[ci];
+            bool ok = hipEventRecord(a, s) == hipSuccess &&
+                      eval_chunks(G, n_dens, dsig, nullptr, du, nullptr, s, G->ctx->lane) == QBX_OK &&
+                      hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
             float ms = 0.f;
-            if (ok && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) tot += ms;   // rep 0 warms up
+            if (ok && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+                best_of[ci] = std::min(best_of[ci], (double)ms);
         }
-        if (ok && tot < best) { best = tot; pick = c; }
-    }
+    int pick = nr;
+    double best = 1e300;
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+        if (best_of[ci] < best) { best = best_of[ci]; pick = cand[ci]; }
     G->profile = prof;
     G->graph_on = graph;
     G->m2l_nw = pick;
