@@ -168,6 +168,14 @@ qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out);
 qbx_status qbx_geom_destroy(qbx_geom geom);
 qbx_status qbx_geom_stats(qbx_geom geom, qbx_stats *out);
 qbx_status qbx_geom_association(qbx_geom geom, int32_t *tgt_ctr_out);
+/* qbx_geom_bytes: device memory the geometry holds once it has evaluated
+ * n_dens densities: the resident part (points, tree, lists, tables) plus the
+ * evaluation scratch (charges, expansions, per-pair rows, radial sequences,
+ * coefficients), whether or not the scratch is allocated yet.  The scratch
+ * serves chunks of up to 4 densities, so the figure grows with n_dens only
+ * by the small GEMM tile lists of the chunk sizes used.  For admission by an
+ * HBM budget (a serving loop).  0 for a NULL geometry. */
+size_t qbx_geom_bytes(qbx_geom geom, int32_t n_dens);
 
 /* ---- per-stage timing and work ----------------------------------------------
  * Stages of one evaluation, in launch order (Sec. 7.2 stage names). */

@@ -1211,6 +1211,29 @@ qbx_status qbx_geom_stats(qbx_geom G, qbx_stats *out)
     return QBX_OK;
 }
 
+size_t qbx_geom_bytes(qbx_geom G, int32_t n_dens)
+{
+    if (!G) return 0;
+    const Plan &pl = G->pl;
+    const size_t nd = kDensChunk, cdb = sizeof(cd);
+    auto at1 = [](long long n) { return (size_t)std::max<long long>(n, 1); };
+    // as ensure_scratch allocates it
+    size_t scratch = 2 * cdb * nd * at1(pl.ns) + cdb * nd * (2 * pl.p + 1) * at1(pl.nc);
+    if (!pl.opt.direct) {
+        scratch += cdb * nd * (2 * at1(G->total_coef) + at1(G->total_vy) + at1(G->total_wy));
+        scratch += sizeof(double) * ((size_t)(G->p2m.Pmax + 2) * at1(pl.ns) + (size_t)(G->l2q.Pmax + pl.p + 8) * at1(pl.nc));
+        // GEMM tile lists of the chunk sizes an n_dens evaluation uses
+        for (int c = 1; c <= kDensChunk; ++c)
+            if (c == std::min(n_dens, kDensChunk) || (n_dens > kDensChunk && c == n_dens % kDensChunk)) {
+                size_t cols = 0;
+                for (const auto &grp : G->m2l_groups) cols += (size_t)grp.count * c / kM2LTileCols + 1;
+                scratch += sizeof(M2LTile) * cols +
+                           sizeof(TTile) * ((G->par_list.size() + 4 * G->chl_list.size()) * c / 16 + 8 * pl.nlev);
+            }
+    }
+    return G->arena.bytes + scratch;
+}
+
 qbx_status qbx_geom_association(qbx_geom G, int32_t *tgt_ctr_out)
 {
     if (!G || (!tgt_ctr_out && G->pl.nt)) return fail(QBX_E_INVAL, "null argument");

@@ -1323,6 +1323,8 @@ __global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_
 // (its phase is a running product), J_n comes from an LDS table filled by
 // Miller's recurrence, one lane per centre.
 // ---------------------------------------------------------------------------
+constexpr int L2Q_THREADS = 256;   // lanes per leaf (at least QCG_MAX)
+
 size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
 {
     int np = 2 * P + 1, N = P + p + QBLK - 1;
@@ -1368,7 +1370,7 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
         }
         __syncthreads();
         int items = nd * cnt * nblk;
-        for (int it0 = 0; it0 < items; it0 += 256 / QSPLIT) {
+        for (int it0 = 0; it0 < items; it0 += (int)blockDim.x / QSPLIT) {
             int it = it0 + tid / QSPLIT, sp = tid % QSPLIT;
             bool active = it < items;
             int t = active ? it % cnt : 0;
@@ -1444,7 +1446,7 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
     }
 }
 
-__global__ void __launch_bounds__(256) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG)
+__global__ void __launch_bounds__(L2Q_THREADS) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG)
 {
     l2qbxl_body(g, nd, list, crad, loc, coef, QCG, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
@@ -1695,7 +1697,7 @@ __global__ void kf_wsum(const FRec *recs, const int *map)
               CP(cd *, out0), bid);
 }
 
-__global__ void __launch_bounds__(256) kf_l2qbxl(const FRec *recs, const int *map)
+__global__ void __launch_bounds__(L2Q_THREADS) kf_l2qbxl(const FRec *recs, const int *map)
 {
     FUSED_BEGIN
     l2qbxl_body(g, r.nd, CP(const int *, in0), CP(const double *, in1), CP(const cd *, in2), CP(cd *, out0), r.i0,
@@ -1937,7 +1939,7 @@ hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int P
     int cg = pick_cg(l2qbxl_lds_bytes, nd, Pmax, g.p);
     size_t lds = l2qbxl_lds_bytes(nd, Pmax, g.p, cg);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-    k_l2qbxl<<<n, 256, lds, s>>>(g, nd, list, crad, loc, coef, cg);
+    k_l2qbxl<<<n, L2Q_THREADS, lds, s>>>(g, nd, list, crad, loc, coef, cg);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -2165,7 +2167,7 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
             if (lds > LDS_BUDGET) return hipErrorInvalidValue;
             FRec r = it.r;
             r.i0 = cg;
-            add(kind, 0, r, it.n, it.n, lds, 256);
+            add(kind, 0, r, it.n, it.n, lds, L2Q_THREADS);
         }
         break;
     case FK_EVAL:

@@ -26,7 +26,8 @@ EXPORTS = [
     "qbx_plan_create", "qbx_plan_destroy", "qbx_plan_stats", "qbx_plan_boxes",
     "qbx_plan_list", "qbx_plan_orders", "qbx_plan_association",
     "qbx_geom_create", "qbx_geom_from_plan", "qbx_geom_destroy", "qbx_geom_stats",
-    "qbx_geom_association", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times", "qbx_geom_work",
+    "qbx_geom_association", "qbx_geom_bytes", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times",
+    "qbx_geom_work",
     "qbx_eval_batch", "qbx_geom_autotune",
     "qbx_eval",
 ]
@@ -101,6 +102,7 @@ def lib():
     L.qbx_geom_destroy.argtypes = [_vp]
     L.qbx_geom_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     L.qbx_geom_association.argtypes = [_vp, _ip]
+    L.qbx_geom_bytes.argtypes = [_vp, i32]
     L.qbx_geom_profile.argtypes = [_vp, i32]
     L.qbx_geom_graph.argtypes = [_vp, i32]
     L.qbx_geom_autotune.argtypes = [_vp, i32, ctypes.POINTER(i32)]
@@ -111,8 +113,9 @@ def lib():
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default"):
+        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes"):
             f.restype = st
+    L.qbx_geom_bytes.restype = ctypes.c_size_t
     _lib = L
     return L
 
@@ -252,6 +255,11 @@ class Geometry:
         s = Stats()
         _check(lib().qbx_geom_stats(self._h, ctypes.byref(s)))
         return s.as_dict()
+
+    def bytes(self, n_dens: int = 1) -> int:
+        """Device memory held once n_dens densities have been evaluated
+        (resident part plus evaluation scratch), qbx_geom_bytes."""
+        return int(lib().qbx_geom_bytes(self._h, int(n_dens)))
 
     def association(self) -> np.ndarray:
         out = np.empty(max(self.n_tgt, 1), dtype=np.int32)

@@ -143,7 +143,7 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
         for fut in [f for f in building if f.done()]:
             r, need = building.pop(fut)
             geo = fut.result()
-            real = float(geo.stats()["device_bytes"])
+            real = float(geo.bytes(1))
             used += real - need
             bytes_per_node = max(bytes_per_node, 1.25 * real / r.geom.n)
             active.append(_Active(r, geo))
@@ -168,7 +168,7 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
             a.k += 1
             if a.k == len(a.req.densities):
                 a.req.done = t
-                used -= float(a.geo.stats()["device_bytes"])
+                used -= float(a.geo.bytes(1))
                 finished += 1
                 a.geo = None                 # frees the resident geometry
             else:

@@ -203,6 +203,26 @@ def test_fmm_with_volume_targets(ctx):
     assert _rel(u, ref) < 1e-10
 
 
+def test_geom_bytes_predicts_allocation(ctx):
+    """qbx_geom_bytes, asked before the first evaluation, matches the device
+    memory the geometry holds after evaluating (resident part + scratch)."""
+    from paper_1602_05301_amd import qbx
+    g = inputs.star(128, 16, lobes=5)
+    tc = np.arange(g.n, dtype=np.int32)
+    for direct in (False, True):
+        geo = qbx.Geometry(ctx, g, 30.0, 1e-10, g.sx, g.sy, tc, qbx.options(p=12, direct=direct))
+        for nd in (1, 6):
+            pred = geo.bytes(nd)
+            if nd == 1:                          # scratch not allocated yet
+                assert pred > geo.stats()["device_bytes"]
+            s = _dev(inputs.complex_gaussian(np.random.default_rng(3), (nd, g.n)))
+            geo.eval(s, s)
+            torch.cuda.synchronize()
+            held = geo.stats()["device_bytes"]
+            print(f"direct={direct} nd={nd}: predicted {pred} held {held}", flush=True)
+            assert abs(held - pred) <= 0.02 * pred
+
+
 def test_no_targets(ctx):
     g = inputs.star(16, 16, lobes=3)
     from paper_1602_05301_amd import qbx
