@@ -928,37 +928,43 @@ __device__ void p2qbxl_finish(cd *acc, int G, int p, bool write, cd *dst, long l
 }
 
 // One workgroup of P2Q_THREADS lanes per leaf: lane = (centre slot, part)
-// with CG centre slots (a power of two, at most 32) and P2Q_THREADS / CG parts.  The leaf's
-// near-list sources (flattened on the host, in list order) are staged in LDS
-// P2Q_SCH at a time and go round-robin to the parts.  Parts are summed by
-// shuffles inside a wave, then wave by wave in order through LDS.
+// with CG = (centres in the leaf, at most P2Q_THREADS / 2) slots and
+// P2Q_THREADS / CG parts, so few lanes idle whatever the centre count.  The
+// leaf's near-list sources (flattened on the host, in list order) are staged
+// in LDS P2Q_SCH at a time and go round-robin to the parts.  The parts of a
+// centre are then summed in part order through LDS, P2Q_RED coefficients at
+// a time ([coefficient][lane] layout: conflict-free writes and reads).
 constexpr int P2Q_SCH = 256;
 constexpr int P2Q_THREADS = 128;   // lanes per leaf
+constexpr int P2Q_RED = 8;         // coefficients per reduction round
+
+size_t p2qbxl_lds_bytes()
+{
+    return sizeof(cd) * ((size_t)P2Q_RED * P2Q_THREADS + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
+}
 
 template <int PB>
 __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int *list, const cd *qs, const cd *qd, cd *coef, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     constexpr int NE = 2 * PB + 1;
-    cd *red = reinterpret_cast<cd *>(lds_raw);          // [32][NE]
-    cd *QS = red + 32 * NE;                             // [P2Q_SCH]
+    cd *red = reinterpret_cast<cd *>(lds_raw);          // [P2Q_RED][P2Q_THREADS]
+    cd *QS = red + P2Q_RED * P2Q_THREADS;               // [P2Q_SCH]
     cd *QD = QS + P2Q_SCH;                              // [P2Q_SCH]
     double *SX = reinterpret_cast<double *>(QD + P2Q_SCH);
     double *SY = SX + P2Q_SCH, *NX = SY + P2Q_SCH, *NY = NX + P2Q_SCH;
     int b = list[bid.x];
     int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
-    int nct = c1 - c0;
-    int CG = 1;
-    while (CG < nct && CG < 32) CG <<= 1;
+    int CG = max(1, min(c1 - c0, P2Q_THREADS / 2));
     int parts = P2Q_THREADS / CG;
-    int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tid = threadIdx.x;
     int gi = tid % CG, part = tid / CG;
     int p = g.p;
     long long ncoef = 2 * p + 1;
     int q0 = g.qsrc_start[bid.x], total = g.qsrc_start[bid.x + 1] - q0;
     for (int cg = c0; cg < c1; cg += CG) {
-        int i = cg + gi;
-        bool active = i < c1;
+        int i = cg + gi, ncg = min(CG, c1 - cg);
+        bool active = part < parts && i < c1;
         double cx = active ? g.cx[i] : 0.0, cy = active ? g.cy[i] : 0.0;
         for (int d = 0; d < nd; ++d) {
             cd acc[NE];
@@ -983,36 +989,22 @@ __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int 
                         p2qbxl_pair<PB>(g.omega, p, cx, cy, SX[f], SY[f], NX[f], NY[f], QS[f], QD[f], acc);
                 }
             }
-            // parts inside the wave (lane bits >= log2 CG)
+            // sum the parts of each centre in part order
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                double re = acc[e].x, im = acc[e].y;
-                for (int m = CG; m < 64; m <<= 1) {
-                    re += shfl_xor_d(re, m);
-                    im += shfl_xor_d(im, m);
-                }
-                acc[e] = mk(re, im);
-            }
-            // waves in order: wave w hands its sums to wave 0 through LDS
-            for (int w = 1; w < P2Q_THREADS / 64; ++w) {
+            for (int e0 = 0; e0 < NE; e0 += P2Q_RED) {
                 __syncthreads();
-                if (wave == w && lane < CG) {
 #pragma unroll
-                    for (int e = 0; e < NE; ++e) red[lane * NE + e] = acc[e];
-                }
+                for (int e = 0; e < P2Q_RED; ++e)
+                    if (e0 + e < NE) red[e * P2Q_THREADS + tid] = acc[e0 + e];
                 __syncthreads();
-                if (wave == 0 && lane < CG) {
-#pragma unroll
-                    for (int e = 0; e < NE; ++e) acc[e] = acc[e] + red[lane * NE + e];
-                }
-            }
-            if (wave == 0 && lane < CG && active) {
-                cd *dst = coef + (long long)d * ncoef * g.nc + i;
-#pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    int ell = e - PB;
-                    if (ell < -p || ell > p) continue;
-                    dst[(long long)(ell + p) * g.nc] = acc[e];
+                for (int it = tid; it < ncg * P2Q_RED; it += blockDim.x) {
+                    int e = it / ncg, c = it - e * ncg;
+                    int ell = e0 + e - PB;
+                    if (e0 + e >= NE || ell < -p || ell > p) continue;
+                    const cd *r = red + e * P2Q_THREADS + c;
+                    cd sum = r[0];
+                    for (int jp = 1; jp < parts; ++jp) sum = sum + r[jp * CG];
+                    coef[((long long)d * ncoef + ell + p) * g.nc + cg + c] = sum;
                 }
             }
         }
@@ -1856,8 +1848,7 @@ template <int PB>
 static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
                                   const cd *qd, cd *coef, hipStream_t s)
 {
-    size_t lds = sizeof(cd) * (32 * (2 * PB + 1) + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
-    k_p2qbxl<PB><<<n, P2Q_THREADS, lds, s>>>(g, nd, list, qs, qd, coef);
+    k_p2qbxl<PB><<<n, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, list, qs, qd, coef);
     return hipGetLastError();
 }
 
@@ -2001,11 +1992,6 @@ int p2q_bucket(int p)
     return p <= 8 ? 8 : p <= 12 ? 12 : p <= 14 ? 14 : p <= 16 ? 16 : p <= 24 ? 24 : p <= 32 ? 32 : 40;
 }
 
-size_t p2qbxl_lds(int PB)
-{
-    return sizeof(cd) * (32 * (2 * (size_t)PB + 1) + 2 * P2Q_SCH) + sizeof(double) * 4 * P2Q_SCH;
-}
-
 // Appends one launch: records (first block filled in) and the block map.
 // Returns its index, -1 without blocks, -2 when the grid is too large.
 int fb_add(FBuf &fb, int kind, int variant, int threads, size_t lds, std::vector<FRec> recs,
@@ -2133,7 +2119,7 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
     case FK_P2QBXL:
         for (const auto &it : items) {
             int pb = p2q_bucket(it.h->p);
-            add(kind, pb, it.r, it.n, it.n, p2qbxl_lds(pb), P2Q_THREADS);
+            add(kind, pb, it.r, it.n, it.n, p2qbxl_lds_bytes(), P2Q_THREADS);
         }
         break;
     case FK_P2QBXL_DIRECT:
