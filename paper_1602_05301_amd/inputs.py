@@ -249,7 +249,8 @@ def _adaptive_edges(f, omega, c_curv, q=16, start=8):
 
 
 def multiscale_curves(n_curves: int = 64, omega: float = 100.0, workload_id: int = 2,
-                      nodes=(570_000, 630_000), box: float = 10.0, gap: float = 0.5, q: int = 16):
+                      nodes=(570_000, 630_000), box: float = 10.0, gap: float = 0.5, q: int = 16,
+                      q_fine: int = 0):
     """Many disjoint curves of different sizes and curvatures in
     [-box, box]^2, as one discretisation: half ellipses (aspect ratio uniform
     in [1, 10]), half stars (3-9 lobes, amplitude 0.3), circumradius uniform
@@ -257,7 +258,8 @@ def multiscale_curves(n_curves: int = 64, omega: float = 100.0, workload_id: int
     each curve stays at least `gap` from the others (distance between 128
     sample points per curve).  Panels are adaptive in theta (_adaptive_edges);
     the curvature bound c is bisected until the total node count lies in
-    `nodes`.  Returns (Geometry, c)."""
+    `nodes`.  Returns (Geometry, c); with q_fine > 0, (Geometry, c, fine)
+    where fine has q_fine Gauss nodes on each of the same panels."""
     rng = rng_for(workload_id, 0)
     draws = []
     for i in range(n_curves):
@@ -288,13 +290,13 @@ def multiscale_curves(n_curves: int = 64, omega: float = 100.0, workload_id: int
         placed.append((cen, R, np.stack([px, py], axis=1)))
         specs.append((kind, rad, par, rot, (float(cen[0]), float(cen[1]))))
 
-    def build(c_curv):
+    def build(c_curv, qq=q):
         parts = []
         for kind, rad, par, rot, cen in specs:
             f = _shape(kind, rad, par, rot, cen)
             e = _adaptive_edges(f, omega, c_curv, q)
-            out = _panelize(e, q, lambda th: f(th, 0), lambda th: f(th, 1))
-            parts.append(_finish(*out, q, dict(kind=kind, rad=rad, par=par, n_panels=e.size - 1)))
+            out = _panelize(e, qq, lambda th: f(th, 0), lambda th: f(th, 1))
+            parts.append(_finish(*out, qq, dict(kind=kind, rad=rad, par=par, n_panels=e.size - 1)))
         return concat(parts)
 
     lo, hi = 1e-3, 10.0          # curvature bounds giving too many / too few nodes
@@ -306,7 +308,7 @@ def multiscale_curves(n_curves: int = 64, omega: float = 100.0, workload_id: int
         elif g.n < nodes[0]:
             hi = c
         else:
-            return g, c
+            return (g, c, build(c, q_fine)) if q_fine else (g, c)
     raise RuntimeError("multiscale_curves: node target not reached")
 
 

@@ -1,0 +1,237 @@
+"""Exterior Dirichlet (sound-soft scattering) solves with GMRES on the QBX-FMM matvec.
+
+The field outside the curve is represented as u = D[sigma] + i omega S[sigma]
+(Sec. 8.3, eq. rep).  Its exterior limit on the curve gives the second-kind
+equation (1/2) sigma + D* sigma + i omega S* sigma = f (Sec. 1, eq. extdir;
+f = -u_inc for scattering, eq. int_eq).  QBX with exterior centres returns
+the exterior limit itself, so one evaluation with sigma_S = i omega sigma,
+sigma_D = sigma and the nodes as targets (each bound to its own centre)
+applies the whole left-hand side; the geometry, its tree and tables stay
+resident across the iterations.
+
+GMRES (Saad and Schultz 1986): restarted, modified Gram-Schmidt Arnoldi and
+Givens rotations, on the host in complex128.  The matvec runs on the GPU;
+the Arnoldi vectors stay on the host.
+
+    python -m paper_1602_05301_amd.solve [--curves 35] [--nodes 105000]
+
+solves the scattering of a plane wave by a set of separated curves (a
+synthetic stand-in for the paper's 35 inclusions, sources oversampled 4x)
+and prints one JSON object: iterations, relative residual, time per
+iteration, and time per matvec (host-device copies, interpolation to the
+source grid and the GPU evaluation).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import inputs
+
+
+def gmres(matvec, b, tol: float = 1e-10, restart: int = 100, maxiter: int = 1000, x0=None):
+    """Solve A x = b for the operator x -> matvec(x) (complex vectors).
+
+    Stops when the relative residual |b - A x| / |b| reaches tol or after
+    maxiter Arnoldi steps.  Within a cycle the residual is the one of the
+    Hessenberg least-squares problem; at every restart, and before
+    returning, it is recomputed from b - A x.  Returns (x, info) with info =
+    {"iterations" (Arnoldi steps), "residual" (relative, recomputed),
+    "history" (relative residual after each step), "converged"}."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.size
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    info = {"iterations": 0, "residual": 0.0, "history": [], "converged": True}
+    if bnorm == 0.0:
+        return np.zeros(n, dtype=np.complex128), info
+    its = 0
+    while True:
+        r = b - matvec(x) if (its or x0 is not None) else b.copy()
+        beta = np.linalg.norm(r)
+        info["residual"] = float(beta / bnorm)
+        if beta / bnorm <= tol or its >= maxiter:
+            info["converged"] = bool(beta / bnorm <= tol)
+            break
+        m = min(restart, maxiter - its)
+        V = np.zeros((m + 1, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        cs = np.zeros(m)                                # rotation: [[c, s], [-conj(s), c]]
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        V[0] = r / beta
+        g[0] = beta
+        kk = 0
+        for k in range(m):
+            w = matvec(V[k])
+            its += 1
+            for i in range(k + 1):                      # modified Gram-Schmidt
+                H[i, k] = np.vdot(V[i], w)
+                w -= H[i, k] * V[i]
+            hn = np.linalg.norm(w)
+            H[k + 1, k] = hn
+            if hn > 0.0:
+                V[k + 1] = w / hn
+            for i in range(k):                          # earlier rotations
+                t = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
+                H[i + 1, k] = -np.conj(sn[i]) * H[i, k] + cs[i] * H[i + 1, k]
+                H[i, k] = t
+            a, c = H[k, k], H[k + 1, k]                 # new rotation zeroes H[k+1, k]
+            den = np.hypot(abs(a), abs(c))
+            if den == 0.0:
+                cs[k], sn[k] = 1.0, 0.0
+            elif a == 0.0:
+                cs[k], sn[k] = 0.0, np.conj(c) / abs(c)
+            else:
+                cs[k], sn[k] = abs(a) / den, (a / abs(a)) * np.conj(c) / den
+            H[k, k] = cs[k] * a + sn[k] * c
+            H[k + 1, k] = 0.0
+            g[k + 1] = -np.conj(sn[k]) * g[k]
+            g[k] = cs[k] * g[k]
+            kk = k + 1
+            est = abs(g[k + 1]) / bnorm
+            info["history"].append(float(est))
+            if est <= tol or its >= maxiter or hn == 0.0:
+                break
+        y = np.linalg.solve(np.triu(H[:kk, :kk]), g[:kk])
+        x = x + y @ V[:kk]
+    info["iterations"] = its
+    return x, info
+
+
+def gl_interp(q: int, qs: int) -> np.ndarray:
+    """[qs, q] matrix taking values at the q Gauss-Legendre nodes of [-1, 1]
+    to the polynomial interpolant's values at the qs Gauss-Legendre nodes
+    (Lagrange basis in barycentric form)."""
+    x = np.polynomial.legendre.leggauss(q)[0]
+    y = np.polynomial.legendre.leggauss(qs)[0]
+    wb = np.array([1.0 / np.prod(x[j] - np.delete(x, j)) for j in range(q)])
+    d = y[:, None] - x[None, :]
+    L = wb[None, :] / d
+    return L / L.sum(axis=1, keepdims=True)
+
+
+class Oversampled:
+    """Sources on a fine grid (q_s Gauss nodes per panel) with the centres
+    of the coarse grid (q nodes per panel, the density nodes), as the paper's
+    oversampled QBX takes them (Sec. 3.2, Table 1).  Both grids have the same
+    panels in the same order; the density is carried to the fine nodes by
+    interpolation within each panel."""
+
+    def __init__(self, coarse, fine):
+        assert fine.n % coarse.n == 0 and fine.n // coarse.n == fine.q // coarse.q
+        self.sx, self.sy, self.w, self.nx, self.ny, self.h = fine.sx, fine.sy, fine.w, fine.nx, fine.ny, fine.h
+        self.cx, self.cy, self.cr = coarse.cx, coarse.cy, coarse.cr
+        self.n_panels = coarse.n // coarse.q
+        self.L = gl_interp(coarse.q, fine.q)
+
+    def upsample(self, sigma: np.ndarray) -> np.ndarray:
+        return (np.asarray(sigma).reshape(self.n_panels, -1) @ self.L.T).ravel()
+
+
+class CFIE:
+    """The operator sigma -> (1/2) sigma + D* sigma + i omega S* sigma on a
+    curve, applied by the GPU QBX-FMM (a resident qbx.Geometry whose targets
+    are the nodes, each with its own centre).  With `fine` (the same panels,
+    more Gauss nodes each) the sources are oversampled: sigma is
+    interpolated to the fine nodes before each evaluation."""
+
+    def __init__(self, ctx, geom, omega: float, eps: float, p: int, fine=None, **opt):
+        import torch
+        from . import qbx
+        self.omega = float(omega)
+        self.n = geom.n
+        self.src = Oversampled(geom, fine) if fine is not None else None
+        disc = self.src if self.src is not None else geom
+        tc = np.arange(geom.n, dtype=np.int32)
+        self.geo = qbx.Geometry(ctx, disc, omega, eps, geom.sx, geom.sy, tc, qbx.options(p=p, **opt))
+        ns = fine.n if fine is not None else geom.n
+        self.ss = torch.empty((1, ns), dtype=torch.complex128, device="cuda")
+        self.sd = torch.empty_like(self.ss)
+        self.u = torch.empty((1, geom.n), dtype=torch.complex128, device="cuda")
+        self.matvecs = 0
+        self.gpu_s = 0.0
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        import torch
+        t0 = time.perf_counter()
+        xs = self.src.upsample(x) if self.src is not None else np.ascontiguousarray(x)
+        self.sd.copy_(torch.from_numpy(xs[None]))
+        self.ss.copy_(torch.from_numpy((1j * self.omega * xs)[None]))
+        self.geo.eval(self.ss, self.sd, u=self.u)
+        out = self.u.cpu().numpy()[0]
+        self.gpu_s += time.perf_counter() - t0
+        self.matvecs += 1
+        return out
+
+
+def field(ctx, geom, omega: float, eps: float, p: int, sigma: np.ndarray, tx, ty, fine=None,
+          **opt) -> np.ndarray:
+    """u = D[sigma] + i omega S[sigma] at off-curve targets (QBX inside the
+    expansion disks, the smooth rule elsewhere), with the GPU path; `fine`
+    as in CFIE."""
+    import torch
+    from . import qbx
+    src = Oversampled(geom, fine) if fine is not None else None
+    disc = src if src is not None else geom
+    s = src.upsample(sigma) if src is not None else np.ascontiguousarray(sigma)
+    geo = qbx.Geometry(ctx, disc, omega, eps, np.asarray(tx, float), np.asarray(ty, float), None,
+                       qbx.options(p=p, **opt))
+    sd = torch.from_numpy(s[None]).cuda()
+    ss = torch.from_numpy((1j * omega * s)[None]).cuda()
+    return geo.eval(ss, sd).cpu().numpy()[0]
+
+
+def plane_wave(omega: float, x, y, dx: float = -2.0 / np.sqrt(5.0), dy: float = 1.0 / np.sqrt(5.0)):
+    """exp(i omega d.x), by default the incident wave of the paper's scattering run (Sec. 8.3)."""
+    return np.exp(1j * omega * (dx * np.asarray(x) + dy * np.asarray(y)))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--curves", type=int, default=35)
+    ap.add_argument("--nodes", type=int, default=105_000)
+    ap.add_argument("--omega", type=float, default=12.43)
+    ap.add_argument("--eps", type=float, default=5e-7)
+    ap.add_argument("--p", type=int, default=9)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--maxiter", type=int, default=2000)
+    ap.add_argument("--oversample", type=int, default=4, help="source nodes per density node (1: none)")
+    args = ap.parse_args(argv)
+    from . import qbx
+    q = 16
+    made = inputs.multiscale_curves(n_curves=args.curves, omega=args.omega,
+                                    nodes=(int(0.95 * args.nodes), int(1.05 * args.nodes)),
+                                    q=q, q_fine=q * args.oversample if args.oversample > 1 else 0)
+    g, c = made[0], made[1]
+    fine = made[2] if len(made) > 2 else None
+    ctx = qbx.Context(0)
+    t0 = time.perf_counter()
+    A = CFIE(ctx, g, args.omega, args.eps, args.p, fine=fine)
+    setup = time.perf_counter() - t0
+    f = -plane_wave(args.omega, g.sx, g.sy)
+    A(f)                                                 # warm-up (scratch, tiles)
+    A.matvecs, A.gpu_s = 0, 0.0
+    t0 = time.perf_counter()
+    sigma, info = gmres(A, f, tol=args.tol, restart=args.restart, maxiter=args.maxiter)
+    wall = time.perf_counter() - t0
+    true_res = float(np.linalg.norm(f - A(sigma)) / np.linalg.norm(f))
+    out = {"workload": f"{args.curves} separated curves (multiscale recipe), {g.n} unknowns, "
+                       f"{fine.n if fine is not None else g.n} sources, omega {args.omega}, "
+                       f"eps {args.eps}, p {args.p}, plane wave, GMRES({args.restart}) to {args.tol}",
+           "unknowns": g.n, "sources": fine.n if fine is not None else g.n, "curvature_bound": c,
+           "setup_s": setup,
+           "iterations": info["iterations"], "converged": info["converged"],
+           "relative_residual": true_res, "wall_s": wall,
+           "ms_per_iteration": 1e3 * wall / max(info["iterations"], 1),
+           "matvec_ms": 1e3 * A.gpu_s / max(A.matvecs, 1)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
