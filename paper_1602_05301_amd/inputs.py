@@ -134,6 +134,42 @@ def circle(n_panels: int, q: int = 16, radius: float = 1.0) -> Geometry:
     return star(n_panels, q, lobes=1, amp=0.0, radius=radius)
 
 
+@dataclass
+class Points:
+    """Sources and centres as the library takes them, without the one
+    centre per node pairing of Geometry: sources sx, sy, w, nx, ny, h
+    (length n_src), centres cx, cy, cr (length n_ctr)."""
+
+    sx: np.ndarray
+    sy: np.ndarray
+    w: np.ndarray
+    nx: np.ndarray
+    ny: np.ndarray
+    h: np.ndarray
+    cx: np.ndarray
+    cy: np.ndarray
+    cr: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.sx.size)
+
+
+def two_sided(geom: Geometry, sources: Geometry | None = None) -> Points:
+    """Centres on both sides of the curve: node j's exterior centre
+    s_j + (h/2) n_j at index j and its interior centre s_j - (h/2) n_j at
+    index n + j.  Binding an on-curve target to one or the other selects the
+    exterior or the interior limit (side preference); their average is the
+    on-surface value.  `sources` (default: the nodes) may be an oversampled
+    grid of the same curve."""
+    src = geom if sources is None else sources
+    r = 0.5 * geom.h
+    return Points(src.sx, src.sy, src.w, src.nx, src.ny, src.h,
+                  np.concatenate([geom.sx + r * geom.nx, geom.sx - r * geom.nx]),
+                  np.concatenate([geom.sy + r * geom.ny, geom.sy - r * geom.ny]),
+                  np.concatenate([r, r]))
+
+
 def concat(geoms) -> Geometry:
     """Several disjoint curves as one discretisation (panel ids renumbered)."""
     off = 0

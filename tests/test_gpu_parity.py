@@ -239,6 +239,43 @@ def test_cfie_gmres_point_source(ctx):
     assert dsig < 1e-8
 
 
+@pytest.mark.parametrize("direct", [True, False])
+def test_two_sided_limits_on_circle(ctx, direct):
+    """Centres on both sides (side preference, Sec. 6.1) give both one-sided
+    limits of Sec. 2 eq. oneside.  Unit circle, sigma = e^{i m theta},
+    x = omega R: S has the limit (i pi R/2) J_m(x) H_m(x) on both sides; D
+    has (i pi omega R/2) J_m'(x) H_m(x) outside and (i pi omega R/2) J_m(x)
+    H_m'(x) inside, so the exterior minus the interior limit is sigma (the
+    Wronskian).  Sources oversampled 4x."""
+    from scipy.special import h1vp, hankel1, jv, jvp
+    from paper_1602_05301_amd import qbx
+    omega, p, R = 10.0, 12, 1.0
+    g = inputs.circle(64, 16, radius=R)
+    fine = inputs.circle(64, 64, radius=R)
+    pts = inputs.two_sided(g, fine)
+    n = g.n
+    tx, ty = np.concatenate([g.sx, g.sx]), np.concatenate([g.sy, g.sy])
+    tc = np.arange(2 * n, dtype=np.int32)          # target j: exterior centre j; n + j: interior
+    geo = qbx.Geometry(ctx, pts, omega, 1e-10, tx, ty, tc, qbx.options(p=p, direct=direct))
+    th = np.arctan2(g.sy, g.sx)
+    thf = np.arctan2(fine.sy, fine.sx)
+    x = omega * R
+    for m in (0, 3, 7):
+        sig = _dev(np.exp(1j * m * thf)[None])
+        uS = geo.eval(sig, None).cpu().numpy()[0]
+        uD = geo.eval(None, sig).cpu().numpy()[0]
+        e = np.exp(1j * m * th)
+        S_ref = (1j * np.pi * R / 2) * jv(m, x) * hankel1(m, x) * e
+        D_ext = (1j * np.pi * omega * R / 2) * jvp(m, x) * hankel1(m, x) * e
+        D_int = (1j * np.pi * omega * R / 2) * jv(m, x) * h1vp(m, x) * e
+        scale = max(np.max(np.abs(D_ext)), np.max(np.abs(S_ref)), 1.0)
+        errs = [np.max(np.abs(uS[:n] - S_ref)), np.max(np.abs(uS[n:] - S_ref)),
+                np.max(np.abs(uD[:n] - D_ext)), np.max(np.abs(uD[n:] - D_int)),
+                np.max(np.abs((uD[:n] - uD[n:]) - e))]
+        print(f"direct={direct} m={m}: errors {[f'{v / scale:.1e}' for v in errs]}", flush=True)
+        assert max(errs) / scale < 1e-9
+
+
 def test_geom_bytes_predicts_allocation(ctx):
     """qbx_geom_bytes, asked before the first evaluation, matches the device
     memory the geometry holds after evaluating (resident part + scratch)."""
