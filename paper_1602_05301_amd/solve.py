@@ -173,21 +173,59 @@ class CFIE:
         return out
 
 
-def field(ctx, geom, omega: float, eps: float, p: int, sigma: np.ndarray, tx, ty, fine=None,
-          **opt) -> np.ndarray:
-    """u = D[sigma] + i omega S[sigma] at off-curve targets (QBX inside the
-    expansion disks, the smooth rule elsewhere), with the GPU path; `fine`
-    as in CFIE."""
+def volume_eval(ctx, disc, omega: float, eps: float, p: int, sigma_s, sigma_d, tx, ty,
+                leaf_max: int = 32) -> np.ndarray:
+    """u = S[sigma_s] + D[sigma_d] at targets anywhere off the curve, every
+    part through the FMM.  Targets inside an expansion disk (the
+    association rule of Sec. 6.1) take QBX as in qbx_eval.  The others take
+    the smooth rule, computed as order-0 expansions centred at the targets
+    themselves: a second geometry whose centres are those targets (p = 0,
+    each target bound to its own centre), so P2QBXL, M2QBXL and L2QBXL are
+    exactly the point FMM's direct sum over near sources, M2P and L2P
+    (Sec. 7, with the targets as tree points).  sigma_s, sigma_d: [n_src]
+    arrays on disc's sources, either may be None."""
     import torch
     from . import qbx
+    tx = np.ascontiguousarray(tx, dtype=float)
+    ty = np.ascontiguousarray(ty, dtype=float)
+    ns = np.asarray(disc.sx).size
+    for a in (sigma_s, sigma_d):
+        if a is not None and np.asarray(a).size != ns:
+            raise ValueError("densities must have one value per source")
+    assoc = qbx.Plan(disc, omega, eps, tx, ty, None, qbx.options(p=p, leaf_max=leaf_max)).association()
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)[None]).cuda()
+    ss, sd = dev(sigma_s), dev(sigma_d)
+    u = np.zeros(tx.size, dtype=np.complex128)
+    q = np.flatnonzero(assoc >= 0)
+    if q.size:
+        geo = qbx.Geometry(ctx, disc, omega, eps, tx[q], ty[q], assoc[q].astype(np.int32),
+                           qbx.options(p=p, leaf_max=leaf_max))
+        u[q] = geo.eval(ss, sd).cpu().numpy()[0]
+    v = np.flatnonzero(assoc < 0)
+    if v.size:
+        pts = inputs.Points(np.asarray(disc.sx), np.asarray(disc.sy), np.asarray(disc.w), np.asarray(disc.nx),
+                            np.asarray(disc.ny), np.asarray(disc.h), tx[v], ty[v],
+                            np.full(v.size, 1e-300))
+        geo = qbx.Geometry(ctx, pts, omega, eps, tx[v], ty[v], np.arange(v.size, dtype=np.int32),
+                           qbx.options(p=0, leaf_max=leaf_max))
+        u[v] = geo.eval(ss, sd).cpu().numpy()[0]
+    return u
+
+
+def field(ctx, geom, omega: float, eps: float, p: int, sigma: np.ndarray, tx, ty, fine=None,
+          both_sides: bool = False, **opt) -> np.ndarray:
+    """u = D[sigma] + i omega S[sigma] at off-curve targets (QBX inside the
+    expansion disks, the FMM's order-0 expansions elsewhere: volume_eval);
+    `fine` as in CFIE.  both_sides: centres on both sides of the curve
+    (inputs.two_sided), so that targets close to the curve on its inner side
+    are served too."""
     src = Oversampled(geom, fine) if fine is not None else None
-    disc = src if src is not None else geom
     s = src.upsample(sigma) if src is not None else np.ascontiguousarray(sigma)
-    geo = qbx.Geometry(ctx, disc, omega, eps, np.asarray(tx, float), np.asarray(ty, float), None,
-                       qbx.options(p=p, **opt))
-    sd = torch.from_numpy(s[None]).cuda()
-    ss = torch.from_numpy((1j * omega * s)[None]).cuda()
-    return geo.eval(ss, sd).cpu().numpy()[0]
+    if both_sides:
+        disc = inputs.two_sided(geom, fine)
+    else:
+        disc = src if src is not None else geom
+    return volume_eval(ctx, disc, omega, eps, p, 1j * omega * s, s, tx, ty, **opt)
 
 
 def plane_wave(omega: float, x, y, dx: float = -2.0 / np.sqrt(5.0), dy: float = 1.0 / np.sqrt(5.0)):
@@ -206,6 +244,9 @@ def main(argv=None) -> int:
     ap.add_argument("--restart", type=int, default=2000)
     ap.add_argument("--maxiter", type=int, default=2000)
     ap.add_argument("--oversample", type=int, default=4, help="source nodes per density node (1: none)")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="also evaluate the scattered field on a grid x grid over the box, inside the "
+                         "curves too (two-sided centres; 0: no)")
     args = ap.parse_args(argv)
     from . import qbx
     q = 16
@@ -234,6 +275,15 @@ def main(argv=None) -> int:
            "relative_residual": true_res, "wall_s": wall,
            "ms_per_iteration": 1e3 * wall / max(info["iterations"], 1),
            "matvec_ms": 1e3 * A.gpu_s / max(A.matvecs, 1)}
+    if args.grid > 0:
+        xs = np.linspace(-10.0, 10.0, args.grid)
+        gx, gy = np.meshgrid(xs, xs)
+        t0 = time.perf_counter()
+        u_sc = field(ctx, g, args.omega, args.eps, args.p, sigma, gx.ravel(), gy.ravel(), fine=fine,
+                     both_sides=True)
+        out["field_targets"] = int(gx.size)
+        out["field_s"] = time.perf_counter() - t0
+        out["field_max_abs_total"] = float(np.max(np.abs(u_sc + plane_wave(args.omega, gx.ravel(), gy.ravel()))))
     print(json.dumps(out), flush=True)
     return 0
 

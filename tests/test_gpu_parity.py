@@ -276,6 +276,30 @@ def test_two_sided_limits_on_circle(ctx, direct):
         assert max(errs) / scale < 1e-9
 
 
+def test_volume_targets_through_the_fmm(ctx):
+    """Targets off the curve, inside expansion disks (QBX), in an annulus
+    and inside the curve (the smooth rule, here as order-0 expansions
+    centred at the targets and so through the FMM's near sums, M2P and
+    L2P): against the oracle's direct QBX plus smooth rule."""
+    from paper_1602_05301_amd import solve
+    g = inputs.star(64, 16, lobes=5)
+    rng = np.random.default_rng(21)
+    j = rng.integers(0, g.n, 200)
+    s = rng.uniform(0.05, 0.6, j.size) * g.h[j]
+    tx_a, ty_a = inputs.annulus_targets(rng, 600, 1.4, 3.0)
+    tx_i, ty_i = inputs.annulus_targets(rng, 200, 0.0, 0.4)
+    tx = np.concatenate([g.sx[j] + s * g.nx[j], tx_a, tx_i])
+    ty = np.concatenate([g.sy[j] + s * g.ny[j], ty_a, ty_i])
+    ss = inputs.complex_gaussian(rng, (g.n,))
+    sd = inputs.complex_gaussian(rng, (g.n,))
+    omega, p, eps = 15.0, 12, 1e-10
+    u = solve.volume_eval(ctx, g, omega, eps, p, ss, sd, tx, ty)
+    ref = oracle.direct_qbx(omega, p, g, tx, ty, ss[None], sd[None])[0]
+    err = _rel(u, ref)
+    print(f"volume targets: rel_l2 {err:.2e}", flush=True)
+    assert err < 1e-9
+
+
 def test_geom_bytes_predicts_allocation(ctx):
     """qbx_geom_bytes, asked before the first evaluation, matches the device
     memory the geometry holds after evaluating (resident part + scratch)."""
