@@ -107,6 +107,25 @@ def gmres(matvec, b, tol: float = 1e-10, restart: int = 100, maxiter: int = 1000
     return x, info
 
 
+# Source Gauss nodes per panel by density nodes per panel q (rows) and
+# tolerance (columns 1e-3, 1e-6, 1e-9, 1e-12), as the paper tabulates them
+# (Table 1, found empirically per kernel).
+_TABLE1_EPS = (1e-3, 1e-6, 1e-9, 1e-12)
+_TABLE1 = {2: (8, 16, 24, 32), 4: (12, 24, 32, 40), 8: (16, 32, 40, 48), 16: (32, 48, 64, 64)}
+
+
+def source_nodes(q: int, eps: float) -> int:
+    """Source nodes per panel for density nodes q and tolerance eps: the
+    tabulated value of the first column whose tolerance is at most eps (the
+    tightest column for eps below 1e-12)."""
+    if q not in _TABLE1:
+        raise ValueError("density nodes per panel must be one of %s" % sorted(_TABLE1))
+    for col, e in enumerate(_TABLE1_EPS):
+        if e <= eps:
+            return _TABLE1[q][col]
+    return _TABLE1[q][-1]
+
+
 def gl_interp(q: int, qs: int) -> np.ndarray:
     """[qs, q] matrix taking values at the q Gauss-Legendre nodes of [-1, 1]
     to the polynomial interpolant's values at the qs Gauss-Legendre nodes
@@ -243,16 +262,18 @@ def main(argv=None) -> int:
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--restart", type=int, default=2000)
     ap.add_argument("--maxiter", type=int, default=2000)
-    ap.add_argument("--oversample", type=int, default=4, help="source nodes per density node (1: none)")
+    ap.add_argument("--oversample", type=int, default=0,
+                    help="source nodes per density node (0: from Table 1 for eps; 1: none)")
     ap.add_argument("--grid", type=int, default=0,
                     help="also evaluate the scattered field on a grid x grid over the box, inside the "
                          "curves too (two-sided centres; 0: no)")
     args = ap.parse_args(argv)
     from . import qbx
     q = 16
+    qs = source_nodes(q, args.eps) if args.oversample == 0 else q * args.oversample
     made = inputs.multiscale_curves(n_curves=args.curves, omega=args.omega,
                                     nodes=(int(0.95 * args.nodes), int(1.05 * args.nodes)),
-                                    q=q, q_fine=q * args.oversample if args.oversample > 1 else 0)
+                                    q=q, q_fine=qs if qs > q else 0)
     g, c = made[0], made[1]
     fine = made[2] if len(made) > 2 else None
     ctx = qbx.Context(0)

@@ -84,3 +84,40 @@ def test_plane_wave_default_direction():
     """The incident wave of the paper's scattering run: unit direction (-2, 1)/sqrt(5)."""
     u = plane_wave(3.0, np.array([1.0]), np.array([2.0]))
     assert np.allclose(u, np.exp(1j * 3.0 * (-2.0 + 2.0) / np.sqrt(5.0)))
+
+
+def test_source_nodes_column_choice():
+    """Table 1 lookup: the first column whose tolerance is at most eps."""
+    from paper_1602_05301_amd.solve import source_nodes
+    assert source_nodes(16, 1e-3) == 32 and source_nodes(16, 1e-6) == 48
+    assert source_nodes(16, 5e-7) == 64           # between columns: the tighter one
+    assert source_nodes(4, 1e-2) == 12 and source_nodes(2, 1e-15) == 32
+    with pytest.raises(ValueError):
+        source_nodes(6, 1e-6)
+
+
+def test_source_nodes_meet_tolerance_on_circle():
+    """With the tabulated source nodes, on-curve QBX of S and D on the unit
+    circle (64 panels of 16 nodes, omega 10, p 12) is within each column's
+    tolerance of the closed forms (i pi R/2) J_m H_m and
+    (i pi omega R/2) J_m' H_m."""
+    from scipy.special import hankel1, jv, jvp
+    from paper_1602_05301_amd.solve import source_nodes
+    omega, R, p = 10.0, 1.0, 12
+    g = inputs.circle(64, 16, radius=R)
+    th = np.arctan2(g.sy, g.sx)
+    x = omega * R
+    tc = np.arange(g.n, dtype=np.int32)
+    for eps in (1e-3, 1e-6, 1e-9):
+        fine = inputs.circle(64, source_nodes(16, eps), radius=R)
+        src = Oversampled(g, fine)
+        thf = np.arctan2(fine.sy, fine.sx)
+        for m in (0, 5, 12):
+            e = np.exp(1j * m * th)
+            sig = np.exp(1j * m * thf)[None]
+            uS = oracle.direct_qbx(omega, p, src, g.sx, g.sy, sig, None, tgt_ctr=tc)[0]
+            uD = oracle.direct_qbx(omega, p, src, g.sx, g.sy, None, sig, tgt_ctr=tc)[0]
+            S = (1j * np.pi * R / 2) * jv(m, x) * hankel1(m, x) * e
+            D = (1j * np.pi * omega * R / 2) * jvp(m, x) * hankel1(m, x) * e
+            assert np.max(np.abs(uS - S)) / np.max(np.abs(S)) < eps
+            assert np.max(np.abs(uD - D)) / np.max(np.abs(D)) < eps
