@@ -442,7 +442,6 @@ qbx_status upload(qbx_geom_s *G)
     auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
     G->p2m = make_list(ar, pl, [&](int b) { return pl.leaf[b] && pl.lev[b] >= 2; });
     G->xl = make_list(ar, pl, [&](int b) { return pl.X_start[b + 1] > pl.X_start[b]; });
-    G->qbx = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b); });
     G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
     // Split every leaf's W list: boxes summed directly join the near list
     // (P2QBXL), the others go through M2QBXL.
@@ -461,10 +460,26 @@ qbx_status upload(qbx_geom_s *G)
         G->near_start = ns; G->near_idx = nidx; G->wf_start = ws; G->wf_idx = widx;
         g.near_start = ar.upload(ns); g.near_idx = ar.upload(nidx);
         g.wf_start = ar.upload(ws); g.wf_idx = ar.upload(widx);
-        // near-list sources of every leaf of the P2QBXL list, in list order
-        std::vector<int32_t> qs0(1, 0), qidx;
+        // the P2QBXL list: leaves with centres, the most (centre, near
+        // source) pairs first, so that long workgroups start early and short
+        // ones fill the tail (each leaf's result is independent of the order)
+        std::vector<int> qlist;
+        std::vector<long long> qwork(nb, 0);
         for (int b = 0; b < nb; ++b) {
             if (!(pl.leaf[b] && has_ctr(b))) continue;
+            long long nsrc = 0;
+            for (int i = ns[b]; i < ns[b + 1]; ++i) nsrc += pl.src_end[nidx[i]] - pl.src_begin[nidx[i]];
+            qwork[b] = nsrc * (pl.ctr_end[b] - pl.ctr_begin[b]);
+            qlist.push_back(b);
+        }
+        std::stable_sort(qlist.begin(), qlist.end(), [&](int a, int b) { return qwork[a] > qwork[b]; });
+        G->qbx.n = (int)qlist.size();
+        G->qbx.Pmax = 0;
+        for (int b : qlist) G->qbx.Pmax = std::max(G->qbx.Pmax, pl.P[pl.lev[b]]);
+        G->qbx.d = ar.upload(qlist);
+        // near-list sources of every leaf of the P2QBXL list, in list order
+        std::vector<int32_t> qs0(1, 0), qidx;
+        for (int b : qlist) {
             for (int i = ns[b]; i < ns[b + 1]; ++i)
                 for (int j = pl.src_begin[nidx[i]]; j < pl.src_end[nidx[i]]; ++j) qidx.push_back(j);
             qs0.push_back((int32_t)qidx.size());
