@@ -121,8 +121,8 @@ def main(argv=None):
                          "a kernel of known traffic for calibrating HBM byte counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is designed, not implemented)", file=sys.stderr)
         return 2
 
     import torch

@@ -51,7 +51,7 @@ typedef enum {
     QBX_E_NOMEM = -2,        /* host or device allocation failed */
     QBX_E_DEVICE = -3,       /* a HIP call failed (no device, launch error) */
     QBX_E_ASSOC = -4,        /* a target in Gamma_near has no eligible centre (Sec. 6.1) */
-    QBX_E_UNSUPPORTED = -5   /* valid request outside what this build implements */
+    QBX_E_UNSUPPORTED = -5   /* valid request outside what the library implements */
 } qbx_status;
 
 typedef struct qbx_ctx_s *qbx_ctx;    /* device + stream */
@@ -216,7 +216,8 @@ qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
  * forked from and joined back to it).  Each result is bitwise the same as
  * from qbx_eval alone.  The launch records are built on the host and copied
  * to the device once per call; the call waits for the previous call's copy
- * to finish.  If stage profiling or graph replay is on for any geometry, the
+ * to finish.  The record buffers belong to the context: calls on one
+ * context from several threads must not overlap.  If stage profiling or graph replay is on for any geometry, the
  * evaluations run one after another through qbx_eval.  Errors: QBX_E_INVAL
  * (null or foreign geometry, n_dens outside 1..64, missing u or densities),
  * QBX_E_DEVICE, QBX_E_NOMEM. */
