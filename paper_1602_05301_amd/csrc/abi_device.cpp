@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -104,6 +105,10 @@ struct WorkList {
     int n = 0;
     int Pmax = 0;
 };
+
+// Largest (centre, source) pair count a P2QBXL lane is given before its leaf
+// is split over several workgroups (about twice the typical leaf's).
+constexpr long long kP2qLanePairs = 8;
 
 }  // namespace
 
@@ -460,31 +465,46 @@ qbx_status upload(qbx_geom_s *G)
         G->near_start = ns; G->near_idx = nidx; G->wf_start = ws; G->wf_idx = widx;
         g.near_start = ar.upload(ns); g.near_idx = ar.upload(nidx);
         g.wf_start = ar.upload(ws); g.wf_idx = ar.upload(widx);
-        // the P2QBXL list: leaves with centres, the most (centre, near
-        // source) pairs first, so that long workgroups start early and short
-        // ones fill the tail (each leaf's result is independent of the order)
-        std::vector<int> qlist;
-        std::vector<long long> qwork(nb, 0);
+        // The P2QBXL work list (items {c0, c1, q0, q1} as the kernel takes
+        // them).  An item of CG = min(centres, P2Q_THREADS / 2) slots gives a
+        // lane ceil(sources / (P2Q_THREADS / CG)) pairs per pass over its
+        // centres; a leaf whose near list would give a lane more than
+        // kP2qLanePairs is split into the fewest groups of consecutive
+        // centres that stay within it, so that one crowded leaf does not hold
+        // its workgroup long after the rest have drained.  Items run in order
+        // of decreasing lane work (each centre's result is independent of the
+        // order and of the split).
+        auto lane_pairs = [](long long n_c, long long n_s) {
+            long long cg = std::max(1LL, std::min(n_c, (long long)P2Q_THREADS / 2));
+            long long parts = P2Q_THREADS / cg;
+            return ((n_s + parts - 1) / parts) * ((n_c + cg - 1) / cg);
+        };
+        std::vector<int32_t> qidx;
+        std::vector<std::array<int32_t, 4>> qitems;
+        std::vector<long long> qwork;
+        G->qbx.Pmax = 0;
         for (int b = 0; b < nb; ++b) {
             if (!(pl.leaf[b] && has_ctr(b))) continue;
-            long long nsrc = 0;
-            for (int i = ns[b]; i < ns[b + 1]; ++i) nsrc += pl.src_end[nidx[i]] - pl.src_begin[nidx[i]];
-            qwork[b] = nsrc * (pl.ctr_end[b] - pl.ctr_begin[b]);
-            qlist.push_back(b);
-        }
-        std::stable_sort(qlist.begin(), qlist.end(), [&](int a, int b) { return qwork[a] > qwork[b]; });
-        G->qbx.n = (int)qlist.size();
-        G->qbx.Pmax = 0;
-        for (int b : qlist) G->qbx.Pmax = std::max(G->qbx.Pmax, pl.P[pl.lev[b]]);
-        G->qbx.d = ar.upload(qlist);
-        // near-list sources of every leaf of the P2QBXL list, in list order
-        std::vector<int32_t> qs0(1, 0), qidx;
-        for (int b : qlist) {
+            G->qbx.Pmax = std::max(G->qbx.Pmax, pl.P[pl.lev[b]]);
+            int q0 = (int)qidx.size();
             for (int i = ns[b]; i < ns[b + 1]; ++i)
                 for (int j = pl.src_begin[nidx[i]]; j < pl.src_end[nidx[i]]; ++j) qidx.push_back(j);
-            qs0.push_back((int32_t)qidx.size());
+            int q1 = (int)qidx.size();
+            long long nc = pl.ctr_end[b] - pl.ctr_begin[b], nsrc = q1 - q0, ng = 1;
+            while (ng < nc && lane_pairs((nc + ng - 1) / ng, nsrc) > kP2qLanePairs) ++ng;
+            for (long long k = 0; k < ng; ++k) {
+                int a = pl.ctr_begin[b] + (int)(k * nc / ng), e = pl.ctr_begin[b] + (int)((k + 1) * nc / ng);
+                qitems.push_back({a, e, q0, q1});
+                qwork.push_back(lane_pairs(e - a, nsrc));
+            }
         }
-        g.qsrc_start = ar.upload(qs0);
+        std::vector<int> qord(qitems.size());
+        for (size_t i = 0; i < qord.size(); ++i) qord[i] = (int)i;
+        std::stable_sort(qord.begin(), qord.end(), [&](int a, int b) { return qwork[a] > qwork[b]; });
+        std::vector<int32_t> qflat;
+        for (int i : qord) qflat.insert(qflat.end(), qitems[i].begin(), qitems[i].end());
+        G->qbx.n = (int)qord.size();
+        G->qbx.d = ar.upload(qflat);
         g.qsrc_idx = ar.upload(qidx);
         // sources of all X-list boxes of every box of the X-list P2L list, in list order
         std::vector<int32_t> xs0(1, 0), xidx;

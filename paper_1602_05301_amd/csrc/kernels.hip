@@ -927,15 +927,16 @@ __device__ void p2qbxl_finish(cd *acc, int G, int p, bool write, cd *dst, long l
     }
 }
 
-// One workgroup of P2Q_THREADS lanes per leaf: lane = (centre slot, part)
-// with CG = (centres in the leaf, at most P2Q_THREADS / 2) slots and
-// P2Q_THREADS / CG parts, so few lanes idle whatever the centre count.  The
-// leaf's near-list sources (flattened on the host, in list order) are staged
-// in LDS P2Q_SCH at a time and go round-robin to the parts.  The parts of a
-// centre are then summed in part order through LDS, P2Q_RED coefficients at
-// a time ([coefficient][lane] layout: conflict-free writes and reads).
+// One workgroup of P2Q_THREADS lanes per work item (a group of one leaf's
+// centres): lane = (centre slot, part) with CG = (centres in the item, at
+// most P2Q_THREADS / 2) slots and P2Q_THREADS / CG parts, so few lanes idle
+// whatever the centre count.  The leaf's near-list sources (flattened on the
+// host) are staged in LDS P2Q_SCH at a time and go round-robin to the parts.
+// The parts of a centre are then summed in part order through LDS, P2Q_RED
+// coefficients at a time ([coefficient][lane] layout: conflict-free writes
+// and reads).  The host splits a leaf into several items when one would give
+// a lane many more pairs than the typical leaf.
 constexpr int P2Q_SCH = 256;
-constexpr int P2Q_THREADS = 128;   // lanes per leaf
 constexpr int P2Q_RED = 8;         // coefficients per reduction round
 
 size_t p2qbxl_lds_bytes()
@@ -944,7 +945,7 @@ size_t p2qbxl_lds_bytes()
 }
 
 template <int PB>
-__device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int *list, const cd *qs, const cd *qd, cd *coef, BlockId bid)
+__device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int *items, const cd *qs, const cd *qd, cd *coef, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     constexpr int NE = 2 * PB + 1;
@@ -953,15 +954,14 @@ __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int 
     cd *QD = QS + P2Q_SCH;                              // [P2Q_SCH]
     double *SX = reinterpret_cast<double *>(QD + P2Q_SCH);
     double *SY = SX + P2Q_SCH, *NX = SY + P2Q_SCH, *NY = NX + P2Q_SCH;
-    int b = list[bid.x];
-    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
+    const int *it = items + 4 * bid.x;
+    int c0 = it[0], c1 = it[1], q0 = it[2], total = it[3] - q0;
     int CG = max(1, min(c1 - c0, P2Q_THREADS / 2));
     int parts = P2Q_THREADS / CG;
     int tid = threadIdx.x;
     int gi = tid % CG, part = tid / CG;
     int p = g.p;
     long long ncoef = 2 * p + 1;
-    int q0 = g.qsrc_start[bid.x], total = g.qsrc_start[bid.x + 1] - q0;
     for (int cg = c0; cg < c1; cg += CG) {
         int i = cg + gi, ncg = min(CG, c1 - cg);
         bool active = part < parts && i < c1;
@@ -1012,9 +1012,9 @@ __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int 
 }
 
 template <int PB>
-__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *list, const cd *qs, const cd *qd, cd *coef)
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *items, const cd *qs, const cd *qd, cd *coef)
 {
-    p2qbxl_body<PB>(g, nd, list, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+    p2qbxl_body<PB>(g, nd, items, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // Direct mode: all sources to every centre (Sec. 3.2, oversampled coefficient sum).
@@ -1845,24 +1845,24 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
 }
 
 template <int PB>
-static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
                                   const cd *qd, cd *coef, hipStream_t s)
 {
-    k_p2qbxl<PB><<<n, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, list, qs, qd, coef);
+    k_p2qbxl<PB><<<n, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, items, qs, qd, coef);
     return hipGetLastError();
 }
 
-hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
                          const cd *qd, cd *coef, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, list, n, qs, qd, coef, s);
-    if (g.p <= 12) return p2qbxl_dispatch<12>(g, nd, list, n, qs, qd, coef, s);
-    if (g.p <= 14) return p2qbxl_dispatch<14>(g, nd, list, n, qs, qd, coef, s);
-    if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, list, n, qs, qd, coef, s);
-    if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, list, n, qs, qd, coef, s);
-    if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, list, n, qs, qd, coef, s);
-    return p2qbxl_dispatch<40>(g, nd, list, n, qs, qd, coef, s);
+    if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 12) return p2qbxl_dispatch<12>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 14) return p2qbxl_dispatch<14>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, items, n, qs, qd, coef, s);
+    return p2qbxl_dispatch<40>(g, nd, items, n, qs, qd, coef, s);
 }
 
 template <int PB>

@@ -39,8 +39,9 @@ struct DevGeom {
     const QBX_G int *U_start, *U_idx, *V_start, *V_idx, *V_off, *W_start, *W_idx, *X_start, *X_idx;
     // near list of a leaf = U list + W boxes summed directly; far W = the rest
     const QBX_G int *near_start, *near_idx, *wf_start, *wf_idx;
-    // near-list sources of the i-th leaf of the P2QBXL list: qsrc_idx[qsrc_start[i]..]
-    const QBX_G int *qsrc_start, *qsrc_idx;
+    // near-list sources of the leaves with centres, one run per leaf; a
+    // P2QBXL work item names its leaf's run
+    const QBX_G int *qsrc_idx;
     // X-list sources of the i-th box of the X-list P2L list: xsrc_idx[xsrc_start[i]..]
     const QBX_G int *xsrc_start, *xsrc_idx;
     const QBX_G int *src_box, *ctr_box;              // leaf (level >= 2) of each source / centre, or -1
@@ -167,7 +168,12 @@ hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, 
                        hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, hipStream_t s);
-hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *list, int n, const cd *qs,
+// P2QBXL: one workgroup of P2Q_THREADS lanes per work item.  An item is
+// four ints {c0, c1, q0, q1}: centres [c0, c1) of one leaf (sorted order) and
+// that leaf's near-list sources qsrc_idx[q0, q1).  The lanes form
+// CG = min(c1 - c0, P2Q_THREADS / 2) centre slots of P2Q_THREADS / CG parts.
+constexpr int P2Q_THREADS = 128;
+hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
                          const cd *qd, cd *coef, hipStream_t s);
 hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *coef,
                                 hipStream_t s);
