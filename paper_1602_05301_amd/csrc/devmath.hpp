@@ -49,11 +49,26 @@ __host__ __device__ __forceinline__ cd cdiv(cd a, cd b)
     return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
 }
 
-// Miller start index for J_0..J_N at argument x.
+// Miller start index M for J_0..J_N at argument x (the recurrence starts
+// from f_{M+1} = 0).  Starting there leaves a relative error of about
+// ((M+1)/n) (J_{M+1}/J_n)^2 in J_n.  For orders k + 1 >= x the ratios obey
+// J_{k+1}/J_k = x / (2(k+1) - x J_{k+2}/J_{k+1}) <= x / (2(k+1) - x), so
+// from k0 = max(N, ceil x) their product bounds J_M / J_k0; M is the first
+// order where it falls below 1e-10.  For small x that is a few orders above
+// N, which keeps the recurrence short and its dynamic range small.  M never
+// exceeds the classical max(x, N) + 24 + 4 cbrt(max(x, N) + 1), which is
+// what governs when x is near or above N (there the bound decays slowly).
 __host__ __device__ __forceinline__ int miller_start(double x, int N)
 {
     double m = x > (double)N ? x : (double)N;
-    return (int)m + 24 + (int)(4.0 * cbrt(m + 1.0));
+    int cap = (int)m + 24 + (int)(4.0 * cbrt(m + 1.0));
+    int k = (int)ceil(m);
+    double bound = 1.0;
+    while (k < cap && bound > 1e-10) {
+        bound *= x / (2.0 * (k + 1) - x);
+        ++k;
+    }
+    return k;
 }
 
 // J_n(x), n = 0..N, written to out[n * stride].  x >= 0.
