@@ -224,13 +224,15 @@ qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
 qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
                           const void *const *sigma_s, const void *const *sigma_d, void *const *u);
 /* qbx_geom_autotune: pick the M2L kernel configuration that makes this
- * geometry's evaluation fastest.  The candidates take turns over 7 rounds of
- * whole evaluations with n_dens zero densities (HIP events on the context's
- * stream; the first round warms up; temporary device buffers; synchronises
- * the stream), and each keeps its fastest time.  Candidates: columns staged
- * in LDS with w waves per tile, w the row-block count of most V pairs or
- * about half of it, and the direct-load kernel.  They compute the same sums in the same order, so results do not
- * change.  *choice_out (may be NULL) receives the waves per tile chosen, 0
+ * geometry's evaluation fastest.  The candidates take turns over 9 rounds,
+ * each a sample of 4 whole evaluations with n_dens zero densities (HIP
+ * events on the context's stream; the first round warms up; temporary device
+ * buffers; synchronises the stream), and each keeps its fastest sample.
+ * Candidates: columns staged in LDS with w waves per tile, w the row-block
+ * count of most V pairs (the default) or about half of it, and the
+ * direct-load kernel; another candidate replaces the default only when at
+ * least 1% faster.  They compute the same sums in the same order, so results
+ * do not change.  *choice_out (may be NULL) receives the waves per tile chosen, 0
  * for the direct kernel.  Overwrites the geometry's scratch (no evaluation
  * may be in flight on it). */
 qbx_status qbx_geom_autotune(qbx_geom geom, int32_t n_dens, int32_t *choice_out);

@@ -1509,22 +1509,28 @@ qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
     G->profile = false;
     G->graph_on = false;
     // rounds over the candidates in turn (drift of clocks and caches hits
-    // them alike); each keeps its fastest evaluation; round 0 warms up
-    constexpr int kRounds = 7;
+    // them alike); a sample is kEvals evaluations back to back and each
+    // candidate keeps its fastest sample; round 0 warms up.  Another
+    // candidate replaces the default only when it is kMargin faster: the
+    // candidates differ by a few per cent of an evaluation at most, about
+    // the spread of single samples.
+    constexpr int kRounds = 9, kEvals = 4;
+    constexpr double kMargin = 0.99;
     std::vector<double> best_of(cand.size(), 1e300);
     for (int rep = 0; rep < kRounds; ++rep)
         for (size_t ci = 0; ci < cand.size(); ++ci) {
             G->m2l_nw = cand[ci];
-            bool ok = hipEventRecord(a, s) == hipSuccess &&
-                      eval_chunks(G, n_dens, dsig, nullptr, du, nullptr, s, G->ctx->lane) == QBX_OK &&
-                      hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+            bool ok = hipEventRecord(a, s) == hipSuccess;
+            for (int k = 0; ok && k < kEvals; ++k)
+                ok = eval_chunks(G, n_dens, dsig, nullptr, du, nullptr, s, G->ctx->lane) == QBX_OK;
+            ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
             float ms = 0.f;
             if (ok && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess)
                 best_of[ci] = std::min(best_of[ci], (double)ms);
         }
     int pick = nr;
-    double best = 1e300;
-    for (size_t ci = 0; ci < cand.size(); ++ci)
+    double best = best_of[0] * kMargin;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
         if (best_of[ci] < best) { best = best_of[ci]; pick = cand[ci]; }
     G->profile = prof;
     G->graph_on = graph;

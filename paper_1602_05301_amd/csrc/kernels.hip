@@ -158,6 +158,23 @@ size_t p2m_lds_bytes(int nd, int P, int ch)
                          3 * sizeof(double));
 }
 
+// u^k for a unit complex u and any integer k (u^{-1} = conj(u)) by binary
+// powering, at most 2 log2|k| products.  Where a lane needs one phase per
+// long run of orders, sincos of k theta is as cheap and needs no loop; this
+// pays where it replaces the angle altogether.
+__device__ __forceinline__ cd unit_ipow(cd u, int k)
+{
+    cd v = k >= 0 ? u : conj(u);
+    int n = k >= 0 ? k : -k;
+    cd r = mk(1.0, 0.0);
+    while (n) {
+        if (n & 1) r = r * v;
+        v = v * v;
+        n >>= 1;
+    }
+    return r;
+}
+
 __device__ __forceinline__ cd p2m_basis(const cd *row, int m)
 {
     if (m >= 0) return row[m];
@@ -1321,7 +1338,7 @@ size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
 {
     int np = 2 * P + 1, N = P + p + QBLK - 1;
     return sizeof(cd) * ((size_t)nd * np + (size_t)cg) +
-           sizeof(double) * ((size_t)cg * (N + 1) + 3 * (size_t)cg);
+           sizeof(double) * ((size_t)cg * (N + 1));
 }
 
 __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG, BlockId bid)
@@ -1338,7 +1355,6 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
     cd *Gb = reinterpret_cast<cd *>(lds_raw);          // [nd][np]
     cd *U = Gb + nd * np;                              // [QCG]
     double *Jt = reinterpret_cast<double *>(U + QCG);  // [QCG][N+1]
-    double *TH = Jt + QCG * (N + 1);                   // [QCG]
     const double *iw = g.invW + g.Woff[l];
     const cd *src = loc + g.box_off[b] * nd;
     for (int i = tid; i < nd * np; i += blockDim.x) {
@@ -1354,7 +1370,6 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
             double dx = mx - g.cx[i], dy = my - g.cy[i];
             double r = sqrt(dx * dx + dy * dy);
             U[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
-            TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
         }
         for (int i = tid; i < cnt * (N + 1); i += blockDim.x) {
             int n = i / cnt, t = i - n * cnt;
@@ -1375,15 +1390,12 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
             const double *jt = Jt + t * (N + 1);
             const cd *G = Gb + d * np + P;
             cd u = U[t];
-            double th = TH[t];
             if (active) {
                 int na, nb;
                 chunk_of(l0 - P, l0 + QBLK - 1 + P, sp, &na, &nb);
                 if (na <= nb) {
                     int k = l0 - (na - QBLK);                 // element of the first step
-                    double sn, cs;
-                    sincos((double)k * th, &sn, &cs);
-                    cd ph = mk(cs, -sn);                      // conj(u)^k
+                    cd ph = unit_ipow(conj(u), k);            // conj(u)^k
 #pragma unroll 1
                     for (int n0 = na - QBLK; n0 <= nb; n0 += QBLK) {
 #pragma unroll
@@ -1420,9 +1432,7 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
                 acc[e] = mk(re, im);
             }
             if (active && sp == 0) {
-                double sn0, cs0;
-                sincos((double)l0 * th, &sn0, &cs0);
-                cd ul = mk(cs0, sn0);                         // u^l
+                cd ul = unit_ipow(u, l0);                     // u^l
                 int ci = cg0 + t;
 #pragma unroll
                 for (int e = 0; e < QBLK; ++e) {
@@ -1458,7 +1468,7 @@ __device__ __forceinline__ void qbx_eval_body(const DevGeom &g, int nd, const cd
     double dx = g.tx[m] - g.cx[i], dy = g.ty[m] - g.cy[i];
     double rho = sqrt(dx * dx + dy * dy);
     double x = g.omega * rho;
-    double th = atan2(dy, dx);
+    cd v = rho > 0.0 ? mk(dx / rho, dy / rho) : mk(1.0, 0.0);    // e^{i theta}
     for (int d = 0; d < nd; ++d) {
         const cd *a = coef + (long long)d * nq * g.nc + i;
         cd a0 = a[(long long)p * g.nc];
@@ -1470,15 +1480,14 @@ __device__ __forceinline__ void qbx_eval_body(const DevGeom &g, int nd, const cd
         double inv = 2.0 / x;
         double fp1 = 0.0, f = 1e-280, f1 = 0.0;
         cd S = mk(0.0, 0.0);
+        cd ep = unit_ipow(conj(v), p);  // e^{-i n theta} at n = p, stepped down with n
         for (int n = M; n > 0; --n) {
             if (n <= p) {
-                double sn, cs;
-                sincos((double)n * th, &sn, &cs);
-                cd ep = mk(cs, -sn);    // e^{-i n theta}
                 cd t = a[(long long)(p + n) * g.nc] * ep;
                 cd tm = a[(long long)(p - n) * g.nc] * conj(ep);
                 if (n & 1) tm = neg(tm);
                 S = S + f * (t + tm);
+                ep = ep * v;
             }
             if (n == 1) f1 = f;
             double fm = (n * inv) * f - fp1;
