@@ -168,6 +168,39 @@ qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out);
 qbx_status qbx_geom_destroy(qbx_geom geom);
 qbx_status qbx_geom_stats(qbx_geom geom, qbx_stats *out);
 qbx_status qbx_geom_association(qbx_geom geom, int32_t *tgt_ctr_out);
+/* qbx_geom_area_query: area queries (Sec. 5: the area query definition,
+ * peer boxes and the guiding-box algorithm) on the geometry's tree, on the
+ * device.  Query i is the closed square |x - (qx[i], qy[i])|_inf <= qr[i];
+ * its result is every leaf box (plan numbering, as qbx_plan_boxes) whose
+ * closed square meets it, in the order the query visits them.  A query
+ * centre outside the root square is answered from the root (all leaves
+ * examined); a negative or NaN radius gives no leaves.  qx, qy, qr: device
+ * arrays of n doubles.  start: device int64[n + 1], written with the
+ * offsets of each query's leaves (start[n] = total).  leaves: device
+ * int32[total], or NULL to count only.  *total_out (host, may be NULL)
+ * receives the total.  Runs on the context's stream and synchronises it.
+ * Errors: QBX_E_INVAL (n < 0, null arrays), QBX_E_NOMEM, QBX_E_DEVICE. */
+qbx_status qbx_geom_area_query(qbx_geom geom, int64_t n, const double *qx, const double *qy,
+                               const double *qr, int64_t *start, int32_t *leaves,
+                               int64_t *total_out);
+/* qbx_geom_associate: target association (Sec. 6.1) on the device through
+ * area queries, by the rule of qbx_plan_create: the nearest centre i with
+ * |t - c_i| <= cr_i (1 + eps_assoc), ties to the lowest index.  As in the
+ * paper, each centre is entered in the lists of the leaves its square meets
+ * (an area query per centre, with the centre's own eligibility radius), and
+ * each source in those its sh/4 square meets; a target then scans the list
+ * of the leaf that holds it (quadrants the tree leaves empty count as
+ * leaves of their own).  tx, ty: device arrays of n_tgt doubles (any
+ * points; targets outside the root square are handled exactly).
+ * tgt_ctr_out: device int32[n_tgt], the centre (user numbering) or -1 for
+ * the smooth rule.  *n_fail_out (host, may be NULL): targets within sh_j/4
+ * of a source j with no eligible centre, where qbx_plan_create fails with
+ * QBX_E_ASSOC.  The comparisons round as the host's, so results agree with
+ * qbx_plan_association bit for bit.  Runs on the context's stream and
+ * synchronises it; temporary device buffers.  Errors: QBX_E_INVAL,
+ * QBX_E_NOMEM, QBX_E_DEVICE. */
+qbx_status qbx_geom_associate(qbx_geom geom, int64_t n_tgt, const double *tx, const double *ty,
+                              int32_t *tgt_ctr_out, int64_t *n_fail_out);
 /* qbx_geom_bytes: device memory the geometry holds once it has evaluated
  * n_dens densities: the resident part (points, tree, lists, tables) plus the
  * evaluation scratch (charges, expansions, per-pair rows, radial sequences,

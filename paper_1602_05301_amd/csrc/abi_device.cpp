@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "abi_common.hpp"
+#include "areaquery.hpp"
 #include "kernels.hpp"
 
 using namespace qbx;
@@ -1546,6 +1547,165 @@ qbx_status qbx_geom_graph(qbx_geom G, int32_t enable)
     if (!G) return fail(QBX_E_INVAL, "null geometry");
     if (!G->ctx->gstream) return fail(QBX_E_UNSUPPORTED, "graph stream unavailable");
     G->graph_on = enable != 0;
+    return QBX_OK;
+}
+
+}  // extern "C"
+
+// ---- area queries and association on the device ---------------------------
+namespace {
+
+// Temporary device buffers of one call, freed when it returns.
+struct DevTmp {
+    std::vector<void *> ptrs;
+    hipError_t err = hipSuccess;
+    template <class T> T *alloc(size_t n)
+    {
+        void *q = nullptr;
+        if (err == hipSuccess) err = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(q);
+        return static_cast<T *>(q);
+    }
+    ~DevTmp()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+};
+
+AQTree aq_tree(const qbx_geom_s *G)
+{
+    AQTree t;
+    t.bcx = G->g.bcx;
+    t.bcy = G->g.bcy;
+    t.blev = G->g.blev;
+    t.leaf = G->g.leaf;
+    t.child4 = G->g.child4;
+    t.R0 = G->pl.R0;
+    return t;
+}
+
+// Exclusive scan of n device counts into start[0..n] (device), on the host.
+hipError_t scan_counts(const int32_t *cnt, int64_t n, int64_t *start, int64_t *total, hipStream_t s)
+{
+    std::vector<int32_t> h((size_t)n);
+    std::vector<int64_t> st((size_t)n + 1, 0);
+    hipError_t e = n ? hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) : hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int64_t i = 0; i < n; ++i) st[i + 1] = st[i] + h[i];
+    *total = st[n];
+    e = hipMemcpyAsync(start, st.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+qbx_status aq_check(hipError_t e, const int *d_err, hipStream_t s, const char *what)
+{
+    int herr = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    if (herr) return fail(QBX_E_DEVICE, std::string(what) + ": traversal stack exceeded");
+    return QBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qbx_status qbx_geom_area_query(qbx_geom G, int64_t n, const double *qx, const double *qy,
+                               const double *qr, int64_t *start, int32_t *leaves, int64_t *total_out)
+{
+    if (!G || n < 0 || !start || (n > 0 && (!qx || !qy || !qr))) return fail(QBX_E_INVAL, "area query: bad argument");
+    hipError_t e = hipSetDevice(G->ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    hipStream_t s = G->ctx->stream;
+    AQTree t = aq_tree(G);
+    DevTmp tmp;
+    int32_t *cnt = tmp.alloc<int32_t>((size_t)n);
+    int *err = tmp.alloc<int>(1);
+    if (tmp.err != hipSuccess) return fail(QBX_E_NOMEM, "area query buffers");
+    e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_area_query(t, n, qx, qy, qr, cnt, nullptr, nullptr, err, s);
+    qbx_status st = aq_check(e, err, s, "area query (count)");
+    if (st != QBX_OK) return st;
+    int64_t total = 0;
+    e = scan_counts(cnt, n, start, &total, s);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("area query (scan): ") + hipGetErrorString(e));
+    if (total_out) *total_out = total;
+    if (!leaves) return QBX_OK;
+    e = launch_area_query(t, n, qx, qy, qr, nullptr, start, leaves, err, s);
+    return aq_check(e, err, s, "area query (fill)");
+}
+
+qbx_status qbx_geom_associate(qbx_geom G, int64_t n_tgt, const double *tx, const double *ty,
+                              int32_t *tgt_ctr_out, int64_t *n_fail_out)
+{
+    if (!G || n_tgt < 0 || (n_tgt > 0 && (!tx || !ty || !tgt_ctr_out))) return fail(QBX_E_INVAL, "associate: bad argument");
+    hipError_t e = hipSetDevice(G->ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    hipStream_t s = G->ctx->stream;
+    const Plan &pl = G->pl;
+    AQTree t = aq_tree(G);
+    int64_t nkey = (int64_t)kAqKeysPerBox * pl.n_boxes();
+    // radii in tree order
+    std::vector<double> hcr((size_t)pl.nc), hsh((size_t)pl.ns);
+    for (int64_t k = 0; k < pl.nc; ++k) hcr[k] = pl.cr[pl.ctr_order[k]];
+    for (int64_t k = 0; k < pl.ns; ++k) hsh[k] = pl.sh[pl.src_order[k]];
+    DevTmp tmp;
+    double *dcr = tmp.alloc<double>(hcr.size()), *dsh = tmp.alloc<double>(hsh.size());
+    int32_t *ccnt = tmp.alloc<int32_t>(nkey), *scnt = tmp.alloc<int32_t>(nkey);
+    int64_t *cstart = tmp.alloc<int64_t>(nkey + 1), *sstart = tmp.alloc<int64_t>(nkey + 1);
+    int *err = tmp.alloc<int>(1);
+    unsigned long long *nfail = tmp.alloc<unsigned long long>(1);
+    if (tmp.err != hipSuccess) return fail(QBX_E_NOMEM, "associate buffers");
+    e = hipMemcpyAsync(dcr, hcr.data(), sizeof(double) * hcr.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dsh, hsh.data(), sizeof(double) * hsh.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nkey, s);
+    if (e == hipSuccess) e = hipMemsetAsync(scnt, 0, sizeof(int32_t) * nkey, s);
+    if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipMemsetAsync(nfail, 0, sizeof(unsigned long long), s);
+    // every centre enters the regions its eligibility square meets, every
+    // source those its sh/4 square meets (squares a relative 1e-12 wider:
+    // the final tests are exact)
+    const double widen = 1.0 + 1e-12, ea = pl.opt.eps_assoc;
+    if (e == hipSuccess)
+        e = launch_region_lists(t, pl.nc, G->g.cx, G->g.cy, dcr, (1.0 + ea) * widen, ccnt, nullptr, nullptr,
+                                nullptr, err, s);
+    if (e == hipSuccess)
+        e = launch_region_lists(t, pl.ns, G->g.sx, G->g.sy, dsh, 0.25 * widen, scnt, nullptr, nullptr, nullptr,
+                                err, s);
+    qbx_status st = aq_check(e, err, s, "associate (count)");
+    if (st != QBX_OK) return st;
+    int64_t ctot = 0, stot = 0;
+    e = scan_counts(ccnt, nkey, cstart, &ctot, s);
+    if (e == hipSuccess) e = scan_counts(scnt, nkey, sstart, &stot, s);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("associate (scan): ") + hipGetErrorString(e));
+    int32_t *clist = tmp.alloc<int32_t>((size_t)ctot), *slist = tmp.alloc<int32_t>((size_t)stot);
+    if (tmp.err != hipSuccess) return fail(QBX_E_NOMEM, "associate lists");
+    // the count arrays serve again as fill cursors
+    e = hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nkey, s);
+    if (e == hipSuccess) e = hipMemsetAsync(scnt, 0, sizeof(int32_t) * nkey, s);
+    if (e == hipSuccess)
+        e = launch_region_lists(t, pl.nc, G->g.cx, G->g.cy, dcr, (1.0 + ea) * widen, nullptr, cstart, ccnt,
+                                clist, err, s);
+    if (e == hipSuccess)
+        e = launch_region_lists(t, pl.ns, G->g.sx, G->g.sy, dsh, 0.25 * widen, nullptr, sstart, scnt, slist,
+                                err, s);
+    AQAssoc a;
+    a.cx = G->g.cx; a.cy = G->g.cy; a.cr = dcr; a.ctr_user = G->g.ctr_perm;
+    a.sx = G->g.sx; a.sy = G->g.sy; a.sh = dsh;
+    a.cstart = cstart; a.sstart = sstart; a.clist = clist; a.slist = slist;
+    a.ea = ea;
+    if (e == hipSuccess) e = launch_associate(t, a, n_tgt, tx, ty, tgt_ctr_out, nfail, s);
+    st = aq_check(e, err, s, "associate");
+    if (st != QBX_OK) return st;
+    unsigned long long hf = 0;
+    e = hipMemcpyAsync(&hf, nfail, sizeof(hf), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("associate: ") + hipGetErrorString(e));
+    if (n_fail_out) *n_fail_out = (int64_t)hf;
     return QBX_OK;
 }
 

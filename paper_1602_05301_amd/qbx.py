@@ -29,7 +29,7 @@ EXPORTS = [
     "qbx_geom_association", "qbx_geom_bytes", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times",
     "qbx_geom_work",
     "qbx_eval_batch", "qbx_geom_autotune",
-    "qbx_eval",
+    "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -111,6 +111,8 @@ def lib():
     L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
     L.qbx_geom_work.argtypes = [_vp, i32, _dp]
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    L.qbx_geom_area_query.argtypes = [_vp, i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(i64)]
+    L.qbx_geom_associate.argtypes = [_vp, i64, _vp, _vp, _vp, ctypes.POINTER(i64)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes"):
@@ -268,6 +270,41 @@ class Geometry:
 
     def profile(self, enable: bool = True):
         _check(lib().qbx_geom_profile(self._h, int(bool(enable))))
+
+    def area_query(self, qx, qy, qr):
+        """Leaves (plan box numbering) meeting the squares |x - (qx, qy)|_inf <= qr,
+        qbx_geom_area_query.  qx, qy, qr: float64 CUDA tensors of one length.
+        Returns (start int64[n + 1], leaves int32[start[n]]) on the device."""
+        import torch
+        n = int(qx.numel())
+        for t in (qx, qy, qr):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("queries must be contiguous float64 CUDA tensors of one length")
+        start = torch.empty(n + 1, dtype=torch.int64, device=qx.device)
+        total = ctypes.c_int64(0)
+        ptr = lambda t: _vp(t.data_ptr())
+        _check(lib().qbx_geom_area_query(self._h, n, ptr(qx), ptr(qy), ptr(qr), ptr(start), None,
+                                         ctypes.byref(total)))
+        leaves = torch.empty(max(total.value, 1), dtype=torch.int32, device=qx.device)
+        _check(lib().qbx_geom_area_query(self._h, n, ptr(qx), ptr(qy), ptr(qr), ptr(start), ptr(leaves),
+                                         None))
+        return start, leaves[: total.value]
+
+    def associate(self, tx, ty):
+        """Centre (user numbering) or -1 per target by the planner's rule,
+        computed on the device through area queries, qbx_geom_associate.
+        tx, ty: float64 CUDA tensors.  Returns (tgt_ctr int32 tensor, number of
+        targets in Gamma_near without an eligible centre)."""
+        import torch
+        n = int(tx.numel())
+        for t in (tx, ty):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("targets must be contiguous float64 CUDA tensors of one length")
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=tx.device)
+        nf = ctypes.c_int64(0)
+        _check(lib().qbx_geom_associate(self._h, n, _vp(tx.data_ptr()), _vp(ty.data_ptr()),
+                                        _vp(out.data_ptr()), ctypes.byref(nf)))
+        return out[:n], int(nf.value)
 
     def autotune(self, n_dens: int = 1) -> int:
         """Pick the fastest M2L configuration on this geometry; returns the

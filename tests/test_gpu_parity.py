@@ -505,3 +505,88 @@ def test_autotune_keeps_results(ctx):
     print(f"autotune choice: {choice}", flush=True)
     assert choice >= 0
     assert np.array_equal(before, after)
+
+
+def _leaf_table(pl):
+    """Leaf boxes of a plan with their centres and radii, by the planner's
+    own formula (so the comparisons below round as the library's)."""
+    bx = pl.boxes()
+    R0 = pl.stats()["root_radius"]
+    side = np.ldexp(2.0 * R0, -bx["level"])
+    mx = -R0 + (bx["ix"] + 0.5) * side
+    my = -R0 + (bx["iy"] + 0.5) * side
+    leaves = np.nonzero(bx["leaf"])[0]
+    return R0, leaves, mx[leaves], my[leaves], np.ldexp(R0, -bx["level"][leaves])
+
+
+def test_area_queries_match_brute_force(ctx):
+    """Area queries (leaves meeting a closed square) on the device against a
+    brute-force scan of every leaf: the same set for each query, no repeats.
+    Centres on the curve, inside and outside the root square; radii from
+    1e-5 |b0| to 2.5 |b0|; point queries (r = 0) and an empty square (r < 0)."""
+    from paper_1602_05301_amd import qbx
+    g = inputs.star(128, 16, lobes=7)
+    tc = np.arange(g.n, dtype=np.int32)
+    opts = qbx.options(p=8, leaf_max=16)
+    geo = qbx.Geometry(ctx, g, 20.0, 1e-8, g.sx, g.sy, tc, opts)
+    pl = qbx.Plan(g, 20.0, 1e-8, g.sx, g.sy, tc, opts)
+    R0, leaves, mx, my, rb = _leaf_table(pl)
+    rng = np.random.default_rng(31)
+    j = rng.integers(0, g.n, 900)
+    qx = np.concatenate([g.sx[j], rng.uniform(-R0, R0, 400), rng.uniform(-2 * R0, 2 * R0, 200)])
+    qy = np.concatenate([g.sy[j], rng.uniform(-R0, R0, 400), rng.uniform(-2 * R0, 2 * R0, 200)])
+    qr = R0 * 10.0 ** rng.uniform(-5.0, 0.4, qx.size)
+    qr[:20] = 0.0
+    qr[-1] = -1.0
+    start, lv = geo.area_query(_dev(qx), _dev(qy), _dev(qr))
+    start, lv = start.cpu().numpy(), lv.cpu().numpy()
+    assert start[0] == 0 and start[-1] == lv.size
+    print(f"area queries: {qx.size} queries, {leaves.size} leaves, {lv.size} hits", flush=True)
+    for i in range(qx.size):
+        got = lv[start[i]:start[i + 1]]
+        assert np.unique(got).size == got.size, i
+        lim = qr[i] + rb
+        want = leaves[(np.abs(mx - qx[i]) <= lim) & (np.abs(my - qy[i]) <= lim)] if qr[i] >= 0 else leaves[:0]
+        assert np.array_equal(np.sort(got), want), (i, qx[i], qy[i], qr[i])
+
+
+def _assoc_targets(rng, g, R0):
+    """On-curve nodes, points across the curve at up to 0.7 h (inside and
+    outside expansion disks, some in Gamma_near without a centre), and a grid
+    reaching past the root square."""
+    j = rng.integers(0, g.n, 3000)
+    s = rng.uniform(-0.7, 0.7, j.size) * g.h[j]
+    gx, gy = np.meshgrid(np.linspace(-1.3 * R0, 1.3 * R0, 61), np.linspace(-1.3 * R0, 1.3 * R0, 61))
+    tx = np.concatenate([g.sx, g.sx[j] + s * g.nx[j], gx.ravel()])
+    ty = np.concatenate([g.sy, g.sy[j] + s * g.ny[j], gy.ravel()])
+    return tx, ty
+
+
+@pytest.mark.parametrize("case", ["star", "two_sided", "multiscale"])
+def test_association_on_device_matches_oracle_and_host(ctx, case):
+    """Target association through area queries on the device against the
+    oracle's brute force (centre, smooth rule, or failure in Gamma_near) and,
+    where no target fails, the host planner: bitwise equal."""
+    from paper_1602_05301_amd import qbx
+    rng = np.random.default_rng(41)
+    if case == "multiscale":
+        g, _ = inputs.multiscale_curves(n_curves=6, omega=20.0, nodes=(6000, 9000), box=4.0)
+    else:
+        g = inputs.star(96, 16, lobes=7)
+    geom = inputs.two_sided(g) if case == "two_sided" else g
+    tc = np.arange(g.n, dtype=np.int32)
+    opts = qbx.options(p=8, leaf_max=24)
+    geo = qbx.Geometry(ctx, geom, 20.0, 1e-8, g.sx, g.sy, tc, opts)
+    R0 = geo.stats()["root_radius"]
+    tx, ty = _assoc_targets(rng, g, R0)
+    ref = oracle.associate(tx, ty, geom.cx, geom.cy, geom.cr, geom.sx, geom.sy, geom.h)
+    got, nfail = geo.associate(_dev(tx), _dev(ty))
+    got = got.cpu().numpy()
+    expect = np.where(ref == -2, -1, ref)
+    print(f"association ({case}): {tx.size} targets, {np.sum(ref >= 0)} to centres, "
+          f"{np.sum(ref == -2)} failing", flush=True)
+    assert np.array_equal(got, expect)
+    assert nfail == int(np.sum(ref == -2))
+    ok = ref != -2
+    pl = qbx.Plan(geom, 20.0, 1e-8, tx[ok], ty[ok], None, opts)
+    assert np.array_equal(pl.association(), expect[ok])
