@@ -183,6 +183,19 @@ qbx_status qbx_geom_association(qbx_geom geom, int32_t *tgt_ctr_out);
 qbx_status qbx_geom_area_query(qbx_geom geom, int64_t n, const double *qx, const double *qy,
                                const double *qr, int64_t *start, int32_t *leaves,
                                int64_t *total_out);
+/* qbx_geom_points_near: disk tests through area queries (Sec. 5): hit_out[i]
+ * = 1 if one of the geometry's sources (which = 0) or centres (which = 1)
+ * lies within distance qr[i] of (qx[i], qy[i]), else 0.  The leaves an area
+ * query over the disk's bounding square returns are scanned, with the exact
+ * test dx^2 + dy^2 <= qr^2.  The geometric refinement conditions of Sec. 5
+ * are such tests: Condition 1 (centres as queries, radius h/2, against the
+ * panels' points) and Condition 3 (panel points as queries, radius h/4,
+ * against the centres).  qx, qy, qr: device arrays of n doubles; hit_out:
+ * device int32[n].  A negative or NaN radius gives 0.  Runs on the
+ * context's stream and synchronises it.  Errors: QBX_E_INVAL (n < 0, which
+ * not 0 or 1, null arrays), QBX_E_NOMEM, QBX_E_DEVICE. */
+qbx_status qbx_geom_points_near(qbx_geom geom, int32_t which, int64_t n, const double *qx,
+                                const double *qy, const double *qr, int32_t *hit_out);
 /* qbx_geom_associate: target association (Sec. 6.1) on the device through
  * area queries, by the rule of qbx_plan_create: the nearest centre i with
  * |t - c_i| <= cr_i (1 + eps_assoc), ties to the lowest index.  As in the

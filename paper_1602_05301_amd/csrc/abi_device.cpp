@@ -1639,6 +1639,25 @@ qbx_status qbx_geom_area_query(qbx_geom G, int64_t n, const double *qx, const do
     return aq_check(e, err, s, "area query (fill)");
 }
 
+qbx_status qbx_geom_points_near(qbx_geom G, int32_t which, int64_t n, const double *qx, const double *qy,
+                                const double *qr, int32_t *hit_out)
+{
+    if (!G || n < 0 || (which != 0 && which != 1) || (n > 0 && (!qx || !qy || !qr || !hit_out)))
+        return fail(QBX_E_INVAL, "points_near: bad argument");
+    hipError_t e = hipSetDevice(G->ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    hipStream_t s = G->ctx->stream;
+    DevTmp tmp;
+    int *err = tmp.alloc<int>(1);
+    if (tmp.err != hipSuccess) return fail(QBX_E_NOMEM, "points_near buffers");
+    const DevGeom &g = G->g;
+    e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e == hipSuccess)
+        e = which == 0 ? launch_points_near(aq_tree(G), n, qx, qy, qr, g.src_begin, g.src_end, g.sx, g.sy, hit_out, err, s)
+                       : launch_points_near(aq_tree(G), n, qx, qy, qr, g.ctr_begin, g.ctr_end, g.cx, g.cy, hit_out, err, s);
+    return aq_check(e, err, s, "points_near");
+}
+
 qbx_status qbx_geom_associate(qbx_geom G, int64_t n_tgt, const double *tx, const double *ty,
                               int32_t *tgt_ctr_out, int64_t *n_fail_out)
 {

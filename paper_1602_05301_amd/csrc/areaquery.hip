@@ -164,6 +164,32 @@ __global__ void k_region_lists(AQTree t, int64_t n, const double *x, const doubl
     });
 }
 
+// A point of the disk lies in the square and so in a leaf meeting it.  The
+// leaves are taken with the widened test (the traversal's region mode, whose
+// empty quadrants hold no points and are skipped), so that rounding in the
+// stored box centres cannot drop a point on a leaf's edge; the point test
+// itself is exact.
+__global__ void k_points_near(AQTree t, int64_t n, const double *qx, const double *qy, const double *qr,
+                              const int *pbeg, const int *pend, const double *px, const double *py,
+                              int32_t *hit, int *err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = qx[i], y = qy[i], r = qr[i];
+    int32_t h = 0;
+    if (r >= 0.0) {
+        double r2 = r * r;
+        aq_visit(t, x, y, r, true, err, [&](int, int b) {
+            if (b < 0) return;
+            for (int k = pbeg[b]; k < pend[b] && !h; ++k) {
+                double dx = px[k] - x, dy = py[k] - y;
+                if (dx * dx + dy * dy <= r2) h = 1;
+            }
+        });
+    }
+    hit[i] = h;
+}
+
 // Region (key) holding the point clamped to the root square.  A square
 // about a point of the root that holds the target holds the clamped point
 // too, so the region's list has every candidate of the target.
@@ -236,6 +262,15 @@ hipError_t launch_region_lists(const AQTree &t, int64_t n, const double *x, cons
 {
     if (n <= 0) return hipSuccess;
     k_region_lists<<<aq_blocks(n), kAqThreads, 0, s>>>(t, n, x, y, rad, scale, kcnt, kstart, kcur, list, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_points_near(const AQTree &t, int64_t n, const double *qx, const double *qy,
+                              const double *qr, const int *pbeg, const int *pend, const double *px,
+                              const double *py, int32_t *hit, int *err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_points_near<<<aq_blocks(n), kAqThreads, 0, s>>>(t, n, qx, qy, qr, pbeg, pend, px, py, hit, err);
     return hipGetLastError();
 }
 

@@ -43,6 +43,15 @@ hipError_t launch_region_lists(const AQTree &t, int64_t n, const double *x, cons
                                const int64_t *kstart, int32_t *kcur, int32_t *list, int *err,
                                hipStream_t s);
 
+// Disk tests: hit[i] = 1 if one of the points (px, py) lies within
+// distance qr[i] of (qx[i], qy[i]), else 0.  The points are the tree's
+// sources or centres in tree order, those of box b at [pbeg[b], pend[b]);
+// only the leaves an area query over the disk's bounding square returns are
+// scanned.
+hipError_t launch_points_near(const AQTree &t, int64_t n, const double *qx, const double *qy,
+                              const double *qr, const int *pbeg, const int *pend, const double *px,
+                              const double *py, int32_t *hit, int *err, hipStream_t s);
+
 // Association of n targets (device tx, ty) by the rule of the host planner:
 // the nearest centre k with |t - c_k|^2 <= (cr_k (1 + ea))^2, ties to the
 // lower user index ctr_user[k]; out[m] = that user index or -1.  A target

@@ -29,7 +29,7 @@ EXPORTS = [
     "qbx_geom_association", "qbx_geom_bytes", "qbx_geom_profile", "qbx_geom_graph", "qbx_geom_stage_times",
     "qbx_geom_work",
     "qbx_eval_batch", "qbx_geom_autotune",
-    "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate",
+    "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate", "qbx_geom_points_near",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -113,6 +113,7 @@ def lib():
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
     L.qbx_geom_area_query.argtypes = [_vp, i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(i64)]
     L.qbx_geom_associate.argtypes = [_vp, i64, _vp, _vp, _vp, ctypes.POINTER(i64)]
+    L.qbx_geom_points_near.argtypes = [_vp, i32, i64, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes"):
@@ -289,6 +290,22 @@ class Geometry:
         _check(lib().qbx_geom_area_query(self._h, n, ptr(qx), ptr(qy), ptr(qr), ptr(start), ptr(leaves),
                                          None))
         return start, leaves[: total.value]
+
+    def points_near(self, which: str, qx, qy, qr):
+        """Per query disk |x - (qx, qy)| <= qr: whether one of the geometry's
+        sources (which="sources") or centres (which="centres") lies in it,
+        found through area queries on the device, qbx_geom_points_near.
+        qx, qy, qr: float64 CUDA tensors.  Returns a bool CUDA tensor."""
+        import torch
+        w = {"sources": 0, "centres": 1}[which]
+        n = int(qx.numel())
+        for t in (qx, qy, qr):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("queries must be contiguous float64 CUDA tensors of one length")
+        hit = torch.empty(max(n, 1), dtype=torch.int32, device=qx.device)
+        _check(lib().qbx_geom_points_near(self._h, w, n, _vp(qx.data_ptr()), _vp(qy.data_ptr()),
+                                          _vp(qr.data_ptr()), _vp(hit.data_ptr())))
+        return hit[:n] != 0
 
     def associate(self, tx, ty):
         """Centre (user numbering) or -1 per target by the planner's rule,

@@ -590,3 +590,53 @@ def test_association_on_device_matches_oracle_and_host(ctx, case):
     ok = ref != -2
     pl = qbx.Plan(geom, 20.0, 1e-8, tx[ok], ty[ok], None, opts)
     assert np.array_equal(pl.association(), expect[ok])
+
+
+def test_points_near_matches_brute_force(ctx):
+    """Disk tests through area queries (any source / any centre within r of
+    a query point) against a scan of every point, with the same arithmetic."""
+    from paper_1602_05301_amd import qbx
+    g = inputs.two_sided(inputs.star(96, 16, lobes=7))
+    tc = np.arange(g.sx.size, dtype=np.int32)
+    geo = qbx.Geometry(ctx, g, 20.0, 1e-8, g.sx, g.sy, tc, qbx.options(p=8, leaf_max=24))
+    R0 = geo.stats()["root_radius"]
+    rng = np.random.default_rng(51)
+    qx = rng.uniform(-1.2 * R0, 1.2 * R0, 4000)
+    qy = rng.uniform(-1.2 * R0, 1.2 * R0, 4000)
+    qr = R0 * 10.0 ** rng.uniform(-4.0, -0.5, qx.size)
+    qr[:5] = -1.0
+    for which, px, py in (("sources", g.sx, g.sy), ("centres", g.cx, g.cy)):
+        hit = geo.points_near(which, _dev(qx), _dev(qy), _dev(qr)).cpu().numpy()
+        dx = px[None, :] - qx[:, None]
+        dy = py[None, :] - qy[:, None]
+        want = np.any(dx * dx + dy * dy <= (qr * qr)[:, None], axis=1) & (qr >= 0)
+        print(f"points near ({which}): {hit.sum()} of {qx.size} queries hit", flush=True)
+        assert np.array_equal(hit, want)
+
+
+def test_refinement_on_device_matches_host(ctx):
+    """Conditions 1 and 3 through area queries on the device give the host
+    k-d tree's flags in every round, hence the same refined panels."""
+    from paper_1602_05301_amd.refine import flags, refine
+    f1 = inputs._shape("ellipse", 1.0, 2.0, 0.0, (0.0, 0.0))
+    f2 = inputs._shape("ellipse", 1.0, 2.0, 0.0, (2.02, 0.0))
+    f3 = inputs._shape("star", 0.6, 5, 0.3, (0.9, 2.9))
+    curves = [f1, f2, f3]
+    edges = [np.linspace(0.0, 2.0 * np.pi, 9) for _ in curves]
+    for rnd in range(3):
+        host, _ = flags(curves, edges, 3.0)
+        dev, _ = flags(curves, edges, 3.0, ctx=ctx)
+        for a, b in zip(host, dev):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), rnd
+        new = []
+        for e, (a, b, c, d) in zip(edges, host):
+            bad = a | b | c | d
+            new.append(np.sort(np.concatenate([e, 0.5 * (e[:-1] + e[1:])[bad]])) if bad.any() else e)
+        edges = new
+    r_host = refine(curves, 3.0)
+    r_dev = refine(curves, 3.0, ctx=ctx)
+    print(f"refinement: {r_dev.rounds} rounds, {r_dev.bisected} bisections", flush=True)
+    assert r_dev.rounds == r_host.rounds and r_dev.bisected == r_host.bisected
+    for a, b in zip(r_host.edges, r_dev.edges):
+        assert np.array_equal(a, b)
