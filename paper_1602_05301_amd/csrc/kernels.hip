@@ -348,15 +348,41 @@ __device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const c
     }
 }
 
-__device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, d4 &yr, d4 &yi)
+// Complex products in three real ones (Gauss): P += ar br, Q += ai bi,
+// S += (ar + ai)(br + bi); then Re = P - Q and Im = S - P - Q (cplx3_done).
+// Three matrix-core operations per k-block instead of four, and three
+// independent accumulation chains.  The imaginary part's rounding error is
+// a few ulps of (|ar| + |ai|)(|br| + |bi|), the same order as the plain
+// product's.
+struct Acc3 {
+    d4 p, q, s;
+};
+
+__device__ __forceinline__ Acc3 cplx3_zero()
+{
+    return Acc3{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+}
+
+__device__ __forceinline__ void cplx3_mfma(cd a, cd b, Acc3 &y)
+{
+    y.p = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, y.p, 0, 0, 0);
+    y.q = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, y.q, 0, 0, 0);
+    y.s = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, y.s, 0, 0, 0);
+}
+
+__device__ __forceinline__ void cplx3_done(const Acc3 &y, d4 &yr, d4 &yi)
 {
 #pragma unroll
-    for (int u = 0; u < TB_U; ++u) {
-        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, yi, 0, 0, 0);
-        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, yi, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+        yr[i] = y.p[i] - y.q[i];
+        yi[i] = (y.s[i] - y.p[i]) - y.q[i];
     }
+}
+
+__device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, Acc3 &y)
+{
+#pragma unroll
+    for (int u = 0; u < TB_U; ++u) cplx3_mfma(a[u], b[u], y);
 }
 
 // Two register sets alternate: one is multiplied while the other loads.
@@ -367,13 +393,15 @@ __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, co
     const cd *bs = bptr ? bptr : Arow;          // any readable address when the column is empty
     bool bvalid = bptr != nullptr;
     cd a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
+    Acc3 y = cplx3_zero();
     tb_load(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
         tb_load(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
-        tb_mfma(a0, b0, yr, yi);
+        tb_mfma(a0, b0, y);
         tb_load(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
-        if (kb + TB_U < kb1) tb_mfma(a1, b1, yr, yi);
+        if (kb + TB_U < kb1) tb_mfma(a1, b1, y);
     }
+    cplx3_done(y, yr, yi);
 }
 
 // M2L: one workgroup per 16-column tile, nw waves over its row blocks
@@ -410,7 +438,7 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
     const cd *A = g.m2l_mf + g.m2l_mf_off[t.lo];
     for (int rb = wave; rb < NR; rb += nw) {
         const cd *Ab = A + (long long)rb * NK * 64 + lane;
-        d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+        Acc3 y = cplx3_zero();
         cd a0[TB_U], a1[TB_U];
 #pragma unroll
         for (int u = 0; u < TB_U; ++u) a0[u] = Ab[min(u, NK - 1) * 64];
@@ -422,10 +450,7 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
                 int kk = kb + u;
                 cd bv = X[(min(kk, NK - 1) * 4 + bk) * M2L_XS + bc];
                 if (kk >= NK) bv = mk(0.0, 0.0);
-                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, bv.x, yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, bv.y, yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0[u].y, bv.y, yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].y, bv.x, yi, 0, 0, 0);
+                cplx3_mfma(a0[u], bv, y);
             }
 #pragma unroll
             for (int u = 0; u < TB_U; ++u) a0[u] = Ab[min(kb + 2 * TB_U + u, NK - 1) * 64];
@@ -435,13 +460,12 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
                     int kk = kb + TB_U + u;
                     cd bv = X[(min(kk, NK - 1) * 4 + bk) * M2L_XS + bc];
                     if (kk >= NK) bv = mk(0.0, 0.0);
-                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, bv.x, yr, 0, 0, 0);
-                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, bv.y, yi, 0, 0, 0);
-                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1[u].y, bv.y, yr, 0, 0, 0);
-                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].y, bv.x, yi, 0, 0, 0);
+                    cplx3_mfma(a1[u], bv, y);
                 }
             }
         }
+        d4 yr, yi;
+        cplx3_done(y, yr, yi);
         if (bc < t.ncol) {
             int col = t.col0 + bc;
             cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
