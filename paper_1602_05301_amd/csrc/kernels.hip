@@ -542,14 +542,18 @@ __device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const
     }
 }
 
-__device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, f4 &yr, f4 &yi)
+// The same three-product form as the FP64 translations (cplx3_mfma).
+struct Acc3f {
+    f4 p, q, s;
+};
+
+__device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, Acc3f &y)
 {
 #pragma unroll
     for (int u = 0; u < TB_U; ++u) {
-        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].x, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].y, yi, 0, 0, 0);
-        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[u].y, b[u].y, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, b[u].x, yi, 0, 0, 0);
+        y.p = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].x, y.p, 0, 0, 0);
+        y.q = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, b[u].y, y.q, 0, 0, 0);
+        y.s = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x + a[u].y, b[u].x + b[u].y, y.s, 0, 0, 0);
     }
 }
 
@@ -560,12 +564,18 @@ __device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, 
     const cd *bs = bptr ? bptr : reinterpret_cast<const cd *>(Arow);
     bool bvalid = bptr != nullptr;
     cf a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
+    Acc3f y{{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     tb_load32(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
         tb_load32(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
-        tb_mfma32(a0, b0, yr, yi);
+        tb_mfma32(a0, b0, y);
         tb_load32(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
-        if (kb + TB_U < kb1) tb_mfma32(a1, b1, yr, yi);
+        if (kb + TB_U < kb1) tb_mfma32(a1, b1, y);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        yr[i] = y.p[i] - y.q[i];
+        yi[i] = (y.s[i] - y.p[i]) - y.q[i];
     }
 }
 
