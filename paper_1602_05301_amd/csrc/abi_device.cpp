@@ -447,7 +447,34 @@ qbx_status upload(qbx_geom_s *G)
 
     auto has_ctr = [&](int b) { return pl.ctr_end[b] > pl.ctr_begin[b]; };
     G->p2m = make_list(ar, pl, [&](int b) { return pl.leaf[b] && pl.lev[b] >= 2; });
-    G->xl = make_list(ar, pl, [&](int b) { return pl.X_start[b + 1] > pl.X_start[b]; });
+    {
+        // the same leaves, the most sources first (long workgroups start early)
+        std::vector<int> v;
+        for (int b = 0; b < nb; ++b)
+            if (pl.leaf[b] && pl.lev[b] >= 2) v.push_back(b);
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) {
+            return pl.src_end[a] - pl.src_begin[a] > pl.src_end[c] - pl.src_begin[c];
+        });
+        G->p2m.d = ar.upload(v);
+    }
+    // the X-list P2L list: boxes with an X list, the most X-list sources
+    // first, so that long workgroups start early and short ones fill the
+    // tail (each box's result is independent of the order)
+    std::vector<int> xorder;
+    {
+        std::vector<long long> xw(nb, 0);
+        for (int b = 0; b < nb; ++b) {
+            if (pl.X_start[b + 1] <= pl.X_start[b]) continue;
+            for (int i = pl.X_start[b]; i < pl.X_start[b + 1]; ++i)
+                xw[b] += pl.src_end[pl.X_idx[i]] - pl.src_begin[pl.X_idx[i]];
+            xorder.push_back(b);
+        }
+        std::stable_sort(xorder.begin(), xorder.end(), [&](int a, int c) { return xw[a] > xw[c]; });
+        G->xl.n = (int)xorder.size();
+        G->xl.Pmax = 0;
+        for (int b : xorder) G->xl.Pmax = std::max(G->xl.Pmax, pl.P[pl.lev[b]]);
+        G->xl.d = ar.upload(xorder);
+    }
     G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
     // Split every leaf's W list: boxes summed directly join the near list
     // (P2QBXL), the others go through M2QBXL.
@@ -509,8 +536,7 @@ qbx_status upload(qbx_geom_s *G)
         g.qsrc_idx = ar.upload(qidx);
         // sources of all X-list boxes of every box of the X-list P2L list, in list order
         std::vector<int32_t> xs0(1, 0), xidx;
-        for (int b = 0; b < nb; ++b) {
-            if (pl.X_start[b + 1] <= pl.X_start[b]) continue;
+        for (int b : xorder) {
             for (int i = pl.X_start[b]; i < pl.X_start[b + 1]; ++i)
                 for (int j = pl.src_begin[pl.X_idx[i]]; j < pl.src_end[pl.X_idx[i]]; ++j) xidx.push_back(j);
             xs0.push_back((int32_t)xidx.size());
