@@ -476,6 +476,16 @@ qbx_status upload(qbx_geom_s *G)
         G->xl.d = ar.upload(xorder);
     }
     G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
+    {
+        // the same leaves, the most centres first (long workgroups start early)
+        std::vector<int> v;
+        for (int b = 0; b < nb; ++b)
+            if (pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2) v.push_back(b);
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) {
+            return pl.ctr_end[a] - pl.ctr_begin[a] > pl.ctr_end[c] - pl.ctr_begin[c];
+        });
+        G->l2q.d = ar.upload(v);
+    }
     // Split every leaf's W list: boxes summed directly join the near list
     // (P2QBXL), the others go through M2QBXL.
     {
