@@ -154,6 +154,9 @@ struct qbx_geom_s {
     // and per L2QBXL centre (n-major)
     int srad_rows = 0, crad_rows = 0;
     double *srad = nullptr, *crad = nullptr;
+    // the radial sequences depend on the geometry only: computed on the
+    // first evaluation (once the scratch exists) and kept, like the tables
+    bool rad_ready = false;
     // captured evaluations (qbx_geom_graph), keyed by their arguments
     struct GraphRec {
         int n_dens;
@@ -760,7 +763,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         if (conc) {
             CHK(hipEventRecord(C->ev_fork, st));
             CHK(hipStreamWaitEvent(s1, C->ev_fork, 0));
-            CHK(launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, s1));
+            if (!G->rad_ready) CHK(launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, s1));
             CHK(launch_fill_zero(G->loc, (long long)nd * G->total_coef, s1));
             CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, s1));
             CHK(hipEventRecord(C->ev_x, s1));
@@ -768,6 +771,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_P2M);
+            if (!G->rad_ready) LAUNCH(QBX_STAGE_P2M, pl.ns, launch_src_rad(g, G->srad, G->srad_rows, st));
             LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->srad, G->srad_rows, G->mp, st));
         }
         {
@@ -826,9 +830,13 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
-            if (!conc) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
+            if (!conc && !G->rad_ready) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
             LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, G->loc, G->coef, st));
         }
+        // both radial sequences are enqueued ahead of every later evaluation
+        // on this geometry (P2M and L2QBXL of later calls follow them in
+        // stream order)
+        G->rad_ready = true;
     }
     {
         STAGE(QBX_STAGE_EVAL);

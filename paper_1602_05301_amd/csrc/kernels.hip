@@ -1792,17 +1792,22 @@ static int pick_ch(int Pmax)
     return ch;
 }
 
+hipError_t launch_src_rad(const DevGeom &g, double *srad, int srad_rows, hipStream_t s)
+{
+    if (!g.ns) return hipSuccess;
+    int lanes = rad_lanes(srad_rows);
+    k_src_rad<<<(g.ns + lanes - 1) / lanes, lanes, (size_t)srad_rows * lanes * sizeof(double), s>>>(
+        g, srad_rows, srad);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, double *srad, int srad_rows, cd *mp, hipStream_t s)
+                      const cd *qd, const double *srad, int srad_rows, cd *mp, hipStream_t s)
 {
     if (!n) return hipSuccess;
     if (nd < 1 || nd > 4) return hipErrorInvalidValue;
-    {
-        int lanes = rad_lanes(srad_rows);
-        k_src_rad<<<(g.ns + lanes - 1) / lanes, lanes, (size_t)srad_rows * lanes * sizeof(double), s>>>(
-            g, srad_rows, srad);
-        QBX_LAUNCH_CHECK();
-    }
+    (void)srad_rows;
     // sources per pass sized for four densities: the same passes for every nd
     int ch = 64;
     while (ch > 1 && p2m_lds_bytes(4, Pmax, ch) > PT_LDS) --ch;

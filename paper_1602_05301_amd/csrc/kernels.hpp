@@ -153,8 +153,10 @@ hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t 
 hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
 hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,
                           hipStream_t s);
+// J_n(omega |s - m_b|) of every source in a leaf of level >= 2 (geometry only)
+hipError_t launch_src_rad(const DevGeom &g, double *srad, int srad_rows, hipStream_t s);
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, double *srad, int srad_rows, cd *mp, hipStream_t s);
+                      const cd *qd, const double *srad, int srad_rows, cd *mp, hipStream_t s);
 hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
                            int nrb, const int *plist, cd *mp, hipStream_t s);
 hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
