@@ -640,3 +640,43 @@ def test_refinement_on_device_matches_host(ctx):
     assert r_dev.rounds == r_host.rounds and r_dev.bisected == r_host.bisected
     for a, b in zip(r_host.edges, r_dev.edges):
         assert np.array_equal(a, b)
+
+
+def test_area_queries_edge_cases(ctx):
+    """Empty inputs; a tree that is a single leaf (a query returns the root
+    or nothing); a square wider than the root (every leaf); targets far
+    outside the root (smooth rule, no failures)."""
+    from paper_1602_05301_amd import qbx
+    e = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    # one panel: 16 sources and 16 centres under leaf_max 64, so the root is a leaf
+    g1 = inputs.star(1, 16, lobes=3)
+    tc1 = np.arange(g1.n, dtype=np.int32)
+    geo1 = qbx.Geometry(ctx, g1, 5.0, 1e-8, g1.sx, g1.sy, tc1, qbx.options(p=6, leaf_max=64))
+    start, lv = geo1.area_query(e, e, e)
+    assert start.cpu().numpy().tolist() == [0] and lv.numel() == 0
+    assert geo1.points_near("sources", e, e, e).numel() == 0
+    out, nf = geo1.associate(e, e)
+    assert out.numel() == 0 and nf == 0
+    R0 = geo1.stats()["root_radius"]
+    qx = np.array([0.0, 0.3 * R0, -2.5 * R0, 5.0 * R0])
+    qy = np.array([0.0, -0.2 * R0, 0.5 * R0, 5.0 * R0])
+    qr = np.array([1e-9, 0.1 * R0, 0.1 * R0, 1.0])
+    start, lv = geo1.area_query(_dev(qx), _dev(qy), _dev(qr))
+    start, lv = start.cpu().numpy(), lv.cpu().numpy()
+    got = [lv[start[i]:start[i + 1]].tolist() for i in range(qx.size)]
+    assert got == [[0], [0], [], []], got
+    # a larger tree: a square wider than the root returns every leaf
+    g = inputs.star(64, 16, lobes=5)
+    tc = np.arange(g.n, dtype=np.int32)
+    opts = qbx.options(p=8, leaf_max=16)
+    geo = qbx.Geometry(ctx, g, 10.0, 1e-8, g.sx, g.sy, tc, opts)
+    pl = qbx.Plan(g, 10.0, 1e-8, g.sx, g.sy, tc, opts)
+    leaves = np.nonzero(pl.boxes()["leaf"])[0]
+    R0 = geo.stats()["root_radius"]
+    start, lv = geo.area_query(_dev(np.array([0.1 * R0])), _dev(np.array([-0.2 * R0])),
+                               _dev(np.array([3.0 * R0])))
+    assert np.array_equal(np.sort(lv.cpu().numpy()), leaves)
+    # far targets: the smooth rule, no failures
+    far = np.linspace(3.0, 9.0, 50) * R0
+    out, nf = geo.associate(_dev(far), _dev(-far))
+    assert np.all(out.cpu().numpy() == -1) and nf == 0
