@@ -306,7 +306,23 @@ qbx_status upload(qbx_geom_s *G)
         }
     G->total_vy = vy_tot;
     std::iota(vpos.begin(), vpos.end(), 0);
-    auto vkey = [&](int v) { return pl.lev[vtgt[v]] * 40 + pl.V_off[v]; };
+    // The V offsets fall into 10 orbits of 4 under rotations by 90 degrees.
+    // Rotating the translation vector by r quarter turns multiplies O_n by
+    // i^{rn}, so the matrix of offset R^r c is diag(i^{rj}) M(c) diag(i^{rk}):
+    // pairs are grouped by (level, representative c) and carry r.  The
+    // representative of an orbit is its offset with dx > 0, dy >= 0.
+    int vrep[40], vrot[40];
+    for (int id = 0; id < 40; ++id) {
+        int x, y;
+        v_offset_from_id(id, &x, &y);
+        vrep[id] = -1;
+        vrot[id] = 0;
+        for (int r = 0; r < 4; ++r) {
+            if (x > 0 && y >= 0) { vrep[id] = v_offset_id(x, y); vrot[id] = r; break; }
+            int t = x; x = y; y = -t;   // a quarter turn back (clockwise)
+        }
+    }
+    auto vkey = [&](int v) { return pl.lev[vtgt[v]] * 40 + vrep[pl.V_off[v]]; };
     std::stable_sort(vpos.begin(), vpos.end(), [&](int a, int b) { return vkey(a) < vkey(b); });
     G->m2l_groups.clear();
     G->m2l_Pmax = 0;
@@ -334,14 +350,18 @@ qbx_status upload(qbx_geom_s *G)
     g.vy_off = ar.upload(vy_off);
     G->vy_off_h = vy_off;
     {
-        // per sorted position: source box multipole offset, output row offset
+        // per sorted position: source box multipole offset, output row
+        // offset, quarter turns from the group's offset
         std::vector<long long> src(std::max(nv, 1)), dst(std::max(nv, 1));
+        std::vector<int> rot(std::max(nv, 1), 0);
         for (int i = 0; i < nv; ++i) {
             src[i] = boff[pl.V_idx[vpos[i]]];
             dst[i] = vy_off[vpos[i]];
+            rot[i] = vrot[pl.V_off[vpos[i]]];
         }
         g.m2l_src = ar.upload(src);
         g.m2l_dst = ar.upload(dst);
+        g.m2l_rot = ar.upload(rot);
     }
     // Row-major [out][in] matrix -> v_mfma_f64_16x16x4f64 A-operand order:
     // 16x4 blocks of 64 values, block (rb, kb) at (rb * NK + kb) * 64, lane l

@@ -330,8 +330,17 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
 // column given by bptr (nin complex inputs, NULL = 0).  The table is in
 // A-operand order (see k_m2l_mfma).  Operands of the next TB_U k-blocks are
 // loaded while the current ones go through the matrix core.
+// z i^e (e taken mod 4): a swap and sign changes, exact
+__device__ __forceinline__ cd mul_ipow(cd z, int e)
+{
+    bool sw = e & 1, ng = e & 2;
+    double re = sw ? -z.y : z.x, im = sw ? z.x : z.y;
+    return ng ? mk(-re, -im) : mk(re, im);
+}
+
+template <bool ROT = false>
 __device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const cd *bs, bool bvalid,
-                                        int nin, int lane, cd *a, cd *b)
+                                        int nin, int lane, cd *a, cd *b, int rot = 0, int P = 0)
 {
     // unconditional loads at clamped addresses, out-of-range operands
     // replaced by zero afterwards: no branches, so the loads stay in flight
@@ -344,6 +353,7 @@ __device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const c
         int k = kbc * 4 + bk;
         a[u] = Arow[kbc * 64 + lane];
         cd v = bs[min(k, nin - 1)];
+        if (ROT) v = mul_ipow(v, rot * (k - P));
         b[u] = (ok && bvalid && k < nin) ? v : mk(0.0, 0.0);
     }
 }
@@ -386,19 +396,20 @@ __device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, Acc3 &y)
 }
 
 // Two register sets alternate: one is multiplied while the other loads.
+template <bool ROT = false>
 __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, const cd *bptr, int nin,
-                                            int lane, d4 &yr, d4 &yi)
+                                            int lane, d4 &yr, d4 &yi, int rot = 0, int P = 0)
 {
     if (kb0 >= kb1) return;
     const cd *bs = bptr ? bptr : Arow;          // any readable address when the column is empty
     bool bvalid = bptr != nullptr;
     cd a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
     Acc3 y = cplx3_zero();
-    tb_load(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
+    tb_load<ROT>(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
-        tb_load(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_load<ROT>(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1, rot, P);
         tb_mfma(a0, b0, y);
-        tb_load(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        tb_load<ROT>(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
         if (kb + TB_U < kb1) tb_mfma(a1, b1, y);
     }
     cplx3_done(y, yr, yi);
@@ -428,11 +439,15 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
         int tpc = blockDim.x >> 4;
         int sc = threadIdx.x / tpc, sr = threadIdx.x - sc * tpc;
         const cd *col = nullptr;
+        int rot = 0;
         if (sc < t.ncol) {
             int cc = t.col0 + sc;
             col = mp + g.m2l_src[t.pair_start + cc / nd] * nd + (long long)(cc % nd) * n;
+            rot = g.m2l_rot[t.pair_start + cc / nd];
         }
-        for (int k = sr; k < 4 * NK; k += tpc) X[k * M2L_XS + sc] = (col && k < n) ? col[k] : mk(0.0, 0.0);
+        // the column of a rotated offset enters as i^{rk} a_k
+        for (int k = sr; k < 4 * NK; k += tpc)
+            X[k * M2L_XS + sc] = (col && k < n) ? mul_ipow(col[k], rot * (k - P)) : mk(0.0, 0.0);
     }
     __syncthreads();
     const cd *A = g.m2l_mf + g.m2l_mf_off[t.lo];
@@ -469,9 +484,10 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
         if (bc < t.ncol) {
             int col = t.col0 + bc;
             cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
+            int rot = g.m2l_rot[t.pair_start + col / nd];
             for (int i = 0; i < 4; ++i) {
                 int row = rb * 16 + 4 * i + bk;
-                if (row < n) o[row] = mk(yr[i], yi[i]);
+                if (row < n) o[row] = mul_ipow(mk(yr[i], yi[i]), rot * (row - P));
             }
         }
     }
@@ -502,13 +518,15 @@ __device__ __forceinline__ void m2l_mfma_direct_body(const DevGeom &g, int nd, c
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
     const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
+    int rot = valid ? g.m2l_rot[t.pair_start + col / nd] : 0;
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
-    trans_block(g.m2l_mf + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
+    trans_block<true>(g.m2l_mf + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi,
+                      rot, P);
     if (!valid) return;
     cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
     for (int i = 0; i < 4; ++i) {
         int row = rb * 16 + 4 * i + bk;
-        if (row < n) o[row] = mk(yr[i], yi[i]);
+        if (row < n) o[row] = mul_ipow(mk(yr[i], yi[i]), rot * (row - P));
     }
 }
 
@@ -526,8 +544,9 @@ __global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const
 // ---------------------------------------------------------------------------
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+template <bool ROT = false>
 __device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const cd *bs, bool bvalid,
-                                          int nin, int lane, cf *a, cf *b)
+                                          int nin, int lane, cf *a, cf *b, int rot = 0, int P = 0)
 {
     int bk = lane >> 4;
 #pragma unroll
@@ -538,6 +557,7 @@ __device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const
         int k = kbc * 4 + bk;
         a[u] = Arow[kbc * 64 + lane];
         cd v = bs[min(k, nin - 1)];
+        if (ROT) v = mul_ipow(v, rot * (k - P));
         b[u] = (ok && bvalid && k < nin) ? cf{(float)v.x, (float)v.y} : cf{0.f, 0.f};
     }
 }
@@ -557,19 +577,20 @@ __device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, Acc3f &y)
     }
 }
 
+template <bool ROT = false>
 __device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, const cd *bptr, int nin,
-                                              int lane, f4 &yr, f4 &yi)
+                                              int lane, f4 &yr, f4 &yi, int rot = 0, int P = 0)
 {
     if (kb0 >= kb1) return;
     const cd *bs = bptr ? bptr : reinterpret_cast<const cd *>(Arow);
     bool bvalid = bptr != nullptr;
     cf a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
     Acc3f y{{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    tb_load32(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
+    tb_load32<ROT>(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
-        tb_load32(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_load32<ROT>(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1, rot, P);
         tb_mfma32(a0, b0, y);
-        tb_load32(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        tb_load32<ROT>(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
         if (kb + TB_U < kb1) tb_mfma32(a1, b1, y);
     }
 #pragma unroll
@@ -593,13 +614,15 @@ __device__ __forceinline__ void m2l_mfma32_body(const DevGeom &g, int nd, const 
     int col = t.col0 + bc;
     bool valid = bc < t.ncol;
     const cd *bptr = valid ? mp + g.m2l_src[t.pair_start + col / nd] * nd + (long long)(col % nd) * n : nullptr;
+    int rot = valid ? g.m2l_rot[t.pair_start + col / nd] : 0;
     f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-    trans_block32(g.m2l_mf32 + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi);
+    trans_block32<true>(g.m2l_mf32 + g.m2l_mf_off[t.lo] + (long long)rb * NK * 64, 0, NK, bptr, n, lane, yr, yi,
+                        rot, P);
     if (!valid) return;
     cd *o = vy + g.m2l_dst[t.pair_start + col / nd] * nd + (long long)(col % nd) * n;
     for (int i = 0; i < 4; ++i) {
         int row = rb * 16 + 4 * bk + i;
-        if (row < n) o[row] = mk((double)yr[i], (double)yi[i]);
+        if (row < n) o[row] = mul_ipow(mk((double)yr[i], (double)yi[i]), rot * (row - P));
     }
 }
 

@@ -72,6 +72,9 @@ struct DevGeom {
     const QBX_G int *vpair_sorted;                   // V-list positions sorted by (level, offset)
     const QBX_G long long *vy_off;                   // per V-list position: output row offset
     const QBX_G long long *m2l_src, *m2l_dst;        // per sorted position: box_off of the source, vy_off
+    // per sorted position: r with offset = R^r (group's offset), R the
+    // rotation by 90 degrees; the pair's matrix is diag(i^{rj}) M diag(i^{rk})
+    const QBX_G int *m2l_rot;
 };
 
 // Block index of a workgroup within one geometry's part of a launch: x
