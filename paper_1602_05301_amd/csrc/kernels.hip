@@ -338,9 +338,8 @@ __device__ __forceinline__ cd mul_ipow(cd z, int e)
     return ng ? mk(-re, -im) : mk(re, im);
 }
 
-template <bool ROT = false>
 __device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const cd *bs, bool bvalid,
-                                        int nin, int lane, cd *a, cd *b, int rot = 0, int P = 0)
+                                        int nin, int lane, cd *a, cd *b)
 {
     // unconditional loads at clamped addresses, out-of-range operands
     // replaced by zero afterwards: no branches, so the loads stay in flight
@@ -353,7 +352,6 @@ __device__ __forceinline__ void tb_load(const cd *Arow, int kb, int kb1, const c
         int k = kbc * 4 + bk;
         a[u] = Arow[kbc * 64 + lane];
         cd v = bs[min(k, nin - 1)];
-        if (ROT) v = mul_ipow(v, rot * (k - P));
         b[u] = (ok && bvalid && k < nin) ? v : mk(0.0, 0.0);
     }
 }
@@ -389,10 +387,14 @@ __device__ __forceinline__ void cplx3_done(const Acc3 &y, d4 &yr, d4 &yi)
     }
 }
 
-__device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, Acc3 &y)
+// ROT: the input coefficients of order k enter times i^{rot k}.  A lane
+// always holds the same k mod 4 (lane / 16), so the factor is one per lane
+// (e, taken mod 4), applied as the operand goes in, after its load.
+template <bool ROT = false>
+__device__ __forceinline__ void tb_mfma(const cd *a, const cd *b, Acc3 &y, int e = 0)
 {
 #pragma unroll
-    for (int u = 0; u < TB_U; ++u) cplx3_mfma(a[u], b[u], y);
+    for (int u = 0; u < TB_U; ++u) cplx3_mfma(a[u], ROT ? mul_ipow(b[u], e) : b[u], y);
 }
 
 // Two register sets alternate: one is multiplied while the other loads.
@@ -405,12 +407,13 @@ __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, co
     bool bvalid = bptr != nullptr;
     cd a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
     Acc3 y = cplx3_zero();
-    tb_load<ROT>(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
+    int e = rot * ((lane >> 4) - P);            // order k = 4 kb + lane/16 - P
+    tb_load(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
-        tb_load<ROT>(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1, rot, P);
-        tb_mfma(a0, b0, y);
-        tb_load<ROT>(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
-        if (kb + TB_U < kb1) tb_mfma(a1, b1, y);
+        tb_load(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_mfma<ROT>(a0, b0, y, e);
+        tb_load(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        if (kb + TB_U < kb1) tb_mfma<ROT>(a1, b1, y, e);
     }
     cplx3_done(y, yr, yi);
 }
@@ -544,9 +547,8 @@ __global__ void __launch_bounds__(64) k_m2l_mfma_direct(DevGeom g, int nd, const
 // ---------------------------------------------------------------------------
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <bool ROT = false>
 __device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const cd *bs, bool bvalid,
-                                          int nin, int lane, cf *a, cf *b, int rot = 0, int P = 0)
+                                          int nin, int lane, cf *a, cf *b)
 {
     int bk = lane >> 4;
 #pragma unroll
@@ -557,7 +559,6 @@ __device__ __forceinline__ void tb_load32(const cf *Arow, int kb, int kb1, const
         int k = kbc * 4 + bk;
         a[u] = Arow[kbc * 64 + lane];
         cd v = bs[min(k, nin - 1)];
-        if (ROT) v = mul_ipow(v, rot * (k - P));
         b[u] = (ok && bvalid && k < nin) ? cf{(float)v.x, (float)v.y} : cf{0.f, 0.f};
     }
 }
@@ -567,13 +568,22 @@ struct Acc3f {
     f4 p, q, s;
 };
 
-__device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, Acc3f &y)
+__device__ __forceinline__ cf mul_ipow32(cf z, int e)
+{
+    bool sw = e & 1, ng = e & 2;
+    float re = sw ? -z.y : z.x, im = sw ? z.x : z.y;
+    return ng ? cf{-re, -im} : cf{re, im};
+}
+
+template <bool ROT = false>
+__device__ __forceinline__ void tb_mfma32(const cf *a, const cf *b, Acc3f &y, int e = 0)
 {
 #pragma unroll
     for (int u = 0; u < TB_U; ++u) {
-        y.p = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b[u].x, y.p, 0, 0, 0);
-        y.q = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, b[u].y, y.q, 0, 0, 0);
-        y.s = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x + a[u].y, b[u].x + b[u].y, y.s, 0, 0, 0);
+        cf bb = ROT ? mul_ipow32(b[u], e) : b[u];
+        y.p = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, bb.x, y.p, 0, 0, 0);
+        y.q = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, bb.y, y.q, 0, 0, 0);
+        y.s = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x + a[u].y, bb.x + bb.y, y.s, 0, 0, 0);
     }
 }
 
@@ -586,12 +596,13 @@ __device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, 
     bool bvalid = bptr != nullptr;
     cf a0[TB_U], b0[TB_U], a1[TB_U], b1[TB_U];
     Acc3f y{{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    tb_load32<ROT>(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
+    int e = rot * ((lane >> 4) - P);            // order k = 4 kb + lane/16 - P
+    tb_load32(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
-        tb_load32<ROT>(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1, rot, P);
-        tb_mfma32(a0, b0, y);
-        tb_load32<ROT>(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0, rot, P);
-        if (kb + TB_U < kb1) tb_mfma32(a1, b1, y);
+        tb_load32(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        tb_mfma32<ROT>(a0, b0, y, e);
+        tb_load32(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        if (kb + TB_U < kb1) tb_mfma32<ROT>(a1, b1, y, e);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
