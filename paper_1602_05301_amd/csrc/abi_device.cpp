@@ -773,6 +773,12 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
     } else {
         qbx_status ts = ensure_tiles(G, nd);
         if (ts != QBX_OK) return ts;
+        if (G->profile || !lane.side) {
+            // in order: the locals are zeroed with the charges (X-list P2L
+            // and L2L both add into them); concurrently, on the side stream
+            STAGE(QBX_STAGE_CHARGES);
+            LAUNCH(QBX_STAGE_CHARGES, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
+        }
         // Fork: the side stream takes the centre J sequences, the X-list P2L,
         // the near field and (once M2M is done) M2QBXL while this stream runs
         // P2M, M2M, M2L and L2L.  With stage profiling on everything stays on
@@ -820,7 +826,6 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             CHK(hipStreamWaitEvent(st, C->ev_x, 0));
         } else {
             STAGE(QBX_STAGE_P2L_X);
-            LAUNCH(QBX_STAGE_P2L_X, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
             LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
         }
         {
