@@ -281,3 +281,34 @@ def test_association_brute_force_on_star_nodes():
     d_own = np.hypot(g.sx - g.cx, g.sy - g.cy)
     d_got = np.hypot(g.sx - g.cx[got], g.sy - g.cy[got])
     assert (d_got <= d_own * (1 + 1e-15)).all()
+
+
+def test_m2l_quarter_turn_identity():
+    """The translation of a V offset turned by r quarter turns equals the
+    unturned one with inputs times i^{rk} and outputs times i^{rl} (O_n
+    carries e^{in theta}); the library keeps one M2L table per orbit of
+    the 40 V offsets on this identity.  Checked with the plain-sum M2L for
+    every V offset against its representative (dx > 0, dy >= 0)."""
+    from oracle import translations as tr
+    omega, P, side = 7.0, 12, 0.3
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal(2 * P + 1) + 1j * rng.standard_normal(2 * P + 1)
+    ipow = np.array([1.0, 1j, -1.0, -1j])
+    k = np.arange(-P, P + 1)
+    m = 0.37 - 0.21j
+    checked = 0
+    for dy in range(-3, 4):
+        for dx in range(-3, 4):
+            if abs(dx) <= 1 and abs(dy) <= 1:
+                continue
+            # quarter turns back (clockwise) until the first quadrant
+            x, y, r = dx, dy, 0
+            while not (x > 0 and y >= 0):
+                x, y, r = y, -x, r + 1
+            assert r < 4
+            direct = tr.m2l(omega, a, m, m + side * complex(dx, dy), P)
+            turned = ipow[(r * k) % 4] * tr.m2l(omega, ipow[(r * k) % 4] * a, m,
+                                                m + side * complex(x, y), P)
+            assert np.max(np.abs(direct - turned)) <= 1e-12 * np.max(np.abs(direct)), (dx, dy, r)
+            checked += 1
+    assert checked == 40
