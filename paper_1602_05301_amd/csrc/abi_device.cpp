@@ -829,16 +829,17 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
         }
         {
-            // V-list sums in list order, then L2L from the parent, level by level
+            // V-list sums in list order for every level at once, then L2L
+            // from the parent, level by level
             STAGE(QBX_STAGE_L2L);
             if (pl.nlev > 2) {
-                int nbox = pl.level_start[3] - pl.level_start[2];
-                LAUNCH(QBX_STAGE_L2L, nbox, launch_down(g, nd, 2, nbox, G->vy, G->loc, st));
+                int nbox = pl.level_start[pl.nlev] - pl.level_start[2];
+                LAUNCH(QBX_STAGE_L2L, nbox, launch_down_all(g, nd, pl.level_start[2], nbox, G->vy, G->loc, st));
             }
             for (int L = 3; L < pl.nlev; ++L) {
                 int t0 = G->l2l_tstart[nd][L], nt = G->l2l_tstart[nd][L + 1] - t0;
                 int nrb = (2 * pl.P[L] + 1 + 15) / 16;
-                LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, G->vy, G->loc, st));
+                LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, nullptr, G->loc, st));
             }
         }
         if (conc) {

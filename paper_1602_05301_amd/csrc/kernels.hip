@@ -325,6 +325,29 @@ __global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
     down_body(g, nd, l, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
+// V-list sums of the boxes b0, b0 + 1, ... (every level from 2 on) in one
+// launch, each box as k_down does it.  L2L, given no V-list rows, then adds
+// its translation to these sums: the same terms in the same order as its own
+// epilogue, so the locals are bitwise those of the level-by-level form, with
+// one bandwidth-bound launch in place of the epilogues' loads in every
+// latency-bound L2L level.
+__global__ void __launch_bounds__(64) k_down_all(DevGeom g, int nd, int b0, const cd *vy, cd *loc)
+{
+    int b = b0 + blockIdx.x;
+    int n = 2 * g.Plev[g.blev[b]] + 1;
+    cd *out = loc + g.box_off[b] * nd;
+    int v0 = g.V_start[b], nv = g.V_start[b + 1] - v0;
+    if (nv == 0) return;
+    const cd *vr = vy + g.vy_off[v0] * nd;
+    long long vs = (long long)n * nd;
+    for (int i = threadIdx.x; i < nd * n; i += blockDim.x) {
+        cd acc = out[i];
+#pragma unroll 4
+        for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs + i];
+        out[i] = acc;
+    }
+}
+
 // Part of one 16x16 output block of a scaled translation on FP64 MFMA: rows
 // rb*16.. (Arow points at the row block), k-blocks [kb0, kb1), the lane's
 // column given by bptr (nin complex inputs, NULL = 0).  The table is in
@@ -747,7 +770,7 @@ __device__ __forceinline__ void l2l_mfma_body(const DevGeom &g, int nd, int L, c
     long long base = g.l2l_coff[pos] * nd + dr;
     // V-list rows of the child follow each other, nc * nd apart
     const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
-    int nv = g.l2l_nv[pos];
+    int nv = vy ? g.l2l_nv[pos] : 0;        // null: V-list rows already in loc
     long long vs = (long long)nc * nd;
     cd acc = loc[base];
 #pragma unroll 4
@@ -799,7 +822,7 @@ __device__ __forceinline__ void l2l_mfma32_body(const DevGeom &g, int nd, int L,
     long long dr = (long long)(oc % nd) * nc + row;
     long long base = g.l2l_coff[pos] * nd + dr;
     const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
-    int nv = g.l2l_nv[pos];
+    int nv = vy ? g.l2l_nv[pos] : 0;        // null: V-list rows already in loc
     long long vs = (long long)nc * nd;
     cd acc = loc[base];
 #pragma unroll 4
@@ -1904,6 +1927,15 @@ hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, 
 {
     if (!nbox) return hipSuccess;
     k_down<<<nbox, 256, 0, s>>>(g, nd, l, vy, loc);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_down_all(const DevGeom &g, int nd, int b0, int nbox, const cd *vy, cd *loc,
+                           hipStream_t s)
+{
+    if (!nbox) return hipSuccess;
+    k_down_all<<<nbox, 64, 0, s>>>(g, nd, b0, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -162,6 +162,7 @@ hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax
                       const cd *qd, const double *srad, int srad_rows, cd *mp, hipStream_t s);
 hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
                            int nrb, const int *plist, cd *mp, hipStream_t s);
+// vy = null: the children's V-list rows are already summed into loc
 hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
                            const int *clist, const cd *vy, cd *loc, hipStream_t s);
 // nw > 0: columns staged in LDS, nw waves per tile (row blocks spread over
@@ -171,6 +172,10 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
                            int nw, const cd *mp, cd *vy, hipStream_t s);
 hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,
                        hipStream_t s);
+// V-list sums of the nbox boxes from b0 on (any levels >= 2) in one launch;
+// launch_l2l_mfma with vy = null then leaves them out of its epilogue.
+hipError_t launch_down_all(const DevGeom &g, int nd, int b0, int nbox, const cd *vy, cd *loc,
+                           hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, hipStream_t s);
 // P2QBXL: one workgroup of P2Q_THREADS lanes per work item.  An item is
