@@ -320,13 +320,8 @@ __device__ __forceinline__ void down_body(const DevGeom &g, int nd, int l, const
     }
 }
 
-__global__ void k_down(DevGeom g, int nd, int l, const cd *vy, cd *loc)
-{
-    down_body(g, nd, l, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
-}
-
 // V-list sums of the boxes b0, b0 + 1, ... (every level from 2 on) in one
-// launch, each box as k_down does it.  L2L, given no V-list rows, then adds
+// launch, each box as down_body does it.  L2L, given no V-list rows, then adds
 // its translation to these sums: the same terms in the same order as its own
 // epilogue, so the locals are bitwise those of the level-by-level form, with
 // one bandwidth-bound launch in place of the epilogues' loads in every
@@ -1918,15 +1913,6 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
             k_m2l_mfma_direct<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
         }
     }
-    QBX_LAUNCH_CHECK();
-    return hipSuccess;
-}
-
-hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,
-                       hipStream_t s)
-{
-    if (!nbox) return hipSuccess;
-    k_down<<<nbox, 256, 0, s>>>(g, nd, l, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

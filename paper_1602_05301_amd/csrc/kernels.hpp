@@ -170,8 +170,6 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
 // block) with operands straight from memory.  Same sums, same order.
 hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
                            int nw, const cd *mp, cd *vy, hipStream_t s);
-hipError_t launch_down(const DevGeom &g, int nd, int l, int nbox, const cd *vy, cd *loc,
-                       hipStream_t s);
 // V-list sums of the nbox boxes from b0 on (any levels >= 2) in one launch;
 // launch_l2l_mfma with vy = null then leaves them out of its epilogue.
 hipError_t launch_down_all(const DevGeom &g, int nd, int b0, int nbox, const cd *vy, cd *loc,
