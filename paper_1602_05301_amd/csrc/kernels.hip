@@ -764,8 +764,9 @@ __device__ __forceinline__ void l2l_mfma_body(const DevGeom &g, int nd, int L, c
     long long dr = (long long)(oc % nd) * nc + row;
     long long base = g.l2l_coff[pos] * nd + dr;
     // V-list rows of the child follow each other, nc * nd apart
-    const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
-    int nv = vy ? g.l2l_nv[pos] : 0;        // null: V-list rows already in loc
+    // vy null: the V-list rows are already in loc
+    const cd *vr = vy ? vy + g.l2l_vy0[pos] * nd + dr : nullptr;
+    int nv = vy ? g.l2l_nv[pos] : 0;
     long long vs = (long long)nc * nd;
     cd acc = loc[base];
 #pragma unroll 4
@@ -816,8 +817,9 @@ __device__ __forceinline__ void l2l_mfma32_body(const DevGeom &g, int nd, int L,
     int pos = t.start + oc / nd;
     long long dr = (long long)(oc % nd) * nc + row;
     long long base = g.l2l_coff[pos] * nd + dr;
-    const cd *vr = vy + g.l2l_vy0[pos] * nd + dr;
-    int nv = vy ? g.l2l_nv[pos] : 0;        // null: V-list rows already in loc
+    // vy null: the V-list rows are already in loc
+    const cd *vr = vy ? vy + g.l2l_vy0[pos] * nd + dr : nullptr;
+    int nv = vy ? g.l2l_nv[pos] : 0;
     long long vs = (long long)nc * nd;
     cd acc = loc[base];
 #pragma unroll 4
