@@ -834,7 +834,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             STAGE(QBX_STAGE_L2L);
             if (pl.nlev > 2) {
                 int nbox = pl.level_start[pl.nlev] - pl.level_start[2];
-                LAUNCH(QBX_STAGE_L2L, nbox, launch_down_all(g, nd, pl.level_start[2], nbox, G->vy, G->loc, st));
+                LAUNCH(QBX_STAGE_L2L, nbox, launch_down_all(g, nd, nbox, G->vy, G->loc, st));
             }
             for (int L = 3; L < pl.nlev; ++L) {
                 int t0 = G->l2l_tstart[nd][L], nt = G->l2l_tstart[nd][L + 1] - t0;
@@ -1097,6 +1097,7 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
         QQ(stage(FK_DOWN, over([](const BItem &b, FItem &it) {
                      const Plan &pl = b.G->pl;
                      if (pl.nlev <= 2) return false;
+                     // level 2 only: the fused L2L levels sum their own V-list rows
                      it.r.i0 = 2; it.r.in0 = b.G->vy; it.r.out0 = b.G->loc;
                      it.n = pl.level_start[3] - pl.level_start[2];
                      return it.n > 0;

@@ -300,12 +300,17 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n)
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
 }
 
-// Level-2 part of the downward pass: local = X-list part (already in loc)
-// + the box's V-list contributions in list order (no parent local exists).
+// V-list part of the downward pass: local = X-list part (already in loc)
+// + the box's V-list contributions in list order.  Block bid.x takes box
+// level_start[l] + bid.x, so a launch of nb - level_start[2] blocks from
+// l = 2 covers every level at once.  L2L, given no V-list rows, then adds its
+// translation to these sums: the same terms in the same order as when its
+// epilogue summed the rows, with one bandwidth-bound launch in place of the
+// epilogues' loads in every latency-bound L2L level.
 __device__ __forceinline__ void down_body(const DevGeom &g, int nd, int l, const cd *vy, cd *loc, BlockId bid)
 {
     int b = g.level_start[l] + bid.x;
-    int P = g.Plev[l], n = 2 * P + 1;
+    int P = g.Plev[g.blev[b]], n = 2 * P + 1;
     cd *out = loc + g.box_off[b] * nd;
     int v0 = g.V_start[b], nv = g.V_start[b + 1] - v0;
     if (nv == 0) return;
@@ -320,27 +325,11 @@ __device__ __forceinline__ void down_body(const DevGeom &g, int nd, int l, const
     }
 }
 
-// V-list sums of the boxes b0, b0 + 1, ... (every level from 2 on) in one
-// launch, each box as down_body does it.  L2L, given no V-list rows, then adds
-// its translation to these sums: the same terms in the same order as its own
-// epilogue, so the locals are bitwise those of the level-by-level form, with
-// one bandwidth-bound launch in place of the epilogues' loads in every
-// latency-bound L2L level.
-__global__ void __launch_bounds__(64) k_down_all(DevGeom g, int nd, int b0, const cd *vy, cd *loc)
+// V-list sums of every box from level 2 on (one block of 64 lanes per
+// density per box)
+__global__ void __launch_bounds__(256) k_down_all(DevGeom g, int nd, const cd *vy, cd *loc)
 {
-    int b = b0 + blockIdx.x;
-    int n = 2 * g.Plev[g.blev[b]] + 1;
-    cd *out = loc + g.box_off[b] * nd;
-    int v0 = g.V_start[b], nv = g.V_start[b + 1] - v0;
-    if (nv == 0) return;
-    const cd *vr = vy + g.vy_off[v0] * nd;
-    long long vs = (long long)n * nd;
-    for (int i = threadIdx.x; i < nd * n; i += blockDim.x) {
-        cd acc = out[i];
-#pragma unroll 4
-        for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs + i];
-        out[i] = acc;
-    }
+    down_body(g, nd, 2, vy, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // Part of one 16x16 output block of a scaled translation on FP64 MFMA: rows
@@ -1919,11 +1908,11 @@ hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int n
     return hipSuccess;
 }
 
-hipError_t launch_down_all(const DevGeom &g, int nd, int b0, int nbox, const cd *vy, cd *loc,
-                           hipStream_t s)
+hipError_t launch_down_all(const DevGeom &g, int nd, int nbox, const cd *vy, cd *loc, hipStream_t s)
 {
     if (!nbox) return hipSuccess;
-    k_down_all<<<nbox, 64, 0, s>>>(g, nd, b0, vy, loc);
+    if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+    k_down_all<<<nbox, 64 * nd, 0, s>>>(g, nd, vy, loc);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }

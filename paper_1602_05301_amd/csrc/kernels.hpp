@@ -170,10 +170,10 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
 // block) with operands straight from memory.  Same sums, same order.
 hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
                            int nw, const cd *mp, cd *vy, hipStream_t s);
-// V-list sums of the nbox boxes from b0 on (any levels >= 2) in one launch;
-// launch_l2l_mfma with vy = null then leaves them out of its epilogue.
-hipError_t launch_down_all(const DevGeom &g, int nd, int b0, int nbox, const cd *vy, cd *loc,
-                           hipStream_t s);
+// V-list sums of the nbox boxes from the first of level 2 on (every level
+// >= 2) in one launch, nd (1-4) densities; launch_l2l_mfma with vy = null
+// then leaves them out of its epilogue.
+hipError_t launch_down_all(const DevGeom &g, int nd, int nbox, const cd *vy, cd *loc, hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, hipStream_t s);
 // P2QBXL: one workgroup of P2Q_THREADS lanes per work item.  An item is
