@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define QBX_ABI_VERSION 1
+#define QBX_ABI_VERSION 2
 
 typedef enum {
     QBX_OK = 0,
@@ -72,6 +72,10 @@ typedef struct {
                              0 = never (every W box through M2QBXL, as in Stage 5),
                              n > 0 = boxes holding at most n sources.  Direct sums
                              are exact, so the choice only removes truncation. */
+    int32_t level_restrict; /* 1 (default) = refine the adaptive tree until leaves
+                             that touch differ by at most one level (2:1 balance, the
+                             level-restricted trees of the paper's experiments, Sec. 8);
+                             0 = the plain adaptive tree of Stage 1 */
     double eps_assoc;     /* association slack epsilon_assoc (Sec. 6.1); default 0.05 */
 } qbx_options;
 
@@ -108,7 +112,8 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx);
  *  - the adaptive quadtree over sources and centres (Sec. 4; Sec. 7.2,
  *    Stage 1): root = smallest origin-centred square holding all sources and
  *    centres (enlarged by a relative 1e-12), split while a box holds more
- *    than leaf_max sources + centres;
+ *    than leaf_max sources + centres; with level_restrict, leaves touching
+ *    a box two or more levels finer are split further (2:1 balance);
  *  - the U, V, W, X lists (Sec. 7.2 definitions);
  *  - FMM orders P_l = p_FMM(l) + p_add, with p_FMM(l) the smallest P such
  *    that |H_n(3 omega R_l) J_n(sqrt(2) omega R_l)| <= eps for all n > P,
@@ -125,7 +130,8 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx);
  * centres may be different point sets (oversampled sources, Sec. 2.2).
  * Errors: QBX_E_INVAL (n < 0, non-finite input, cr <= 0, w < 0, |n| not 1
  * within 1e-6, omega <= 0, eps outside [1e-15, 1e-2], p outside 0..40,
- * leaf_max < 1, far_fp32 with eps < 1e-6), QBX_E_ASSOC, QBX_E_NOMEM. */
+ * leaf_max < 1, far_fp32 with eps < 1e-6, level_restrict not 0 or 1),
+ * QBX_E_ASSOC, QBX_E_NOMEM. */
 qbx_status qbx_plan_create(double omega, double eps, const qbx_options *opt,
                            int64_t n_src, const double *sx, const double *sy,
                            const double *w, const double *nx, const double *ny,

@@ -52,9 +52,9 @@ def box_centre(t, b):
     return complex(-t["R0"] + (t["ix"][b] + 0.5) * side, -t["R0"] + (t["iy"][b] + 0.5) * side)
 
 
-def qbx_fmm_coefficients(omega, p, P_levels, geom, sigma_s, sigma_d, n_max):
+def qbx_fmm_coefficients(omega, p, P_levels, geom, sigma_s, sigma_d, n_max, level_restrict=False):
     """alpha[d, l+p, i] at every centre, one density at a time."""
-    t = build_tree(geom.sx, geom.sy, geom.cx, geom.cy, n_max)
+    t = build_tree(geom.sx, geom.sy, geom.cx, geom.cy, n_max, level_restrict=level_restrict)
     L = build_lists(t)
     nb = t["level"].size
     lev, par, leaf = t["level"], t["parent"], t["leaf"]
@@ -118,7 +118,8 @@ def qbx_fmm_coefficients(omega, p, P_levels, geom, sigma_s, sigma_d, n_max):
     return alpha, t
 
 
-def qbx_fmm(omega, p, P_levels, geom, tx, ty, tgt_ctr, sigma_s, sigma_d, n_max):
+def qbx_fmm(omega, p, P_levels, geom, tx, ty, tgt_ctr, sigma_s, sigma_d, n_max, level_restrict=False):
     """Potentials at targets with explicit centres (on-curve or near targets)."""
-    alpha, _ = qbx_fmm_coefficients(omega, p, P_levels, geom, sigma_s, sigma_d, n_max)
+    alpha, _ = qbx_fmm_coefficients(omega, p, P_levels, geom, sigma_s, sigma_d, n_max,
+                                    level_restrict=level_restrict)
     return qbx_eval(omega, p, geom.cx, geom.cy, alpha, tx, ty, np.asarray(tgt_ctr, np.int32)), alpha

@@ -20,6 +20,12 @@ A particle with coordinate x lies in the level-l box of integer index
 floor(u 2^l), u = (x + R0) / (2 R0) evaluated once in double precision.
 Two boxes are adjacent when their closed squares intersect and neither
 contains the other.  Everything here is brute force over all boxes.
+
+Level restriction (the 2:1 balance the paper's experiments use, Sec. 8 with
+its remark on level-restricted trees): the leaves that touch one another
+differ by at most one level.  With ``level_restrict`` the adaptive tree is
+refined until that holds: while some leaf b touches a box two or more levels
+finer than b, b is split into its non-empty quadrants.
 """
 from __future__ import annotations
 
@@ -38,7 +44,7 @@ def root_radius(*coords) -> float:
     return m * (1.0 + 1e-12)
 
 
-def build(sx, sy, cx, cy, n_max):
+def build(sx, sy, cx, cy, n_max, level_restrict=False):
     """Returns dict(R0, level, ix, iy, parent, leaf, nsrc, nctr, src, ctr) with
     boxes ordered by (level, Morton order of (ix, iy)); src / ctr hold the
     source and centre indices inside each box."""
@@ -51,27 +57,50 @@ def build(sx, sy, cx, cy, n_max):
     boxes = [(0, 0, 0, -1)]            # (level, ix, iy, parent)
     members = [np.arange(px.size)]
     is_src = np.concatenate([np.ones(sx.size, bool), np.zeros(cx.size, bool)])
-    leaf = []
-    level_start = 0
-    out_level, out_ix, out_iy, out_par, out_leaf, out_ns, out_nc = [], [], [], [], [], [], []
+
+    def split(b):
+        """Appends the non-empty quadrants of box b; returns their indices."""
+        lev, ix, iy, par = boxes[b]
+        mem = members[b]
+        cl = lev + 1
+        jx = np.floor(ux[mem] * 2.0 ** cl).astype(np.int64)
+        jy = np.floor(uy[mem] * 2.0 ** cl).astype(np.int64)
+        keys = sorted(set(zip(jx.tolist(), jy.tolist())), key=lambda k: _morton(k[0], k[1]))
+        out = []
+        for kx, ky in keys:
+            sel = mem[(jx == kx) & (jy == ky)]
+            boxes.append((cl, kx, ky, b))
+            members.append(sel)
+            out.append(len(boxes) - 1)
+        return out
+
     frontier = [0]
     while frontier:
         nxt = []
         for b in frontier:
-            lev, ix, iy, par = boxes[b]
-            mem = members[b]
-            split = mem.size > n_max and lev < MAX_LEVEL
-            if split:
-                cl = lev + 1
-                jx = np.floor(ux[mem] * 2.0 ** cl).astype(np.int64)
-                jy = np.floor(uy[mem] * 2.0 ** cl).astype(np.int64)
-                keys = sorted(set(zip(jx.tolist(), jy.tolist())), key=lambda k: _morton(k[0], k[1]))
-                for kx, ky in keys:
-                    sel = mem[(jx == kx) & (jy == ky)]
-                    boxes.append((cl, kx, ky, b))
-                    members.append(sel)
-                    nxt.append(len(boxes) - 1)
+            if members[b].size > n_max and boxes[b][0] < MAX_LEVEL:
+                nxt += split(b)
         frontier = nxt
+    if level_restrict:
+        while True:
+            parents = set(p for (_, _, _, p) in boxes if p >= 0)
+            lev = np.array([bb[0] for bb in boxes])
+            x0, y0 = np.array([bb[1] for bb in boxes]), np.array([bb[2] for bb in boxes])
+            L = int(lev.max())
+            s = np.left_shift(1, L - lev)
+            bad = []
+            for b in range(len(boxes)):
+                if b in parents:
+                    continue
+                fine = lev >= lev[b] + 2
+                touch = ((x0 * s <= (x0[b] + 1) * s[b]) & (x0[b] * s[b] <= (x0 + 1) * s) &
+                         (y0 * s <= (y0[b] + 1) * s[b]) & (y0[b] * s[b] <= (y0 + 1) * s))
+                if np.any(fine & touch):
+                    bad.append(b)
+            if not bad:
+                break
+            for b in bad:
+                split(b)
     # renumber by (level, Morton)
     order = sorted(range(len(boxes)), key=lambda b: (boxes[b][0], _morton(boxes[b][1], boxes[b][2])))
     newid = {b: i for i, b in enumerate(order)}

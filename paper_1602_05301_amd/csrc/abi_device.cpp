@@ -150,8 +150,7 @@ struct qbx_geom_s {
     // per-eval scratch, sized for kDensChunk densities
     DeviceArena scratch;
     cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
-    // radial sequences, recomputed on every evaluation: J_n per P2M source
-    // and per L2QBXL centre (n-major)
+    // radial sequences: J_n per P2M source and per L2QBXL centre (n-major)
     int srad_rows = 0, crad_rows = 0;
     double *srad = nullptr, *crad = nullptr;
     // the radial sequences depend on the geometry only: computed on the
@@ -1413,18 +1412,30 @@ qbx_status graph_for(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const v
     hipStream_t gs = G->ctx->gstream;
     hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    // A captured pipeline only records the radial-sequence launches; they run
+    // when the graph does.  Until then the flag that lets later evaluations
+    // skip them must not stand (the caller clears it again if the launch
+    // fails).
+    bool rad0 = G->rad_ready;
     qbx_status q = eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, gs, G->ctx->lane);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(gs, &graph);
     if (q != QBX_OK) {
+        G->rad_ready = rad0;
         if (graph) (void)hipGraphDestroy(graph);
         return q;
     }
-    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        G->rad_ready = rad0;
+        return fail(QBX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        G->rad_ready = rad0;
+        return fail(QBX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
     if (G->graphs.size() >= kMaxGraphs) {
         size_t lru = 0;
         for (size_t i = 1; i < G->graphs.size(); ++i)
@@ -1455,9 +1466,14 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
         hipGraphExec_t exec = nullptr;
         st = graph_for(G, n_dens, sigma_s, sigma_d, u, coef, &exec);
         if (st != QBX_OK) return st;
-        CHK(hipEventRecord(C->ev_in, C->stream));
-        CHK(hipStreamWaitEvent(C->gstream, C->ev_in, 0));
-        CHK(hipGraphLaunch(exec, C->gstream));
+        e = hipEventRecord(C->ev_in, C->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(C->gstream, C->ev_in, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, C->gstream);
+        if (e != hipSuccess) {
+            // the radial sequences recorded in the graph may never have run
+            G->rad_ready = false;
+            return fail(QBX_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        }
         CHK(hipEventRecord(C->ev_out, C->gstream));
         CHK(hipStreamWaitEvent(C->stream, C->ev_out, 0));
         return QBX_OK;

@@ -74,6 +74,7 @@ void qbx_options_default(qbx_options *opt)
     opt->direct = 0;
     opt->far_fp32 = 0;
     opt->w_direct = -1;
+    opt->level_restrict = 1;
     opt->eps_assoc = 0.05;
 }
 

@@ -277,8 +277,9 @@ __global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd
 // columns, each the scaled multipole of one V-list source box for one
 // density; column c of the result is that pair's contribution to the target
 // box's local, written to its own output row (vy) and summed in a fixed
-// order by the downward pass.  Complex product with four real MFMAs:
-//   Yr += Mr Xr - Mi Xi,  Yi += Mr Xi + Mi Xr.
+// order by the downward pass.  Complex product with three real MFMAs
+// (Gauss's form): P += Mr Xr, Q += Mi Xi, S += (Mr + Mi)(Xr + Xi), then
+//   Yr = P - Q,  Yi = S - P - Q.
 // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16], B[l/16][l%16];
 // result D[4i + l/16][l%16] in element i.  The matrix is stored in that
 // A-operand order, 16x4 blocks of 64 complex values, block (rb, kb) at

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <unordered_map>
+#include <unordered_set>
 
 namespace qbx {
 
@@ -258,7 +260,90 @@ void to_csr(const std::vector<std::vector<int32_t>> &L, std::vector<int32_t> &st
     for (size_t b = 0; b < L.size(); ++b) std::copy(L[b].begin(), L[b].end(), idx.begin() + start[b]);
 }
 
-void build_tree(Plan &pl)
+// Location code of box (l, ix, iy): a leading one above its 2l Morton bits,
+// unique across levels.
+inline uint64_t loc_code(int l, uint32_t ix, uint32_t iy) { return (1ull << (2 * l)) | morton(ix, iy); }
+
+// Source and centre ranges of box (l, ix, iy) in the Morton-sorted keys.
+struct Ranges {
+    int s0, s1, c0, c1;
+    int count() const { return s1 - s0 + c1 - c0; }
+};
+
+Ranges box_ranges(const std::vector<uint64_t> &sk, const std::vector<uint64_t> &ck, int l, uint32_t ix,
+                  uint32_t iy)
+{
+    int shift = 2 * (kMaxLevel - l);
+    uint64_t pref = morton(ix, iy);
+    uint64_t k0 = pref << shift, k1 = (pref + 1) << shift;
+    Ranges r;
+    r.s0 = (int)(std::lower_bound(sk.begin(), sk.end(), k0) - sk.begin());
+    r.s1 = (int)(std::lower_bound(sk.begin(), sk.end(), k1) - sk.begin());
+    r.c0 = (int)(std::lower_bound(ck.begin(), ck.end(), k0) - ck.begin());
+    r.c1 = (int)(std::lower_bound(ck.begin(), ck.end(), k1) - ck.begin());
+    return r;
+}
+
+// Level restriction (2:1 balance; the paper's experiments use level-
+// restricted trees, Sec. 8): no leaf may touch a box two or more levels
+// finer than itself.  Returns the location codes of the leaves of the
+// adaptive tree (lev, bix, biy, leaf as built) that must be split for that,
+// found in one sweep from the finest level up.  A box d at level m >= 2 can
+// only be touched by a too-coarse leaf through one of the level-(m-2) cells
+// around its grandparent; the box covering such a cell, if it is a leaf at
+// level <= m-2, is split, and so are its children covering the cell, down
+// to level m-1.  Splits only create boxes coarser than m, so the sweep
+// visits them later.
+std::unordered_set<uint64_t> balance_splits(const Plan &pl, const std::vector<uint64_t> &sk,
+                                            const std::vector<uint64_t> &ck)
+{
+    std::unordered_map<uint64_t, bool> split;   // code -> has children
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> at(kMaxLevel + 1);
+    int nb = pl.n_boxes();
+    for (int b = 0; b < nb; ++b) {
+        split[loc_code(pl.lev[b], pl.bix[b], pl.biy[b])] = !pl.leaf[b];
+        at[pl.lev[b]].push_back({(uint32_t)pl.bix[b], (uint32_t)pl.biy[b]});
+    }
+    std::unordered_set<uint64_t> forced;
+    auto force = [&](int l, uint32_t ix, uint32_t iy) {
+        uint64_t code = loc_code(l, ix, iy);
+        split[code] = true;
+        forced.insert(code);
+        for (int q = 0; q < 4; ++q) {
+            uint32_t jx = 2 * ix + (q & 1), jy = 2 * iy + (q >> 1);
+            if (box_ranges(sk, ck, l + 1, jx, jy).count() == 0) continue;
+            split.emplace(loc_code(l + 1, jx, jy), false);
+            at[l + 1].push_back({jx, jy});
+        }
+    };
+    for (int m = kMaxLevel; m >= 2; --m) {
+        for (size_t i = 0; i < at[m].size(); ++i) {
+            uint32_t dx = at[m][i].first, dy = at[m][i].second;
+            int64_t gx = dx >> 2, gy = dy >> 2, n = 1ll << (m - 2);
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    int64_t cx = gx + ox, cy = gy + oy;
+                    if ((ox == 0 && oy == 0) || cx < 0 || cy < 0 || cx >= n || cy >= n) continue;
+                    // closed squares in level-m units: cell [4cx, 4cx+4], d [dx, dx+1]
+                    if (4 * cx > (int64_t)dx + 1 || (int64_t)dx > 4 * cx + 4) continue;
+                    if (4 * cy > (int64_t)dy + 1 || (int64_t)dy > 4 * cy + 4) continue;
+                    // deepest existing box holding the cell
+                    int k = m - 2;
+                    while (k > 0 && !split.count(loc_code(k, (uint32_t)(cx >> (m - 2 - k)), (uint32_t)(cy >> (m - 2 - k))))) --k;
+                    for (; k <= m - 2; ++k) {
+                        uint32_t ax = (uint32_t)(cx >> (m - 2 - k)), ay = (uint32_t)(cy >> (m - 2 - k));
+                        auto it = split.find(loc_code(k, ax, ay));
+                        if (it == split.end()) break;       // empty quadrant: nothing there
+                        if (!it->second) force(k, ax, ay);
+                    }
+                }
+        }
+    }
+    return forced;
+}
+
+void build_tree(Plan &pl, const std::unordered_set<uint64_t> *forced, std::vector<uint64_t> *sk_out,
+                std::vector<uint64_t> *ck_out)
 {
     double m = 0.0;
     for (int64_t i = 0; i < pl.ns; ++i) m = std::max(m, std::max(std::fabs(pl.sx[i]), std::fabs(pl.sy[i])));
@@ -294,7 +379,8 @@ void build_tree(Plan &pl)
         pl.level_start.push_back(hi);
         for (int b = lo; b < hi; ++b) {
             int cnt = (pl.src_end[b] - pl.src_begin[b]) + (pl.ctr_end[b] - pl.ctr_begin[b]);
-            if (cnt <= pl.opt.leaf_max || l >= kMaxLevel) continue;
+            bool must = forced && forced->count(loc_code(l, pl.bix[b], pl.biy[b]));
+            if ((cnt <= pl.opt.leaf_max && !must) || l >= kMaxLevel) continue;
             int shift = 2 * (kMaxLevel - (l + 1));
             uint64_t pref = morton((uint32_t)pl.bix[b], (uint32_t)pl.biy[b]);
             for (int q = 0; q < 4; ++q) {
@@ -324,6 +410,26 @@ void build_tree(Plan &pl)
     int nb = pl.n_boxes();
     pl.leaf.resize(nb);
     for (int b = 0; b < nb; ++b) pl.leaf[b] = pl.child_count[b] == 0;
+    if (sk_out) sk_out->swap(sk);
+    if (ck_out) ck_out->swap(ck);
+}
+
+void clear_tree(Plan &pl)
+{
+    for (auto *v : {&pl.lev, &pl.bix, &pl.biy, &pl.parent, &pl.leaf, &pl.child_begin, &pl.child_count,
+                    &pl.src_begin, &pl.src_end, &pl.ctr_begin, &pl.ctr_end, &pl.level_start})
+        v->clear();
+}
+
+void build_tree(Plan &pl)
+{
+    std::vector<uint64_t> sk, ck;
+    build_tree(pl, nullptr, &sk, &ck);
+    if (!pl.opt.level_restrict) return;
+    std::unordered_set<uint64_t> forced = balance_splits(pl, sk, ck);
+    if (forced.empty()) return;
+    clear_tree(pl);
+    build_tree(pl, &forced, nullptr, nullptr);
 }
 
 void build_lists(Plan &pl)
@@ -497,6 +603,7 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
     if (!(opt.eps_assoc >= 0 && opt.eps_assoc < 1)) return {QBX_E_INVAL, "eps_assoc must lie in [0, 1)"};
     if (opt.p_add < -1 || opt.p_add > 200) return {QBX_E_INVAL, "p_add must be -1 or in 0..200"};
     if (opt.w_direct < -1) return {QBX_E_INVAL, "w_direct must be -1, 0 or a positive source count"};
+    if (opt.level_restrict != 0 && opt.level_restrict != 1) return {QBX_E_INVAL, "level_restrict must be 0 or 1"};
     if (ns && (!sx || !sy || !w || !nx || !ny || !sh)) return {QBX_E_INVAL, "null source array"};
     if (nc && (!cx || !cy || !cr)) return {QBX_E_INVAL, "null centre array"};
     if (nt && (!tx || !ty)) return {QBX_E_INVAL, "null target array"};

@@ -45,7 +45,8 @@ class QbxError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("p_add", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("direct", ctypes.c_int32), ("far_fp32", ctypes.c_int32),
-                ("w_direct", ctypes.c_int32), ("eps_assoc", ctypes.c_double)]
+                ("w_direct", ctypes.c_int32), ("level_restrict", ctypes.c_int32),
+                ("eps_assoc", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -129,13 +130,52 @@ def _check(status):
 
 
 def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05, w_direct=-1,
-            far_fp32=False) -> Options:
+            far_fp32=False, level_restrict=True) -> Options:
     o = Options()
     lib().qbx_options_default(ctypes.byref(o))
     o.p, o.p_add, o.leaf_max, o.direct, o.eps_assoc = int(p), int(p_add), int(leaf_max), int(bool(direct)), float(eps_assoc)
     o.w_direct = int(w_direct)
     o.far_fp32 = int(bool(far_fp32))
+    o.level_restrict = int(bool(level_restrict))
     return o
+
+
+def _need_c128(t, numel, what, device=None):
+    """Checks a buffer the library reads or writes through a raw device
+    pointer: complex128, contiguous, numel elements, on the CUDA device.
+    Raises ValueError before any library call."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what} must be a torch tensor")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{what} must be complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must hold {numel} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what} is on cuda:{t.device.index}, the context on cuda:{device}")
+
+
+def _n_dens(sigma_s, sigma_d, n_src, what):
+    """Density count of a (sigma_s, sigma_d) pair; both must agree."""
+    if sigma_s is None and sigma_d is None:
+        raise ValueError(f"{what}: at least one of sigma_s, sigma_d is needed")
+    nds = set()
+    for s in (sigma_s, sigma_d):
+        if s is not None:
+            if s.dim() not in (1, 2) or (s.dim() == 2 and s.shape[1] != n_src) or \
+                    (s.dim() == 1 and s.shape[0] != n_src):
+                raise ValueError(f"{what}: densities must be [n_dens, {n_src}] or [{n_src}]")
+            nds.add(int(s.shape[0]) if s.dim() == 2 else 1)
+    if len(nds) != 1:
+        raise ValueError(f"{what}: sigma_s and sigma_d must have the same number of densities")
+    nd = nds.pop()
+    if not 1 <= nd <= 64:
+        raise ValueError(f"{what}: 1 to 64 densities per call, got {nd}")
+    return nd
 
 
 def _arr(a, dtype=np.float64):
@@ -222,9 +262,21 @@ class Context:
         sigmas_s[i] / sigmas_d[i]: [n_dens_i, n_src_i] complex128 CUDA tensors or
         None; us[i]: [n_dens_i, n_tgt_i] outputs."""
         n = len(geoms)
+        if not (len(sigmas_s) == len(sigmas_d) == len(us) == n):
+            raise ValueError("eval_batch: one sigma_s, sigma_d and u entry per geometry")
+        nds = []
+        for i, (g, s, d, u) in enumerate(zip(geoms, sigmas_s, sigmas_d, us)):
+            if not isinstance(g, Geometry) or g.ctx is not self:
+                raise ValueError(f"eval_batch: geometry {i} does not belong to this context")
+            nd = _n_dens(s, d, g.n_src, f"eval_batch[{i}]")
+            for t, nm in ((s, "sigma_s"), (d, "sigma_d")):
+                if t is not None:
+                    _need_c128(t, nd * g.n_src, f"eval_batch[{i}] {nm}", self.device)
+            _need_c128(u, nd * g.n_tgt, f"eval_batch[{i}] u", self.device)
+            nds.append(nd)
         ptr = lambda t: None if t is None else t.data_ptr()
         G = (_vp * n)(*[g._h for g in geoms])
-        ND = (ctypes.c_int32 * n)(*[int((s if s is not None else d).shape[0]) for s, d in zip(sigmas_s, sigmas_d)])
+        ND = (ctypes.c_int32 * n)(*nds)
         S = (_vp * n)(*[ptr(s) for s in sigmas_s])
         D = (_vp * n)(*[ptr(d) for d in sigmas_d])
         U = (_vp * n)(*[u.data_ptr() for u in us])
@@ -350,19 +402,18 @@ class Geometry:
     def eval(self, sigma_s, sigma_d, u=None, coef=None):
         """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); device complex128 tensors."""
         import torch
-        ref = sigma_s if sigma_s is not None else sigma_d
-        nd = int(ref.shape[0]) if ref.dim() == 2 else 1
-        dev = ref.device
-        for s in (sigma_s, sigma_d):
-            if s is not None:
-                if s.dtype != torch.complex128 or not s.is_cuda or not s.is_contiguous():
-                    raise ValueError("densities must be contiguous complex128 CUDA tensors")
-                if s.numel() != nd * self.n_src:
-                    raise ValueError("density shape must be [n_dens, n_src]")
+        nd = _n_dens(sigma_s, sigma_d, self.n_src, "eval")
+        dev = (sigma_s if sigma_s is not None else sigma_d).device
+        for t, nm in ((sigma_s, "sigma_s"), (sigma_d, "sigma_d")):
+            if t is not None:
+                _need_c128(t, nd * self.n_src, nm, self.ctx.device)
         if u is None:
             u = torch.empty((nd, self.n_tgt), dtype=torch.complex128, device=dev)
+        _need_c128(u, nd * self.n_tgt, "u", self.ctx.device)
         if coef is True:
             coef = torch.empty((nd, 2 * self.p + 1, self.n_ctr), dtype=torch.complex128, device=dev)
+        if coef is not None and coef is not False:
+            _need_c128(coef, nd * (2 * self.p + 1) * self.n_ctr, "coef", self.ctx.device)
         ptr = lambda t: None if t is None else _vp(t.data_ptr())
         _check(lib().qbx_eval(self._h, nd, ptr(sigma_s), ptr(sigma_d), ptr(u),
                               ptr(coef) if coef is not None and coef is not False else None))

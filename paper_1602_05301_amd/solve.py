@@ -264,9 +264,6 @@ def main(argv=None) -> int:
     ap.add_argument("--maxiter", type=int, default=2000)
     ap.add_argument("--oversample", type=int, default=0,
                     help="source nodes per density node (0: from Table 1 for eps; 1: none)")
-    ap.add_argument("--grid", type=int, default=0,
-                    help="also evaluate the scattered field on a grid x grid over the box, inside the "
-                         "curves too (two-sided centres; 0: no)")
     args = ap.parse_args(argv)
     from . import qbx
     q = 16
@@ -296,15 +293,6 @@ def main(argv=None) -> int:
            "relative_residual": true_res, "wall_s": wall,
            "ms_per_iteration": 1e3 * wall / max(info["iterations"], 1),
            "matvec_ms": 1e3 * A.gpu_s / max(A.matvecs, 1)}
-    if args.grid > 0:
-        xs = np.linspace(-10.0, 10.0, args.grid)
-        gx, gy = np.meshgrid(xs, xs)
-        t0 = time.perf_counter()
-        u_sc = field(ctx, g, args.omega, args.eps, args.p, sigma, gx.ravel(), gy.ravel(), fine=fine,
-                     both_sides=True)
-        out["field_targets"] = int(gx.size)
-        out["field_s"] = time.perf_counter() - t0
-        out["field_max_abs_total"] = float(np.max(np.abs(u_sc + plane_wave(args.omega, gx.ravel(), gy.ravel()))))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -312,3 +312,114 @@ def test_m2l_quarter_turn_identity():
             assert np.max(np.abs(direct - turned)) <= 1e-12 * np.max(np.abs(direct)), (dx, dy, r)
             checked += 1
     assert checked == 40
+
+
+# ---------------------------------------------------------------------------
+# The stage-by-stage FMM oracle (Sec. 7.2) against the direct sum
+# ---------------------------------------------------------------------------
+
+def _fmm_geometries():
+    return {"star": inputs.star(20, 16, lobes=5),
+            "ellipse": inputs.ellipse(20, 16, a=1.0, b=0.35, rotation=0.3),
+            "two_curves": inputs.concat([
+                inputs.star(12, 16, lobes=3, radius=0.5, center=(-0.8, 0.1)),
+                inputs.ellipse(12, 16, a=0.6, b=0.25, center=(0.75, -0.3))])}
+
+
+@pytest.mark.parametrize("p", [8, 12])
+@pytest.mark.parametrize("omega", [5.0, 30.0])
+@pytest.mark.parametrize("name", ["star", "ellipse", "two_curves"])
+def test_fmm_oracle_matches_direct_sum(name, omega, p):
+    """oracle.fmm (Stages 1-8 box by box) reproduces the direct QBX sum over
+    all sources to eps: the lists and stages only regroup that sum, and
+    every translation is truncated at P_l = p_FMM(l) + p_add.  A dropped
+    list, a wrong W or X definition, a sign or index slip in any stage
+    leaves an O(1) part of the field wrong.  Trees with V lists on two or
+    more levels and non-empty W and X lists, plain and level-restricted."""
+    from oracle import fmm
+    from oracle import tree as otree
+    g = _fmm_geometries()[name]
+    eps, p_add = 1e-8, 40
+    rng = np.random.default_rng([5, int(omega), p])
+    ss = inputs.complex_gaussian(rng, (1, g.n))
+    sd = inputs.complex_gaussian(rng, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    ref = oracle.direct_qbx(omega, p, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    lr = name != "ellipse"
+    t = otree.build(g.sx, g.sy, g.cx, g.cy, 32, level_restrict=lr)
+    L = otree.lists(t)
+    assert len(set(lv for v, lv in zip(L["V"], t["level"]) if len(v))) >= 2
+    assert sum(len(w) for w in L["W"]) > 0 and sum(len(x) for x in L["X"]) > 0
+    P = fmm.orders(omega, t["R0"], int(t["level"].max()) + 1, eps, p_add)
+    u, _ = fmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, 32, level_restrict=lr)
+    rel = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    mx = np.max(np.abs(u - ref)) / np.max(np.abs(ref))
+    assert rel <= eps and mx <= 10 * eps, (rel, mx)
+
+
+def test_fmm_oracle_error_falls_with_p_add():
+    """The FMM error is truncation only: it falls geometrically as the
+    orders grow (Sec. 7.1), by orders of magnitude per ten extra terms."""
+    from oracle import fmm
+    from oracle import tree as otree
+    g = _fmm_geometries()["star"]
+    omega, p = 5.0, 8
+    rng = np.random.default_rng(17)
+    ss = inputs.complex_gaussian(rng, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    ref = oracle.direct_qbx(omega, p, g, g.sx, g.sy, ss, None, tgt_ctr=tc)
+    t = otree.build(g.sx, g.sy, g.cx, g.cy, 32)
+    errs = []
+    for p_add in (10, 20, 30):
+        P = fmm.orders(omega, t["R0"], int(t["level"].max()) + 1, 1e-8, p_add)
+        u, _ = fmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, None, 32)
+        errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    assert errs[0] > 100 * errs[1] > 100 * 100 * errs[2], errs
+
+
+def test_fmm_oracle_without_far_field():
+    """A tree of one or two levels has no V list: the FMM oracle is then the
+    direct sum itself (U lists cover every source) up to rounding."""
+    from oracle import fmm
+    from oracle import tree as otree
+    g = inputs.star(6, 8, lobes=3)
+    omega, p = 8.0, 10
+    rng = np.random.default_rng(23)
+    ss = inputs.complex_gaussian(rng, (1, g.n))
+    sd = inputs.complex_gaussian(rng, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    ref = oracle.direct_qbx(omega, p, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    for n_max in (200, 40):
+        t = otree.build(g.sx, g.sy, g.cx, g.cy, n_max)
+        assert int(t["level"].max()) + 1 == (1 if n_max == 200 else 2)
+        P = fmm.orders(omega, t["R0"], int(t["level"].max()) + 1, 1e-10, 20)
+        u, _ = fmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, n_max)
+        assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-13
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-10, 1e-14])
+def test_fmm_order_low_frequency_limit(eps):
+    """For omega R -> 0, |H_n(3 omega R) J_n(sqrt2 omega R)| tends to
+    (sqrt2/3)^n / (pi n) (leading terms of both series, DLMF 10.7.3 and
+    10.7.7), so the order of Sec. 7.1 tends to the last n where that bound
+    exceeds eps."""
+    from oracle import fmm
+    n = np.arange(1, 200)
+    lim = (np.sqrt(2.0) / 3.0) ** n / (np.pi * n)
+    expect = int(n[lim > eps].max())
+    # keep away from a threshold crossing the O(x^2) corrections could move
+    assert np.min(np.abs(np.log(lim[expect - 2:expect + 1] / eps))) > 1e-3
+    assert fmm.fmm_order(1.0, 1e-4, eps) == expect
+
+
+def test_fmm_order_grows_with_frequency_and_accuracy():
+    """The order is non-decreasing in omega R and in 1/eps, and at high
+    frequency exceeds the 3 omega R terms the Hankel factor needs to
+    start decaying."""
+    from oracle import fmm
+    xs = [0.05, 0.5, 2.0, 8.0, 20.0]
+    for eps in (1e-6, 1e-10):
+        o = [fmm.fmm_order(1.0, x, eps) for x in xs]
+        assert all(a <= b for a, b in zip(o, o[1:])), o
+        assert o[-1] >= np.sqrt(2) * xs[-1]
+    assert fmm.fmm_order(1.0, 2.0, 1e-10) > fmm.fmm_order(1.0, 2.0, 1e-6)

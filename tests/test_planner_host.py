@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(qbx.EXPORTS) == declared
-    assert L.qbx_abi_version() == 1
+    assert L.qbx_abi_version() == 2
 
 
 def _geometries():
@@ -40,25 +40,96 @@ def _geometries():
     yield "star5_small", inputs.star(8, 4, lobes=5)
 
 
+def _far_field_partition_holds(t, lists_of):
+    """Sec. 7.2: for a target in leaf b, every source is reached exactly once:
+    directly through U(b), by a multipole through W(b), or through the local
+    expansion of b, which gathers V(a) (multipoles) and X(a) (sources) over a
+    = b and its ancestors.  lists_of(name, box) gives a list as box indices."""
+    nb = t["level"].size
+    ns = sum(len(t["src"][b]) for b in range(nb) if t["leaf"][b])
+    for b in np.flatnonzero(t["leaf"]):
+        hit = np.zeros(ns, np.int64)
+        for u in lists_of("U", b):
+            hit[t["src"][u]] += 1
+        for w in lists_of("W", b):
+            hit[t["src"][w]] += 1
+        a = b
+        while a >= 0:
+            for v in lists_of("V", a):
+                hit[t["src"][v]] += 1
+            for x in lists_of("X", a):
+                hit[t["src"][x]] += 1
+            a = t["parent"][a]
+        if not np.all(hit == 1):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("level_restrict", [False, True])
 @pytest.mark.parametrize("leaf_max", [8, 32, 64])
 @pytest.mark.parametrize("name,geom", list(_geometries()))
-def test_tree_and_lists_match_definitions(name, geom, leaf_max):
+def test_tree_and_lists_match_definitions(name, geom, leaf_max, level_restrict):
     pl = qbx.Plan(geom, 20.0, 1e-8, geom.sx, geom.sy, np.arange(geom.n),
-                  qbx.options(p=8, leaf_max=leaf_max))
+                  qbx.options(p=8, leaf_max=leaf_max, level_restrict=level_restrict))
     bx = pl.boxes()
-    t = otree.build(geom.sx, geom.sy, geom.cx, geom.cy, leaf_max)
+    t = otree.build(geom.sx, geom.sy, geom.cx, geom.cy, leaf_max, level_restrict=level_restrict)
     for k in ("level", "ix", "iy", "parent"):
         assert np.array_equal(bx[k], t[k]), k
     assert np.array_equal(bx["leaf"].astype(bool), t["leaf"])
     assert np.array_equal(bx["nsrc"], t["nsrc"]) and np.array_equal(bx["nctr"], t["nctr"])
     L = otree.lists(t)
+    csr = {}
     for lname, which in (("U", qbx.LIST_U), ("V", qbx.LIST_V), ("W", qbx.LIST_W), ("X", qbx.LIST_X)):
         s, idx = pl.list(which)
+        csr[lname] = (s, idx)
         for b in range(len(s) - 1):
             assert np.array_equal(idx[s[b]:s[b + 1]], L[lname][b]), (lname, b)
-    # the lists partition every leaf's sources: U + W + far field = everything
+    # the planner's lists partition the sources seen from every leaf
+    assert _far_field_partition_holds(t, lambda n, b: csr[n][1][csr[n][0][b]:csr[n][0][b + 1]])
     st = pl.stats()
     assert st["n_boxes"] == t["level"].size
+
+
+@pytest.mark.parametrize("leaf_max", [4, 16])
+def test_level_restricted_tree_is_balanced(leaf_max):
+    """2:1 balance: touching leaves differ by at most one level, and the
+    restricted tree refines the adaptive one (every adaptive box is kept)."""
+    g = inputs.concat([inputs.star(16, 16, lobes=5, radius=0.5, center=(-0.6, 0.0)),
+                       inputs.ellipse(24, 16, a=0.5, b=0.05, center=(0.55, 0.2), rotation=0.4)])
+    free = qbx.Plan(g, 20.0, 1e-8, g.sx, g.sy, np.arange(g.n),
+                    qbx.options(p=8, leaf_max=leaf_max, level_restrict=False)).boxes()
+    bal = qbx.Plan(g, 20.0, 1e-8, g.sx, g.sy, np.arange(g.n),
+                   qbx.options(p=8, leaf_max=leaf_max, level_restrict=True)).boxes()
+
+    def unbalanced_pairs(bx):
+        lv, ix, iy = (bx[k].astype(np.int64) for k in ("level", "ix", "iy"))
+        lf = np.flatnonzero(bx["leaf"] != 0)
+        L = int(lv.max())
+        s = np.left_shift(1, L - lv[lf])
+        x0, x1, y0, y1 = ix[lf] * s, (ix[lf] + 1) * s, iy[lf] * s, (iy[lf] + 1) * s
+        touch = ((x0[:, None] <= x1[None, :]) & (x0[None, :] <= x1[:, None]) &
+                 (y0[:, None] <= y1[None, :]) & (y0[None, :] <= y1[:, None]))
+        gap = np.abs(lv[lf][:, None] - lv[lf][None, :])
+        return int(np.count_nonzero(touch & (gap >= 2)))
+
+    assert unbalanced_pairs(free) > 0, "the test geometry must need balancing"
+    assert unbalanced_pairs(bal) == 0
+    keys = lambda bx: set(zip(bx["level"].tolist(), bx["ix"].tolist(), bx["iy"].tolist()))
+    assert keys(free) < keys(bal)
+
+
+def test_partition_check_catches_a_wrong_w_list():
+    """The partition invariant fails for a plausible mistake in the lists: W
+    boxes one level too coarse (their parents instead of themselves)."""
+    g = inputs.concat([inputs.star(24, 16, lobes=3, radius=0.5, center=(-0.9, 0.1)),
+                       inputs.ellipse(30, 16, a=0.6, b=0.2, center=(0.8, -0.4))])
+    t = otree.build(g.sx, g.sy, g.cx, g.cy, 8)
+    L = otree.lists(t)
+    assert _far_field_partition_holds(t, lambda n, b: L[n][b])
+    assert any(len(w) for w in L["W"])
+    bad = {k: list(v) for k, v in L.items()}
+    bad["W"] = [np.unique(t["parent"][w]) if len(w) else w for w in L["W"]]
+    assert not _far_field_partition_holds(t, lambda n, b: bad[n][b])
 
 
 def test_single_box_tree():
