@@ -35,28 +35,42 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
 METRIC = "QBX-FMM potential evals/s (targets·densities/s) at ε=1e-10; p50/p99 latency"
 
 
-def cpu_baseline(wl, target_seconds=12.0):
+def cpu_baseline(wl, run_seconds=2.0, runs=5, one_thread_seconds=2.0, one_thread_runs=3):
     """The oracle (direct O(N_s N_c) QBX, C + OpenMP) on a sample of the
     workload's targets: their centres' coefficients over all sources, then
-    the evaluation at those targets."""
+    the evaluation at those targets.  The oracle is rebuilt with -O3
+    -march=native for this host; the sample is sized for about run_seconds a
+    run; the figure is the median of `runs` runs after one warm-up, on every
+    host thread, and the median of `one_thread_runs` runs on one thread."""
+    import tempfile
+
     import oracle
     g = wl.geom
     threads = oracle.default_threads()
+    native = tempfile.mkdtemp(prefix="qbx_oracle_")
+    oracle.use_native_build(native)
     rng = np.random.default_rng(1234)
 
-    def run(n):
+    def run(n, nthr):
         pick = np.sort(rng.choice(g.n, n, replace=False))
         t0 = time.perf_counter()
         alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny,
-                                        wl.sigma_s, wl.sigma_d, g.cx[pick], g.cy[pick], threads)
+                                        wl.sigma_s, wl.sigma_d, g.cx[pick], g.cy[pick], nthr)
         oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick], wl.ty[pick],
-                        np.arange(n, dtype=np.int32), threads)
+                        np.arange(n, dtype=np.int32), nthr)
         return time.perf_counter() - t0
 
-    probe = max(threads, 16)
-    t = run(probe)
-    n = int(min(g.n, max(probe, probe * target_seconds / max(t, 1e-6))))
-    t = run(n)
+    def sized(nthr, seconds):
+        probe = max(nthr, 4)
+        t = run(probe, nthr)
+        return int(min(g.n, max(probe, probe * seconds / max(t, 1e-6))))
+
+    n = sized(threads, run_seconds)
+    run(n, threads)                                      # warm-up
+    times = [run(n, threads) for _ in range(runs)]
+    t_med = float(np.median(times))
+    n1 = sized(1, one_thread_seconds)
+    t1 = float(np.median([run(n1, 1) for _ in range(one_thread_runs)]))
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -65,11 +79,14 @@ def cpu_baseline(wl, target_seconds=12.0):
                 break
     except OSError:
         pass
-    return {"value": n * wl.n_dens / t, "unit": "targets*densities/s", "cores": threads,
+    return {"value": n * wl.n_dens / t_med, "unit": "targets*densities/s", "cores": threads,
             "kind": "oracle",
+            "one_thread_value": n1 * wl.n_dens / t1,
             "sample": f"{n} of {g.n} targets (their centres' coefficients over all {g.n} sources, "
-                      f"then QBX evaluation), {wl.n_dens} density, {t:.1f} s on {threads} "
-                      f"threads of {cpu}"}
+                      f"then QBX evaluation), {wl.n_dens} density; median of {runs} runs after a "
+                      f"warm-up ({t_med:.2f} s each) on {threads} threads of {cpu}; one thread: "
+                      f"{n1} targets, median of {one_thread_runs} runs ({t1:.2f} s each); "
+                      f"gcc -O3 -march=native"}
 
 
 # stage -> its main kernel, as rocprofv3 names it

@@ -37,21 +37,43 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (plain -O2, OpenMP over centres)."""
+    """Compile the C oracle with gcc (-O3 for any x86-64 with AVX2, OpenMP
+    over centres).  The library travels with the repository, so it is built
+    for a portable instruction set, not for the machine that builds it."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
+        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
                "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
 
 
-def lib():
+def use_native_build(workdir: str) -> str:
+    """Rebuilds the oracle with -O3 -march=native for the host it runs on,
+    in workdir, and makes this process use that copy (for timing it as a
+    CPU baseline).  Returns the library path."""
     global _lib
+    out = os.path.join(workdir, "libqbxoracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
+           "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    _lib = None
+    _load(out)
+    return out
+
+
+def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        _load(_LIB)
+    return _lib
+
+
+def _load(path):
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(path)
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.oracle_hankel1_seq.argtypes = [dbl, i32, _dp]
         L.oracle_besselj_seq.argtypes = [dbl, i32, _dp]

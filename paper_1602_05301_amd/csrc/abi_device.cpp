@@ -156,6 +156,14 @@ struct qbx_geom_s {
     // the radial sequences depend on the geometry only: computed on the
     // first evaluation (once the scratch exists) and kept, like the tables
     bool rad_ready = false;
+    // FMM mode: the targets no expansion disk holds are the centres of an
+    // order-0 geometry on the same sources (each target bound to its own
+    // centre), which writes their potentials into this geometry's output:
+    // its P2QBXL, M2QBXL and L2QBXL are then the point FMM's near-field sum,
+    // M2P and L2P (Sec. 7) at those targets
+    qbx_geom_s *sub = nullptr;
+    std::vector<int32_t> out_map;   // of a sub-geometry: the owner's target per target
+    long long out_stride = 0;       // of a sub-geometry: the owner's target count
     // captured evaluations (qbx_geom_graph), keyed by their arguments
     struct GraphRec {
         int n_dens;
@@ -255,7 +263,10 @@ qbx_status upload(qbx_geom_s *G)
     }
     g.tx = ar.upload(pl.tx); g.ty = ar.upload(pl.ty); g.tgt_cs = ar.upload(tcs);
     g.smooth_list = ar.upload(smooth);
-    g.n_smooth = (int)smooth.size();
+    // in FMM mode the order-0 sub-geometry serves these targets
+    g.n_smooth = pl.opt.direct ? (int)smooth.size() : 0;
+    g.tgt_out = G->out_map.empty() ? nullptr : ar.upload(G->out_map);
+    g.u_stride = G->out_stride > 0 ? G->out_stride : (long long)pl.nt;
 
     std::vector<double> bcx(nb), bcy(nb);
     for (int b = 0; b < nb; ++b) pl.box_center(b, &bcx[b], &bcy[b]);
@@ -623,6 +634,10 @@ qbx_status upload(qbx_geom_s *G)
 
 qbx_status ensure_scratch(qbx_geom_s *G)
 {
+    if (G->sub && !G->sub->qs) {
+        qbx_status q = ensure_scratch(G->sub);
+        if (q != QBX_OK) return q;
+    }
     if (G->qs) return QBX_OK;
     DeviceArena &s = G->scratch;
     const Plan &pl = G->pl;
@@ -656,6 +671,10 @@ qbx_status ensure_scratch(qbx_geom_s *G)
 // its (pair, density) combinations, cut into tiles of 16.
 qbx_status ensure_tiles(qbx_geom_s *G, int nd)
 {
+    if (G->sub) {
+        qbx_status q = ensure_tiles(G->sub, nd);
+        if (q != QBX_OK) return q;
+    }
     if (G->m2m_tiles[nd]) return QBX_OK;
     std::vector<M2LTile> t;
     for (const auto &grp : G->m2l_groups) {
@@ -867,7 +886,14 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         STAGE(QBX_STAGE_EVAL);
         LAUNCH(QBX_STAGE_EVAL, pl.nt, launch_qbx_eval(g, nd, G->coef, u, st));
     }
-    {
+    if (G->sub) {
+        // the targets outside every expansion disk, through the order-0
+        // geometry (it writes into u at their indices)
+        STAGE(QBX_STAGE_SMOOTH);
+        timer_QBX_STAGE_SMOOTH.launches++;
+        qbx_status q = run_pipeline(G->sub, nd, ss, sd, u, nullptr, st, lane);
+        if (q != QBX_OK) return q;
+    } else {
         STAGE(QBX_STAGE_SMOOTH);
         LAUNCH(QBX_STAGE_SMOOTH, G->g.n_smooth, launch_smooth(g, nd, G->qs, G->qd, u, st));
     }
@@ -916,6 +942,13 @@ void stage_work(const qbx_geom_s *G, int nd, double *f)
         }
     }
     for (int s = 0; s < QBX_N_STAGES; ++s) f[s] *= nd;
+    if (G->sub) {
+        // FMM mode: the smooth-rule targets go through the order-0 geometry
+        double fs[QBX_N_STAGES];
+        stage_work(G->sub, nd, fs);
+        f[QBX_STAGE_SMOOTH] = 0.0;
+        for (int s = 0; s < QBX_N_STAGES; ++s) f[QBX_STAGE_SMOOTH] += fs[s];
+    }
 }
 
 
@@ -1251,6 +1284,62 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx)
     return QBX_OK;
 }
 
+namespace {
+
+void free_geom(qbx_geom_s *G)
+{
+    if (!G) return;
+    free_geom(G->sub);
+    G->sub = nullptr;
+    G->scratch.release();
+    G->arena.release();
+    delete G;
+}
+
+// FMM mode with targets outside every expansion disk: the order-0 geometry
+// that serves them (sources as G's, centres at those targets, each target
+// bound to its own centre, p = 0; the same tolerance and tree options).
+qbx_status make_smooth_sub(qbx_geom_s *G)
+{
+    const Plan &pl = G->pl;
+    if (pl.opt.direct) return QBX_OK;
+    std::vector<int32_t> idx;
+    for (int64_t m = 0; m < pl.nt; ++m)
+        if (pl.tgt_ctr[m] < 0) idx.push_back((int32_t)m);
+    if (idx.empty()) return QBX_OK;
+    int64_t n = (int64_t)idx.size();
+    std::vector<double> px(n), py(n), pr(n, 1e-300);
+    std::vector<int32_t> own(n);
+    for (int64_t i = 0; i < n; ++i) {
+        px[i] = pl.tx[idx[i]];
+        py[i] = pl.ty[idx[i]];
+        own[i] = (int32_t)i;
+    }
+    qbx_options o = pl.opt;
+    o.p = 0;
+    o.p_add = -1;
+    qbx_geom_s *S = new qbx_geom_s();
+    S->ctx = G->ctx;
+    Error e = build_plan(S->pl, pl.omega, pl.eps, o, pl.ns, pl.sx.data(), pl.sy.data(), pl.w.data(),
+                         pl.nx.data(), pl.ny.data(), pl.sh.data(), n, px.data(), py.data(), pr.data(), n,
+                         px.data(), py.data(), own.data());
+    if (e.status != QBX_OK) {
+        delete S;
+        return fail(e.status, "order-0 geometry of the smooth-rule targets: " + e.msg);
+    }
+    S->out_map = idx;
+    S->out_stride = pl.nt;
+    qbx_status st = upload(S);
+    if (st != QBX_OK) {
+        free_geom(S);
+        return st;
+    }
+    G->sub = S;
+    return QBX_OK;
+}
+
+}  // namespace
+
 qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
 {
     if (!ctx || !plan || !out) return fail(QBX_E_INVAL, "null argument");
@@ -1263,13 +1352,13 @@ qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
         G->ctx = ctx;
         G->pl = plan->pl;
         qbx_status st = upload(G);
+        if (st == QBX_OK) st = make_smooth_sub(G);
         if (st != QBX_OK) {
-            G->arena.release();
-            delete G;
+            free_geom(G);
             return st;
         }
     } catch (const std::bad_alloc &) {
-        if (G) { G->arena.release(); delete G; }
+        free_geom(G);
         return fail(QBX_E_NOMEM, "host allocation failed while building tables");
     }
     *out = G;
@@ -1303,9 +1392,7 @@ qbx_status qbx_geom_destroy(qbx_geom G)
     else (void)hipDeviceSynchronize();
     if (G->ctx->gstream) (void)hipStreamSynchronize(G->ctx->gstream);
     if (G->ctx->lane.side) (void)hipStreamSynchronize(G->ctx->lane.side);
-    G->scratch.release();
-    G->arena.release();
-    delete G;
+    free_geom(G);
     return QBX_OK;
 }
 
@@ -1314,12 +1401,21 @@ qbx_status qbx_geom_stats(qbx_geom G, qbx_stats *out)
     if (!G || !out) return fail(QBX_E_INVAL, "null argument");
     fill_stats(G->pl, out);
     out->device_bytes = G->arena.bytes + G->scratch.bytes;
+    if (G->sub) out->device_bytes += G->sub->arena.bytes + G->sub->scratch.bytes;
     return QBX_OK;
 }
 
 size_t qbx_geom_bytes(qbx_geom G, int32_t n_dens)
 {
     if (!G) return 0;
+    if (G->sub) {
+        // the order-0 geometry of the smooth-rule targets, counted once
+        qbx_geom_s *S = G->sub;
+        G->sub = nullptr;
+        size_t b = qbx_geom_bytes(G, n_dens) + qbx_geom_bytes(S, n_dens);
+        G->sub = S;
+        return b;
+    }
     const Plan &pl = G->pl;
     const size_t nd = kDensChunk, cdb = sizeof(cd);
     auto at1 = [](long long n) { return (size_t)std::max<long long>(n, 1); };
@@ -1416,24 +1512,28 @@ qbx_status graph_for(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const v
     // when the graph does.  Until then the flag that lets later evaluations
     // skip them must not stand (the caller clears it again if the launch
     // fails).
-    bool rad0 = G->rad_ready;
+    bool rad0 = G->rad_ready, srad0 = G->sub && G->sub->rad_ready;
+    auto undo = [&]() {
+        G->rad_ready = rad0;
+        if (G->sub) G->sub->rad_ready = srad0;
+    };
     qbx_status q = eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, gs, G->ctx->lane);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(gs, &graph);
     if (q != QBX_OK) {
-        G->rad_ready = rad0;
+        undo();
         if (graph) (void)hipGraphDestroy(graph);
         return q;
     }
     if (e != hipSuccess) {
-        G->rad_ready = rad0;
+        undo();
         return fail(QBX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        G->rad_ready = rad0;
+        undo();
         return fail(QBX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     if (G->graphs.size() >= kMaxGraphs) {
@@ -1472,6 +1572,7 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
         if (e != hipSuccess) {
             // the radial sequences recorded in the graph may never have run
             G->rad_ready = false;
+            if (G->sub) G->sub->rad_ready = false;
             return fail(QBX_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
         }
         CHK(hipEventRecord(C->ev_out, C->gstream));
@@ -1527,9 +1628,16 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
             if ((int)passes.size() <= k) passes.resize(k + 1);
             const Plan &pl = G->pl;
             const void *ss = dens(sigma_s, i), *sd = dens(sigma_d, i);
-            passes[k].push_back({G, nd, ss ? static_cast<const cd *>(ss) + (long long)d0 * pl.ns : nullptr,
-                                 sd ? static_cast<const cd *>(sd) + (long long)d0 * pl.ns : nullptr,
-                                 static_cast<cd *>(u[i]) + (long long)d0 * pl.nt});
+            BItem it{G, nd, ss ? static_cast<const cd *>(ss) + (long long)d0 * pl.ns : nullptr,
+                     sd ? static_cast<const cd *>(sd) + (long long)d0 * pl.ns : nullptr,
+                     static_cast<cd *>(u[i]) + (long long)d0 * pl.nt};
+            passes[k].push_back(it);
+            if (G->sub) {
+                // the smooth-rule targets: the order-0 geometry in the same
+                // pass, writing into the same output
+                it.G = G->sub;
+                passes[k].push_back(it);
+            }
         }
         if (!any) break;
     }

@@ -1547,11 +1547,12 @@ __device__ __forceinline__ void qbx_eval_body(const DevGeom &g, int nd, const cd
     double rho = sqrt(dx * dx + dy * dy);
     double x = g.omega * rho;
     cd v = rho > 0.0 ? mk(dx / rho, dy / rho) : mk(1.0, 0.0);    // e^{i theta}
+    long long o = g.tgt_out ? (long long)g.tgt_out[m] : (long long)m;
     for (int d = 0; d < nd; ++d) {
         const cd *a = coef + (long long)d * nq * g.nc + i;
         cd a0 = a[(long long)p * g.nc];
         if (x == 0.0) {
-            u[(long long)d * g.nt + m] = a0;
+            u[(long long)d * g.u_stride + o] = a0;
             continue;
         }
         int M = miller_start(x, p);
@@ -1578,7 +1579,7 @@ __device__ __forceinline__ void qbx_eval_body(const DevGeom &g, int nd, const cd
         }
         double jz = j0(x), jo = j1(x);
         double s = fabs(jz) >= fabs(jo) ? jz / f : jo / f1;
-        u[(long long)d * g.nt + m] = s * S + jz * a0;
+        u[(long long)d * g.u_stride + o] = s * S + jz * a0;
     }
 }
 

@@ -32,6 +32,11 @@ struct DevGeom {
     const QBX_G double *tx, *ty;                     // targets, user order
     const QBX_G int *tgt_cs;                         // per target: sorted centre or -1
     const QBX_G int *smooth_list;                    // targets served by the smooth rule
+    // where the evaluation writes: u[d * u_stride + tgt_out[m]] (tgt_out null:
+    // the target's own index m); a geometry that serves some targets of
+    // another writes into that one's output
+    const QBX_G int *tgt_out;
+    long long u_stride;
     const QBX_G double *bcx, *bcy;                   // box centres
     const QBX_G int *blev, *leaf, *parent, *child_begin, *child_count;
     const QBX_G int *src_begin, *src_end, *ctr_begin, *ctr_end;

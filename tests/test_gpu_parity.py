@@ -38,6 +38,24 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def _assert_fmm(u, ref, eps, what):
+    """FMM against direct QBX: relative l2 error over the targets at most eps
+    and the largest error at most 10 eps relative to the largest value."""
+    err = _rel(u, ref)
+    mx = float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))
+    print(f"{what}: rel_l2={err:.3e} max={mx:.3e} (eps {eps:g})", flush=True)
+    assert err <= eps and mx <= 10 * eps, (what, err, mx)
+
+
+def _oracle_at_nodes(g, omega, p, ss, sd, pick):
+    """Direct QBX (oracle) at the on-curve targets `pick`, each bound to its
+    own centre: [n_dens, pick.size]."""
+    alpha = oracle.qbx_coefficients(omega, p, g.sx, g.sy, g.w, g.nx, g.ny, ss, sd,
+                                    g.cx[pick], g.cy[pick])
+    return oracle.qbx_eval(omega, p, g.cx[pick], g.cy[pick], alpha, g.sx[pick], g.sy[pick],
+                           np.arange(pick.size, dtype=np.int32))
+
+
 def _coef_err(alpha_gpu, alpha_ref, omega, cr, p):
     """Coefficient error weighted by J_|l|(omega r), the factor each alpha_l
     carries at the edge of its disk, relative to the largest such term."""
@@ -85,19 +103,19 @@ def test_fmm_matches_direct_oracle(ctx, n_panels, omega, eps, p):
                        coef=True, p=p, leaf_max=32)
     ref, alpha, _ = oracle.direct_qbx(omega, p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d,
                                       tgt_ctr=wl.tgt_ctr, return_coef=True)
-    err = _rel(u, ref)
-    print(f"fmm n={g.n} omega={omega} eps={eps} p={p}: rel_l2={err:.3e} "
-          f"max={np.max(np.abs(u - ref)) / np.max(np.abs(ref)):.3e} "
+    print(f"fmm n={g.n} omega={omega} eps={eps} p={p}: "
           f"coef={_coef_err(coef, alpha, omega, g.cr, p):.3e}", flush=True)
-    assert err < eps
+    _assert_fmm(u, ref, eps, f"fmm n={g.n} omega={omega} p={p}")
 
 
+@pytest.mark.parametrize("level_restrict", [True, False])
 @pytest.mark.parametrize("n_panels,omega,p,p_add,leaf_max", [(64, 20.0, 12, 30, 32),
                                                              (40, 60.0, 8, 20, 16)])
-def test_fmm_matches_oracle_fmm_stage_by_stage(ctx, n_panels, omega, p, p_add, leaf_max):
+def test_fmm_matches_oracle_fmm_stage_by_stage(ctx, n_panels, omega, p, p_add, leaf_max, level_restrict):
     """Same tree, same orders, same translations: the GPU FMM reproduces the
     oracle's plain stage-by-stage FMM to rounding (coefficients and
-    potentials), independently of how close either is to direct QBX."""
+    potentials), independently of how close either is to direct QBX.  Plain
+    and level-restricted trees."""
     from oracle import fmm as ofmm
     from oracle import tree as otree
     g = inputs.star(n_panels, 16, lobes=7)
@@ -107,10 +125,11 @@ def test_fmm_matches_oracle_fmm_stage_by_stage(ctx, n_panels, omega, p, p_add, l
     tc = np.arange(g.n, dtype=np.int32)
     eps = 1e-10
     _, u, coef = _eval(ctx, g, omega, eps, g.sx, g.sy, tc, ss, sd, coef=True, p=p,
-                       p_add=p_add, leaf_max=leaf_max, w_direct=0)
-    t = otree.build(g.sx, g.sy, g.cx, g.cy, leaf_max)
+                       p_add=p_add, leaf_max=leaf_max, w_direct=0, level_restrict=level_restrict)
+    t = otree.build(g.sx, g.sy, g.cx, g.cy, leaf_max, level_restrict=level_restrict)
     P = ofmm.orders(omega, t["R0"], int(t["level"].max()) + 1, eps, p_add)
-    u_o, alpha_o = ofmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, leaf_max)
+    u_o, alpha_o = ofmm.qbx_fmm(omega, p, P, g, g.sx, g.sy, tc, ss, sd, leaf_max,
+                                level_restrict=level_restrict)
     assert _rel(u, u_o) < 1e-13
     assert _coef_err(coef, alpha_o, omega, g.cr, p) < 1e-12
 
@@ -125,7 +144,7 @@ def test_w_list_direct_switch(ctx, w_direct):
                  p=wl.p, w_direct=w_direct)
     ref = oracle.direct_qbx(wl.omega, wl.p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d,
                             tgt_ctr=wl.tgt_ctr)
-    assert _rel(u, ref) < wl.eps
+    _assert_fmm(u, ref, wl.eps, f"w_direct={w_direct}")
 
 
 def test_fmm_full_size_sampled(ctx):
@@ -137,20 +156,30 @@ def test_fmm_full_size_sampled(ctx):
     _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
                  p=wl.p, leaf_max=wl.leaf_max)
     pick = np.sort(np.random.default_rng(0).choice(g.n, 512, replace=False))
-    alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny, wl.sigma_s,
-                                    wl.sigma_d, g.cx[pick], g.cy[pick])
-    ref = oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick],
-                          wl.ty[pick], np.arange(pick.size, dtype=np.int32))
-    err = _rel(u[:, pick], ref)
-    print(f"full-size sampled rel_l2={err:.3e}", flush=True)
-    assert err < wl.eps
+    ref = _oracle_at_nodes(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, pick)
+    _assert_fmm(u[:, pick], ref, wl.eps, "full-size sampled")
+
+
+def test_fmm_full_size_four_densities_sampled(ctx):
+    """The 32768-node star with 4 densities in one call (one chunk: every
+    GEMM stage takes 4 columns per box): each density against the oracle at
+    512 sampled targets."""
+    wl = inputs.fmm_star(n_dens=4)
+    g = wl.geom
+    _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                 p=wl.p, leaf_max=wl.leaf_max)
+    assert u.shape == (4, g.n)
+    pick = np.sort(np.random.default_rng(4).choice(g.n, 512, replace=False))
+    ref = _oracle_at_nodes(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, pick)
+    for d in range(4):
+        _assert_fmm(u[d, pick], ref[d], wl.eps, f"full-size density {d}")
 
 
 def test_fmm_multiscale_sampled(ctx):
     """64 curves of different sizes and curvatures in [-10, 10]^2 with
     adaptive panels, about 600k nodes = centres = targets, omega = 100,
     eps = 1e-8, p = 12, leaves of up to 64 points: orders run from 54 at the
-    leaves to 425 at level 2.  Potentials at 128 sampled targets against the
+    leaves to 425 at level 2.  Potentials at 512 sampled targets against the
     oracle evaluated for exactly those targets' centres."""
     g, _ = inputs.multiscale_curves()
     r = inputs.rng_for(2, 2)
@@ -160,13 +189,9 @@ def test_fmm_multiscale_sampled(ctx):
     omega, eps, p = 100.0, 1e-8, 12
     print(f"multiscale n={g.n}", flush=True)
     _, u = _eval(ctx, g, omega, eps, g.sx, g.sy, tc, ss, sd, p=p, leaf_max=64)
-    pick = np.sort(np.random.default_rng(1).choice(g.n, 128, replace=False))
-    alpha = oracle.qbx_coefficients(omega, p, g.sx, g.sy, g.w, g.nx, g.ny, ss, sd, g.cx[pick], g.cy[pick])
-    ref = oracle.qbx_eval(omega, p, g.cx[pick], g.cy[pick], alpha, g.sx[pick], g.sy[pick],
-                          np.arange(pick.size, dtype=np.int32))
-    err = _rel(u[:, pick], ref)
-    print(f"multiscale sampled rel_l2={err:.3e}", flush=True)
-    assert err < eps
+    pick = np.sort(np.random.default_rng(1).choice(g.n, 512, replace=False))
+    ref = _oracle_at_nodes(g, omega, p, ss, sd, pick)
+    _assert_fmm(u[:, pick], ref, eps, "multiscale sampled")
 
 
 def test_multi_density_chunks_and_determinism(ctx):
@@ -199,8 +224,23 @@ def test_fmm_with_volume_targets(ctx):
     sd = inputs.complex_gaussian(rng, (1, g.n))
     geo, u = _eval(ctx, g, 15.0, 1e-10, tx, ty, None, ss, sd, p=12)
     ref = oracle.direct_qbx(15.0, 12, g, tx, ty, ss, sd)
-    assert np.array_equal(geo.association(), oracle.associate(tx, ty, g.cx, g.cy, g.cr, g.sx, g.sy, g.h))
-    assert _rel(u, ref) < 1e-10
+    assoc = geo.association()
+    assert np.array_equal(assoc, oracle.associate(tx, ty, g.cx, g.cy, g.cr, g.sx, g.sy, g.h))
+    n_smooth = int((assoc < 0).sum())
+    assert n_smooth > 100
+    err, mx = _rel(u, ref), np.max(np.abs(u - ref)) / np.max(np.abs(ref))
+    sm = np.flatnonzero(assoc < 0)
+    err_s = _rel(u[0, sm], ref[0, sm])
+    print(f"volume targets (FMM mode): rel_l2 {err:.2e} max {mx:.2e} smooth-rule targets {err_s:.2e}",
+          flush=True)
+    assert err < 1e-10 and mx < 1e-9 and err_s < 1e-10
+    # the smooth-rule targets go through the order-0 FMM, not a sum over all sources
+    assert geo.work(1)["smooth"] != 16.0 * n_smooth * g.n
+    # the batched path serves them the same way, bit for bit
+    ub = torch.empty((1, tx.size), dtype=torch.complex128, device="cuda")
+    ctx.eval_batch([geo], [_dev(ss)], [_dev(sd)], [ub])
+    torch.cuda.synchronize()
+    assert np.array_equal(ub.cpu().numpy(), u)
 
 
 def test_cfie_gmres_point_source(ctx):
@@ -384,9 +424,7 @@ def test_fp32_far_field_matches_direct_oracle(ctx, n_panels, omega, eps, p):
     _, u = _eval(ctx, g, omega, eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
                  p=p, far_fp32=True)
     ref = oracle.direct_qbx(omega, p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d, tgt_ctr=wl.tgt_ctr)
-    err = _rel(u, ref)
-    print(f"fp32 far field n={g.n} omega={omega} eps={eps}: rel_l2={err:.3e}", flush=True)
-    assert err < eps
+    _assert_fmm(u, ref, eps, f"fp32 far field n={g.n} omega={omega}")
 
 
 def test_batch_matches_each_alone(ctx):
@@ -414,6 +452,13 @@ def test_batch_matches_each_alone(ctx):
     torch.cuda.synchronize()
     for k, i in enumerate(order):
         assert np.array_equal(us[k].cpu().numpy(), alone[k]), (k, i)
+    # and each against the oracle at sampled targets, to its eps
+    for i, (npan, omega, eps, p, nd) in enumerate(specs):
+        g = inputs.star(npan, 16, lobes=3 + i)
+        pick = np.sort(r.choice(g.n, 64, replace=False))
+        ref = _oracle_at_nodes(g, omega, p, ss[i].cpu().numpy(),
+                               None if sd[i] is None else sd[i].cpu().numpy(), pick)
+        _assert_fmm(us[order.index(i)].cpu().numpy()[:, pick], ref, eps, f"batch geometry {i}")
 
 
 def test_batch_mixed_modes_match_alone(ctx):
@@ -471,6 +516,15 @@ def test_served_requests_equal_alone(ctx):
         assert len(r.outputs) == len(a.outputs) == len(r.densities)
         for x, y in zip(r.outputs, a.outputs):
             assert np.array_equal(x, y), r.rid
+    # served results against the oracle: first and last matvec of each request
+    rng = np.random.default_rng(6)
+    for r in reqs:
+        g = r.geom
+        pick = np.sort(rng.choice(g.n, 48, replace=False))
+        for k in (0, len(r.densities) - 1):
+            d = r.densities[k][None]
+            ref = _oracle_at_nodes(g, r.omega, r.p, d, d, pick)
+            _assert_fmm(r.outputs[k][None, pick], ref, r.eps, f"served request {r.rid} matvec {k}")
 
 
 def test_fmm_high_frequency_large_orders(ctx):
@@ -486,9 +540,7 @@ def test_fmm_high_frequency_large_orders(ctx):
     assert qbx.Plan(g, omega, eps, g.sx, g.sy, tc, qbx.options(p=p)).orders()[2] > 120   # M2L at level 2
     u = geo.eval(_dev(ss), None).cpu().numpy()
     ref = oracle.direct_qbx(omega, p, g, g.sx, g.sy, ss, None, tgt_ctr=tc)
-    err = _rel(u, ref)
-    print(f"omega=200 rel_l2={err:.3e}", flush=True)
-    assert err < eps
+    _assert_fmm(u, ref, eps, "omega=200")
 
 
 def test_autotune_keeps_results(ctx):
@@ -680,3 +732,93 @@ def test_area_queries_edge_cases(ctx):
     far = np.linspace(3.0, 9.0, 50) * R0
     out, nf = geo.associate(_dev(far), _dev(-far))
     assert np.all(out.cpu().numpy() == -1) and nf == 0
+
+
+@pytest.mark.parametrize("eps", [1e-10, 1e-6])
+def test_batched_256_geometries(ctx, eps):
+    """The batched workload at full size: 256 star and ellipse curves of
+    512-16384 nodes (1.04M in all), omega in [5, 150], 4 densities each, one
+    qbx_eval_batch over all of them; FP64 at eps = 1e-10 (p = 14), FP32 far
+    field at 1e-6 (p = 9).  Every geometry's result is bitwise equal to its
+    evaluation alone, and matches the oracle at 64 sampled targets to eps."""
+    import concurrent.futures as cf
+
+    from paper_1602_05301_amd import qbx
+    far32 = eps >= 1e-6
+    p = 9 if far32 else 14
+    curves = inputs.batched_geometries(256)
+    dr = inputs.rng_for(3, 2)
+    dens = [inputs.complex_gaussian(dr, (4, g.n)) for g, _ in curves]
+
+    def build(item):
+        g, w = item
+        return qbx.Geometry(ctx, g, w, eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32),
+                            qbx.options(p=p, far_fp32=far32))
+    with cf.ThreadPoolExecutor(max_workers=8) as pool:
+        geos = list(pool.map(build, curves))
+    s = [_dev(d) for d in dens]
+    ub = [torch.empty_like(x) for x in s]
+    ctx.eval_batch(geos, s, s, ub)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    worst = 0.0
+    for i, ((g, w), geo) in enumerate(zip(curves, geos)):
+        got = ub[i].cpu().numpy()
+        assert np.array_equal(geo.eval(s[i], s[i]).cpu().numpy(), got), i
+        pick = np.sort(rng.choice(g.n, 64, replace=False))
+        ref = _oracle_at_nodes(g, w, p, dens[i], dens[i], pick)
+        err = _rel(got[:, pick], ref)
+        mx = float(np.max(np.abs(got[:, pick] - ref)) / np.max(np.abs(ref)))
+        worst = max(worst, err)
+        assert err <= eps and mx <= 10 * eps, (i, g.n, w, err, mx)
+    print(f"256 geometries eps={eps:g}: worst sampled rel_l2 {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("p", [16, 24, 40])
+def test_direct_mode_high_orders(ctx, p):
+    """Direct mode at the larger QBX orders (the P2QBXL buckets above 14)."""
+    g = inputs.star(32, 16, lobes=5)
+    r = np.random.default_rng(40 + p)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    sd = inputs.complex_gaussian(r, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    _, u = _eval(ctx, g, 10.0, 1e-10, g.sx, g.sy, tc, ss, sd, p=p, direct=True)
+    ref = oracle.direct_qbx(10.0, p, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    err = _rel(u, ref)
+    print(f"direct p={p}: rel_l2={err:.3e}", flush=True)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("p", [16, 24, 40])
+def test_fmm_high_orders(ctx, p):
+    """FMM at the larger QBX orders, with the default p_add, against direct
+    QBX to eps."""
+    g = inputs.star(64, 16, lobes=5)
+    r = np.random.default_rng(50 + p)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    sd = inputs.complex_gaussian(r, (1, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    eps = 1e-10
+    _, u = _eval(ctx, g, 20.0, eps, g.sx, g.sy, tc, ss, sd, p=p)
+    ref = oracle.direct_qbx(20.0, p, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    _assert_fmm(u, ref, eps, f"fmm p={p}")
+
+
+@pytest.mark.parametrize("leaf_max,levels", [(600, 1), (200, 2)])
+def test_fmm_shallow_trees(ctx, leaf_max, levels):
+    """FMM mode on trees of one and two levels: no V list exists, every
+    source reaches every centre through the U lists, so the result is direct
+    QBX up to rounding."""
+    from paper_1602_05301_amd import qbx
+    g = inputs.star(16, 16, lobes=3)
+    r = np.random.default_rng(60 + levels)
+    ss = inputs.complex_gaussian(r, (2, g.n))
+    sd = inputs.complex_gaussian(r, (2, g.n))
+    tc = np.arange(g.n, dtype=np.int32)
+    assert qbx.Plan(g, 12.0, 1e-10, g.sx, g.sy, tc,
+                    qbx.options(p=10, leaf_max=leaf_max)).stats()["n_levels"] == levels
+    _, u = _eval(ctx, g, 12.0, 1e-10, g.sx, g.sy, tc, ss, sd, p=10, leaf_max=leaf_max)
+    ref = oracle.direct_qbx(12.0, 10, g, g.sx, g.sy, ss, sd, tgt_ctr=tc)
+    err = _rel(u, ref)
+    print(f"shallow tree levels={levels}: rel_l2={err:.3e}", flush=True)
+    assert err < 1e-12
