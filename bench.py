@@ -13,9 +13,12 @@ Prints one JSON line with the throughput (targets x densities per second)
 over the timed steps, per-step latency percentiles, the roofline figure of
 the dominant kernel (HIP events on the library's stream over K further steps
 run with stage profiling on, which keeps every stage on that one stream), and
-the CPU oracle timed on a bounded sample of the same workload.
+the CPU oracle timed on a bounded sample of the same workload.  Further keys
+hold the other workloads (--legs): the 256-curve batch at eps 1e-10 and
+1e-6, the 606k-node multiscale set, and a bounded served request stream
+against the plain per-request path.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--n-dens 1]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--n-dens 1] [--legs ...]
 """
 from __future__ import annotations
 
@@ -96,12 +99,44 @@ STAGE_KERNEL = {"p2m": "k_p2m", "m2m": "k_m2m_mfma", "m2l": "k_m2l_mfma", "p2l_x
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qbx_fmm_star7_32768_traffic.json")
 
 
-def measured_traffic(stage):
-    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+def stage_kernel(stage, m2l_choice):
+    """The kernel a stage ran: M2L runs the direct-load form when the
+    autotuner picked it (waves per tile 0)."""
+    if stage == "m2l" and m2l_choice == 0:
+        return "k_m2l_mfma_direct"
+    return STAGE_KERNEL.get(stage)
+
+
+def m2l_algorithmic_bytes(plan, n_dens, far_fp32=False):
+    """HBM bytes M2L must move at the least (Stage 4): each (level, rotation
+    orbit) translation matrix read once, the multipole of every V-list source
+    box read once and the V-list sum of every target box written once."""
+    st = plan.stats()
+    bx = plan.boxes()
+    P = plan.orders()
+    vs, vi = plan.list(1)
+    lev, ix, iy = bx["level"], bx["ix"].astype(np.int64), bx["iy"].astype(np.int64)
+    groups, srcs, tgts = set(), set(), set()
+    for b in range(st["n_boxes"]):
+        for v in vi[vs[b]:vs[b + 1]]:
+            dx, dy, r = int(ix[v] - ix[b]), int(iy[v] - iy[b]), 0
+            while not (dx > 0 and dy >= 0):          # quarter turns to the orbit representative
+                dx, dy, r = dy, -dx, r + 1
+            groups.add((int(lev[b]), dx, dy))
+            srcs.add(int(v))
+            tgts.add(b)
+    n = lambda b: 2 * int(P[lev[b]]) + 1
+    tab = (8 if far_fp32 else 16) * sum((2 * int(P[l]) + 1) ** 2 for l, _, _ in groups)
+    vec = (8 if far_fp32 else 16) * n_dens
+    return {"tables": tab, "multipoles": vec * sum(n(b) for b in srcs),
+            "locals": 16 * n_dens * sum(n(b) for b in tgts)}
+
+
+def measured_traffic(kname):
+    """HBM bytes per launch of a kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary (copy-calibrated), or None when there is
     none or the kernel source has changed since the counters were taken."""
     import hashlib
-    kname = STAGE_KERNEL.get(stage)
     if not kname or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -114,6 +149,148 @@ def measured_traffic(stage):
         if k == kname or k.startswith(kname + "<"):
             return v["hbm_bytes_per_dispatch"]
     return None
+
+
+def _oracle_rel(g, omega, p, ss, sd, got, pick):
+    """Relative l2 and largest error of `got` [n_dens, pick] against the
+    oracle's direct QBX at the on-curve targets `pick` (own centres)."""
+    import oracle
+    alpha = oracle.qbx_coefficients(omega, p, g.sx, g.sy, g.w, g.nx, g.ny, ss, sd, g.cx[pick], g.cy[pick])
+    ref = oracle.qbx_eval(omega, p, g.cx[pick], g.cy[pick], alpha, g.sx[pick], g.sy[pick],
+                          np.arange(pick.size, dtype=np.int32))
+    return (float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+
+
+def leg_batched(ctx, eps, rounds=3, n_geom=256, n_dens=4, check_geoms=8, check_targets=32):
+    """Batched workload: 256 star and ellipse curves of 512-16384 nodes,
+    omega in [5, 150], 4 densities each, every geometry resident; one
+    qbx_eval_batch over all of them against qbx_eval on each in turn.  FP64
+    at eps = 1e-10 (p = 14); FP32 far field at 1e-6 (p = 9)."""
+    import concurrent.futures as cf
+
+    import torch
+
+    from paper_1602_05301_amd import inputs, qbx
+    far32 = eps >= 1e-6
+    p = 9 if far32 else 14
+    # 8 orders above the default increment: some of these small,
+    # high-frequency curves need them to stay within eps at every target
+    tiny = inputs.star(4, 4, lobes=3)
+    p_add = qbx.Plan(tiny, 1.0, eps, tiny.sx, tiny.sy, np.arange(tiny.n, dtype=np.int32),
+                     qbx.options(p=p)).stats()["p_add"] + 8
+    curves = inputs.batched_geometries(n_geom)
+    dr = inputs.rng_for(3, inputs.PURPOSE_DENSITY)
+    dens = [inputs.complex_gaussian(dr, (n_dens, g.n)) for g, _ in curves]
+
+    def build(item):
+        g, w = item
+        return qbx.Geometry(ctx, g, w, eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32),
+                            qbx.options(p=p, p_add=p_add, far_fp32=far32))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=8) as pool:
+        geos = list(pool.map(build, curves))
+    setup = time.perf_counter() - t0
+    s = [torch.from_numpy(d).cuda() for d in dens]
+    u = [torch.empty_like(x) for x in s]
+    ub = [torch.empty_like(x) for x in s]
+    for g, x, y in zip(geos, s, u):
+        g.eval(x, x, u=y)
+    ctx.eval_batch(geos, s, s, ub)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(u, ub))
+    t0 = time.perf_counter()
+    for g, x, y in zip(geos, s, u):
+        g.eval(x, x, u=y)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        ctx.eval_batch(geos, s, s, ub)
+    torch.cuda.synchronize()
+    bat = (time.perf_counter() - t0) / rounds
+    work = sum(g.n * n_dens for g, _ in curves)
+    rng = np.random.default_rng(77)
+    worst = [0.0, 0.0]
+    for i in np.linspace(0, n_geom - 1, check_geoms).astype(int):
+        g, w = curves[i]
+        pick = np.sort(rng.choice(g.n, check_targets, replace=False))
+        rel, mx = _oracle_rel(g, w, p, dens[i], dens[i], ub[i].cpu().numpy()[:, pick], pick)
+        worst = [max(worst[0], rel), max(worst[1], mx)]
+    flops = sum(sum(geo.work(n_dens).values()) for geo in geos)
+    nodes = np.array([g.n for g, _ in curves])
+    return {"workload": f"{n_geom} star/ellipse curves, {int(nodes.min())}-{int(nodes.max())} nodes "
+                        f"({int(nodes.sum())} in all), omega U[5,150], {n_dens} densities each",
+            "eps": eps, "p": p, "p_add": p_add, "far_fp32": far32, "setup_s": setup,
+            "batched_ms": bat * 1e3, "one_by_one_ms": seq * 1e3,
+            "value": work / bat, "one_by_one_value": work / seq, "unit": "targets*densities/s",
+            "algorithmic_tflops": flops / bat / 1e12,
+            "batched_equals_alone": bool(same),
+            "rel_err_vs_oracle_sampled": worst[0], "max_err_vs_oracle_sampled": worst[1],
+            "sample": f"{check_geoms} geometries x {check_targets} targets x {n_dens} densities"}
+
+
+def leg_multiscale(ctx, steps=10, warmup=2):
+    """64 curves in [-10, 10]^2 with adaptive panels, about 606k nodes =
+    centres = on-curve targets, omega = 100, eps = 1e-8, p = 12, leaves of
+    64; one density."""
+    import torch
+
+    from paper_1602_05301_amd import inputs, qbx
+    g, _c = inputs.multiscale_curves()
+    r = inputs.rng_for(2, inputs.PURPOSE_DENSITY)
+    ss = inputs.complex_gaussian(r, (1, g.n))
+    sd = inputs.complex_gaussian(r, (1, g.n))
+    omega, eps, p = 100.0, 1e-8, 12
+    t0 = time.perf_counter()
+    geo = qbx.Geometry(ctx, g, omega, eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32),
+                       qbx.options(p=p, leaf_max=64))
+    setup = time.perf_counter() - t0
+    dss, dsd = torch.from_numpy(ss).cuda(), torch.from_numpy(sd).cuda()
+    u = torch.empty((1, g.n), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        geo.eval(dss, dsd, u=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        geo.eval(dss, dsd, u=u)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    pick = np.sort(np.random.default_rng(5).choice(g.n, 64, replace=False))
+    rel, mx = _oracle_rel(g, omega, p, ss, sd, u.cpu().numpy()[:, pick], pick)
+    st = geo.stats()
+    return {"workload": f"64 curves, {g.n} nodes = centres = targets, omega 100, eps 1e-8, p 12, leaves of 64",
+            "setup_s": setup, "ms_per_step": t * 1e3, "value": g.n / t, "unit": "targets*densities/s",
+            "p_add": st["p_add"], "n_boxes": st["n_boxes"], "n_levels": st["n_levels"],
+            "algorithmic_tflops": sum(geo.work(1).values()) / t / 1e12,
+            "rel_err_vs_oracle_sampled": rel, "max_err_vs_oracle_sampled": mx, "sample": "64 targets"}
+
+
+def leg_served(ctx, n_requests=16, max_nodes=200_000, frac=0.8, hbm_gib=64.0):
+    """Bounded served stream: n_requests star requests of 1k-200k nodes
+    (log-uniform), omega U[1,200], eps in {1e-6, 1e-10}, 20-60 chained
+    matvecs each.  The closed-loop rate (all requests at once) gives the
+    saturation QPS; then Poisson arrivals at frac of it, served by
+    continuous batching and by the plain per-request FIFO path."""
+    from paper_1602_05301_amd import serve
+    budget = hbm_gib * 2 ** 30
+    w = serve.make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2))
+    serve.serve(ctx, w, budget)                       # warm-up
+    reqs = serve.make_requests(n_requests, nodes=(1024, max_nodes))
+    for r in reqs:
+        r.arrival = 0.0
+    closed = serve.serve(ctx, reqs, budget)
+    sat = n_requests / closed["wall_s"]
+    reqs = serve.make_requests(n_requests, nodes=(1024, max_nodes))
+    serve._poisson(reqs, frac * sat)
+    fifo = serve.fifo(ctx, reqs)
+    reqs = serve.make_requests(n_requests, nodes=(1024, max_nodes))
+    serve._poisson(reqs, frac * sat)
+    served = serve.serve(ctx, reqs, budget)
+    return {"workload": f"{n_requests} star requests, 1024-{max_nodes} nodes log-uniform, omega U[1,200], "
+                        "eps in {1e-6 (FP32 far field), 1e-10}, 20-60 chained matvecs, Poisson arrivals",
+            "saturation_qps": sat, "qps": frac * sat, "closed_loop": closed,
+            "served": served, "fifo": fifo}
 
 
 def main(argv=None):
@@ -133,6 +310,10 @@ def main(argv=None):
     ap.add_argument("--graph", action="store_true",
                     help="replay a captured HIP graph per evaluation instead of enqueueing every "
                          "kernel (measured slower here: the eager two-stream schedule overlaps more)")
+    ap.add_argument("--legs", default="batched,multiscale,served",
+                    help="further workloads after the headline (comma list; empty for none): "
+                         "batched (256 curves, both tolerances), multiscale (606k nodes), "
+                         "served (bounded stream of 1k-200k-node requests)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warm-up, copy a buffer of this many MiB once on the device: "
                          "a kernel of known traffic for calibrating HBM byte counters")
@@ -212,22 +393,24 @@ def main(argv=None):
     # translations on the FP64 matrix cores; everything else on the FP64 vector ALUs
     bound = "mfma" if dom in ("m2m", "m2l", "l2l") else "alu"
     peak = FP32_PEAK_TFLOPS if (args.far_fp32 and dom in ("m2l", "l2l")) else FP64_PEAK_TFLOPS
-    traffic = measured_traffic(dom) if not args.far_fp32 else None
-    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak,
+    kname = stage_kernel(dom, m2l_choice)
+    traffic = measured_traffic(kname) if not args.far_fp32 else None
+    roof = {"bound": bound, "kernel": dom, "kernel_name": kname, "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
             "algorithmic_flops_per_step": work[dom], "ms_per_step": dom_ms,
             "launches_per_step": stages[dom][1] / args.steps}
+    if dom == "m2l":
+        plan = qbx.Plan(g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
+                        qbx.options(p=wl.p, leaf_max=wl.leaf_max, far_fp32=args.far_fp32))
+        ab = m2l_algorithmic_bytes(plan, wl.n_dens, args.far_fp32)
+        roof["algorithmic_bytes"] = int(sum(ab.values()))
+        roof["algorithmic_bytes_parts"] = ab
 
     err = None
     if not args.no_check:
-        import oracle
-        pick = np.sort(np.random.default_rng(0).choice(g.n, 64, replace=False))
-        alpha = oracle.qbx_coefficients(wl.omega, wl.p, g.sx, g.sy, g.w, g.nx, g.ny,
-                                        wl.sigma_s[:1], wl.sigma_d[:1], g.cx[pick], g.cy[pick])
-        ref = oracle.qbx_eval(wl.omega, wl.p, g.cx[pick], g.cy[pick], alpha, wl.tx[pick],
-                              wl.ty[pick], np.arange(pick.size, dtype=np.int32))[0]
-        got = u[0].cpu().numpy()[pick]
-        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        pick = np.sort(np.random.default_rng(0).choice(g.n, 512, replace=False))
+        rel, mx = _oracle_rel(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, u.cpu().numpy()[:, pick], pick)
+        err = {"rel_l2": rel, "max": mx, "sample": f"{pick.size} targets x {wl.n_dens} densities"}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "targets*densities/s", "n_gpus": 1,
@@ -250,8 +433,24 @@ def main(argv=None):
         "stages_tflops": {k: work[k] / (v[0] / args.steps * 1e-3) / 1e12
                           for k, v in stages.items() if v[1] and v[0] > 0 and work.get(k)},
         "setup_s": setup_s,
-        "rel_err_vs_oracle_sampled": err,
+        "err_vs_oracle_sampled": err,
     }
+    legs = [x for x in args.legs.split(",") if x]
+    del geo
+    torch.cuda.synchronize()
+    for leg in legs:
+        t0 = time.perf_counter()
+        print(f"bench: leg {leg}", file=sys.stderr, flush=True)
+        if leg == "batched":
+            rec["batched"] = [leg_batched(ctx, e) for e in (1e-10, 1e-6)]
+        elif leg == "multiscale":
+            rec["multiscale"] = leg_multiscale(ctx)
+        elif leg == "served":
+            rec["served"] = leg_served(ctx)
+        else:
+            raise SystemExit(f"bench.py: unknown leg {leg}")
+        torch.cuda.synchronize()
+        print(f"bench: leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

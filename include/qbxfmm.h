@@ -105,6 +105,9 @@ void qbx_options_default(qbx_options *opt);
  * be set. */
 qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out);
 qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream);
+/* qbx_ctx_destroy releases the caller's handle; the context's streams and
+ * events live on until the last geometry made on it is destroyed, so
+ * geometries may be destroyed before or after their context. */
 qbx_status qbx_ctx_destroy(qbx_ctx ctx);
 
 /* ---- host planning (no GPU needed) ---------------------------------------
@@ -228,6 +231,13 @@ qbx_status qbx_geom_associate(qbx_geom geom, int64_t n_tgt, const double *tx, co
  * by the small GEMM tile lists of the chunk sizes used.  For admission by an
  * HBM budget (a serving loop).  0 for a NULL geometry. */
 size_t qbx_geom_bytes(qbx_geom geom, int32_t n_dens);
+/* qbx_plan_bytes: the same figure for the geometry qbx_geom_from_plan would
+ * make from this plan (its resident part, evaluation scratch and the
+ * order-0 geometry of smooth-rule targets), computed on the host without
+ * allocating device memory: admission by an HBM budget can decide before
+ * anything is allocated.  It runs the host part of the upload (tables
+ * included) once.  0 for a NULL plan or on failure. */
+size_t qbx_plan_bytes(qbx_plan plan, int32_t n_dens);
 
 /* ---- per-stage timing and work ----------------------------------------------
  * Stages of one evaluation, in launch order (Sec. 7.2 stage names). */

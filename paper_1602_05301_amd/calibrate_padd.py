@@ -24,6 +24,8 @@ the reference.
     batched     8 curves of the 256-curve batched set (spread over its
                 sizes), eps 1e-10 / p 14 and eps 1e-6 / p 9
     star4k      7-lobe star, 256 panels, omega 50, eps 1e-10, p 14
+    python -m paper_1602_05301_amd.calibrate_padd batched_all
+        every curve of the 256-curve batched set at both tolerances.
 
 Prints one JSON object per measurement.
 """
@@ -206,19 +208,53 @@ def sweep(args, out):
                 del geo
 
 
+def batched_all(args, out):
+    """Every curve of the 256-curve batched set at eps 1e-10 (p 14, FP64) and
+    1e-6 (p 9, FP32 far field), each at a list of p_add: relative l2 and
+    largest error against the direct sum over every node, with the curve's
+    size, omega and panel lengths."""
+    import torch
+
+    from . import inputs, qbx
+    ctx = qbx.Context(0)
+    curves = inputs.batched_geometries()
+    for eps, p, padds in ((1e-10, 14, [int(v) for v in args.p_adds.split(",")]),
+                          (1e-6, 9, [int(v) for v in args.p_adds_loose.split(",")])):
+        for i, (g, omega) in enumerate(curves):
+            tc = np.arange(g.n, dtype=np.int32)
+            r = inputs.rng_for(3, inputs.PURPOSE_DENSITY)
+            ss = torch.from_numpy(inputs.complex_gaussian(r, (1, g.n))).cuda()
+            sd = torch.from_numpy(inputs.complex_gaussian(r, (1, g.n))).cuda()
+            ref = qbx.Geometry(ctx, g, omega, eps, g.sx, g.sy, tc,
+                               qbx.options(p=p, direct=True)).eval(ss, sd).cpu().numpy()[0]
+            rec = dict(index=i, n=g.n, omega=omega, eps=eps, p=p, omega_h_max=float(omega * g.h.max()),
+                       omega_h_min=float(omega * g.h.min()))
+            for pa in padds:
+                geo = qbx.Geometry(ctx, g, omega, eps, g.sx, g.sy, tc,
+                                   qbx.options(p=p, p_add=pa, far_fp32=eps >= 1e-6))
+                got = geo.eval(ss, sd).cpu().numpy()[0]
+                rec[f"rel_{pa}"] = _rel(got, ref)
+                rec[f"max_{pa}"] = _maxrel(got, ref)
+                del geo
+            _emit(out, rec)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["bisect", "sweep"])
+    ap.add_argument("mode", choices=["bisect", "sweep", "batched_all"])
     ap.add_argument("--out", default=None)
     ap.add_argument("--ps", default="4,6,8,10,12,14,16,20")
     ap.add_argument("--eps", default="1e-4,1e-6,1e-8,1e-10,1e-12")
     ap.add_argument("--level-restrict", type=int, default=1)
     ap.add_argument("--workloads", default="star32k,star4k,batched,multiscale")
     ap.add_argument("--p-adds", default="12,16,20,24,28,32,36,40")
+    ap.add_argument("--p-adds-loose", default="17,21,25,29")
     args = ap.parse_args(argv)
     out = open(args.out, "a") if args.out else None
     if args.mode == "bisect":
         bisect(args, out)
+    elif args.mode == "batched_all":
+        batched_all(args, out)
     else:
         sweep(args, out)
     return 0

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,6 +24,10 @@ struct QbxLane {
 };
 
 struct qbx_ctx_s {
+    // the caller's handle and every geometry made on the context hold a
+    // reference; the context is torn down when the last one goes, so a
+    // geometry destroyed after qbx_ctx_destroy still finds its streams
+    std::atomic<int> refs{1};
     int device = 0;
     hipStream_t stream = nullptr;
     // the side stream of plain evaluations: the near field and the X-list
@@ -66,38 +71,82 @@ void lane_destroy(QbxLane &L)
 constexpr int kDensChunk = 4;   // densities per pass through the pipeline
 constexpr int kM2LTileCols = 16; // columns per M2L tile (one MFMA column block)
 
+// Device memory of one geometry.  The resident part is built in two passes
+// of the same code: a sizing pass (`sizing`: nothing is allocated or copied,
+// offsets are counted) and a packed pass into one allocation of that size,
+// staged in host memory and copied once (commit).  Without a reserved block
+// every request is its own allocation (the evaluation scratch).
 struct DeviceArena {
     std::vector<void *> ptrs;
     size_t bytes = 0;
     hipError_t err = hipSuccess;
-    template <class T>
-    T *upload(const std::vector<T> &v)
+    bool sizing = false;
+    unsigned char *block = nullptr;          // packed pass: the one allocation
+    size_t cap = 0, off = 0;
+    std::vector<unsigned char> stage;        // its host image
+    static size_t aligned(size_t n) { return (n + 255) & ~(size_t)255; }
+    void *take(size_t n, const void *src, size_t nsrc)
     {
         if (err != hipSuccess) return nullptr;
-        size_t n = std::max<size_t>(v.size(), 1) * sizeof(T);
+        n = std::max<size_t>(n, 16);
+        if (sizing) {
+            size_t o = off;
+            off += aligned(n);
+            bytes = off;
+            return reinterpret_cast<void *>((uintptr_t)256 + o);   // never dereferenced
+        }
+        if (block) {
+            if (off + n > cap) {
+                err = hipErrorInvalidValue;            // sizing and packed passes disagree
+                return nullptr;
+            }
+            void *p = block + off;
+            if (nsrc) std::memcpy(stage.data() + off, src, nsrc);
+            off += aligned(n);
+            return p;
+        }
         void *p = nullptr;
         err = hipMalloc(&p, n);
         if (err != hipSuccess) return nullptr;
         ptrs.push_back(p);
         bytes += n;
-        if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-        return static_cast<T *>(p);
-    }
-    void *alloc(size_t n)
-    {
-        if (err != hipSuccess) return nullptr;
-        void *p = nullptr;
-        err = hipMalloc(&p, std::max<size_t>(n, 16));
-        if (err != hipSuccess) return nullptr;
-        ptrs.push_back(p);
-        bytes += n;
+        if (nsrc) err = hipMemcpy(p, src, nsrc, hipMemcpyHostToDevice);
         return p;
+    }
+    template <class T>
+    T *upload(const std::vector<T> &v)
+    {
+        return static_cast<T *>(take(std::max<size_t>(v.size(), 1) * sizeof(T), v.data(), v.size() * sizeof(T)));
+    }
+    void *alloc(size_t n) { return take(n, nullptr, 0); }
+    // packed pass: one allocation of the sized bytes (the sizing pass's offset)
+    hipError_t reserve(size_t n)
+    {
+        cap = std::max<size_t>(n, 256);
+        err = hipMalloc((void **)&block, cap);
+        if (err != hipSuccess) { block = nullptr; return err; }
+        ptrs.push_back(block);
+        stage.assign(cap, 0);
+        off = 0;
+        bytes += cap;
+        return hipSuccess;
+    }
+    hipError_t commit()
+    {
+        if (err == hipSuccess && block && off) err = hipMemcpy(block, stage.data(), off, hipMemcpyHostToDevice);
+        stage.clear();
+        stage.shrink_to_fit();
+        block = nullptr;   // later requests are allocations of their own
+        return err;
     }
     void release()
     {
-        for (void *p : ptrs) (void)hipFree(p);
+        if (!sizing)
+            for (void *p : ptrs) (void)hipFree(p);
         ptrs.clear();
         bytes = 0;
+        off = 0;
+        block = nullptr;
     }
 };
 
@@ -626,10 +675,36 @@ qbx_status upload(qbx_geom_s *G)
             for (int i = G->wf_start[b]; i < G->wf_start[b + 1]; ++i) pw = std::max(pw, pl.P[pl.lev[G->wf_idx[i]]]);
     G->wl.Pmax = pw;
 
+    G->srad_rows = G->p2m.Pmax + 2;
+    G->crad_rows = G->l2q.Pmax + pl.p + 8;
     G->d_self = ar.upload(std::vector<DevGeom>{g});
     if (ar.err != hipSuccess) return fail(ar.err == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                                           std::string("device upload failed: ") + hipGetErrorString(ar.err));
     return QBX_OK;
+}
+
+// Bytes of each evaluation buffer for chunks of c densities.
+struct ScratchPlan {
+    size_t qs, qd, coef, mp, loc, vy, wy, srad, crad;
+    size_t total() const { return qs + qd + coef + mp + loc + vy + wy + srad + crad; }
+};
+
+ScratchPlan scratch_plan(const qbx_geom_s *G, int c)
+{
+    const Plan &pl = G->pl;
+    const size_t cdb = sizeof(cd);
+    auto at1 = [](long long n) { return (size_t)std::max<long long>(n, 1); };
+    ScratchPlan sp{};
+    sp.qs = sp.qd = cdb * c * at1(pl.ns);
+    sp.coef = cdb * c * (2 * pl.p + 1) * at1(pl.nc);
+    if (!pl.opt.direct) {
+        sp.mp = sp.loc = cdb * c * at1(G->total_coef);
+        sp.vy = cdb * c * at1(G->total_vy);
+        sp.wy = cdb * c * at1(G->total_wy);
+        sp.srad = sizeof(double) * (size_t)(G->p2m.Pmax + 2) * at1(pl.ns);
+        sp.crad = sizeof(double) * (size_t)(G->l2q.Pmax + pl.p + 8) * at1(pl.nc);
+    }
+    return sp;
 }
 
 qbx_status ensure_scratch(qbx_geom_s *G)
@@ -640,20 +715,17 @@ qbx_status ensure_scratch(qbx_geom_s *G)
     }
     if (G->qs) return QBX_OK;
     DeviceArena &s = G->scratch;
-    const Plan &pl = G->pl;
-    size_t nd = kDensChunk;
-    G->qs = (cd *)s.alloc(sizeof(cd) * nd * std::max<int64_t>(pl.ns, 1));
-    G->qd = (cd *)s.alloc(sizeof(cd) * nd * std::max<int64_t>(pl.ns, 1));
-    G->coef = (cd *)s.alloc(sizeof(cd) * nd * (2 * pl.p + 1) * std::max<int64_t>(pl.nc, 1));
-    if (!pl.opt.direct) {
-        G->mp = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
-        G->loc = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_coef, 1));
-        G->vy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_vy, 1));
-        G->wy = (cd *)s.alloc(sizeof(cd) * nd * std::max<long long>(G->total_wy, 1));
-        G->srad_rows = G->p2m.Pmax + 2;
-        G->crad_rows = G->l2q.Pmax + pl.p + 8;
-        G->srad = (double *)s.alloc(sizeof(double) * G->srad_rows * std::max<int64_t>(pl.ns, 1));
-        G->crad = (double *)s.alloc(sizeof(double) * G->crad_rows * std::max<int64_t>(pl.nc, 1));
+    ScratchPlan sp = scratch_plan(G, kDensChunk);
+    G->qs = (cd *)s.alloc(sp.qs);
+    G->qd = (cd *)s.alloc(sp.qd);
+    G->coef = (cd *)s.alloc(sp.coef);
+    if (!G->pl.opt.direct) {
+        G->mp = (cd *)s.alloc(sp.mp);
+        G->loc = (cd *)s.alloc(sp.loc);
+        G->vy = (cd *)s.alloc(sp.vy);
+        G->wy = (cd *)s.alloc(sp.wy);
+        G->srad = (double *)s.alloc(sp.srad);
+        G->crad = (double *)s.alloc(sp.crad);
     }
     if (s.err != hipSuccess) {
         hipError_t e = s.err;
@@ -682,7 +754,7 @@ qbx_status ensure_tiles(qbx_geom_s *G, int nd)
         for (int c0 = 0; c0 < cols; c0 += kM2LTileCols)
             t.push_back({grp.key, grp.start, c0, std::min(kM2LTileCols, cols - c0)});
     }
-    G->m2l_tiles[nd] = G->scratch.upload(t);
+    G->m2l_tiles[nd] = G->arena.upload(t);
     G->m2l_ntiles[nd] = (int)t.size();
     // M2M: per parent level, 16-column tiles of (parent, density)
     int nlev = G->pl.nlev;
@@ -704,11 +776,11 @@ qbx_status ensure_tiles(qbx_geom_s *G, int nd)
         }
     }
     G->l2l_tstart[nd][nlev] = (int)tl.size();
-    G->m2m_tiles[nd] = G->scratch.upload(tm);
-    G->l2l_tiles[nd] = G->scratch.upload(tl);
-    if (G->scratch.err != hipSuccess) {
-        hipError_t e = G->scratch.err;
-        G->scratch.err = hipSuccess;
+    G->m2m_tiles[nd] = G->arena.upload(tm);
+    G->l2l_tiles[nd] = G->arena.upload(tl);
+    if (G->arena.err != hipSuccess) {
+        hipError_t e = G->arena.err;
+        G->arena.err = hipSuccess;
         G->m2l_tiles[nd] = nullptr;
         return fail(QBX_E_DEVICE, std::string("tile upload failed: ") + hipGetErrorString(e));
     }
@@ -739,9 +811,9 @@ struct StageTimer {
     int stage;
     int launches = 0;
     hipEvent_t a = nullptr;
-    StageTimer(qbx_geom_s *g, int s) : G(g), stage(s)
+    StageTimer(qbx_geom_s *g, int s, bool on) : G(g), stage(s)
     {
-        if (G->profile && (a = take_event(G))) (void)hipEventRecord(a, G->ctx->stream);
+        if (on && (a = take_event(G))) (void)hipEventRecord(a, G->ctx->stream);
     }
     ~StageTimer()
     {
@@ -769,82 +841,104 @@ qbx_status harvest(qbx_geom_s *G)
     return QBX_OK;
 }
 
-#define STAGE(id) StageTimer timer_##id(G, id)
+#define STAGE(id) StageTimer timer_##id(G, id, B.timing)
 #define LAUNCH(id, n, expr)        \
     do {                           \
         if ((n) > 0) timer_##id.launches++; \
         CHK(expr);                 \
     } while (0)
 
+// The evaluation buffers of one pass through the pipeline: the geometry's
+// own scratch, or parts of another region.
+struct EvalBufs {
+    cd *qs, *qd, *mp, *loc, *coef, *vy, *wy;
+    double *srad, *crad;
+    bool *rad_ready;            // srad / crad hold the geometry's radial sequences
+    const EvalBufs *sub;        // the order-0 geometry's buffers (null: its own)
+    bool timing;                // per-stage events, every stage in order on one stream
+};
+
+EvalBufs own_bufs(qbx_geom_s *G)
+{
+    return {G->qs, G->qd, G->mp, G->loc, G->coef, G->vy, G->wy, G->srad, G->crad, &G->rad_ready, nullptr,
+            G->profile};
+}
+
 qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u, cd *coef_out,
-                        hipStream_t st, const QbxLane &lane)
+                        hipStream_t st, const QbxLane &lane, const EvalBufs *bufs = nullptr)
 {
     const Plan &pl = G->pl;
     const DevGeom &g = G->g;
+    EvalBufs own;
+    if (!bufs) {
+        own = own_bufs(G);
+        bufs = &own;
+    }
+    const EvalBufs &B = *bufs;
     {
         STAGE(QBX_STAGE_CHARGES);
-        LAUNCH(QBX_STAGE_CHARGES, pl.ns, launch_charges(g, nd, ss, sd, G->qs, G->qd, st));
+        LAUNCH(QBX_STAGE_CHARGES, pl.ns, launch_charges(g, nd, ss, sd, B.qs, B.qd, st));
     }
     if (pl.opt.direct) {
         STAGE(QBX_STAGE_DIRECT);
-        LAUNCH(QBX_STAGE_DIRECT, pl.nc, launch_p2qbxl_direct(g, nd, G->qs, G->qd, G->coef, st));
+        LAUNCH(QBX_STAGE_DIRECT, pl.nc, launch_p2qbxl_direct(g, nd, B.qs, B.qd, B.coef, st));
     } else {
         qbx_status ts = ensure_tiles(G, nd);
         if (ts != QBX_OK) return ts;
-        if (G->profile || !lane.side) {
+        if (B.timing || !lane.side) {
             // in order: the locals are zeroed with the charges (X-list P2L
             // and L2L both add into them); concurrently, on the side stream
             STAGE(QBX_STAGE_CHARGES);
-            LAUNCH(QBX_STAGE_CHARGES, G->total_coef, launch_fill_zero(G->loc, (long long)nd * G->total_coef, st));
+            LAUNCH(QBX_STAGE_CHARGES, G->total_coef, launch_fill_zero(B.loc, (long long)nd * G->total_coef, st));
         }
         // Fork: the side stream takes the centre J sequences, the X-list P2L,
         // the near field and (once M2M is done) M2QBXL while this stream runs
         // P2M, M2M, M2L and L2L.  With stage profiling on everything stays on
         // one stream, in order.
         const QbxLane *C = &lane;
-        bool conc = !G->profile && C->side;
+        bool conc = !B.timing && C->side;
         hipStream_t s1 = conc ? C->side : st;
         if (conc) {
             CHK(hipEventRecord(C->ev_fork, st));
             CHK(hipStreamWaitEvent(s1, C->ev_fork, 0));
-            if (!G->rad_ready) CHK(launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, s1));
-            CHK(launch_fill_zero(G->loc, (long long)nd * G->total_coef, s1));
-            CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, s1));
+            if (!(*B.rad_ready)) CHK(launch_ctr_rad(g, G->l2q.n, B.crad, G->crad_rows, s1));
+            CHK(launch_fill_zero(B.loc, (long long)nd * G->total_coef, s1));
+            CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, s1));
             CHK(hipEventRecord(C->ev_x, s1));
-            CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, s1));
+            CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, s1));
         }
         {
             STAGE(QBX_STAGE_P2M);
-            if (!G->rad_ready) LAUNCH(QBX_STAGE_P2M, pl.ns, launch_src_rad(g, G->srad, G->srad_rows, st));
-            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, G->qs, G->qd, G->srad, G->srad_rows, G->mp, st));
+            if (!(*B.rad_ready)) LAUNCH(QBX_STAGE_P2M, pl.ns, launch_src_rad(g, B.srad, G->srad_rows, st));
+            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, B.qs, B.qd, B.srad, G->srad_rows, B.mp, st));
         }
         {
             STAGE(QBX_STAGE_M2M);
             for (int l = pl.nlev - 2; l >= 2; --l) {
                 int t0 = G->m2m_tstart[nd][l], nt = G->m2m_tstart[nd][l + 1] - t0;
                 int nrb = (2 * pl.P[l] + 1 + 15) / 16;
-                LAUNCH(QBX_STAGE_M2M, nt, launch_m2m_mfma(g, nd, l, G->m2m_tiles[nd] + t0, nt, nrb, G->d_par_list, G->mp, st));
+                LAUNCH(QBX_STAGE_M2M, nt, launch_m2m_mfma(g, nd, l, G->m2m_tiles[nd] + t0, nt, nrb, G->d_par_list, B.mp, st));
             }
         }
         if (conc) {
             // multipoles complete: M2QBXL joins the side stream after the near field
             CHK(hipEventRecord(C->ev_m, st));
             CHK(hipStreamWaitEvent(s1, C->ev_m, 0));
-            CHK(launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, G->mp, G->wy,
-                              G->wl.d, G->d_wleaf_start, G->wl.n, G->coef, s1));
+            CHK(launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, B.mp, B.wy,
+                              G->wl.d, G->d_wleaf_start, G->wl.n, B.coef, s1));
             CHK(hipEventRecord(C->ev_q, s1));
         }
         {
             STAGE(QBX_STAGE_M2L);
             LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
                    launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->m2l_nw,
-                                   G->mp, G->vy, st));
+                                   B.mp, B.vy, st));
         }
         if (conc) {
             CHK(hipStreamWaitEvent(st, C->ev_x, 0));
         } else {
             STAGE(QBX_STAGE_P2L_X);
-            LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, G->qs, G->qd, G->loc, st));
+            LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, st));
         }
         {
             // V-list sums in list order for every level at once, then L2L
@@ -852,12 +946,12 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             STAGE(QBX_STAGE_L2L);
             if (pl.nlev > 2) {
                 int nbox = pl.level_start[pl.nlev] - pl.level_start[2];
-                LAUNCH(QBX_STAGE_L2L, nbox, launch_down_all(g, nd, nbox, G->vy, G->loc, st));
+                LAUNCH(QBX_STAGE_L2L, nbox, launch_down_all(g, nd, nbox, B.vy, B.loc, st));
             }
             for (int L = 3; L < pl.nlev; ++L) {
                 int t0 = G->l2l_tstart[nd][L], nt = G->l2l_tstart[nd][L + 1] - t0;
                 int nrb = (2 * pl.P[L] + 1 + 15) / 16;
-                LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, nullptr, G->loc, st));
+                LAUNCH(QBX_STAGE_L2L, nt, launch_l2l_mfma(g, nd, L, G->l2l_tiles[nd] + t0, nt, nrb, G->d_chl_list, nullptr, B.loc, st));
             }
         }
         if (conc) {
@@ -865,41 +959,41 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         } else {
             {
                 STAGE(QBX_STAGE_P2QBXL);
-                LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, G->qs, G->qd, G->coef, st));
+                LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, st));
             }
             STAGE(QBX_STAGE_M2QBXL);
             LAUNCH(QBX_STAGE_M2QBXL, G->n_wpairs,
-                   launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, G->mp,
-                                 G->wy, G->wl.d, G->d_wleaf_start, G->wl.n, G->coef, st));
+                   launch_m2qbxl(g, nd, G->d_wpairs, G->d_wpair_off, G->n_wpairs, G->wl.Pmax, B.mp,
+                                 B.wy, G->wl.d, G->d_wleaf_start, G->wl.n, B.coef, st));
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
-            if (!conc && !G->rad_ready) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
-            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, G->loc, G->coef, st));
+            if (!conc && !(*B.rad_ready)) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, B.crad, G->crad_rows, st));
+            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, B.crad, G->crad_rows, B.loc, B.coef, st));
         }
         // both radial sequences are enqueued ahead of every later evaluation
         // on this geometry (P2M and L2QBXL of later calls follow them in
         // stream order)
-        G->rad_ready = true;
+        (*B.rad_ready) = true;
     }
     {
         STAGE(QBX_STAGE_EVAL);
-        LAUNCH(QBX_STAGE_EVAL, pl.nt, launch_qbx_eval(g, nd, G->coef, u, st));
+        LAUNCH(QBX_STAGE_EVAL, pl.nt, launch_qbx_eval(g, nd, B.coef, u, st));
     }
     if (G->sub) {
         // the targets outside every expansion disk, through the order-0
         // geometry (it writes into u at their indices)
         STAGE(QBX_STAGE_SMOOTH);
         timer_QBX_STAGE_SMOOTH.launches++;
-        qbx_status q = run_pipeline(G->sub, nd, ss, sd, u, nullptr, st, lane);
+        qbx_status q = run_pipeline(G->sub, nd, ss, sd, u, nullptr, st, lane, B.sub);
         if (q != QBX_OK) return q;
     } else {
         STAGE(QBX_STAGE_SMOOTH);
-        LAUNCH(QBX_STAGE_SMOOTH, G->g.n_smooth, launch_smooth(g, nd, G->qs, G->qd, u, st));
+        LAUNCH(QBX_STAGE_SMOOTH, G->g.n_smooth, launch_smooth(g, nd, B.qs, B.qd, u, st));
     }
     if (coef_out) {
         STAGE(QBX_STAGE_COEF_OUT);
-        LAUNCH(QBX_STAGE_COEF_OUT, pl.nc, launch_coef_out(g, nd, G->coef, coef_out, st));
+        LAUNCH(QBX_STAGE_COEF_OUT, pl.nc, launch_coef_out(g, nd, B.coef, coef_out, st));
     }
     return QBX_OK;
 }
@@ -1263,13 +1357,16 @@ qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream)
     return QBX_OK;
 }
 
-qbx_status qbx_ctx_destroy(qbx_ctx ctx)
+namespace {
+
+void ctx_release(qbx_ctx_s *ctx)
 {
-    if (!ctx) return QBX_OK;
+    if (--ctx->refs > 0) return;
     (void)hipSetDevice(ctx->device);
-    lane_destroy(ctx->lane);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->lane.side) (void)hipStreamSynchronize(ctx->lane.side);
+    lane_destroy(ctx->lane);
     if (ctx->fz_copied) (void)hipEventDestroy(ctx->fz_copied);
     if (ctx->fz_done) (void)hipEventDestroy(ctx->fz_done);
     if (ctx->fz_host) (void)hipHostFree(ctx->fz_host);
@@ -1281,6 +1378,14 @@ qbx_status qbx_ctx_destroy(qbx_ctx ctx)
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     delete ctx;
+}
+
+}  // namespace
+
+qbx_status qbx_ctx_destroy(qbx_ctx ctx)
+{
+    if (!ctx) return QBX_OK;
+    ctx_release(ctx);
     return QBX_OK;
 }
 
@@ -1296,17 +1401,18 @@ void free_geom(qbx_geom_s *G)
     delete G;
 }
 
-// FMM mode with targets outside every expansion disk: the order-0 geometry
-// that serves them (sources as G's, centres at those targets, each target
-// bound to its own centre, p = 0; the same tolerance and tree options).
-qbx_status make_smooth_sub(qbx_geom_s *G)
+// FMM mode with targets outside every expansion disk: the plan of the
+// order-0 geometry that serves them (sources as pl's, centres at those
+// targets, each target bound to its own centre, p = 0; the same tolerance
+// and tree options), and the targets' indices.  False when there is none.
+bool smooth_sub_plan(const Plan &pl, Plan &out, std::vector<int32_t> &idx, Error &err)
 {
-    const Plan &pl = G->pl;
-    if (pl.opt.direct) return QBX_OK;
-    std::vector<int32_t> idx;
+    err = {QBX_OK, ""};
+    idx.clear();
+    if (pl.opt.direct) return false;
     for (int64_t m = 0; m < pl.nt; ++m)
         if (pl.tgt_ctr[m] < 0) idx.push_back((int32_t)m);
-    if (idx.empty()) return QBX_OK;
+    if (idx.empty()) return false;
     int64_t n = (int64_t)idx.size();
     std::vector<double> px(n), py(n), pr(n, 1e-300);
     std::vector<int32_t> own(n);
@@ -1318,24 +1424,79 @@ qbx_status make_smooth_sub(qbx_geom_s *G)
     qbx_options o = pl.opt;
     o.p = 0;
     o.p_add = -1;
+    err = build_plan(out, pl.omega, pl.eps, o, pl.ns, pl.sx.data(), pl.sy.data(), pl.w.data(), pl.nx.data(),
+                     pl.ny.data(), pl.sh.data(), n, px.data(), py.data(), pr.data(), n, px.data(), py.data(),
+                     own.data());
+    return true;
+}
+
+qbx_status build_device(qbx_geom_s *G);
+
+qbx_status make_smooth_sub(qbx_geom_s *G)
+{
     qbx_geom_s *S = new qbx_geom_s();
-    S->ctx = G->ctx;
-    Error e = build_plan(S->pl, pl.omega, pl.eps, o, pl.ns, pl.sx.data(), pl.sy.data(), pl.w.data(),
-                         pl.nx.data(), pl.ny.data(), pl.sh.data(), n, px.data(), py.data(), pr.data(), n,
-                         px.data(), py.data(), own.data());
+    Error e;
+    std::vector<int32_t> idx;
+    if (!smooth_sub_plan(G->pl, S->pl, idx, e)) {
+        delete S;
+        return QBX_OK;
+    }
     if (e.status != QBX_OK) {
         delete S;
         return fail(e.status, "order-0 geometry of the smooth-rule targets: " + e.msg);
     }
+    S->ctx = G->ctx;
     S->out_map = idx;
-    S->out_stride = pl.nt;
-    qbx_status st = upload(S);
+    S->out_stride = G->pl.nt;
+    qbx_status st = build_device(S);
     if (st != QBX_OK) {
         free_geom(S);
         return st;
     }
     G->sub = S;
     return QBX_OK;
+}
+
+// Resident data of G without allocating: the bytes its packed allocation
+// takes (G->pl, out_map and out_stride set; G itself is not modified), and
+// optionally those of its evaluation scratch.
+qbx_status sized_resident(qbx_geom_s *G, size_t *bytes, size_t *scratch_bytes = nullptr)
+{
+    qbx_geom_s D;
+    D.ctx = G->ctx;
+    std::swap(D.pl, G->pl);
+    D.out_map = G->out_map;
+    D.out_stride = G->out_stride;
+    D.arena.sizing = true;
+    qbx_status st = upload(&D);
+    for (int nd = 1; st == QBX_OK && !D.pl.opt.direct && nd <= kDensChunk; ++nd) st = ensure_tiles(&D, nd);
+    if (scratch_bytes) *scratch_bytes = scratch_plan(&D, kDensChunk).total();
+    std::swap(D.pl, G->pl);
+    *bytes = D.arena.off;
+    return st;
+}
+
+// G's resident device data (G->pl, out_map and out_stride set): points,
+// tree, lists, tables and the GEMM tile lists of every chunk size, made now
+// so that evaluations never allocate them,
+// in one allocation filled by one copy; then the order-0 geometry of the
+// smooth-rule targets.
+qbx_status build_device(qbx_geom_s *G)
+{
+    size_t need = 0;
+    qbx_status st = sized_resident(G, &need);
+    if (st != QBX_OK) return st;
+    hipError_t e = G->arena.reserve(need);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
+                    std::string("device allocation of the geometry: ") + hipGetErrorString(e));
+    st = upload(G);
+    for (int nd = 1; st == QBX_OK && !G->pl.opt.direct && nd <= kDensChunk; ++nd) st = ensure_tiles(G, nd);
+    e = G->arena.commit();
+    if (st != QBX_OK) return st;
+    if (e != hipSuccess)
+        return fail(QBX_E_DEVICE, std::string("geometry upload: ") + hipGetErrorString(e));
+    return make_smooth_sub(G);
 }
 
 }  // namespace
@@ -1351,8 +1512,7 @@ qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
         G = new qbx_geom_s();
         G->ctx = ctx;
         G->pl = plan->pl;
-        qbx_status st = upload(G);
-        if (st == QBX_OK) st = make_smooth_sub(G);
+        qbx_status st = build_device(G);
         if (st != QBX_OK) {
             free_geom(G);
             return st;
@@ -1361,6 +1521,7 @@ qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
         free_geom(G);
         return fail(QBX_E_NOMEM, "host allocation failed while building tables");
     }
+    ++ctx->refs;
     *out = G;
     return QBX_OK;
 }
@@ -1392,7 +1553,9 @@ qbx_status qbx_geom_destroy(qbx_geom G)
     else (void)hipDeviceSynchronize();
     if (G->ctx->gstream) (void)hipStreamSynchronize(G->ctx->gstream);
     if (G->ctx->lane.side) (void)hipStreamSynchronize(G->ctx->lane.side);
+    qbx_ctx_s *ctx = G->ctx;
     free_geom(G);
+    ctx_release(ctx);
     return QBX_OK;
 }
 
@@ -1416,24 +1579,36 @@ size_t qbx_geom_bytes(qbx_geom G, int32_t n_dens)
         G->sub = S;
         return b;
     }
-    const Plan &pl = G->pl;
-    const size_t nd = kDensChunk, cdb = sizeof(cd);
-    auto at1 = [](long long n) { return (size_t)std::max<long long>(n, 1); };
-    // as ensure_scratch allocates it
-    size_t scratch = 2 * cdb * nd * at1(pl.ns) + cdb * nd * (2 * pl.p + 1) * at1(pl.nc);
-    if (!pl.opt.direct) {
-        scratch += cdb * nd * (2 * at1(G->total_coef) + at1(G->total_vy) + at1(G->total_wy));
-        scratch += sizeof(double) * ((size_t)(G->p2m.Pmax + 2) * at1(pl.ns) + (size_t)(G->l2q.Pmax + pl.p + 8) * at1(pl.nc));
-        // GEMM tile lists of the chunk sizes an n_dens evaluation uses
-        for (int c = 1; c <= kDensChunk; ++c)
-            if (c == std::min(n_dens, kDensChunk) || (n_dens > kDensChunk && c == n_dens % kDensChunk)) {
-                size_t cols = 0;
-                for (const auto &grp : G->m2l_groups) cols += (size_t)grp.count * c / kM2LTileCols + 1;
-                scratch += sizeof(M2LTile) * cols +
-                           sizeof(TTile) * ((G->par_list.size() + 4 * G->chl_list.size()) * c / 16 + 8 * pl.nlev);
-            }
+    // the scratch serves chunks of kDensChunk densities; the GEMM tile lists are resident
+    (void)n_dens;
+    return G->arena.bytes + scratch_plan(G, kDensChunk).total();
+}
+
+size_t qbx_plan_bytes(qbx_plan plan, int32_t n_dens)
+{
+    if (!plan) return 0;
+    (void)n_dens;
+    try {
+        size_t total = 0;
+        qbx_geom_s G;
+        G.pl = plan->pl;
+        size_t res = 0, scr = 0;
+        if (sized_resident(&G, &res, &scr) != QBX_OK) return 0;
+        total = res + scr;
+        qbx_geom_s S;
+        Error e;
+        std::vector<int32_t> idx;
+        if (smooth_sub_plan(G.pl, S.pl, idx, e)) {
+            if (e.status != QBX_OK) return 0;
+            S.out_map = idx;
+            S.out_stride = G.pl.nt;
+            if (sized_resident(&S, &res, &scr) != QBX_OK) return 0;
+            total += res + scr;
+        }
+        return total;
+    } catch (const std::bad_alloc &) {
+        return 0;
     }
-    return G->arena.bytes + scratch;
 }
 
 qbx_status qbx_geom_association(qbx_geom G, int32_t *tgt_ctr_out)

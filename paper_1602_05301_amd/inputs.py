@@ -190,9 +190,9 @@ def batched_geometries(n: int = 256, workload_id: int = 3, nodes=(512, 16384),
     indices stars (3-9 lobes, amplitude 0.3), odd indices ellipses (aspect
     ratio uniform in [1, 10]); node counts log-uniform in `nodes`, rounded
     to whole 16-node panels; omega uniform in `omega`.  Each curve is scaled
-    by min(1, 5 n_panels / (omega L_1)), L_1 its perimeter at unit scale, so
-    that omega times the mean panel length stays at most 5.  Returns a list
-    of (Geometry, omega)."""
+    by min(1, 5 / (omega h_1)), h_1 its longest panel at unit scale, so that
+    omega h <= 5 holds on every panel (Condition 4 of Sec. 5).  Returns a
+    list of (Geometry, omega)."""
     rng = rng_for(workload_id, 0)
     out = []
     for i in range(n):
@@ -205,8 +205,8 @@ def batched_geometries(n: int = 256, workload_id: int = 3, nodes=(512, 16384),
         else:
             ar = float(rng.uniform(1.0, 10.0))
             make = lambda sc: ellipse(npan, 16, a=sc, b=sc / ar)
-        L1 = float(np.sum(make(1.0).w))
-        out.append((make(min(1.0, 5.0 * npan / (w * L1))), w))
+        h1 = float(np.max(make(1.0).h))
+        out.append((make(min(1.0, 5.0 / (w * h1))), w))
     return out
 
 

@@ -30,6 +30,7 @@ EXPORTS = [
     "qbx_geom_work",
     "qbx_eval_batch", "qbx_geom_autotune",
     "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate", "qbx_geom_points_near",
+    "qbx_plan_bytes",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -104,6 +105,7 @@ def lib():
     L.qbx_geom_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     L.qbx_geom_association.argtypes = [_vp, _ip]
     L.qbx_geom_bytes.argtypes = [_vp, i32]
+    L.qbx_plan_bytes.argtypes = [_vp, i32]
     L.qbx_geom_profile.argtypes = [_vp, i32]
     L.qbx_geom_graph.argtypes = [_vp, i32]
     L.qbx_geom_autotune.argtypes = [_vp, i32, ctypes.POINTER(i32)]
@@ -117,9 +119,11 @@ def lib():
     L.qbx_geom_points_near.argtypes = [_vp, i32, i64, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes"):
+        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes",
+                        "qbx_plan_bytes"):
             f.restype = st
     L.qbx_geom_bytes.restype = ctypes.c_size_t
+    L.qbx_plan_bytes.restype = ctypes.c_size_t
     _lib = L
     return L
 
@@ -240,6 +244,11 @@ class Plan:
         _check(lib().qbx_plan_association(self._h, out.ctypes.data_as(_ip)))
         return out[: self.stats()["n_tgt"]]
 
+    def bytes(self, n_dens: int = 1) -> int:
+        """Device memory the geometry made from this plan would hold once
+        evaluated (qbx_plan_bytes), computed on the host."""
+        return int(lib().qbx_plan_bytes(self._h, int(n_dens)))
+
 
 class Context:
     def __init__(self, device: int = 0, stream=None):
@@ -256,6 +265,11 @@ class Context:
         if getattr(self, "_h", None):
             lib().qbx_ctx_destroy(self._h)
             self._h = None
+
+    def set_stream(self, stream):
+        """Later work of this context goes to `stream` (a torch CUDA stream)."""
+        _check(lib().qbx_ctx_set_stream(self._h, _vp(stream.cuda_stream)))
+        self.stream = stream
 
     def eval_batch(self, geoms, sigmas_s, sigmas_d, us):
         """One evaluation per geometry, every stage one launch over all of them (qbx_eval_batch).
@@ -288,12 +302,17 @@ class Geometry:
     """A device-resident geometry (tree, lists, translation tables)."""
 
     def __init__(self, ctx: Context, geom, omega, eps, tx, ty, tgt_ctr=None,
-                 opts: Options | None = None):
+                 opts: Options | None = None, plan: "Plan | None" = None):
+        """From the arrays (qbx_geom_create), or from a host plan made with
+        the same arrays and options (qbx_geom_from_plan)."""
         self.opts = opts or options()
-        args, keep = _geom_args(geom, tx, ty, tgt_ctr)
         h = _vp()
-        _check(lib().qbx_geom_create(ctx._h, float(omega), float(eps), ctypes.byref(self.opts),
-                                     *args, ctypes.byref(h)))
+        if plan is not None:
+            _check(lib().qbx_geom_from_plan(ctx._h, plan._h, ctypes.byref(h)))
+        else:
+            args, keep = _geom_args(geom, tx, ty, tgt_ctr)
+            _check(lib().qbx_geom_create(ctx._h, float(omega), float(eps), ctypes.byref(self.opts),
+                                         *args, ctypes.byref(h)))
         self._h = h
         self.ctx = ctx
         self.n_src = int(np.asarray(geom.sx).size)

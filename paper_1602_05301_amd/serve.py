@@ -76,13 +76,25 @@ def make_requests(n: int, seed: int = 4, nodes=(1024, 32768), omega=(1.0, 200.0)
     return reqs
 
 
-def _build(ctx, req: Request):
+def _options(req: Request):
+    from . import qbx
+    return qbx.options(p=req.p, far_fp32=req.eps >= 1e-6)
+
+
+def _build(ctx, req: Request, plan=None):
     from . import qbx
     g = req.geom
     tc = np.arange(g.n, dtype=np.int32)
-    far32 = req.eps >= 1e-6
-    return qbx.Geometry(ctx, g, req.omega, req.eps, g.sx, g.sy, tc,
-                        qbx.options(p=req.p, far_fp32=far32))
+    return qbx.Geometry(ctx, g, req.omega, req.eps, g.sx, g.sy, tc, _options(req), plan=plan)
+
+
+def _plan(req: Request):
+    """Host planning of a request and the device memory its geometry will
+    hold (qbx_plan_bytes), before anything is allocated."""
+    from . import qbx
+    g = req.geom
+    pl = qbx.Plan(g, req.omega, req.eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32), _options(req))
+    return pl, float(pl.bytes(1))
 
 
 def fifo(ctx, reqs, keep_outputs: bool = False) -> dict:
@@ -110,72 +122,123 @@ def fifo(ctx, reqs, keep_outputs: bool = False) -> dict:
 
 
 class _Active:
-    def __init__(self, req, geo):
+    """An admitted request: its geometry, two device density buffers (the
+    next matvec's density is uploaded into one while a step reads the
+    other), their pinned host staging, and the output buffer."""
+
+    def __init__(self, req, geo, nbytes):
         import torch
-        self.req, self.geo, self.k = req, geo, 0
-        self.s = torch.empty((1, req.geom.n), dtype=torch.complex128, device="cuda")
-        self.u = torch.empty_like(self.s)
+        self.req, self.geo, self.k, self.bytes = req, geo, 0, nbytes
+        n = req.geom.n
+        self.s = [torch.empty((1, n), dtype=torch.complex128, device="cuda") for _ in range(2)]
+        self.h = [torch.empty((1, n), dtype=torch.complex128, pin_memory=True) for _ in range(2)]
+        self.up = [None, None]          # event: upload into s[i] done (h[i] free again)
+        self.u = torch.empty((1, n), dtype=torch.complex128, device="cuda")
+
+    def upload(self, k, stream):
+        """Density k into s[k % 2] on the upload stream."""
+        import torch
+        i = k % 2
+        if self.up[i] is not None:
+            self.up[i].synchronize()    # its previous upload has left h[i]
+        self.h[i].numpy()[0] = self.req.densities[k]
+        with torch.cuda.stream(stream):
+            self.s[i].copy_(self.h[i], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.up[i] = ev
 
 
 def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int = 4,
           keep_outputs: bool = False) -> dict:
-    """Continuous batching (see the module docstring)."""
+    """Continuous batching (see the module docstring).  Arrived requests are
+    planned on the host (tree, lists, orders) and their device footprint is
+    taken from the plan (qbx_plan_bytes), so admission never allocates
+    beyond the budget.  Admitted requests get their geometry made from the
+    plan on the thread pool.  One step (the next matvec of up to max_batch
+    admitted requests, one qbx_eval_batch) is in flight at a time, as the
+    chained matvecs require; while it runs, the next densities are uploaded
+    on a second stream and the host plans and admits, and completion is
+    polled through an event instead of synchronising the device."""
     import torch
+    comp = torch.cuda.Stream(device=ctx.device)
+    upl = torch.cuda.Stream(device=ctx.device)
+    ctx.set_stream(comp)
     pending = sorted(reqs, key=lambda r: r.arrival)
-    building: dict = {}                   # future -> (request, reserved bytes)
+    planning: dict = {}                   # future -> request
+    planned: list = []                    # (request, plan, bytes), in arrival order
+    building: dict = {}                   # future -> (request, bytes)
     active: list = []
     used = 0.0
-    bytes_per_node = 60e3                 # running estimate of resident bytes per node
     pool = cf.ThreadPoolExecutor(max_workers=setup_threads)
+    step, step_ev = None, None
     t0 = time.perf_counter()
     finished = 0
-    while finished < len(reqs):
-        now = time.perf_counter() - t0
-        # admission: arrived requests, in order, while the budget allows
-        while pending and pending[0].arrival <= now:
-            r = pending[0]
-            need = bytes_per_node * r.geom.n
-            if used + need > hbm_budget and (active or building):
-                break
-            pending.pop(0)
-            used += need
-            building[pool.submit(_build, ctx, r)] = (r, need)
-        for fut in [f for f in building if f.done()]:
-            r, need = building.pop(fut)
-            geo = fut.result()
-            real = float(geo.bytes(1))
-            used += real - need
-            bytes_per_node = max(bytes_per_node, 1.25 * real / r.geom.n)
-            active.append(_Active(r, geo))
-        if not active:
-            if building:
-                cf.wait(list(building), timeout=0.01, return_when=cf.FIRST_COMPLETED)
-            elif pending:
-                time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
-            continue
-        # one step: the next matvec of up to max_batch active requests
-        step = active[:max_batch]
-        for a in step:
-            a.s.copy_(torch.from_numpy(a.req.densities[a.k][None]))
-        ctx.eval_batch([a.geo for a in step], [a.s for a in step], [a.s for a in step],
-                       [a.u for a in step])
+    try:
+        while finished < len(reqs):
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.pop(0)
+                planning[pool.submit(_plan, r)] = r
+            for fut in [f for f in planning if f.done()]:
+                r = planning.pop(fut)
+                pl, nb = fut.result()
+                planned.append((r, pl, nb))
+            planned.sort(key=lambda x: x[0].arrival)
+            # admission by the planned footprint, in arrival order
+            while planned and (used + planned[0][2] <= hbm_budget or not (active or building or step)):
+                r, pl, nb = planned.pop(0)
+                used += nb
+                building[pool.submit(_build, ctx, r, pl)] = (r, nb)
+            for fut in [f for f in building if f.done()]:
+                r, nb = building.pop(fut)
+                a = _Active(r, fut.result(), nb)
+                a.upload(0, upl)
+                active.append(a)
+            if step is not None:
+                if not step_ev.query():
+                    time.sleep(2e-5)
+                    continue
+                t = time.perf_counter() - t0
+                keep = []
+                for a in step:
+                    if keep_outputs:
+                        a.req.outputs.append(a.u.cpu().numpy()[0])
+                    a.k += 1
+                    if a.k == len(a.req.densities):
+                        a.req.done = t
+                        used -= a.bytes
+                        finished += 1
+                        a.geo = None             # frees the resident geometry
+                    else:
+                        keep.append(a)
+                # round robin: the requests just served go behind those that waited
+                active = active[len(step):] + keep
+                step = None
+                continue
+            if not active:
+                waits = list(planning) + list(building)
+                if waits:
+                    cf.wait(waits, timeout=0.002, return_when=cf.FIRST_COMPLETED)
+                elif pending:
+                    time.sleep(max(0.0, min(0.002, pending[0].arrival - (time.perf_counter() - t0))))
+                continue
+            # issue one step: the next matvec of up to max_batch requests
+            step = active[:max_batch]
+            for a in step:
+                comp.wait_event(a.up[a.k % 2])
+            ctx.eval_batch([a.geo for a in step], [a.s[a.k % 2] for a in step],
+                           [a.s[a.k % 2] for a in step], [a.u for a in step])
+            step_ev = torch.cuda.Event()
+            step_ev.record(comp)
+            # the next densities go up while the step runs
+            for a in step:
+                if a.k + 1 < len(a.req.densities):
+                    a.upload(a.k + 1, upl)
+    finally:
+        pool.shutdown()
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        keep = []
-        for a in step:
-            if keep_outputs:
-                a.req.outputs.append(a.u.cpu().numpy()[0])
-            a.k += 1
-            if a.k == len(a.req.densities):
-                a.req.done = t
-                used -= float(a.geo.bytes(1))
-                finished += 1
-                a.geo = None                 # frees the resident geometry
-            else:
-                keep.append(a)
-        # round robin: the requests just served go behind those that waited
-        active = active[len(step):] + keep
-    pool.shutdown()
+        ctx.set_stream(torch.cuda.current_stream(ctx.device))
     return _summary(reqs, time.perf_counter() - t0)
 
 
