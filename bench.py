@@ -174,11 +174,11 @@ def leg_batched(ctx, eps, rounds=3, n_geom=256, n_dens=4, check_geoms=8, check_t
     from paper_1602_05301_amd import inputs, qbx
     far32 = eps >= 1e-6
     p = 9 if far32 else 14
-    # 8 orders above the default increment: some of these small,
+    # 12 orders above the default increment: some of these small,
     # high-frequency curves need them to stay within eps at every target
     tiny = inputs.star(4, 4, lobes=3)
     p_add = qbx.Plan(tiny, 1.0, eps, tiny.sx, tiny.sy, np.arange(tiny.n, dtype=np.int32),
-                     qbx.options(p=p)).stats()["p_add"] + 8
+                     qbx.options(p=p)).stats()["p_add"] + 12
     curves = inputs.batched_geometries(n_geom)
     dr = inputs.rng_for(3, inputs.PURPOSE_DENSITY)
     dens = [inputs.complex_gaussian(dr, (n_dens, g.n)) for g, _ in curves]

@@ -752,14 +752,15 @@ def test_batched_256_geometries(ctx, eps):
     qbx_eval_batch over all of them; FP64 at eps = 1e-10 (p = 14), FP32 far
     field at 1e-6 (p = 9).  Every geometry's result is bitwise equal to its
     evaluation alone, and matches the oracle at 64 sampled targets to eps.
-    The FMM orders are 8 above the default increment: a few of these small,
-    high-frequency curves need them to stay within eps at every target."""
+    The FMM orders are 12 above the default increment: a few of these small,
+    high-frequency curves need them to stay within eps at every target (the
+    default meets eps on all but a handful of the 256)."""
     import concurrent.futures as cf
 
     from paper_1602_05301_amd import qbx
     far32 = eps >= 1e-6
     p = 9 if far32 else 14
-    p_add = _default_p_add(p, eps) + 8
+    p_add = _default_p_add(p, eps) + 12
     curves = inputs.batched_geometries(256)
     dr = inputs.rng_for(3, 2)
     dens = [inputs.complex_gaussian(dr, (4, g.n)) for g, _ in curves]
