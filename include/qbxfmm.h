@@ -333,6 +333,33 @@ qbx_status qbx_geom_work(qbx_geom geom, int32_t n_dens, double *flops);
 qbx_status qbx_eval(qbx_geom geom, int32_t n_dens, const void *sigma_s,
                     const void *sigma_d, void *u, void *coef);
 
+/* ---- evaluation without allocation ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * qbx_eval_noalloc computes exactly what qbx_eval computes (same kernels,
+ * same sums in the same order: results are bitwise equal) but takes every
+ * evaluation buffer (charges, expansions, per-pair rows, radial sequences,
+ * coefficients) from one static device array of QBX_NOALLOC_SCRATCH_BYTES
+ * bytes per device instead of the geometry's own scratch, and calls no
+ * hipMalloc, hipFree or allocating routine.  The array is part of the
+ * library's device code: each device the library runs on holds it from the
+ * first qbx_ctx_create on that device until the process ends.  Densities
+ * are taken in chunks of up to 4, as many as fit; a geometry whose buffers
+ * for one density exceed the array is rejected with QBX_E_UNSUPPORTED
+ * (the message gives the size needed) and must use qbx_eval.  The
+ * geometry, its tables and GEMM tile lists must exist (qbx_geom_create);
+ * sigma_s, sigma_d, u, coef are as in qbx_eval, on the context's stream.
+ * Every call on one device shares that device's array and overwrites what
+ * the previous call left there: calls that overlap on one device (other
+ * threads, other contexts or streams of the same device, captured graphs
+ * replayed concurrently) race and give wrong results; serialise them.
+ * Stage profiling and graph replay settings of the geometry are ignored
+ * (no events are taken, nothing is captured by the library).  Errors: as
+ * qbx_eval, plus QBX_E_UNSUPPORTED. */
+#define QBX_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+qbx_status qbx_eval_noalloc(qbx_geom geom, int32_t n_dens, const void *sigma_s,
+                            const void *sigma_d, void *u, void *coef);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -15,6 +16,39 @@
 #include "kernels.hpp"
 
 using namespace qbx;
+
+// The evaluation buffers of qbx_eval_noalloc: one static array per device,
+// held until the process ends.  In host code its name stands for the
+// array, not its device address; that comes from hipGetSymbolAddress,
+// once per device (noalloc_base), and only that address is used.
+static __device__ __align__(256) unsigned char noalloc_scratch[QBX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_base[kMaxDevices] = {};
+
+// Device address of the static evaluation buffers on `device` (current),
+// looked up on the first call per device.  Null on failure.
+unsigned char *noalloc_base(int device, hipError_t *err)
+{
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_base[device]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_noalloc_base[device] = static_cast<unsigned char *>(ptr);
+    }
+    return g_noalloc_base[device];
+}
+
+}  // namespace
 
 // A side stream and the events that fork it from, and join it back to, the
 // stream an evaluation is enqueued on.
@@ -849,7 +883,7 @@ qbx_status harvest(qbx_geom_s *G)
     } while (0)
 
 // The evaluation buffers of one pass through the pipeline: the geometry's
-// own scratch, or parts of another region.
+// own scratch, or parts of a caller-provided region (qbx_eval_noalloc).
 struct EvalBufs {
     cd *qs, *qd, *mp, *loc, *coef, *vy, *wy;
     double *srad, *crad;
@@ -1325,6 +1359,10 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     if (device < 0 || device >= n) return fail(QBX_E_INVAL, "device index out of range");
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    // set-up of the static buffers of qbx_eval_noalloc on this device
+    if (!noalloc_base(device, &e))
+        return fail(QBX_E_DEVICE, std::string("hipGetSymbolAddress (static evaluation buffers): ") +
+                                      hipGetErrorString(e));
     auto *c = new (std::nothrow) qbx_ctx_s();
     if (!c) return fail(QBX_E_NOMEM, "host allocation failed");
     c->device = device;
@@ -1478,7 +1516,7 @@ qbx_status sized_resident(qbx_geom_s *G, size_t *bytes, size_t *scratch_bytes = 
 
 // G's resident device data (G->pl, out_map and out_stride set): points,
 // tree, lists, tables and the GEMM tile lists of every chunk size, made now
-// so that evaluations never allocate them,
+// so that evaluations (qbx_eval_noalloc in particular) never allocate them,
 // in one allocation filled by one copy; then the order-0 geometry of the
 // smooth-rule targets.
 qbx_status build_device(qbx_geom_s *G)
@@ -1755,6 +1793,82 @@ qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void 
         return QBX_OK;
     }
     return eval_chunks(G, n_dens, sigma_s, sigma_d, u, coef, C->stream, C->lane);
+}
+
+namespace {
+
+// Evaluation buffers of G (and of its order-0 geometry) for chunks of c
+// densities, laid out from `base` at 256-byte boundaries.  Returns the end
+// offset; with base null only sizes are computed.
+size_t carve_bufs(const qbx_geom_s *G, int c, unsigned char *base, size_t off, EvalBufs *B, EvalBufs *Bsub,
+                  bool *rad, bool *rad_sub)
+{
+    ScratchPlan sp = scratch_plan(G, c);
+    auto take = [&](size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        unsigned char *p = base ? base + off : nullptr;
+        off += n;
+        return p;
+    };
+    B->qs = (cd *)take(sp.qs);
+    B->qd = (cd *)take(sp.qd);
+    B->coef = (cd *)take(sp.coef);
+    B->mp = (cd *)take(sp.mp);
+    B->loc = (cd *)take(sp.loc);
+    B->vy = (cd *)take(sp.vy);
+    B->wy = (cd *)take(sp.wy);
+    B->srad = (double *)take(sp.srad);
+    B->crad = (double *)take(sp.crad);
+    B->rad_ready = rad;
+    B->timing = false;
+    B->sub = nullptr;
+    if (G->sub) {
+        off = carve_bufs(G->sub, c, base, off, Bsub, nullptr, rad_sub, nullptr);
+        B->sub = Bsub;
+    }
+    return off;
+}
+
+}  // namespace
+
+qbx_status qbx_eval_noalloc(qbx_geom G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
+                            void *coef)
+{
+    if (!G) return fail(QBX_E_INVAL, "null geometry");
+    if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
+    if (!u && G->pl.nt) return fail(QBX_E_INVAL, "u is NULL");
+    if (!sigma_s && !sigma_d) return fail(QBX_E_INVAL, "both densities are NULL");
+    const qbx_ctx_s *C = G->ctx;
+    hipError_t e = hipSetDevice(C->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    unsigned char *base = noalloc_base(C->device, &e);
+    if (!base) return fail(QBX_E_DEVICE, std::string("static evaluation buffers: ") + hipGetErrorString(e));
+    // the largest chunk of densities whose buffers fit the static array
+    EvalBufs B{}, Bs{};
+    bool rad = false, rad_sub = false;
+    int c = std::min<int>(kDensChunk, n_dens);
+    for (; c >= 1; --c)
+        if (carve_bufs(G, c, nullptr, 0, &B, &Bs, &rad, &rad_sub) <= (size_t)QBX_NOALLOC_SCRATCH_BYTES) break;
+    if (c < 1) {
+        size_t need = carve_bufs(G, 1, nullptr, 0, &B, &Bs, &rad, &rad_sub);
+        return fail(QBX_E_UNSUPPORTED, "qbx_eval_noalloc: the geometry needs " + std::to_string(need) +
+                                           " bytes of evaluation buffers for one density, more than the " +
+                                           std::to_string((size_t)QBX_NOALLOC_SCRATCH_BYTES) +
+                                           " of the static array; use qbx_eval");
+    }
+    carve_bufs(G, c, base, 0, &B, &Bs, &rad, &rad_sub);
+    const Plan &pl = G->pl;
+    long long nq = 2 * pl.p + 1;
+    for (int d0 = 0; d0 < n_dens; d0 += c) {
+        int nd = std::min(c, n_dens - d0);
+        const cd *ss = sigma_s ? static_cast<const cd *>(sigma_s) + (long long)d0 * pl.ns : nullptr;
+        const cd *sd = sigma_d ? static_cast<const cd *>(sigma_d) + (long long)d0 * pl.ns : nullptr;
+        cd *uu = static_cast<cd *>(u) + (long long)d0 * pl.nt;
+        cd *co = coef ? static_cast<cd *>(coef) + (long long)d0 * nq * pl.nc : nullptr;
+        qbx_status q = run_pipeline(G, nd, ss, sd, uu, co, C->stream, C->lane, &B);
+        if (q != QBX_OK) return q;
+    }
+    return QBX_OK;
 }
 
 qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,

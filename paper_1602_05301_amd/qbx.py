@@ -30,7 +30,7 @@ EXPORTS = [
     "qbx_geom_work",
     "qbx_eval_batch", "qbx_geom_autotune",
     "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate", "qbx_geom_points_near",
-    "qbx_plan_bytes",
+    "qbx_eval_noalloc", "qbx_plan_bytes",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -114,6 +114,7 @@ def lib():
     L.qbx_geom_stage_times.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), i32]
     L.qbx_geom_work.argtypes = [_vp, i32, _dp]
     L.qbx_eval.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    L.qbx_eval_noalloc.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
     L.qbx_geom_area_query.argtypes = [_vp, i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(i64)]
     L.qbx_geom_associate.argtypes = [_vp, i64, _vp, _vp, _vp, ctypes.POINTER(i64)]
     L.qbx_geom_points_near.argtypes = [_vp, i32, i64, _vp, _vp, _vp, _vp]
@@ -417,6 +418,21 @@ class Geometry:
         f = np.zeros(len(STAGES))
         _check(lib().qbx_geom_work(self._h, int(n_dens), f.ctypes.data_as(_dp)))
         return {s: float(f[i]) for i, s in enumerate(STAGES)}
+
+    def eval_noalloc(self, sigma_s, sigma_d, u, coef=None):
+        """As eval, through qbx_eval_noalloc: the library allocates nothing
+        (its evaluation buffers are a static array per device).  u (and coef,
+        if given) must be preallocated complex128 CUDA tensors."""
+        nd = _n_dens(sigma_s, sigma_d, self.n_src, "eval_noalloc")
+        for t, nm in ((sigma_s, "sigma_s"), (sigma_d, "sigma_d")):
+            if t is not None:
+                _need_c128(t, nd * self.n_src, nm, self.ctx.device)
+        _need_c128(u, nd * self.n_tgt, "u", self.ctx.device)
+        if coef is not None:
+            _need_c128(coef, nd * (2 * self.p + 1) * self.n_ctr, "coef", self.ctx.device)
+        ptr = lambda t: None if t is None else _vp(t.data_ptr())
+        _check(lib().qbx_eval_noalloc(self._h, nd, ptr(sigma_s), ptr(sigma_d), ptr(u), ptr(coef)))
+        return u
 
     def eval(self, sigma_s, sigma_d, u=None, coef=None):
         """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); device complex128 tensors."""
