@@ -333,6 +333,35 @@ qbx_status qbx_geom_work(qbx_geom geom, int32_t n_dens, double *flops);
 qbx_status qbx_eval(qbx_geom geom, int32_t n_dens, const void *sigma_s,
                     const void *sigma_d, void *u, void *coef);
 
+/* ---- GMRES building blocks (the solve of Sec. 8.3 on the device) ------------
+ * The Arnoldi step of GMRES on a QBX matvec, run on the context's stream so
+ * that the Krylov basis never leaves the device.  V holds Krylov vectors as
+ * rows: vector i at V + i * ldv (complex128, device), n entries each.  Sums
+ * run in a fixed order (results do not depend on timing).
+ * qbx_krylov_dot:       h[i] = sum_j conj(V[i][j]) w[j] for i < k (Gram-Schmidt
+ *                       coefficients; k = 1, V = w gives |w|^2 in h[0]).
+ *                       h: device complex128[k].  Uses a workspace of the
+ *                       context (grown on demand: the call may allocate).
+ * qbx_krylov_update:    w[j] -= sum_i h[i] V[i][j], i < k (h device [k]).
+ * qbx_krylov_normalize: v[j] = w[j] / sqrt(Re nrm2[0]), nrm2 a device
+ *                       complex128 (e.g. from qbx_krylov_dot); 0 if it is 0.
+ *                       v may equal w.
+ * qbx_upsample:         densities on Gauss panels of q nodes carried to the
+ *                       same panels with qs nodes (Sec. 3.2, Table 1):
+ *                       yd[p qs + a] = sum_b L[a q + b] x[p q + b] and
+ *                       ys = alpha yd (alpha = alpha_re + i alpha_im), for
+ *                       the n_panels panels; L: device float64 [qs][q];
+ *                       either output may be NULL.
+ * Errors: QBX_E_INVAL (sizes, ldv < n, null arrays), QBX_E_NOMEM,
+ * QBX_E_DEVICE. */
+qbx_status qbx_krylov_dot(qbx_ctx ctx, int64_t n, int32_t k, const void *V, int64_t ldv,
+                          const void *w, void *h);
+qbx_status qbx_krylov_update(qbx_ctx ctx, int64_t n, int32_t k, const void *V, int64_t ldv,
+                             const void *h, void *w);
+qbx_status qbx_krylov_normalize(qbx_ctx ctx, int64_t n, const void *w, const void *nrm2, void *v);
+qbx_status qbx_upsample(qbx_ctx ctx, int64_t n_panels, int32_t q, int32_t qs, const double *L,
+                        double alpha_re, double alpha_im, const void *x, void *ys, void *yd);
+
 /* ---- evaluation without allocation ----------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libqbxfmm.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRC = ["planner.cpp", "abi_plan.cpp"]
-HIP_SRC = ["kernels.hip", "areaquery.hip", "abi_device.cpp"]
+HIP_SRC = ["kernels.hip", "areaquery.hip", "krylov.hip", "abi_device.cpp"]
 
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

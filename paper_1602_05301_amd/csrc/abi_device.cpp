@@ -14,6 +14,7 @@
 #include "abi_common.hpp"
 #include "areaquery.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 
 using namespace qbx;
 
@@ -81,6 +82,9 @@ struct qbx_ctx_s {
     hipEvent_t fz_copied = nullptr;   // the last copy out of fz_host
     hipEvent_t fz_done = nullptr;     // the last launch reading fz_dev was enqueued before this
     bool fz_used = false;
+    // workspace of qbx_krylov_dot (partial sums), grown on demand
+    cd *kw = nullptr;
+    size_t kw_cap = 0;
 };
 
 namespace {
@@ -1415,6 +1419,7 @@ void ctx_release(qbx_ctx_s *ctx)
     }
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->kw) (void)hipFree(ctx->kw);
     delete ctx;
 }
 
@@ -2213,3 +2218,70 @@ qbx_status qbx_geom_associate(qbx_geom G, int64_t n_tgt, const double *tx, const
 }
 
 }  // extern "C"
+
+// ---- GMRES building blocks ---------------------------------------------------
+
+qbx_status qbx_krylov_dot(qbx_ctx ctx, int64_t n, int32_t k, const void *V, int64_t ldv, const void *w, void *h)
+{
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    if (n < 0 || k < 0 || ldv < n) return fail(QBX_E_INVAL, "qbx_krylov_dot: need n >= 0, k >= 0, ldv >= n");
+    if (k == 0) return QBX_OK;
+    if (!h || (n > 0 && (!V || !w))) return fail(QBX_E_INVAL, "qbx_krylov_dot: null array");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    size_t need = (size_t)k * std::max(krylov_dot_chunks(n), 1);
+    if (need > ctx->kw_cap) {
+        // the previous workspace may still be read by enqueued work
+        if (ctx->kw) {
+            CHK(hipStreamSynchronize(ctx->stream));
+            CHK(hipFree(ctx->kw));
+            ctx->kw = nullptr;
+            ctx->kw_cap = 0;
+        }
+        size_t cap = std::max(need, ctx->kw_cap * 2);
+        e = hipMalloc((void **)&ctx->kw, cap * sizeof(cd));
+        if (e != hipSuccess) return fail(QBX_E_NOMEM, std::string("krylov workspace: ") + hipGetErrorString(e));
+        ctx->kw_cap = cap;
+    }
+    CHK(launch_krylov_dot(n, k, static_cast<const cd *>(V), ldv, static_cast<const cd *>(w), ctx->kw,
+                          static_cast<cd *>(h), ctx->stream));
+    return QBX_OK;
+}
+
+qbx_status qbx_krylov_update(qbx_ctx ctx, int64_t n, int32_t k, const void *V, int64_t ldv, const void *h,
+                             void *w)
+{
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    if (n < 0 || k < 0 || ldv < n) return fail(QBX_E_INVAL, "qbx_krylov_update: need n >= 0, k >= 0, ldv >= n");
+    if (n == 0 || k == 0) return QBX_OK;
+    if (!V || !h || !w) return fail(QBX_E_INVAL, "qbx_krylov_update: null array");
+    CHK(hipSetDevice(ctx->device));
+    CHK(launch_krylov_update(n, k, static_cast<const cd *>(V), ldv, static_cast<const cd *>(h),
+                             static_cast<cd *>(w), ctx->stream));
+    return QBX_OK;
+}
+
+qbx_status qbx_krylov_normalize(qbx_ctx ctx, int64_t n, const void *w, const void *nrm2, void *v)
+{
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    if (n < 0) return fail(QBX_E_INVAL, "qbx_krylov_normalize: n < 0");
+    if (n == 0) return QBX_OK;
+    if (!w || !nrm2 || !v) return fail(QBX_E_INVAL, "qbx_krylov_normalize: null array");
+    CHK(hipSetDevice(ctx->device));
+    CHK(launch_krylov_normalize(n, static_cast<const cd *>(w), static_cast<const cd *>(nrm2),
+                                static_cast<cd *>(v), ctx->stream));
+    return QBX_OK;
+}
+
+qbx_status qbx_upsample(qbx_ctx ctx, int64_t n_panels, int32_t q, int32_t qs, const double *L, double alpha_re,
+                        double alpha_im, const void *x, void *ys, void *yd)
+{
+    if (!ctx) return fail(QBX_E_INVAL, "null context");
+    if (n_panels < 0 || q < 1 || qs < 1) return fail(QBX_E_INVAL, "qbx_upsample: need n_panels >= 0, q, qs >= 1");
+    if (n_panels == 0) return QBX_OK;
+    if (!L || !x || (!ys && !yd)) return fail(QBX_E_INVAL, "qbx_upsample: null array");
+    CHK(hipSetDevice(ctx->device));
+    CHK(launch_upsample(n_panels, q, qs, L, mk(alpha_re, alpha_im), static_cast<const cd *>(x),
+                        static_cast<cd *>(ys), static_cast<cd *>(yd), ctx->stream));
+    return QBX_OK;
+}

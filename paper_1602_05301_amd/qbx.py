@@ -31,6 +31,7 @@ EXPORTS = [
     "qbx_eval_batch", "qbx_geom_autotune",
     "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate", "qbx_geom_points_near",
     "qbx_eval_noalloc", "qbx_plan_bytes",
+    "qbx_krylov_dot", "qbx_krylov_update", "qbx_krylov_normalize", "qbx_upsample",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -106,6 +107,10 @@ def lib():
     L.qbx_geom_association.argtypes = [_vp, _ip]
     L.qbx_geom_bytes.argtypes = [_vp, i32]
     L.qbx_plan_bytes.argtypes = [_vp, i32]
+    L.qbx_krylov_dot.argtypes = [_vp, i64, i32, _vp, i64, _vp, _vp]
+    L.qbx_krylov_update.argtypes = [_vp, i64, i32, _vp, i64, _vp, _vp]
+    L.qbx_krylov_normalize.argtypes = [_vp, i64, _vp, _vp, _vp]
+    L.qbx_upsample.argtypes = [_vp, i64, i32, i32, _vp, dbl, dbl, _vp, _vp, _vp]
     L.qbx_geom_profile.argtypes = [_vp, i32]
     L.qbx_geom_graph.argtypes = [_vp, i32]
     L.qbx_geom_autotune.argtypes = [_vp, i32, ctypes.POINTER(i32)]
@@ -271,6 +276,63 @@ class Context:
         """Later work of this context goes to `stream` (a torch CUDA stream)."""
         _check(lib().qbx_ctx_set_stream(self._h, _vp(stream.cuda_stream)))
         self.stream = stream
+
+    # ---- GMRES building blocks (qbx_krylov_*, qbx_upsample) ----
+    @staticmethod
+    def _basis(V, k, n):
+        import torch
+        if not isinstance(V, torch.Tensor) or V.dtype != torch.complex128 or not V.is_cuda or V.dim() != 2:
+            raise ValueError("V must be a 2-D complex128 CUDA tensor of Krylov vectors (rows)")
+        if V.stride(1) != 1 or V.shape[0] < k or V.shape[1] < n:
+            raise ValueError("V must hold k rows of n contiguous entries")
+        return V.stride(0)
+
+    def krylov_dot(self, V, k, w, h):
+        """h[i] = sum_j conj(V[i, j]) w[j] for i < k (qbx_krylov_dot)."""
+        n = int(w.numel())
+        ld = self._basis(V, k, n)
+        _need_c128(w, n, "w", self.device)
+        _need_c128(h, int(h.numel()), "h", self.device)
+        if h.numel() < k:
+            raise ValueError("h needs k entries")
+        _check(lib().qbx_krylov_dot(self._h, n, int(k), _vp(V.data_ptr()), ld, _vp(w.data_ptr()),
+                                    _vp(h.data_ptr())))
+
+    def krylov_update(self, V, k, h, w):
+        """w[j] -= sum_i h[i] V[i, j] for i < k (qbx_krylov_update)."""
+        n = int(w.numel())
+        ld = self._basis(V, k, n)
+        _need_c128(w, n, "w", self.device)
+        _need_c128(h, int(h.numel()), "h", self.device)
+        if h.numel() < k:
+            raise ValueError("h needs k entries")
+        _check(lib().qbx_krylov_update(self._h, n, int(k), _vp(V.data_ptr()), ld, _vp(h.data_ptr()),
+                                       _vp(w.data_ptr())))
+
+    def krylov_normalize(self, w, nrm2, v):
+        """v = w / sqrt(Re nrm2[0]) (qbx_krylov_normalize)."""
+        n = int(w.numel())
+        _need_c128(w, n, "w", self.device)
+        _need_c128(v, n, "v", self.device)
+        _need_c128(nrm2, int(nrm2.numel()), "nrm2", self.device)
+        _check(lib().qbx_krylov_normalize(self._h, n, _vp(w.data_ptr()), _vp(nrm2.data_ptr()),
+                                          _vp(v.data_ptr())))
+
+    def upsample(self, L, q, qs, x, alpha=1.0, ys=None, yd=None):
+        """Panel densities from q to qs Gauss nodes (qbx_upsample): yd = L x per
+        panel, ys = alpha yd.  L: float64 CUDA tensor [qs, q]."""
+        import torch
+        n_panels = int(x.numel()) // q
+        if L.dtype != torch.float64 or not L.is_cuda or not L.is_contiguous() or tuple(L.shape) != (qs, q):
+            raise ValueError("L must be a contiguous float64 CUDA tensor [qs, q]")
+        _need_c128(x, n_panels * q, "x", self.device)
+        for t, nm in ((ys, "ys"), (yd, "yd")):
+            if t is not None:
+                _need_c128(t, n_panels * qs, nm, self.device)
+        ptr = lambda t: None if t is None else _vp(t.data_ptr())
+        a = complex(alpha)
+        _check(lib().qbx_upsample(self._h, n_panels, int(q), int(qs), _vp(L.data_ptr()), a.real, a.imag,
+                                  _vp(x.data_ptr()), ptr(ys), ptr(yd)))
 
     def eval_batch(self, geoms, sigmas_s, sigmas_d, us):
         """One evaluation per geometry, every stage one launch over all of them (qbx_eval_batch).

@@ -30,6 +30,7 @@ import argparse
 import concurrent.futures as cf
 import dataclasses
 import json
+import sys
 import time
 
 import numpy as np
@@ -40,23 +41,52 @@ from . import inputs
 @dataclasses.dataclass
 class Request:
     rid: int
-    geom: inputs.Geometry
+    n_panels: int            # 16-node panels of its star curve
+    lobes: int
+    scale: float             # curve radius
     omega: float
     eps: float
     p: int
-    densities: list          # [n_matvec] complex128 arrays [n_src] (sigma_s; sigma_d = sigma_s)
+    n_matvec: int            # chained matvecs (densities) of the request
+    seed: int                # of its densities
     arrival: float = 0.0     # seconds after the start of the run
     # filled in by the server
     outputs: list = dataclasses.field(default_factory=list)
     done: float = 0.0
+    _geom: object = None
+    _base: np.ndarray = None
+
+    @property
+    def n(self) -> int:
+        return 16 * self.n_panels
+
+    @property
+    def geom(self) -> inputs.Geometry:
+        """The discretised curve (made on first use)."""
+        if self._geom is None:
+            self._geom = inputs.star(self.n_panels, 16, lobes=self.lobes, radius=self.scale)
+        return self._geom
+
+    def density(self, k: int) -> np.ndarray:
+        """Density k (sigma_s = sigma_d), complex128 [n]: a seeded Gaussian
+        vector of the request turned by a phase of k (made on first use, so
+        that long request streams need not hold every density)."""
+        if self._base is None:
+            self._base = inputs.complex_gaussian(inputs.rng_for(self.seed, 100 + self.rid), (self.n,))
+        return self._base * np.exp(0.7j * k)
+
+    def release(self):
+        """Drops the host copies of the curve and densities."""
+        self._geom = None
+        self._base = None
 
 
 def make_requests(n: int, seed: int = 4, nodes=(1024, 32768), omega=(1.0, 200.0),
                   eps_choices=(1e-6, 1e-10), matvecs=(20, 60)) -> list:
     """Seeded stream of star-curve requests: node counts log-uniform (rounded
     to whole 16-node panels), omega uniform, eps from eps_choices, 20-60
-    chained Gaussian densities each.  Each curve is scaled so that its
-    panels stay below 5 wavelengths (omega h <= 5)."""
+    chained densities each (Request.density).  Each curve is scaled so that
+    its longest panel stays within omega h <= 5 (Condition 4)."""
     rng = inputs.rng_for(seed, 0)
     reqs = []
     for i in range(n):
@@ -64,15 +94,13 @@ def make_requests(n: int, seed: int = 4, nodes=(1024, 32768), omega=(1.0, 200.0)
         npan = max(8, nn // 16)
         lobes = int(rng.integers(3, 10))
         w = float(rng.uniform(*omega))
-        g0 = inputs.star(npan, 16, lobes=lobes)
-        scale = min(1.0, 5.0 / (w * float(np.max(g0.h))))
-        g = inputs.star(npan, 16, lobes=lobes, radius=scale)
+        # the longest panel of the unit star with npan equal-theta panels
+        h1 = float(np.max(inputs.star(npan, 16, lobes=lobes).h))
+        scale = min(1.0, 5.0 / (w * h1))
         eps = float(eps_choices[int(rng.integers(0, len(eps_choices)))])
         p = 9 if eps >= 1e-6 else 14
         k = int(rng.integers(matvecs[0], matvecs[1] + 1))
-        dr = inputs.rng_for(seed, 100 + i)
-        dens = [inputs.complex_gaussian(dr, (g.n,)) for _ in range(k)]
-        reqs.append(Request(i, g, w, eps, p, dens))
+        reqs.append(Request(i, npan, lobes, scale, w, eps, p, k, seed))
     return reqs
 
 
@@ -94,6 +122,7 @@ def _plan(req: Request):
     from . import qbx
     g = req.geom
     pl = qbx.Plan(g, req.omega, req.eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32), _options(req))
+    req.density(0)                       # the request's densities, made here off the serving thread
     return pl, float(pl.bytes(1))
 
 
@@ -107,17 +136,18 @@ def fifo(ctx, reqs, keep_outputs: bool = False) -> dict:
         if now < r.arrival:
             time.sleep(r.arrival - now)
         geo = _build(ctx, r)
-        s = torch.empty((1, r.geom.n), dtype=torch.complex128, device="cuda")
+        s = torch.empty((1, r.n), dtype=torch.complex128, device="cuda")
         u = torch.empty_like(s)
         r.outputs = []
-        for d in r.densities:
-            s.copy_(torch.from_numpy(d[None]))
+        for k in range(r.n_matvec):
+            s.copy_(torch.from_numpy(r.density(k)[None]))
             geo.eval(s, s, u=u)
             if keep_outputs:
                 r.outputs.append(u.cpu().numpy()[0])
         torch.cuda.synchronize()
         r.done = time.perf_counter() - t0
         del geo
+        r.release()
     return _summary(reqs, time.perf_counter() - t0)
 
 
@@ -129,7 +159,7 @@ class _Active:
     def __init__(self, req, geo, nbytes):
         import torch
         self.req, self.geo, self.k, self.bytes = req, geo, 0, nbytes
-        n = req.geom.n
+        n = req.n
         self.s = [torch.empty((1, n), dtype=torch.complex128, device="cuda") for _ in range(2)]
         self.h = [torch.empty((1, n), dtype=torch.complex128, pin_memory=True) for _ in range(2)]
         self.up = [None, None]          # event: upload into s[i] done (h[i] free again)
@@ -141,7 +171,7 @@ class _Active:
         i = k % 2
         if self.up[i] is not None:
             self.up[i].synchronize()    # its previous upload has left h[i]
-        self.h[i].numpy()[0] = self.req.densities[k]
+        self.h[i].numpy()[0] = self.req.density(k)
         with torch.cuda.stream(stream):
             self.s[i].copy_(self.h[i], non_blocking=True)
             ev = torch.cuda.Event()
@@ -205,11 +235,12 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
                     if keep_outputs:
                         a.req.outputs.append(a.u.cpu().numpy()[0])
                     a.k += 1
-                    if a.k == len(a.req.densities):
+                    if a.k == a.req.n_matvec:
                         a.req.done = t
                         used -= a.bytes
                         finished += 1
                         a.geo = None             # frees the resident geometry
+                        a.req.release()
                     else:
                         keep.append(a)
                 # round robin: the requests just served go behind those that waited
@@ -233,7 +264,7 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
             step_ev.record(comp)
             # the next densities go up while the step runs
             for a in step:
-                if a.k + 1 < len(a.req.densities):
+                if a.k + 1 < a.req.n_matvec:
                     a.upload(a.k + 1, upl)
     finally:
         pool.shutdown()
@@ -244,9 +275,24 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
 
 def _summary(reqs, wall: float) -> dict:
     lat = np.array([r.done - r.arrival for r in reqs])
-    work = sum(r.geom.n * len(r.densities) for r in reqs)
-    return {"requests": len(reqs), "matvecs": sum(len(r.densities) for r in reqs),
+    work = sum(r.n * r.n_matvec for r in reqs)
+    return {"requests": len(reqs), "matvecs": sum(r.n_matvec for r in reqs),
             "wall_s": wall, "targets_x_matvecs_per_s": work / wall,
+            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+
+
+def measured(run: dict, reqs, skip: int) -> dict:
+    """A run's figures over the requests after the first `skip` (warm-up):
+    latency percentiles of those, throughput over the span from the first
+    of them arriving to the last finishing."""
+    rest = sorted(reqs, key=lambda r: r.arrival)[skip:]
+    if not rest:
+        return run
+    span = max(r.done for r in rest) - min(r.arrival for r in rest)
+    lat = np.array([r.done - r.arrival for r in rest])
+    work = sum(r.n * r.n_matvec for r in rest)
+    return {"requests": len(rest), "warmup_requests": skip, "matvecs": sum(r.n_matvec for r in rest),
+            "span_s": span, "targets_x_matvecs_per_s": work / span,
             "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
 
 
@@ -256,7 +302,7 @@ def batch_vs_sequential(ctx, n_geom: int = 16, rounds: int = 10, max_nodes: int 
     import torch
     reqs = make_requests(n_geom, seed=11, nodes=(512, max_nodes), matvecs=(4, 4))
     geos = [_build(ctx, r) for r in reqs]
-    s = [torch.from_numpy(np.stack(r.densities)).cuda() for r in reqs]
+    s = [torch.from_numpy(np.stack([r.density(k) for k in range(4)])).cuda() for r in reqs]
     u = [torch.empty_like(x) for x in s]
     for g, x, y in zip(geos, s, u):                  # warm-up (scratch, tiles)
         g.eval(x, x, u=y)
@@ -273,8 +319,8 @@ def batch_vs_sequential(ctx, n_geom: int = 16, rounds: int = 10, max_nodes: int 
         ctx.eval_batch(geos, s, s, u)
     torch.cuda.synchronize()
     bat = (time.perf_counter() - t0) / rounds
-    work = sum(r.geom.n * 4 for r in reqs)
-    return {"geometries": n_geom, "densities_each": 4, "nodes": [r.geom.n for r in reqs],
+    work = sum(r.n * 4 for r in reqs)
+    return {"geometries": n_geom, "densities_each": 4, "nodes": [r.n for r in reqs],
             "sequential_ms": seq * 1e3, "batched_ms": bat * 1e3,
             "batched_targets_x_densities_per_s": work / bat}
 
@@ -342,9 +388,12 @@ def _poisson(reqs, qps: float, seed: int = 7):
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--requests", type=int, default=24, help="measured requests per arrival rate")
+    ap.add_argument("--warmup-requests", type=int, default=0,
+                    help="requests served first at each rate and left out of its figures")
     ap.add_argument("--max-nodes", type=int, default=32768)
     ap.add_argument("--qps-fracs", default="0.5,0.8,0.95")
+    ap.add_argument("--fifo-frac", type=float, default=0.8)
     ap.add_argument("--hbm-gib", type=float, default=64.0)
     ap.add_argument("--batched", action="store_true",
                     help="only the batched workload (256 geometries, 4 densities, eps 1e-10 and 1e-6)")
@@ -357,26 +406,31 @@ def main(argv=None) -> int:
         print(json.dumps(out), flush=True)
         return 0
     budget = args.hbm_gib * 2 ** 30
+    nw, n = args.warmup_requests, args.requests
+    stream = lambda: make_requests(nw + n, nodes=(1024, args.max_nodes))
     # warm-up: library, kernels, one small request each way
     w = make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2))
     fifo(ctx, w)
     serve(ctx, make_requests(2, seed=99, nodes=(1024, 2048), matvecs=(2, 2)), budget)
-    reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
+    reqs = stream()
     for r in reqs:
         r.arrival = 0.0
     closed = serve(ctx, reqs, budget)                  # all at once: saturation rate
-    sat_qps = args.requests / closed["wall_s"]
-    reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
-    _poisson(reqs, 0.8 * sat_qps)
-    out = {"workload": f"{args.requests} star requests, {1024}-{args.max_nodes} nodes, omega U[1,200], "
-                       "eps in {1e-6 (FP32 far field), 1e-10}, 20-60 chained matvecs",
-           "batch": batch_vs_sequential(ctx),
-           "saturation_qps": sat_qps, "closed_loop": closed,
-           "fifo_at_0.8": fifo(ctx, reqs), "served": {}}
+    sat_qps = (nw + n) / closed["wall_s"]
+    print(f"serve: saturation {sat_qps:.2f} requests/s", file=sys.stderr, flush=True)
+    out = {"workload": f"{n} measured star requests after {nw} warm-up ones, 1024-{args.max_nodes} nodes "
+                       "log-uniform, omega U[1,200], eps in {1e-6 (FP32 far field), 1e-10}, 20-60 chained "
+                       "matvecs, Poisson arrivals",
+           "saturation_qps": sat_qps, "closed_loop": closed, "served": {}}
+    reqs = stream()
+    _poisson(reqs, args.fifo_frac * sat_qps)
+    out[f"fifo_at_{args.fifo_frac}"] = measured(fifo(ctx, reqs), reqs, nw)
+    print("serve: fifo done", file=sys.stderr, flush=True)
     for f in [float(x) for x in args.qps_fracs.split(",")]:
-        reqs = make_requests(args.requests, nodes=(1024, args.max_nodes))
+        reqs = stream()
         _poisson(reqs, f * sat_qps)
-        out["served"][str(f)] = serve(ctx, reqs, budget)
+        out["served"][str(f)] = measured(serve(ctx, reqs, budget), reqs, nw)
+        print(f"serve: {f} x saturation done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     return 0

@@ -280,6 +280,68 @@ def test_cfie_gmres_point_source(ctx):
     assert dsig < 1e-8
 
 
+def test_krylov_kernels_match_numpy(ctx):
+    """The GMRES building blocks against numpy: Gram-Schmidt coefficients,
+    the update, the normalisation (rows with a leading dimension larger
+    than their length), and the panel interpolation."""
+    r = np.random.default_rng(71)
+    k, n, ld = 37, 5003, 5011
+    Vh = inputs.complex_gaussian(r, (k, ld))
+    wh = inputs.complex_gaussian(r, (n,))
+    hh = inputs.complex_gaussian(r, (k,))
+    V = _dev(Vh)[:, :n]
+    w, h, out = _dev(wh), _dev(hh), torch.empty(k, dtype=torch.complex128, device="cuda")
+    ctx.krylov_dot(V, k, w, out)
+    ref = Vh[:, :n].conj() @ wh
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    ctx.krylov_update(V, k, h, w)
+    ref = wh - hh @ Vh[:, :n]
+    assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    nr = torch.empty(1, dtype=torch.complex128, device="cuda")
+    ctx.krylov_dot(w.view(1, n), 1, w, nr)
+    ctx.krylov_normalize(w, nr, w)
+    assert abs(np.linalg.norm(w.cpu().numpy()) - 1.0) < 1e-13
+    from paper_1602_05301_amd import solve
+    L = solve.gl_interp(16, 64)
+    x = inputs.complex_gaussian(r, (40 * 16,))
+    ys = torch.empty(40 * 64, dtype=torch.complex128, device="cuda")
+    yd = torch.empty_like(ys)
+    ctx.upsample(_dev(L), 16, 64, _dev(x), alpha=2.5j, ys=ys, yd=yd)
+    ref = (x.reshape(40, 16) @ L.T).ravel()
+    assert np.max(np.abs(yd.cpu().numpy() - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert np.max(np.abs(ys.cpu().numpy() - 2.5j * ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_cfie_gmres_on_device(ctx):
+    """GMRES with the Krylov basis on the device (qbx_krylov_*) and the
+    interpolation to the oversampled sources on the device (qbx_upsample)
+    solves the point-source problem of test_cfie_gmres_point_source: the
+    field outside matches H0(omega |x - x0|), and the density matches the
+    host GMRES on the same GPU matvec."""
+    from scipy.special import hankel1
+    from paper_1602_05301_amd import solve
+    omega, p, eps = 10.0, 14, 1e-10
+    g = inputs.star(40, 16, lobes=5, amp=0.2)
+    fine = inputs.star(40, 64, lobes=5, amp=0.2)
+    x0 = np.array([0.1, 0.05])
+    hank = lambda x, y: hankel1(0, omega * np.hypot(x - x0[0], y - x0[1]))
+    f = hank(g.sx, g.sy)
+    A = solve.CFIEDevice(ctx, g, omega, eps, p, fine=fine)
+    sig_d, info = solve.gmres_device(ctx, A, _dev(f), tol=1e-9, restart=100, maxiter=300)
+    sig_d = sig_d.cpu().numpy()
+    Ah = solve.CFIE(ctx, g, omega, eps, p, fine=fine)
+    sig_h, info_h = solve.gmres(Ah, f, tol=1e-9, restart=100, maxiter=300)
+    dsig = np.linalg.norm(sig_d - sig_h) / np.linalg.norm(sig_h)
+    rng = np.random.default_rng(4)
+    tx, ty = inputs.annulus_targets(rng, 300, 1.3, 2.0)
+    u = solve.field(ctx, g, omega, eps, p, sig_d, tx, ty, fine=fine)
+    err = np.max(np.abs(u - hank(tx, ty))) / np.max(np.abs(hank(tx, ty)))
+    print(f"device GMRES: {info['iterations']} iterations (host {info_h['iterations']}), residual "
+          f"{info['residual']:.2e}; density vs host GMRES {dsig:.2e}; field error {err:.2e}", flush=True)
+    assert info["converged"] and abs(info["iterations"] - info_h["iterations"]) <= 1
+    assert dsig < 1e-8 and err < 1e-8
+
+
 @pytest.mark.parametrize("direct", [True, False])
 def test_two_sided_limits_on_circle(ctx, direct):
     """Centres on both sides (side preference, Sec. 6.1) give both one-sided
@@ -517,7 +579,7 @@ def test_served_requests_equal_alone(ctx):
     alone = serve.make_requests(6, seed=5, nodes=(512, 4096), matvecs=(3, 5))
     serve.fifo(ctx, alone, keep_outputs=True)
     for r, a in zip(reqs, alone):
-        assert len(r.outputs) == len(a.outputs) == len(r.densities)
+        assert len(r.outputs) == len(a.outputs) == r.n_matvec
         for x, y in zip(r.outputs, a.outputs):
             assert np.array_equal(x, y), r.rid
     # served results against the oracle: first and last matvec of each request
@@ -525,8 +587,8 @@ def test_served_requests_equal_alone(ctx):
     for r in reqs:
         g = r.geom
         pick = np.sort(rng.choice(g.n, 48, replace=False))
-        for k in (0, len(r.densities) - 1):
-            d = r.densities[k][None]
+        for k in (0, r.n_matvec - 1):
+            d = r.density(k)[None]
             ref = _oracle_at_nodes(g, r.omega, r.p, d, d, pick)
             _assert_fmm(r.outputs[k][None, pick], ref, r.eps, f"served request {r.rid} matvec {k}")
 
