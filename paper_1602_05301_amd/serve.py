@@ -126,12 +126,19 @@ def _plan(req: Request):
     return pl, float(pl.bytes(1))
 
 
-def fifo(ctx, reqs, keep_outputs: bool = False) -> dict:
+def _progress(every, done, total, what):
+    if every and (done % every == 0 or done == total):
+        print(f"serve: {what} {done}/{total} requests done", file=sys.stderr, flush=True)
+
+
+def fifo(ctx, reqs, keep_outputs: bool = False, progress: int = 0) -> dict:
     """Plain per-request path: setup, then every matvec with qbx_eval, one
-    request after another, each request starting at max(arrival, previous done)."""
+    request after another, each request starting at max(arrival, previous done).
+    progress > 0: a line on stderr every that many finished requests."""
     import torch
     t0 = time.perf_counter()
-    for r in sorted(reqs, key=lambda r: r.arrival):
+    for i, r in enumerate(sorted(reqs, key=lambda r: r.arrival)):
+        _progress(progress, i, len(reqs), "fifo")
         now = time.perf_counter() - t0
         if now < r.arrival:
             time.sleep(r.arrival - now)
@@ -180,7 +187,7 @@ class _Active:
 
 
 def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int = 4,
-          keep_outputs: bool = False) -> dict:
+          keep_outputs: bool = False, progress: int = 0) -> dict:
     """Continuous batching (see the module docstring).  Arrived requests are
     planned on the host (tree, lists, orders) and their device footprint is
     taken from the plan (qbx_plan_bytes), so admission never allocates
@@ -241,6 +248,7 @@ def serve(ctx, reqs, hbm_budget: float, max_batch: int = 32, setup_threads: int 
                         finished += 1
                         a.geo = None             # frees the resident geometry
                         a.req.release()
+                        _progress(progress, finished, len(reqs), "served")
                     else:
                         keep.append(a)
                 # round robin: the requests just served go behind those that waited
@@ -415,7 +423,7 @@ def main(argv=None) -> int:
     reqs = stream()
     for r in reqs:
         r.arrival = 0.0
-    closed = serve(ctx, reqs, budget)                  # all at once: saturation rate
+    closed = serve(ctx, reqs, budget, progress=100)    # all at once: saturation rate
     sat_qps = (nw + n) / closed["wall_s"]
     print(f"serve: saturation {sat_qps:.2f} requests/s", file=sys.stderr, flush=True)
     out = {"workload": f"{n} measured star requests after {nw} warm-up ones, 1024-{args.max_nodes} nodes "
@@ -424,12 +432,12 @@ def main(argv=None) -> int:
            "saturation_qps": sat_qps, "closed_loop": closed, "served": {}}
     reqs = stream()
     _poisson(reqs, args.fifo_frac * sat_qps)
-    out[f"fifo_at_{args.fifo_frac}"] = measured(fifo(ctx, reqs), reqs, nw)
+    out[f"fifo_at_{args.fifo_frac}"] = measured(fifo(ctx, reqs, progress=100), reqs, nw)
     print("serve: fifo done", file=sys.stderr, flush=True)
     for f in [float(x) for x in args.qps_fracs.split(",")]:
         reqs = stream()
         _poisson(reqs, f * sat_qps)
-        out["served"][str(f)] = measured(serve(ctx, reqs, budget), reqs, nw)
+        out["served"][str(f)] = measured(serve(ctx, reqs, budget, progress=100), reqs, nw)
         print(f"serve: {f} x saturation done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
