@@ -22,15 +22,28 @@
  * Conventions for every entry point
  * ---------------------------------
  * - All functions are extern "C", never throw, and return a qbx_status.  On
- *   failure qbx_last_error() returns a message for the calling thread.
+ *   failure qbx_last_error() returns a message for the calling thread, and
+ *   qbx_ctx_last_error(ctx) the message of the last failed call on a context.
+ * - Evaluations (qbx_eval, qbx_eval_noalloc, qbx_eval_batch,
+ *   qbx_geom_autotune), qbx_krylov_dot and qbx_ctx_set_stream use the
+ *   context's streams, events and buffers, so one thread at a time may be
+ *   inside one of them: such a call made while another thread is inside one
+ *   on the same context returns QBX_E_BUSY and does nothing.  Geometry
+ *   creation and destruction, area queries and the other calls may run from
+ *   other threads alongside (a server builds geometries on worker threads
+ *   while it evaluates others).
  * - Geometry arrays (qbx_plan_create, qbx_geom_create) are HOST pointers to
  *   float64 arrays; the library copies what it needs.  The caller keeps
  *   ownership.
- * - Density, potential and coefficient arrays of qbx_eval are DEVICE
- *   pointers (HBM of the context's device) to complex128 data, i.e.
- *   interleaved (re, im) float64.  They are read and written asynchronously
+ * - Density, potential and coefficient arrays of the evaluation calls are
+ *   complex128 data, i.e. interleaved (re, im) float64.  Where each lives is
+ *   found with hipPointerGetAttributes.  Device memory of the context's
+ *   device (or managed memory) is read and written in place, asynchronously
  *   on the context's stream; the caller synchronises that stream before
- *   reading the results on the host.
+ *   reading the results on the host.  qbx_eval also takes host memory
+ *   (pageable or pinned): it copies those arrays through buffers of its own
+ *   and returns once the results are back in host memory.  The other
+ *   evaluation calls refuse host memory with QBX_E_INVAL.
  * - Indices are 0-based; counts are int64_t.
  */
 #ifndef QBXFMM_H
@@ -43,7 +56,7 @@
 extern "C" {
 #endif
 
-#define QBX_ABI_VERSION 2
+#define QBX_ABI_VERSION 3
 
 typedef enum {
     QBX_OK = 0,
@@ -51,7 +64,8 @@ typedef enum {
     QBX_E_NOMEM = -2,        /* host or device allocation failed */
     QBX_E_DEVICE = -3,       /* a HIP call failed (no device, launch error) */
     QBX_E_ASSOC = -4,        /* a target in Gamma_near has no eligible centre (Sec. 6.1) */
-    QBX_E_UNSUPPORTED = -5   /* valid request outside what the library implements */
+    QBX_E_UNSUPPORTED = -5,  /* valid request outside what the library implements */
+    QBX_E_BUSY = -6          /* the context is inside a call made by another thread */
 } qbx_status;
 
 typedef struct qbx_ctx_s *qbx_ctx;    /* device + stream */
@@ -76,6 +90,11 @@ typedef struct {
                              that touch differ by at most one level (2:1 balance, the
                              level-restricted trees of the paper's experiments, Sec. 8);
                              0 = the plain adaptive tree of Stage 1 */
+    int32_t keep_x_rows;  /* 1 (default) = keep the X-list P2L basis rows (Stage 6; one
+                             row of 2 P_b + 3 values per source of each X-list box,
+                             geometry only) in device memory from the first evaluation
+                             on, when they take at most 1 GiB; 0 = rebuild them inside
+                             every evaluation (less memory, a slower X-list stage) */
     double eps_assoc;     /* association slack epsilon_assoc (Sec. 6.1); default 0.05 */
 } qbx_options;
 
@@ -97,6 +116,11 @@ enum { QBX_LIST_U = 0, QBX_LIST_V = 1, QBX_LIST_W = 2, QBX_LIST_X = 3 };
 
 int32_t qbx_abi_version(void);
 const char *qbx_last_error(void);
+
+/* The message of the last call on ctx (or on one of its geometries) that
+ * failed, "" if none has; the text stays valid until the calling thread
+ * calls this again.  ctx NULL gives "". */
+const char *qbx_ctx_last_error(qbx_ctx ctx);
 void qbx_options_default(qbx_options *opt);
 
 /* ---- context ------------------------------------------------------------

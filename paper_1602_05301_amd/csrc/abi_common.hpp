@@ -14,5 +14,8 @@ struct qbx_plan_s {
 namespace qbx {
 void set_error(const std::string &msg);
 qbx_status fail(qbx_status st, const std::string &msg);
+// the calling thread's last message and a count of the messages it has set
+std::string error_msg();
+unsigned long long error_seq();
 void fill_stats(const Plan &pl, qbx_stats *out);
 }  // namespace qbx

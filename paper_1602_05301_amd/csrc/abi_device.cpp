@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "abi_common.hpp"
@@ -85,9 +86,83 @@ struct qbx_ctx_s {
     // workspace of qbx_krylov_dot (partial sums), grown on demand
     cd *kw = nullptr;
     size_t kw_cap = 0;
+    // the thread inside a call on this context (nested calls of that thread
+    // count in depth), and the message of the last failed call
+    std::atomic<std::thread::id> owner{};
+    int depth = 0;
+    std::mutex err_mu;
+    std::string err;
 };
 
 namespace {
+
+void ctx_release(qbx_ctx_s *ctx);
+
+// One call on a context.  It holds a reference, so a context dropped inside
+// it (its last geometry destroyed) lives until the call returns, and a
+// message the call sets becomes the context's last error.  An exclusive call
+// (evaluations and what else uses the context's streams, events and
+// buffers) admits one thread at a time: a second thread that enters while
+// another is inside one gets QBX_E_BUSY.  Geometry set-up, area queries and
+// the plain kernels of GMRES touch none of that state and run alongside.
+class CtxCall {
+public:
+    CtxCall(qbx_ctx_s *c, bool exclusive) : c_(c), seq_(error_seq())
+    {
+        if (exclusive) {
+            std::thread::id me = std::this_thread::get_id(), none{};
+            if (c_->owner.load() == me) {
+                ++c_->depth;
+                excl_ = true;
+            } else if (c_->owner.compare_exchange_strong(none, me)) {
+                c_->depth = 1;
+                excl_ = true;
+            } else {
+                return;
+            }
+        }
+        ok_ = true;
+        ++c_->refs;
+    }
+    ~CtxCall()
+    {
+        if (!ok_) return;
+        if (error_seq() != seq_) {
+            std::lock_guard<std::mutex> lk(c_->err_mu);
+            c_->err = error_msg();
+        }
+        if (excl_ && --c_->depth == 0) c_->owner.store(std::thread::id{});
+        ctx_release(c_);
+    }
+    bool ok() const { return ok_; }
+    CtxCall(const CtxCall &) = delete;
+    CtxCall &operator=(const CtxCall &) = delete;
+
+private:
+    qbx_ctx_s *c_;
+    unsigned long long seq_;
+    bool ok_ = false, excl_ = false;
+};
+
+#define QBX_CTX_CALL(c) CtxCall ctx_call_(c, false)
+#define QBX_CTX_EXCLUSIVE(c)                                                               \
+    CtxCall ctx_call_(c, true);                                                            \
+    if (!ctx_call_.ok()) return fail(QBX_E_BUSY, "the context is inside a call from another thread")
+
+// Whether a caller's array is memory the context's device reads in place
+// (its own device memory, or managed memory).  Host memory, pinned or not,
+// is not: qbx_eval stages it, the other entry points refuse it.
+bool device_readable(const void *p, int device)
+{
+    if (!p) return true;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();            // unregistered host memory
+        return false;
+    }
+    if (a.type == hipMemoryTypeManaged || a.type == hipMemoryTypeUnified) return true;
+    return a.type == hipMemoryTypeDevice && a.device == device;
+}
 
 bool lane_create(QbxLane &L)
 {
@@ -107,6 +182,9 @@ void lane_destroy(QbxLane &L)
 }
 
 constexpr int kDensChunk = 4;   // densities per pass through the pipeline
+// The X-list P2L basis is kept when it takes at most this much device memory
+// (else its rows are rebuilt in every evaluation).
+constexpr size_t kXBasisCap = size_t(1) << 30;
 constexpr int kM2LTileCols = 16; // columns per M2L tile (one MFMA column block)
 
 // Device memory of one geometry.  The resident part is built in two passes
@@ -238,8 +316,13 @@ struct qbx_geom_s {
     DeviceArena scratch;
     cd *qs = nullptr, *qd = nullptr, *mp = nullptr, *loc = nullptr, *coef = nullptr;
     // radial sequences: J_n per P2M source and per L2QBXL centre (n-major)
+    // geometry-only sequences, resident: the P2M and X-list P2L bases (in
+    // the view g) and J_n(omega |m_b - c|) per L2QBXL centre (n-major),
+    // built on the first evaluation
     int srad_rows = 0, crad_rows = 0;
-    double *srad = nullptr, *crad = nullptr;
+    cd *sbas = nullptr, *xbas = nullptr;
+    double *crad = nullptr;
+    int n_xpos = 0;                 // flattened X-list positions
     // the radial sequences depend on the geometry only: computed on the
     // first evaluation (once the scratch exists) and kept, like the tables
     bool rad_ready = false;
@@ -318,6 +401,7 @@ qbx_status upload(qbx_geom_s *G)
     DeviceArena &ar = G->arena;
     DevGeom &g = G->g;
     int nb = pl.n_boxes();
+    long long xbas_total = 0;     // entries of the cached X-list basis
     g.ns = (int)pl.ns; g.nc = (int)pl.nc; g.nt = (int)pl.nt; g.nb = nb; g.nlev = pl.nlev;
     g.p = pl.p; g.omega = pl.omega;
     g.max_leaf_ctr = 1;
@@ -673,6 +757,21 @@ qbx_status upload(qbx_geom_s *G)
         }
         g.xsrc_start = ar.upload(xs0);
         g.xsrc_idx = ar.upload(xidx);
+        // the cached X-list basis: per position its box and the start of its
+        // row of 2 P_b + 3 entries (a box's positions are consecutive rows)
+        std::vector<int32_t> xbox(std::max<size_t>(xidx.size(), 1), -1);
+        std::vector<long long> xoff(std::max<size_t>(xidx.size(), 1), 0);
+        for (size_t i = 0; i + 1 < xs0.size(); ++i) {
+            int b = xorder[i];
+            for (int q = xs0[i]; q < xs0[i + 1]; ++q) {
+                xbox[q] = b;
+                xoff[q] = xbas_total;
+                xbas_total += 2 * pl.P[pl.lev[b]] + 3;
+            }
+        }
+        G->n_xpos = (int)xidx.size();
+        g.xsrc_box = ar.upload(xbox);
+        g.xbas_off = ar.upload(xoff);
         // the leaf (level >= 2) of every source and of every centre, else -1
         std::vector<int32_t> sbox(std::max<int64_t>(pl.ns, 1), -1), cbox(std::max<int64_t>(pl.nc, 1), -1);
         for (int b = 0; b < nb; ++b) {
@@ -715,6 +814,15 @@ qbx_status upload(qbx_geom_s *G)
 
     G->srad_rows = G->p2m.Pmax + 2;
     G->crad_rows = G->l2q.Pmax + pl.p + 8;
+    if (!pl.opt.direct) {
+        g.srow = G->srad_rows;
+        G->sbas = (cd *)ar.alloc(sizeof(cd) * (size_t)G->srad_rows * std::max<int64_t>(pl.ns, 1));
+        G->crad = (double *)ar.alloc(sizeof(double) * (size_t)G->crad_rows * std::max<int64_t>(pl.nc, 1));
+        g.sbas = G->sbas;
+        bool keep = pl.opt.keep_x_rows && xbas_total > 0 && xbas_total * sizeof(cd) <= kXBasisCap;
+        G->xbas = keep ? (cd *)ar.alloc(sizeof(cd) * xbas_total) : nullptr;
+        g.xbas = G->xbas;
+    }
     G->d_self = ar.upload(std::vector<DevGeom>{g});
     if (ar.err != hipSuccess) return fail(ar.err == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                                           std::string("device upload failed: ") + hipGetErrorString(ar.err));
@@ -723,8 +831,8 @@ qbx_status upload(qbx_geom_s *G)
 
 // Bytes of each evaluation buffer for chunks of c densities.
 struct ScratchPlan {
-    size_t qs, qd, coef, mp, loc, vy, wy, srad, crad;
-    size_t total() const { return qs + qd + coef + mp + loc + vy + wy + srad + crad; }
+    size_t qs, qd, coef, mp, loc, vy, wy;
+    size_t total() const { return qs + qd + coef + mp + loc + vy + wy; }
 };
 
 ScratchPlan scratch_plan(const qbx_geom_s *G, int c)
@@ -739,8 +847,6 @@ ScratchPlan scratch_plan(const qbx_geom_s *G, int c)
         sp.mp = sp.loc = cdb * c * at1(G->total_coef);
         sp.vy = cdb * c * at1(G->total_vy);
         sp.wy = cdb * c * at1(G->total_wy);
-        sp.srad = sizeof(double) * (size_t)(G->p2m.Pmax + 2) * at1(pl.ns);
-        sp.crad = sizeof(double) * (size_t)(G->l2q.Pmax + pl.p + 8) * at1(pl.nc);
     }
     return sp;
 }
@@ -762,15 +868,12 @@ qbx_status ensure_scratch(qbx_geom_s *G)
         G->loc = (cd *)s.alloc(sp.loc);
         G->vy = (cd *)s.alloc(sp.vy);
         G->wy = (cd *)s.alloc(sp.wy);
-        G->srad = (double *)s.alloc(sp.srad);
-        G->crad = (double *)s.alloc(sp.crad);
     }
     if (s.err != hipSuccess) {
         hipError_t e = s.err;
         s.release();
         s.err = hipSuccess;
         G->qs = G->qd = G->coef = G->mp = G->loc = G->vy = G->wy = nullptr;
-        G->srad = G->crad = nullptr;
         return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
                     std::string("scratch allocation failed: ") + hipGetErrorString(e));
     }
@@ -890,15 +993,13 @@ qbx_status harvest(qbx_geom_s *G)
 // own scratch, or parts of a caller-provided region (qbx_eval_noalloc).
 struct EvalBufs {
     cd *qs, *qd, *mp, *loc, *coef, *vy, *wy;
-    double *srad, *crad;
-    bool *rad_ready;            // srad / crad hold the geometry's radial sequences
     const EvalBufs *sub;        // the order-0 geometry's buffers (null: its own)
     bool timing;                // per-stage events, every stage in order on one stream
 };
 
 EvalBufs own_bufs(qbx_geom_s *G)
 {
-    return {G->qs, G->qd, G->mp, G->loc, G->coef, G->vy, G->wy, G->srad, G->crad, &G->rad_ready, nullptr,
+    return {G->qs, G->qd, G->mp, G->loc, G->coef, G->vy, G->wy, nullptr,
             G->profile};
 }
 
@@ -939,16 +1040,24 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         if (conc) {
             CHK(hipEventRecord(C->ev_fork, st));
             CHK(hipStreamWaitEvent(s1, C->ev_fork, 0));
-            if (!(*B.rad_ready)) CHK(launch_ctr_rad(g, G->l2q.n, B.crad, G->crad_rows, s1));
+            if (!G->rad_ready) {
+                CHK(launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, s1));
+                CHK(launch_x_bas(g, G->n_xpos, G->xbas, s1));
+            }
             CHK(launch_fill_zero(B.loc, (long long)nd * G->total_coef, s1));
             CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, s1));
-            CHK(hipEventRecord(C->ev_x, s1));
+            if (G->n_wpairs > 0) CHK(hipEventRecord(C->ev_x, s1));
             CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, s1));
+            // Without M2QBXL work one event marks the end of the side stream
+            // and the caller's stream waits for it once, before L2L: each
+            // event costs the waiting stream a few microseconds, and the near
+            // field is done long before the downward pass.
+            if (G->n_wpairs == 0) CHK(hipEventRecord(C->ev_q, s1));
         }
         {
             STAGE(QBX_STAGE_P2M);
-            if (!(*B.rad_ready)) LAUNCH(QBX_STAGE_P2M, pl.ns, launch_src_rad(g, B.srad, G->srad_rows, st));
-            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, B.qs, B.qd, B.srad, G->srad_rows, B.mp, st));
+            if (!G->rad_ready) LAUNCH(QBX_STAGE_P2M, pl.ns, launch_src_bas(g, G->sbas, st));
+            LAUNCH(QBX_STAGE_P2M, G->p2m.n, launch_p2m(g, nd, G->p2m.d, G->p2m.n, G->p2m.Pmax, B.qs, B.qd, B.mp, st));
         }
         {
             STAGE(QBX_STAGE_M2M);
@@ -958,7 +1067,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
                 LAUNCH(QBX_STAGE_M2M, nt, launch_m2m_mfma(g, nd, l, G->m2m_tiles[nd] + t0, nt, nrb, G->d_par_list, B.mp, st));
             }
         }
-        if (conc) {
+        if (conc && G->n_wpairs > 0) {
             // multipoles complete: M2QBXL joins the side stream after the near field
             CHK(hipEventRecord(C->ev_m, st));
             CHK(hipStreamWaitEvent(s1, C->ev_m, 0));
@@ -973,9 +1082,10 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
                                    B.mp, B.vy, st));
         }
         if (conc) {
-            CHK(hipStreamWaitEvent(st, C->ev_x, 0));
+            CHK(hipStreamWaitEvent(st, G->n_wpairs > 0 ? C->ev_x : C->ev_q, 0));
         } else {
             STAGE(QBX_STAGE_P2L_X);
+            if (!G->rad_ready) LAUNCH(QBX_STAGE_P2L_X, G->n_xpos, launch_x_bas(g, G->n_xpos, G->xbas, st));
             LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, st));
         }
         {
@@ -993,7 +1103,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             }
         }
         if (conc) {
-            CHK(hipStreamWaitEvent(st, C->ev_q, 0));
+            if (G->n_wpairs > 0) CHK(hipStreamWaitEvent(st, C->ev_q, 0));
         } else {
             {
                 STAGE(QBX_STAGE_P2QBXL);
@@ -1006,13 +1116,13 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         }
         {
             STAGE(QBX_STAGE_L2QBXL);
-            if (!conc && !(*B.rad_ready)) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, B.crad, G->crad_rows, st));
-            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, B.crad, G->crad_rows, B.loc, B.coef, st));
+            if (!conc && !G->rad_ready) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
+            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, B.loc, B.coef, st));
         }
         // both radial sequences are enqueued ahead of every later evaluation
         // on this geometry (P2M and L2QBXL of later calls follow them in
         // stream order)
-        (*B.rad_ready) = true;
+        G->rad_ready = true;
     }
     {
         STAGE(QBX_STAGE_EVAL);
@@ -1168,13 +1278,19 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
     auto v_ctr_rad = [&]() {
         return over([](const BItem &b, FItem &it) {
             it.r.i0 = b.G->crad_rows; it.r.out0 = b.G->crad; it.n = b.G->l2q.n;
-            return it.n > 0;
+            return it.n > 0 && !b.G->rad_ready;
         });
     };
     auto v_fill = [&]() {
         return over([](const BItem &b, FItem &it) {
             it.r.out0 = b.G->loc; it.n = (long long)b.nd * b.G->total_coef;
             return true;
+        });
+    };
+    auto v_x_bas = [&]() {
+        return over([](const BItem &b, FItem &it) {
+            it.r.out0 = b.G->xbas; it.r.n64 = b.G->n_xpos; it.n = b.G->n_xpos;
+            return it.n > 0 && b.G->xbas && !b.G->rad_ready;
         });
     };
     auto v_p2l_x = [&]() {
@@ -1216,17 +1332,18 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
             wait(1, L.ev_fork);
             QQ(stage(FK_CTR_RAD, v_ctr_rad(), 1));
             QQ(stage(FK_FILL, v_fill(), 1));
+            QQ(stage(FK_X_BAS, v_x_bas(), 1));
             QQ(stage(FK_P2L_X, v_p2l_x(), 1));
             record(L.ev_x, 1);
             QQ(stage(FK_P2QBXL, v_p2qbxl(), 1));
         }
-        QQ(stage(FK_SRC_RAD, over([](const BItem &b, FItem &it) {
-                     it.r.i0 = b.G->srad_rows; it.r.out0 = b.G->srad; it.n = b.G->p2m.n;
-                     return it.n > 0;
+        QQ(stage(FK_SRC_BAS, over([](const BItem &b, FItem &it) {
+                     it.r.out0 = b.G->sbas; it.n = b.G->p2m.n;
+                     return it.n > 0 && !b.G->rad_ready;
                  }), 0));
         QQ(stage(FK_P2M, over([](const BItem &b, FItem &it) {
                      const qbx_geom_s *G = b.G;
-                     it.r.in0 = G->p2m.d; it.r.in1 = G->qs; it.r.in2 = G->qd; it.r.in3 = G->srad; it.r.out0 = G->mp;
+                     it.r.in0 = G->p2m.d; it.r.in1 = G->qs; it.r.in2 = G->qd; it.r.out0 = G->mp;
                      it.n = G->p2m.n; it.P = G->p2m.Pmax;
                      return it.n > 0;
                  }), 0));
@@ -1256,6 +1373,7 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
             wait(0, L.ev_x);
         } else {
             QQ(stage(FK_FILL, v_fill(), 0));
+            QQ(stage(FK_X_BAS, v_x_bas(), 0));
             QQ(stage(FK_P2L_X, v_p2l_x(), 0));
         }
         QQ(stage(FK_DOWN, over([](const BItem &b, FItem &it) {
@@ -1392,9 +1510,22 @@ qbx_status qbx_ctx_create(int32_t device, void *stream, qbx_ctx *out)
     return QBX_OK;
 }
 
+const char *qbx_ctx_last_error(qbx_ctx ctx)
+{
+    static thread_local std::string copy;
+    if (!ctx) {
+        copy.clear();
+        return copy.c_str();
+    }
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    copy = ctx->err;
+    return copy.c_str();
+}
+
 qbx_status qbx_ctx_set_stream(qbx_ctx ctx, void *stream)
 {
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_EXCLUSIVE(ctx);
     ctx->stream = static_cast<hipStream_t>(stream);
     return QBX_OK;
 }
@@ -1547,6 +1678,7 @@ qbx_status build_device(qbx_geom_s *G)
 qbx_status qbx_geom_from_plan(qbx_ctx ctx, qbx_plan plan, qbx_geom *out)
 {
     if (!ctx || !plan || !out) return fail(QBX_E_INVAL, "null argument");
+    QBX_CTX_CALL(ctx);
     *out = nullptr;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -1579,6 +1711,7 @@ qbx_status qbx_geom_create(qbx_ctx ctx, double omega, double eps, const qbx_opti
     if (!out) return fail(QBX_E_INVAL, "out is NULL");
     *out = nullptr;
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_CALL(ctx);
     qbx_plan plan = nullptr;
     qbx_status st = qbx_plan_create(omega, eps, opt, n_src, sx, sy, w, nx, ny, sh, n_ctr, cx, cy,
                                     cr, n_tgt, tx, ty, tgt_ctr, &plan);
@@ -1591,6 +1724,7 @@ qbx_status qbx_geom_create(qbx_ctx ctx, double omega, double eps, const qbx_opti
 qbx_status qbx_geom_destroy(qbx_geom G)
 {
     if (!G) return QBX_OK;
+    QBX_CTX_CALL(G->ctx);
     (void)hipSetDevice(G->ctx->device);
     if (G->ctx->stream) (void)hipStreamSynchronize(G->ctx->stream);
     else (void)hipDeviceSynchronize();
@@ -1664,6 +1798,7 @@ qbx_status qbx_geom_association(qbx_geom G, int32_t *tgt_ctr_out)
 qbx_status qbx_geom_profile(qbx_geom G, int32_t enable)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_CALL(G->ctx);
     G->profile = enable != 0;
     return QBX_OK;
 }
@@ -1671,6 +1806,7 @@ qbx_status qbx_geom_profile(qbx_geom G, int32_t enable)
 qbx_status qbx_geom_stage_times(qbx_geom G, double *ms, int64_t *launches, int32_t reset)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_CALL(G->ctx);
     qbx_status st = harvest(G);
     if (st != QBX_OK) return st;
     for (int s = 0; s < QBX_N_STAGES; ++s) {
@@ -1768,15 +1904,83 @@ qbx_status graph_for(qbx_geom_s *G, int32_t n_dens, const void *sigma_s, const v
     return QBX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// qbx_eval with some arrays in host memory: those are copied through device
+// buffers of the call's own on the context's stream, and the call returns
+// once the results are back in host memory (the device-memory form returns
+// at once).  The copies cross PCIe: for repeated evaluations keep the arrays
+// in device memory.
+qbx_status eval_staged(qbx_geom_s *G, int n_dens, const void *sigma_s, const void *sigma_d, void *u, void *coef)
+{
+    const Plan &pl = G->pl;
+    const int dev = G->ctx->device;
+    hipStream_t st = G->ctx->stream;
+    const size_t nq = 2 * (size_t)pl.p + 1;
+    struct Arg {
+        const void *host_in;   // copied in before the evaluation
+        void *host_out;        // copied out after it
+        size_t bytes;
+        void *dev = nullptr;
+    };
+    Arg a[4] = {{sigma_s, nullptr, sigma_s ? sizeof(cd) * (size_t)n_dens * pl.ns : 0},
+                {sigma_d, nullptr, sigma_d ? sizeof(cd) * (size_t)n_dens * pl.ns : 0},
+                {nullptr, u, u ? sizeof(cd) * (size_t)n_dens * pl.nt : 0},
+                {nullptr, coef, coef ? sizeof(cd) * (size_t)n_dens * nq * pl.nc : 0}};
+    const void *where[4] = {sigma_s, sigma_d, u, coef};
+    auto cleanup = [&]() {
+        for (Arg &x : a)
+            if (x.dev) (void)hipFree(x.dev);
+    };
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        if (!where[i] || a[i].bytes == 0 || device_readable(where[i], dev)) {
+            a[i].host_in = nullptr;
+            a[i].host_out = nullptr;
+            continue;
+        }
+        e = hipMalloc(&a[i].dev, a[i].bytes);
+        if (e == hipSuccess && a[i].host_in)
+            e = hipMemcpyAsync(a[i].dev, a[i].host_in, a[i].bytes, hipMemcpyHostToDevice, st);
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(e == hipErrorOutOfMemory ? QBX_E_NOMEM : QBX_E_DEVICE,
+                    std::string("staging host arrays: ") + hipGetErrorString(e));
+    }
+    auto pick = [&](int i) { return a[i].dev ? a[i].dev : const_cast<void *>(where[i]); };
+    qbx_status q = ensure_scratch(G);
+    if (q == QBX_OK) q = eval_chunks(G, n_dens, pick(0), pick(1), pick(2), pick(3), st, G->ctx->lane);
+    for (int i = 2; i < 4 && q == QBX_OK && e == hipSuccess; ++i)
+        if (a[i].dev) e = hipMemcpyAsync(a[i].host_out, a[i].dev, a[i].bytes, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    cleanup();
+    if (q != QBX_OK) return q;
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("staged evaluation: ") + hipGetErrorString(e));
+    return QBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 qbx_status qbx_eval(qbx_geom G, int32_t n_dens, const void *sigma_s, const void *sigma_d, void *u,
                     void *coef)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_EXCLUSIVE(G->ctx);
     if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
     if (!u && G->pl.nt) return fail(QBX_E_INVAL, "u is NULL");
     if (!sigma_s && !sigma_d) return fail(QBX_E_INVAL, "both densities are NULL");
     hipError_t e = hipSetDevice(G->ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    const int dev = G->ctx->device;
+    if (!device_readable(sigma_s, dev) || !device_readable(sigma_d, dev) || !device_readable(u, dev) ||
+        !device_readable(coef, dev))
+        return eval_staged(G, n_dens, sigma_s, sigma_d, u, coef);
     qbx_status st = ensure_scratch(G);
     if (st != QBX_OK) return st;
     const qbx_ctx_s *C = G->ctx;
@@ -1805,8 +2009,7 @@ namespace {
 // Evaluation buffers of G (and of its order-0 geometry) for chunks of c
 // densities, laid out from `base` at 256-byte boundaries.  Returns the end
 // offset; with base null only sizes are computed.
-size_t carve_bufs(const qbx_geom_s *G, int c, unsigned char *base, size_t off, EvalBufs *B, EvalBufs *Bsub,
-                  bool *rad, bool *rad_sub)
+size_t carve_bufs(const qbx_geom_s *G, int c, unsigned char *base, size_t off, EvalBufs *B, EvalBufs *Bsub)
 {
     ScratchPlan sp = scratch_plan(G, c);
     auto take = [&](size_t n) {
@@ -1822,13 +2025,10 @@ size_t carve_bufs(const qbx_geom_s *G, int c, unsigned char *base, size_t off, E
     B->loc = (cd *)take(sp.loc);
     B->vy = (cd *)take(sp.vy);
     B->wy = (cd *)take(sp.wy);
-    B->srad = (double *)take(sp.srad);
-    B->crad = (double *)take(sp.crad);
-    B->rad_ready = rad;
     B->timing = false;
     B->sub = nullptr;
     if (G->sub) {
-        off = carve_bufs(G->sub, c, base, off, Bsub, nullptr, rad_sub, nullptr);
+        off = carve_bufs(G->sub, c, base, off, Bsub, nullptr);
         B->sub = Bsub;
     }
     return off;
@@ -1840,28 +2040,31 @@ qbx_status qbx_eval_noalloc(qbx_geom G, int32_t n_dens, const void *sigma_s, con
                             void *coef)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_EXCLUSIVE(G->ctx);
     if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
     if (!u && G->pl.nt) return fail(QBX_E_INVAL, "u is NULL");
     if (!sigma_s && !sigma_d) return fail(QBX_E_INVAL, "both densities are NULL");
     const qbx_ctx_s *C = G->ctx;
     hipError_t e = hipSetDevice(C->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    if (!device_readable(sigma_s, C->device) || !device_readable(sigma_d, C->device) ||
+        !device_readable(u, C->device) || !device_readable(coef, C->device))
+        return fail(QBX_E_INVAL, "qbx_eval_noalloc: every array must be device memory of the context's device");
     unsigned char *base = noalloc_base(C->device, &e);
     if (!base) return fail(QBX_E_DEVICE, std::string("static evaluation buffers: ") + hipGetErrorString(e));
     // the largest chunk of densities whose buffers fit the static array
     EvalBufs B{}, Bs{};
-    bool rad = false, rad_sub = false;
     int c = std::min<int>(kDensChunk, n_dens);
     for (; c >= 1; --c)
-        if (carve_bufs(G, c, nullptr, 0, &B, &Bs, &rad, &rad_sub) <= (size_t)QBX_NOALLOC_SCRATCH_BYTES) break;
+        if (carve_bufs(G, c, nullptr, 0, &B, &Bs) <= (size_t)QBX_NOALLOC_SCRATCH_BYTES) break;
     if (c < 1) {
-        size_t need = carve_bufs(G, 1, nullptr, 0, &B, &Bs, &rad, &rad_sub);
+        size_t need = carve_bufs(G, 1, nullptr, 0, &B, &Bs);
         return fail(QBX_E_UNSUPPORTED, "qbx_eval_noalloc: the geometry needs " + std::to_string(need) +
                                            " bytes of evaluation buffers for one density, more than the " +
                                            std::to_string((size_t)QBX_NOALLOC_SCRATCH_BYTES) +
                                            " of the static array; use qbx_eval");
     }
-    carve_bufs(G, c, base, 0, &B, &Bs, &rad, &rad_sub);
+    carve_bufs(G, c, base, 0, &B, &Bs);
     const Plan &pl = G->pl;
     long long nq = 2 * pl.p + 1;
     for (int d0 = 0; d0 < n_dens; d0 += c) {
@@ -1880,6 +2083,7 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
                           const void *const *sigma_s, const void *const *sigma_d, void *const *u)
 {
     if (!ctx || n_geom < 0 || (n_geom && (!geoms || !n_dens || !u))) return fail(QBX_E_INVAL, "invalid argument");
+    QBX_CTX_EXCLUSIVE(ctx);
     if (n_geom == 0) return QBX_OK;
     for (int i = 0; i < n_geom; ++i) {
         qbx_geom G = geoms[i];
@@ -1891,6 +2095,11 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     auto dens = [&](const void *const *a, int i) { return a ? a[i] : nullptr; };
+    for (int i = 0; i < n_geom; ++i)
+        if (!device_readable(dens(sigma_s, i), ctx->device) || !device_readable(dens(sigma_d, i), ctx->device) ||
+            !device_readable(u[i], ctx->device))
+            return fail(QBX_E_INVAL, "qbx_eval_batch: entry " + std::to_string(i) +
+                                         " has an array outside the context's device memory");
     bool serial = !ctx->fz_copied;
     for (int i = 0; i < n_geom; ++i) serial = serial || geoms[i]->profile || geoms[i]->graph_on;
     if (serial) {
@@ -1953,6 +2162,11 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
         case FOp::WAIT: CHK(hipStreamWaitEvent(s, op.ev, 0)); break;
         }
     }
+    // the geometry-only sequences of every geometry in the batch are now
+    // enqueued ahead of any later evaluation
+    for (const auto &P : passes)
+        for (const auto &b : P)
+            if (!b.G->pl.opt.direct) b.G->rad_ready = true;
     CHK(hipEventRecord(ctx->fz_done, st));
     return QBX_OK;
 }
@@ -1960,6 +2174,7 @@ qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, co
 qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_EXCLUSIVE(G->ctx);
     if (n_dens < 1 || n_dens > 64) return fail(QBX_E_INVAL, "n_dens must lie in 1..64");
     hipError_t e = hipSetDevice(G->ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -2034,6 +2249,7 @@ qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
 qbx_status qbx_geom_graph(qbx_geom G, int32_t enable)
 {
     if (!G) return fail(QBX_E_INVAL, "null geometry");
+    QBX_CTX_CALL(G->ctx);
     if (!G->ctx->gstream) return fail(QBX_E_UNSUPPORTED, "graph stream unavailable");
     G->graph_on = enable != 0;
     return QBX_OK;
@@ -2107,6 +2323,7 @@ qbx_status qbx_geom_area_query(qbx_geom G, int64_t n, const double *qx, const do
                                const double *qr, int64_t *start, int32_t *leaves, int64_t *total_out)
 {
     if (!G || n < 0 || !start || (n > 0 && (!qx || !qy || !qr))) return fail(QBX_E_INVAL, "area query: bad argument");
+    QBX_CTX_CALL(G->ctx);
     hipError_t e = hipSetDevice(G->ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     hipStream_t s = G->ctx->stream;
@@ -2133,6 +2350,7 @@ qbx_status qbx_geom_points_near(qbx_geom G, int32_t which, int64_t n, const doub
 {
     if (!G || n < 0 || (which != 0 && which != 1) || (n > 0 && (!qx || !qy || !qr || !hit_out)))
         return fail(QBX_E_INVAL, "points_near: bad argument");
+    QBX_CTX_CALL(G->ctx);
     hipError_t e = hipSetDevice(G->ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     hipStream_t s = G->ctx->stream;
@@ -2151,6 +2369,7 @@ qbx_status qbx_geom_associate(qbx_geom G, int64_t n_tgt, const double *tx, const
                               int32_t *tgt_ctr_out, int64_t *n_fail_out)
 {
     if (!G || n_tgt < 0 || (n_tgt > 0 && (!tx || !ty || !tgt_ctr_out))) return fail(QBX_E_INVAL, "associate: bad argument");
+    QBX_CTX_CALL(G->ctx);
     hipError_t e = hipSetDevice(G->ctx->device);
     if (e != hipSuccess) return fail(QBX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     hipStream_t s = G->ctx->stream;
@@ -2224,6 +2443,7 @@ qbx_status qbx_geom_associate(qbx_geom G, int64_t n_tgt, const double *tx, const
 qbx_status qbx_krylov_dot(qbx_ctx ctx, int64_t n, int32_t k, const void *V, int64_t ldv, const void *w, void *h)
 {
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_EXCLUSIVE(ctx);
     if (n < 0 || k < 0 || ldv < n) return fail(QBX_E_INVAL, "qbx_krylov_dot: need n >= 0, k >= 0, ldv >= n");
     if (k == 0) return QBX_OK;
     if (!h || (n > 0 && (!V || !w))) return fail(QBX_E_INVAL, "qbx_krylov_dot: null array");
@@ -2252,6 +2472,7 @@ qbx_status qbx_krylov_update(qbx_ctx ctx, int64_t n, int32_t k, const void *V, i
                              void *w)
 {
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_CALL(ctx);
     if (n < 0 || k < 0 || ldv < n) return fail(QBX_E_INVAL, "qbx_krylov_update: need n >= 0, k >= 0, ldv >= n");
     if (n == 0 || k == 0) return QBX_OK;
     if (!V || !h || !w) return fail(QBX_E_INVAL, "qbx_krylov_update: null array");
@@ -2264,6 +2485,7 @@ qbx_status qbx_krylov_update(qbx_ctx ctx, int64_t n, int32_t k, const void *V, i
 qbx_status qbx_krylov_normalize(qbx_ctx ctx, int64_t n, const void *w, const void *nrm2, void *v)
 {
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_CALL(ctx);
     if (n < 0) return fail(QBX_E_INVAL, "qbx_krylov_normalize: n < 0");
     if (n == 0) return QBX_OK;
     if (!w || !nrm2 || !v) return fail(QBX_E_INVAL, "qbx_krylov_normalize: null array");
@@ -2277,6 +2499,7 @@ qbx_status qbx_upsample(qbx_ctx ctx, int64_t n_panels, int32_t q, int32_t qs, co
                         double alpha_im, const void *x, void *ys, void *yd)
 {
     if (!ctx) return fail(QBX_E_INVAL, "null context");
+    QBX_CTX_CALL(ctx);
     if (n_panels < 0 || q < 1 || qs < 1) return fail(QBX_E_INVAL, "qbx_upsample: need n_panels >= 0, q, qs >= 1");
     if (n_panels == 0) return QBX_OK;
     if (!L || !x || (!ys && !yd)) return fail(QBX_E_INVAL, "qbx_upsample: null array");

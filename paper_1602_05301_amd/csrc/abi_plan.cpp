@@ -8,8 +8,17 @@
 namespace qbx {
 
 static thread_local std::string g_last_error;
+static thread_local unsigned long long g_error_seq = 0;
 
-void set_error(const std::string &msg) { g_last_error = msg; }
+void set_error(const std::string &msg)
+{
+    g_last_error = msg;
+    ++g_error_seq;
+}
+
+std::string error_msg() { return g_last_error; }
+
+unsigned long long error_seq() { return g_error_seq; }
 
 qbx_status fail(qbx_status st, const std::string &msg)
 {
@@ -75,6 +84,7 @@ void qbx_options_default(qbx_options *opt)
     opt->far_fp32 = 0;
     opt->w_direct = -1;
     opt->level_restrict = 1;
+    opt->keep_x_rows = 1;
     opt->eps_assoc = 0.05;
 }
 

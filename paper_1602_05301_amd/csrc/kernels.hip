@@ -60,33 +60,43 @@ constexpr int QBLK = 8;       // l values per lane; the planner keeps P_l >= p +
 // ---------------------------------------------------------------------------
 // Radial sequences, one lane per source / centre (so every lane does a
 // whole recurrence), written n-major: element n of item i at rad[n * count + i].
-//   k_src_rad: J_n(omega |s - m_b|), n = 0..P_b+1, s in a leaf b of level >= 2
+//   (k_src_bas, P2M's basis, is built the same way, below)
 //   k_ctr_rad: J_n(omega |m_b - c|), n = 0..P_b+p+7, c in such a leaf
 // Miller's recurrence rewrites earlier values when it rescales and
 // normalises at the end, so it runs in LDS ([rows][lanes]) and each lane
 // then copies its own column out.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void src_rad_body(const DevGeom &g, int rows, double *rad, BlockId bid)
+__device__ __forceinline__ void src_bas_body(const DevGeom &g, cd *bas, BlockId bid)
 {
     extern __shared__ double lds_raw[];
     int lanes = blockDim.x;
     int s = bid.x * lanes + threadIdx.x;
-    int N = -1;
-    if (s < g.ns) {
-        int b = g.src_box[s];
-        if (b >= 0) {
-            N = g.Plev[g.blev[b]] + 1;
-            double dx = g.sx[s] - g.bcx[b], dy = g.sy[s] - g.bcy[b];
-            besselj_seq(g.omega * sqrt(dx * dx + dy * dy), N, lds_raw + threadIdx.x, lanes);
+    if (s >= g.ns) return;
+    int b = g.src_box[s];
+    if (b < 0) return;
+    int N = g.Plev[g.blev[b]] + 1;
+    double dx = g.sx[s] - g.bcx[b], dy = g.sy[s] - g.bcy[b];
+    double r = sqrt(dx * dx + dy * dy);
+    double *J = lds_raw + threadIdx.x;
+    besselj_seq(g.omega * r, N, J, lanes);
+    // L_n = J_n(x) conj(v)^n, the phase from one sincos per run of orders
+    double th = r > 0.0 ? atan2(dy, dx) : 0.0;
+    cd v = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
+    cd *row = bas + (long long)s * g.srow;
+    for (int n0 = 0; n0 <= N; n0 += 8) {
+        double sn, cs;
+        sincos((double)n0 * th, &sn, &cs);
+        cd ph = mk(cs, -sn);
+        for (int n = n0; n < n0 + 8 && n <= N; ++n) {
+            row[n] = J[n * lanes] * ph;
+            ph = ph * conj(v);
         }
     }
-    (void)rows;
-    for (int n = 0; n <= N; ++n) rad[(long long)n * g.ns + s] = lds_raw[n * lanes + threadIdx.x];
 }
 
-__global__ void k_src_rad(DevGeom g, int rows, double *rad)
+__global__ void k_src_bas(DevGeom g, cd *bas)
 {
-    src_rad_body(g, rows, rad, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+    src_bas_body(g, bas, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 __device__ __forceinline__ void ctr_rad_body(const DevGeom &g, int rows, double *rad, BlockId bid)
@@ -150,13 +160,23 @@ size_t ptab_lds_bytes(int nd, int P, int ch)
 // L_n(z) = J_n(x) conj(v)^n with z = (x/omega) v, |v| = 1, and
 // L_{-n} = (-1)^n J_n v^n.
 // ---------------------------------------------------------------------------
-// P2M keeps only the orders n = 0..P+1 of a row (J_n is real, so
-// L_{-n} = (-1)^n conj(L_n)): rows of P+2 entries, twice the sources per pass.
-size_t p2m_lds_bytes(int nd, int P, int ch)
-{
-    return (size_t)ch * (((size_t)P + 2) * sizeof(cd) + 3 * (size_t)nd * sizeof(cd) + sizeof(cd) +
-                         3 * sizeof(double));
-}
+// P2M reads each source's row of orders n = 0..P+1 (J_n is real, so
+// L_{-n} = (-1)^n conj(L_n)) from the rows k_src_bas keeps with the
+// geometry.  One wave per (box, run of 64 orders k >= 0): lane k sums the
+// box's sources in order for the orders k and -k, which need the same three
+// row entries (L_{-n} = (-1)^n conj(L_n)), read straight from those rows
+// (neighbouring lanes read neighbouring entries); only the sources' weights,
+// a pass of P2M_CH at a time, go through LDS.  The grid has boxes x runs of
+// orders, enough waves to cover the loads' latency.
+constexpr int P2M_CH = 64;
+constexpr int BATCH = 8;      // sources whose basis loads are in flight together
+
+size_t p2m_lds_bytes(int nd) { return (size_t)P2M_CH * 3 * (size_t)nd * sizeof(cd); }
+
+int order_runs(int Pmax) { return (2 * Pmax + 1 + 63) / 64; }
+
+// P2M lanes take the orders k and -k together: runs of 64 over k = 0..P.
+int half_order_runs(int Pmax) { return (Pmax + 1 + 63) / 64; }
 
 // u^k for a unit complex u and any integer k (u^{-1} = conj(u)) by binary
 // powering, at most 2 log2|k| products.  Where a lane needs one phase per
@@ -175,43 +195,53 @@ __device__ __forceinline__ cd unit_ipow(cd u, int k)
     return r;
 }
 
-__device__ __forceinline__ cd p2m_basis(const cd *row, int m)
-{
-    if (m >= 0) return row[m];
-    cd c = conj(row[-m]);
-    return (m & 1) ? neg(c) : c;
-}
+// L_m from the row entry v = L_|m| (L_{-n} = (-1)^n conj(L_n)): f = 0 for
+// m >= 0, 1 for even m < 0 (conjugate), 2 for odd m < 0 (minus the
+// conjugate).  Sign changes only, so exact.
+__device__ __forceinline__ cd bfix(cd v, int f) { return mk(f == 2 ? -v.x : v.x, f == 1 ? -v.y : v.y); }
 
 template <int ND>
-__device__ __forceinline__ void p2m_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, const double *srad, cd *mp, int CH, BlockId bid)
+__device__ __forceinline__ void p2m_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, cd *mp, BlockId bid)
 {
     extern __shared__ double lds_raw[];
+    cd *Wt = reinterpret_cast<cd *>(lds_raw);           // [P2M_CH][ND][3]
     int b = list[bid.x];
     int l = g.blev[b];
-    int P = g.Plev[l], np = 2 * P + 1, NT = P + 2;
-    cd *T = reinterpret_cast<cd *>(lds_raw);           // [CH][NT], order n at row[n]
-    cd *Wt = T + CH * NT;                              // [CH][ND][3]
-    cd *V = Wt + CH * ND * 3;                          // [CH]
-    double *TH = reinterpret_cast<double *>(V + CH);   // [CH]
-    int tid = threadIdx.x;
-    double mx = g.bcx[b], my = g.bcy[b], hw = 0.5 * g.omega;
+    int P = g.Plev[l], np = 2 * P + 1;
+    if (bid.y * 64 > P) return;                         // uniform: a run past this box's orders
+    // lane k forms orders k and -k from the same three row entries
+    int tid = threadIdx.x, k = bid.y * 64 + tid;
+    bool active = k <= P;
+    double hw = 0.5 * g.omega;
     const double *iw = g.invW + g.Woff[l];
     cd *out = mp + g.box_off[b] * ND;
     int s_begin = g.src_begin[b], s_end = g.src_end[b];
-    if (s_begin == s_end) {                             // leaf without sources
-        for (int i = tid; i < ND * np; i += blockDim.x) out[i] = mk(0.0, 0.0);
-        return;
-    }
-    int nseg = (P + 2 + PT_SEG - 1) / PT_SEG;
-    for (int s0 = s_begin; s0 < s_end; s0 += CH) {
-        int cnt = min(CH, s_end - s0);
+    // entries a = L_|k-1| (L_1 when k = 0), b = L_k, c = L_{k+1}; then
+    //   order k:   L_{k-1} = a (k >= 1) or -conj(a) (k = 0), L_k = b, L_{k+1} = c
+    //   order -k:  L_{-k-1}, L_{-k}, L_{-k+1} from c, b, a by bfix (a as is for k = 1)
+    int ia = k == 0 ? 1 : k - 1;
+    int fa = k == 0 ? 2 : 0;
+    int fc_n = (k + 1) & 1 ? 2 : 1, fb_n = k & 1 ? 2 : 1, fa_n = k == 1 ? 0 : ((k - 1) & 1 ? 2 : 1);
+    cd accp[ND], accn[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) accp[d] = accn[d] = mk(0.0, 0.0);
+    auto add = [&](cd ea, cd eb, cd ec, const cd *w) {
+        cd lm = bfix(ea, fa), mm = bfix(ec, fc_n), m0 = bfix(eb, fb_n), mp_ = bfix(ea, fa_n);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            cfma(accp[d], w[3 * d], eb);
+            cfma(accp[d], w[3 * d + 1], lm);
+            cfma(accp[d], w[3 * d + 2], ec);
+            cfma(accn[d], w[3 * d], m0);
+            cfma(accn[d], w[3 * d + 1], mm);
+            cfma(accn[d], w[3 * d + 2], mp_);
+        }
+    };
+    for (int s0 = s_begin; s0 < s_end; s0 += P2M_CH) {
+        int cnt = min(P2M_CH, s_end - s0);
         __syncthreads();
         if (tid < cnt) {
             int j = s0 + tid;
-            double dx = g.sx[j] - mx, dy = g.sy[j] - my;
-            double r = sqrt(dx * dx + dy * dy);
-            V[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
-            TH[tid] = r > 0.0 ? atan2(dy, dx) : 0.0;
             cd nu = mk(g.snx[j], g.sny[j]);
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
@@ -223,52 +253,45 @@ __device__ __forceinline__ void p2m_body(const DevGeom &g, const int *list, cons
             }
         }
         __syncthreads();
-        for (int it = tid; it < cnt * nseg; it += blockDim.x) {
-            int t = it % cnt, n0 = (it / cnt) * PT_SEG;
-            cd v = V[t];
-            double sn, cs;
-            sincos((double)n0 * TH[t], &sn, &cs);
-            cd ph = mk(cs, -sn);                       // conj(v)^n
-            cd *row = T + t * NT;
-            const double *jr = srad + s0 + t;
-            for (int n = n0; n < n0 + PT_SEG && n <= P + 1; ++n) {
-                row[n] = jr[(long long)n * g.ns] * ph;
-                ph = ph * conj(v);
+        if (active) {
+            // the sources of a box are consecutive, so are their rows.  The
+            // entries of BATCH sources are loaded before any is used, so a
+            // lane waits for memory once per batch, not once per source.
+            const cd *rows = g.sbas + (long long)s0 * g.srow;
+            int t = 0;
+            for (; t + BATCH <= cnt; t += BATCH) {
+                cd E[BATCH][3];
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u) {
+                    const cd *row = rows + (long long)(t + u) * g.srow;
+                    E[u][0] = row[ia];
+                    E[u][1] = row[k];
+                    E[u][2] = row[k + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u) add(E[u][0], E[u][1], E[u][2], Wt + (t + u) * ND * 3);
+            }
+            for (; t < cnt; ++t) {
+                const cd *row = rows + (long long)t * g.srow;
+                add(row[ia], row[k], row[k + 1], Wt + t * ND * 3);
             }
         }
-        __syncthreads();
-        bool first = s0 == s_begin;
-        for (int kk = tid; kk < np; kk += blockDim.x) {
-            int k = kk - P;
-            cd acc[ND];
+    }
+    if (active) {
+        // a leaf without sources gets a zero expansion
+        double f = iw[k];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) acc[d] = mk(0.0, 0.0);
-            for (int t = 0; t < cnt; ++t) {
-                const cd *row = T + t * NT;
-                cd lm = p2m_basis(row, k - 1), l0 = p2m_basis(row, k), lp = p2m_basis(row, k + 1);
-                const cd *w = Wt + t * ND * 3;
-#pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    cfma(acc[d], w[3 * d], l0);
-                    cfma(acc[d], w[3 * d + 1], lm);
-                    cfma(acc[d], w[3 * d + 2], lp);
-                }
-            }
-            double f = iw[k < 0 ? -k : k];
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                cd v = mk(f * acc[d].x, f * acc[d].y);
-                if (!first) v = out[d * np + kk] + v;
-                out[d * np + kk] = v;
-            }
+        for (int d = 0; d < ND; ++d) {
+            out[d * np + P + k] = mk(f * accp[d].x, f * accp[d].y);
+            if (k > 0) out[d * np + P - k] = mk(f * accn[d].x, f * accn[d].y);
         }
     }
 }
 
 template <int ND>
-__global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd, const double *srad, cd *mp, int CH)
+__global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd *qs, const cd *qd, cd *mp)
 {
-    p2m_body<ND>(g, list, qs, qd, srad, mp, CH, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+    p2m_body<ND>(g, list, qs, qd, mp, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -832,6 +855,48 @@ __global__ void __launch_bounds__(64 * L2L_KS) k_l2l_mfma32(DevGeom g, int nd, i
 // sources of all X-list boxes of b are taken in list order (flattened on
 // the host).
 // ---------------------------------------------------------------------------
+// The X-list P2L row of flattened X-list position q, as p2l_x_body builds
+// it in LDS when it is not cached: S_n O_n(s - m_b), n = -(P+1)..P+1, at
+// xbas[xbas_off[q] + P + 1 + n].  One lane per position.
+__device__ __forceinline__ void x_bas_body(const DevGeom &g, int nx, cd *xbas, BlockId bid)
+{
+    int q = bid.x * blockDim.x + threadIdx.x;
+    if (q >= nx) return;
+    int b = g.xsrc_box[q], j = g.xsrc_idx[q];
+    int l = g.blev[b];
+    int P = g.Plev[l];
+    const double *Wl = g.Wtab + g.Woff[l], *iWl = g.invW + g.Woff[l], *lWl = g.logW + g.Woff[l];
+    double dx = g.sx[j] - g.bcx[b], dy = g.sy[j] - g.bcy[b];
+    double r = sqrt(dx * dx + dy * dy);
+    double x = g.omega * r;
+    double tau = fmin(1.0, 0.5 * x);
+    cd *row = xbas + g.xbas_off[q] + P + 1;
+    scaled_hankel_seq(x, tau, P + 1, row, 1);
+    cd v = mk(dx / r, dy / r);
+    double th = atan2(dy, dx), lt = log(tau), itau = 1.0 / tau;
+    for (int n0 = 0; n0 <= P + 1; n0 += PT_SEG) {
+        double sn, cs;
+        sincos((double)n0 * th, &sn, &cs);
+        cd ph = mk(cs, sn);                            // v^n
+        double sc = exp(lWl[min(n0, P)] - n0 * lt);    // S_n tau^{-n}
+        for (int n = n0; n < n0 + PT_SEG && n <= P + 1; ++n) {
+            cd e = sc * row[n];
+            row[n] = e * ph;
+            if (n > 0) {
+                cd m = e * conj(ph);
+                row[-n] = (n & 1) ? neg(m) : m;
+            }
+            ph = ph * v;
+            sc *= (Wl[min(n + 1, P)] * iWl[min(n, P)]) * itau;
+        }
+    }
+}
+
+__global__ void k_x_bas(DevGeom g, int nx, cd *xbas)
+{
+    x_bas_body(g, nx, xbas, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 template <int ND>
 __device__ __forceinline__ void p2l_x_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, cd *loc, int CH, BlockId bid)
 {
@@ -935,6 +1000,106 @@ template <int ND>
 __global__ void __launch_bounds__(64) k_p2l_x(DevGeom g, const int *list, const cd *qs, const cd *qd, cd *loc, int CH)
 {
     p2l_x_body<ND>(g, list, qs, qd, loc, CH, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
+// X-list P2L from the rows kept with the geometry (x_bas_body): one wave per
+// (box, run of 64 output orders), as P2M.  Lane kk reads its three entries of
+// each position's row straight from memory (neighbouring lanes, neighbouring
+// entries); the weights of a pass of XC_CH positions go through LDS.  Sums
+// run over the box's positions in list order and are scaled once at the end.
+constexpr int XC_CH = 64;
+
+size_t p2l_xc_lds_bytes(int nd) { return (size_t)XC_CH * 3 * (size_t)nd * sizeof(cd); }
+
+template <int ND>
+__device__ __forceinline__ void p2l_xc_body(const DevGeom &g, const int *list, const cd *qs, const cd *qd, cd *loc, BlockId bid)
+{
+    extern __shared__ double lds_raw[];
+    cd *Wt = reinterpret_cast<cd *>(lds_raw);          // [XC_CH][ND][3]
+    int b = list[bid.x];
+    int l = g.blev[b];
+    int P = g.Plev[l], np = 2 * P + 1, NT = 2 * P + 3;
+    if (bid.y * 64 >= np) return;                      // uniform: a run past this box's orders
+    int tid = threadIdx.x, kk = bid.y * 64 + tid;
+    const double *Wl = g.Wtab + g.Woff[l], *iWl = g.invW + g.Woff[l];
+    double hw = 0.5 * g.omega;
+    cd *out = loc + g.box_off[b] * ND;
+    int q0 = g.xsrc_start[bid.x], total = g.xsrc_start[bid.x + 1] - q0;
+    cd acc[3][ND];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[e][d] = mk(0.0, 0.0);
+    for (int f0 = 0; f0 < total; f0 += XC_CH) {
+        int cnt = min(XC_CH, total - f0);
+        __syncthreads();
+        if (tid < cnt) {
+            int j = g.xsrc_idx[q0 + f0 + tid];
+            cd nu = mk(g.snx[j], g.sny[j]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                cd c = qd[(long long)d * g.ns + j];
+                cd *w = Wt + (tid * ND + d) * 3;
+                w[0] = qs[(long long)d * g.ns + j];
+                w[1] = hw * (c * nu);
+                w[2] = neg(hw * (c * conj(nu)));
+            }
+        }
+        __syncthreads();
+        if (kk < np) {
+            // one box's positions are consecutive rows of NT entries; order
+            // l = kk - P sits at entry kk + 1 of a row.  Loads of BATCH
+            // positions go out before any is used (as in P2M).
+            const cd *rows = g.xbas + g.xbas_off[q0 + f0] + kk + 1;
+            int t = 0;
+            for (; t + BATCH <= cnt; t += BATCH) {
+                cd O[BATCH][3];
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u) {
+                    const cd *row = rows + (long long)(t + u) * NT;
+                    O[u][0] = row[-1];
+                    O[u][1] = row[0];
+                    O[u][2] = row[1];
+                }
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u) {
+                    const cd *w = Wt + (t + u) * ND * 3;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        cfma(acc[0][d], w[3 * d], O[u][1]);
+                        cfma(acc[1][d], w[3 * d + 1], O[u][0]);
+                        cfma(acc[2][d], w[3 * d + 2], O[u][2]);
+                    }
+                }
+            }
+            for (; t < cnt; ++t) {
+                const cd *row = rows + (long long)t * NT;
+                cd om = row[-1], o0 = row[0], op = row[1];
+                const cd *w = Wt + t * ND * 3;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    cfma(acc[0][d], w[3 * d], o0);
+                    cfma(acc[1][d], w[3 * d + 1], om);
+                    cfma(acc[2][d], w[3 * d + 2], op);
+                }
+            }
+        }
+    }
+    if (kk < np) {
+        int ell = kk - P, al = ell < 0 ? -ell : ell;
+        int am = ell - 1 < 0 ? 1 - ell : ell - 1, ap = ell + 1 < 0 ? -ell - 1 : ell + 1;
+        double rm = Wl[al] * iWl[min(am, P)], rp = Wl[al] * iWl[min(ap, P)];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            out[d * np + kk] = mk(fma(rp, acc[2][d].x, fma(rm, acc[1][d].x, acc[0][d].x)),
+                                  fma(rp, acc[2][d].y, fma(rm, acc[1][d].y, acc[0][d].y)));
+    }
+}
+
+template <int ND>
+__global__ void __launch_bounds__(64) k_p2l_xc(DevGeom g, const int *list, const cd *qs, const cd *qd, cd *loc)
+{
+    p2l_xc_body<ND>(g, list, qs, qd, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -1679,10 +1844,16 @@ __global__ void kf_charges(const FRec *recs, const int *map)
     charges_body(g, r.nd, CP(const cd *, in0), CP(const cd *, in1), CP(cd *, out0), CP(cd *, out1), bid);
 }
 
-__global__ void kf_src_rad(const FRec *recs, const int *map)
+__global__ void kf_src_bas(const FRec *recs, const int *map)
 {
     FUSED_BEGIN
-    src_rad_body(g, r.i0, CP(double *, out0), bid);
+    src_bas_body(g, CP(cd *, out0), bid);
+}
+
+__global__ void kf_x_bas(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    x_bas_body(g, (int)r.n64, CP(cd *, out0), bid);
 }
 
 __global__ void kf_ctr_rad(const FRec *recs, const int *map)
@@ -1695,8 +1866,7 @@ template <int ND>
 __global__ void __launch_bounds__(64) kf_p2m(const FRec *recs, const int *map)
 {
     FUSED_BEGIN
-    p2m_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(const double *, in3),
-                 CP(cd *, out0), r.i0, bid);
+    p2m_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(cd *, out0), bid);
 }
 
 __global__ void __launch_bounds__(256 * M2M_KS) kf_m2m(const FRec *recs, const int *map)
@@ -1747,6 +1917,13 @@ __global__ void __launch_bounds__(64) kf_p2l_x(const FRec *recs, const int *map)
 {
     FUSED_BEGIN
     p2l_x_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(cd *, out0), r.i0, bid);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(64) kf_p2l_xc(const FRec *recs, const int *map)
+{
+    FUSED_BEGIN
+    p2l_xc_body<ND>(g, CP(const int *, in0), CP(const cd *, in1), CP(const cd *, in2), CP(cd *, out0), bid);
 }
 
 template <int PB>
@@ -1837,31 +2014,36 @@ static int pick_ch(int Pmax)
     return ch;
 }
 
-hipError_t launch_src_rad(const DevGeom &g, double *srad, int srad_rows, hipStream_t s)
+hipError_t launch_src_bas(const DevGeom &g, cd *sbas, hipStream_t s)
 {
     if (!g.ns) return hipSuccess;
-    int lanes = rad_lanes(srad_rows);
-    k_src_rad<<<(g.ns + lanes - 1) / lanes, lanes, (size_t)srad_rows * lanes * sizeof(double), s>>>(
-        g, srad_rows, srad);
+    int lanes = rad_lanes(g.srow);
+    k_src_bas<<<(g.ns + lanes - 1) / lanes, lanes, (size_t)g.srow * lanes * sizeof(double), s>>>(g, sbas);
+    QBX_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_x_bas(const DevGeom &g, int nx, cd *xbas, hipStream_t s)
+{
+    if (nx <= 0 || !xbas) return hipSuccess;    // no kept rows: P2L builds them itself
+    k_x_bas<<<(nx + 63) / 64, 64, 0, s>>>(g, nx, xbas);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, const double *srad, int srad_rows, cd *mp, hipStream_t s)
+                      const cd *qd, cd *mp, hipStream_t s)
 {
     if (!n) return hipSuccess;
     if (nd < 1 || nd > 4) return hipErrorInvalidValue;
-    (void)srad_rows;
-    // sources per pass sized for four densities: the same passes for every nd
-    int ch = 64;
-    while (ch > 1 && p2m_lds_bytes(4, Pmax, ch) > PT_LDS) --ch;
-    size_t lds = p2m_lds_bytes(nd, Pmax, ch);
+    if (!g.sbas) return hipErrorInvalidValue;
+    dim3 grid(n, half_order_runs(Pmax));
+    size_t lds = p2m_lds_bytes(nd);
     switch (nd) {
-    case 1: k_p2m<1><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
-    case 2: k_p2m<2><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
-    case 3: k_p2m<3><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
-    default: k_p2m<4><<<n, 64, lds, s>>>(g, list, qs, qd, srad, mp, ch); break;
+    case 1: k_p2m<1><<<grid, 64, lds, s>>>(g, list, qs, qd, mp); break;
+    case 2: k_p2m<2><<<grid, 64, lds, s>>>(g, list, qs, qd, mp); break;
+    case 3: k_p2m<3><<<grid, 64, lds, s>>>(g, list, qs, qd, mp); break;
+    default: k_p2m<4><<<grid, 64, lds, s>>>(g, list, qs, qd, mp); break;
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
@@ -1924,6 +2106,19 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
 {
     if (!n) return hipSuccess;
     if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+    if (g.xbas) {
+        // rows kept with the geometry (launch_x_bas)
+        dim3 grid(n, order_runs(Pmax));
+        size_t lds = p2l_xc_lds_bytes(nd);
+        switch (nd) {
+        case 1: k_p2l_xc<1><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
+        case 2: k_p2l_xc<2><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
+        case 3: k_p2l_xc<3><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
+        default: k_p2l_xc<4><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
+        }
+        QBX_LAUNCH_CHECK();
+        return hipSuccess;
+    }
     int ch = pick_ch(Pmax);
     size_t lds = ptab_lds_bytes(nd, Pmax, ch);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
@@ -2144,28 +2339,30 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
             add(kind, 0, it.r, b, b, 0, 256);
         }
         break;
-    case FK_SRC_RAD:
+    case FK_SRC_BAS:
     case FK_CTR_RAD: {
         int rmax = 1;
-        for (const auto &it : items) rmax = std::max(rmax, it.r.i0);
+        for (const auto &it : items) rmax = std::max(rmax, kind == FK_SRC_BAS ? it.h->srow : it.r.i0);
         int lanes = rad_lanes(rmax);
         size_t lds = (size_t)rmax * lanes * sizeof(double);
         for (const auto &it : items) {
-            long long cnt = it.n > 0 ? (kind == FK_SRC_RAD ? it.h->ns : it.h->nc) : 0;
+            long long cnt = it.n > 0 ? (kind == FK_SRC_BAS ? it.h->ns : it.h->nc) : 0;
             long long b = (cnt + lanes - 1) / lanes;
             add(kind, 0, it.r, b, b, lds, lanes);
         }
         break;
     }
+    case FK_X_BAS:
+        for (const auto &it : items) {
+            long long b = (it.r.n64 + 63) / 64;
+            add(kind, 0, it.r, b, b, 0, 64);
+        }
+        break;
     case FK_P2M:
         for (const auto &it : items) {
             int nd = it.r.nd;
             if (nd < 1 || nd > 4) return hipErrorInvalidValue;
-            int ch = 64;
-            while (ch > 1 && p2m_lds_bytes(4, it.P, ch) > PT_LDS) --ch;
-            FRec r = it.r;
-            r.i0 = ch;
-            add(kind, nd, r, it.n, it.n, p2m_lds_bytes(nd, it.P, ch), 64);
+            add(kind, nd, it.r, it.n * half_order_runs(it.P), it.n, p2m_lds_bytes(nd), 64);
         }
         break;
     case FK_M2M:
@@ -2201,6 +2398,10 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
         for (const auto &it : items) {
             int nd = it.r.nd;
             if (nd < 1 || nd > 4) return hipErrorInvalidValue;
+            if (it.h->xbas) {
+                add(FK_P2L_XC, nd, it.r, it.n * order_runs(it.P), it.n, p2l_xc_lds_bytes(nd), 64);
+                continue;
+            }
             int ch = pick_ch(it.P);
             size_t lds = ptab_lds_bytes(nd, it.P, ch);
             if (lds > LDS_BUDGET) return hipErrorInvalidValue;
@@ -2295,7 +2496,8 @@ hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t 
     switch (L.kind) {
     case FK_FILL: FL(kf_fill); break;
     case FK_CHARGES: FL(kf_charges); break;
-    case FK_SRC_RAD: FL(kf_src_rad); break;
+    case FK_SRC_BAS: FL(kf_src_bas); break;
+    case FK_X_BAS: FL(kf_x_bas); break;
     case FK_CTR_RAD: FL(kf_ctr_rad); break;
     case FK_P2M:
         switch (L.variant) {
@@ -2312,6 +2514,14 @@ hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t 
     case FK_DOWN: FL(kf_down); break;
     case FK_L2L: FL(kf_l2l); break;
     case FK_L2L32: FL(kf_l2l32); break;
+    case FK_P2L_XC:
+        switch (L.variant) {
+        case 1: FL(kf_p2l_xc<1>); break;
+        case 2: FL(kf_p2l_xc<2>); break;
+        case 3: FL(kf_p2l_xc<3>); break;
+        default: FL(kf_p2l_xc<4>); break;
+        }
+        break;
     case FK_P2L_X:
         switch (L.variant) {
         case 1: FL(kf_p2l_x<1>); break;

@@ -50,6 +50,18 @@ struct DevGeom {
     // X-list sources of the i-th box of the X-list P2L list: xsrc_idx[xsrc_start[i]..]
     const QBX_G int *xsrc_start, *xsrc_idx;
     const QBX_G int *src_box, *ctr_box;              // leaf (level >= 2) of each source / centre, or -1
+    // Geometry-only bases, built on the first evaluation and kept: the P2M
+    // row of every source in a leaf b of level >= 2, L_n(s - m_b) for
+    // n = 0..P_b+1 at sbas[s * srow + n]; the X-list P2L row of every
+    // flattened X-list position q (source xsrc_idx[q] for box xsrc_box[q]),
+    // S_n O_n(s - m_b) for n = -(P_b+1)..P_b+1 at xbas[xbas_off[q] + P_b+1 + n]
+    // (rows of 2 P_b + 3; the positions of one box are consecutive rows).
+    // xbas is null when too large to keep: rows are then built in every
+    // evaluation.
+    const QBX_G cd *sbas, *xbas;
+    const QBX_G int *xsrc_box;
+    const QBX_G long long *xbas_off;
+    int srow;
     const QBX_G int *Plev;                           // FMM order per level
     const QBX_G int *Woff;                           // per level offset into Wtab/invW/logW
     const QBX_G double *Wtab, *invW, *logW;
@@ -124,10 +136,10 @@ struct FRec {
 };
 
 enum FKind {
-    FK_FILL, FK_CHARGES, FK_SRC_RAD, FK_CTR_RAD, FK_P2M, FK_M2M, FK_M2L, FK_DOWN, FK_L2L, FK_P2L_X,
+    FK_FILL, FK_CHARGES, FK_SRC_BAS, FK_X_BAS, FK_CTR_RAD, FK_P2M, FK_M2M, FK_M2L, FK_DOWN, FK_L2L, FK_P2L_X,
     FK_P2QBXL, FK_P2QBXL_DIRECT, FK_M2QBXL, FK_WSUM, FK_L2QBXL, FK_EVAL, FK_SMOOTH,
     // chosen by the planner
-    FK_M2L_DIRECT, FK_M2L32, FK_L2L32
+    FK_M2L_DIRECT, FK_M2L32, FK_L2L32, FK_P2L_XC
 };
 
 // One geometry's part of a stage, as the host describes it.  The record's
@@ -161,10 +173,12 @@ hipError_t fused_launch(const FLaunch &L, const unsigned char *dev, hipStream_t 
 hipError_t launch_fill_zero(cd *p, long long n, hipStream_t s);
 hipError_t launch_charges(const DevGeom &g, int nd, const cd *ss, const cd *sd, cd *qs, cd *qd,
                           hipStream_t s);
-// J_n(omega |s - m_b|) of every source in a leaf of level >= 2 (geometry only)
-hipError_t launch_src_rad(const DevGeom &g, double *srad, int srad_rows, hipStream_t s);
+// The geometry-only bases of P2M (into sbas, g.srow per source) and of the
+// X-list P2L (into xbas, rows at g.xbas_off; nx flattened positions).
+hipError_t launch_src_bas(const DevGeom &g, cd *sbas, hipStream_t s);
+hipError_t launch_x_bas(const DevGeom &g, int nx, cd *xbas, hipStream_t s);
 hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                      const cd *qd, const double *srad, int srad_rows, cd *mp, hipStream_t s);
+                      const cd *qd, cd *mp, hipStream_t s);
 hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
                            int nrb, const int *plist, cd *mp, hipStream_t s);
 // vy = null: the children's V-list rows are already summed into loc

@@ -609,6 +609,7 @@ Error build_plan(Plan &pl, double omega, double eps, const qbx_options &opt, int
     if (opt.p_add < -1 || opt.p_add > 200) return {QBX_E_INVAL, "p_add must be -1 or in 0..200"};
     if (opt.w_direct < -1) return {QBX_E_INVAL, "w_direct must be -1, 0 or a positive source count"};
     if (opt.level_restrict != 0 && opt.level_restrict != 1) return {QBX_E_INVAL, "level_restrict must be 0 or 1"};
+    if (opt.keep_x_rows != 0 && opt.keep_x_rows != 1) return {QBX_E_INVAL, "keep_x_rows must be 0 or 1"};
     if (ns && (!sx || !sy || !w || !nx || !ny || !sh)) return {QBX_E_INVAL, "null source array"};
     if (nc && (!cx || !cy || !cr)) return {QBX_E_INVAL, "null centre array"};
     if (nt && (!tx || !ty)) return {QBX_E_INVAL, "null target array"};

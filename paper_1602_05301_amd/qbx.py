@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqbxfmm.so")
 
 QBX_OK, QBX_E_INVAL, QBX_E_NOMEM, QBX_E_DEVICE, QBX_E_ASSOC, QBX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
-_STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "ASSOC", -5: "UNSUPPORTED"}
+_STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "ASSOC", -5: "UNSUPPORTED", -6: "BUSY"}
 
 # Every symbol declared in include/qbxfmm.h.
 EXPORTS = [
@@ -32,6 +32,7 @@ EXPORTS = [
     "qbx_eval", "qbx_geom_area_query", "qbx_geom_associate", "qbx_geom_points_near",
     "qbx_eval_noalloc", "qbx_plan_bytes",
     "qbx_krylov_dot", "qbx_krylov_update", "qbx_krylov_normalize", "qbx_upsample",
+    "qbx_ctx_last_error",
 ]
 
 STAGES = ["charges", "p2m", "m2m", "m2l", "p2l_x", "l2l", "p2qbxl", "m2qbxl", "l2qbxl",
@@ -48,7 +49,7 @@ class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("p_add", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("direct", ctypes.c_int32), ("far_fp32", ctypes.c_int32),
                 ("w_direct", ctypes.c_int32), ("level_restrict", ctypes.c_int32),
-                ("eps_assoc", ctypes.c_double)]
+                ("keep_x_rows", ctypes.c_int32), ("eps_assoc", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -87,6 +88,8 @@ def lib():
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.qbx_abi_version.restype = i32
     L.qbx_last_error.restype = ctypes.c_char_p
+    L.qbx_ctx_last_error.restype = ctypes.c_char_p
+    L.qbx_ctx_last_error.argtypes = [_vp]
     L.qbx_options_default.argtypes = [ctypes.POINTER(Options)]
     L.qbx_ctx_create.argtypes = [i32, _vp, ctypes.POINTER(_vp)]
     L.qbx_ctx_set_stream.argtypes = [_vp, _vp]
@@ -125,8 +128,8 @@ def lib():
     L.qbx_geom_points_near.argtypes = [_vp, i32, i64, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_options_default", "qbx_geom_bytes",
-                        "qbx_plan_bytes"):
+        if name not in ("qbx_abi_version", "qbx_last_error", "qbx_ctx_last_error", "qbx_options_default",
+                        "qbx_geom_bytes", "qbx_plan_bytes"):
             f.restype = st
     L.qbx_geom_bytes.restype = ctypes.c_size_t
     L.qbx_plan_bytes.restype = ctypes.c_size_t
@@ -140,20 +143,22 @@ def _check(status):
 
 
 def options(p=12, p_add=-1, leaf_max=32, direct=False, eps_assoc=0.05, w_direct=-1,
-            far_fp32=False, level_restrict=True) -> Options:
+            far_fp32=False, level_restrict=True, keep_x_rows=True) -> Options:
     o = Options()
     lib().qbx_options_default(ctypes.byref(o))
     o.p, o.p_add, o.leaf_max, o.direct, o.eps_assoc = int(p), int(p_add), int(leaf_max), int(bool(direct)), float(eps_assoc)
     o.w_direct = int(w_direct)
     o.far_fp32 = int(bool(far_fp32))
     o.level_restrict = int(bool(level_restrict))
+    o.keep_x_rows = int(bool(keep_x_rows))
     return o
 
 
-def _need_c128(t, numel, what, device=None):
-    """Checks a buffer the library reads or writes through a raw device
-    pointer: complex128, contiguous, numel elements, on the CUDA device.
-    Raises ValueError before any library call."""
+def _need_c128(t, numel, what, device=None, host_ok=False):
+    """Checks a buffer the library reads or writes through a raw pointer:
+    complex128, contiguous, numel elements, on the context's CUDA device (or,
+    with host_ok, in host memory, which qbx_eval stages itself).  Raises
+    ValueError before any library call."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise ValueError(f"{what} must be a torch tensor")
@@ -164,6 +169,8 @@ def _need_c128(t, numel, what, device=None):
     if t.numel() != numel:
         raise ValueError(f"{what} must hold {numel} elements, got {t.numel()}")
     if not t.is_cuda:
+        if host_ok and t.device.type == "cpu":
+            return
         raise ValueError(f"{what} must be a CUDA tensor")
     if device is not None and t.device.index != device:
         raise ValueError(f"{what} is on cuda:{t.device.index}, the context on cuda:{device}")
@@ -271,6 +278,10 @@ class Context:
         if getattr(self, "_h", None):
             lib().qbx_ctx_destroy(self._h)
             self._h = None
+
+    def last_error(self) -> str:
+        """Message of the last failed call on this context (qbx_ctx_last_error)."""
+        return lib().qbx_ctx_last_error(self._h).decode()
 
     def set_stream(self, stream):
         """Later work of this context goes to `stream` (a torch CUDA stream)."""
@@ -497,20 +508,22 @@ class Geometry:
         return u
 
     def eval(self, sigma_s, sigma_d, u=None, coef=None):
-        """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); device complex128 tensors."""
+        """u[d, m] = S[sigma_s[d]](t_m) + D[sigma_d[d]](t_m); complex128
+        tensors on the context's device, or CPU tensors (qbx_eval copies
+        those through device buffers and returns once u is filled)."""
         import torch
         nd = _n_dens(sigma_s, sigma_d, self.n_src, "eval")
         dev = (sigma_s if sigma_s is not None else sigma_d).device
         for t, nm in ((sigma_s, "sigma_s"), (sigma_d, "sigma_d")):
             if t is not None:
-                _need_c128(t, nd * self.n_src, nm, self.ctx.device)
+                _need_c128(t, nd * self.n_src, nm, self.ctx.device, host_ok=True)
         if u is None:
             u = torch.empty((nd, self.n_tgt), dtype=torch.complex128, device=dev)
-        _need_c128(u, nd * self.n_tgt, "u", self.ctx.device)
+        _need_c128(u, nd * self.n_tgt, "u", self.ctx.device, host_ok=True)
         if coef is True:
             coef = torch.empty((nd, 2 * self.p + 1, self.n_ctr), dtype=torch.complex128, device=dev)
         if coef is not None and coef is not False:
-            _need_c128(coef, nd * (2 * self.p + 1) * self.n_ctr, "coef", self.ctx.device)
+            _need_c128(coef, nd * (2 * self.p + 1) * self.n_ctr, "coef", self.ctx.device, host_ok=True)
         ptr = lambda t: None if t is None else _vp(t.data_ptr())
         _check(lib().qbx_eval(self._h, nd, ptr(sigma_s), ptr(sigma_d), ptr(u),
                               ptr(coef) if coef is not None and coef is not False else None))

@@ -1,6 +1,7 @@
 """The Python binding checks every buffer before the library sees a raw
 pointer (no GPU): wrong dtype, layout, size or device raise ValueError, and
-no library call is made."""
+no library call is made.  Host tensors are refused everywhere except by
+eval, whose library call stages host arrays itself."""
 import numpy as np
 import pytest
 import torch
@@ -33,7 +34,7 @@ def c128(*shape):
     return torch.zeros(shape, dtype=torch.complex128)
 
 
-@pytest.mark.parametrize("case", ["dtype", "numel", "rows", "noncontig", "none", "cpu",
+@pytest.mark.parametrize("case", ["dtype", "numel", "rows", "noncontig", "none",
                                   "u_numel", "u_dtype", "coef_numel", "too_many"])
 def test_eval_rejects_bad_buffers(no_lib, case):
     g = _fake_geometry(_Ctx())
@@ -56,12 +57,19 @@ def test_eval_rejects_bad_buffers(no_lib, case):
         coef = c128(2, 7, 9)
     elif case == "too_many":
         ss = sd = c128(65, 10)
-    # "cpu": every shape right, but host tensors
     with pytest.raises(ValueError):
         g.eval(ss, sd, u=u, coef=coef)
 
 
-@pytest.mark.parametrize("case", ["count", "foreign", "rows", "u_numel", "dtype"])
+def test_eval_noalloc_rejects_host_tensors(no_lib):
+    # every shape right, but host tensors: the static-buffer path takes
+    # device memory only
+    g = _fake_geometry(_Ctx())
+    with pytest.raises(ValueError):
+        g.eval_noalloc(c128(2, 10), c128(2, 10), c128(2, 7))
+
+
+@pytest.mark.parametrize("case", ["count", "foreign", "rows", "u_numel", "dtype", "cpu"])
 def test_eval_batch_rejects_bad_buffers(no_lib, case):
     ctx = qbx.Context.__new__(qbx.Context)
     ctx._h, ctx.device = None, 0

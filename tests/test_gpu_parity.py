@@ -529,8 +529,9 @@ def test_batch_matches_each_alone(ctx):
 
 def test_batch_mixed_modes_match_alone(ctx):
     """Geometries that need different kernel variants in one batch: FP32 and
-    FP64 far fields, different p, a direct-mode geometry whose off-curve
-    targets partly use the smooth rule, and six densities (two passes).
+    FP64 far fields, different p, X-list rows kept and rebuilt, a direct-mode
+    geometry whose off-curve targets partly use the smooth rule, and six
+    densities (two passes).
     Each result equals the geometry evaluated alone, bit for bit."""
     from paper_1602_05301_amd import qbx
     r = np.random.default_rng(23)
@@ -546,7 +547,7 @@ def test_batch_mixed_modes_match_alone(ctx):
 
     add(inputs.star(80, 16, lobes=4), 70.0, 1e-6, 2, p=9, far_fp32=True)
     add(inputs.star(48, 16, lobes=6), 25.0, 1e-10, 6, p=14)
-    add(inputs.ellipse(64, 16, a=1.0, b=0.4), 40.0, 1e-6, 3, p=9)
+    add(inputs.ellipse(64, 16, a=1.0, b=0.4), 40.0, 1e-6, 3, p=9, keep_x_rows=False)
     gd = inputs.star(24, 16, lobes=5)
     tx_a, ty_a = inputs.annulus_targets(r, 150, 1.4, 2.0)
     j = r.integers(0, gd.n, 100)
@@ -906,3 +907,103 @@ def test_fmm_shallow_trees(ctx, leaf_max, levels):
     err = _rel(u, ref)
     print(f"shallow tree levels={levels}: rel_l2={err:.3e}", flush=True)
     assert err < 1e-12
+
+
+def test_x_rows_kept_and_rebuilt_agree(ctx):
+    """X-list P2L from basis rows kept with the geometry and from rows rebuilt
+    in every evaluation: both meet direct QBX at sampled targets and agree to
+    rounding.  The kept rows are built by whichever schedule runs first: a
+    fresh geometry evaluated in order (stage profiling) and then concurrently
+    gives the same numbers, bit for bit."""
+    from paper_1602_05301_amd import qbx
+    wl = inputs.fmm_star(n_panels=512, omega=50.0, eps=1e-10, p=14, n_dens=2)
+    g = wl.geom
+    ss, sd = _dev(wl.sigma_s), _dev(wl.sigma_d)
+    keep = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    rebuild = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
+                           qbx.options(p=wl.p, keep_x_rows=False))
+    assert keep.bytes() > rebuild.bytes()
+    keep.profile(True)
+    u_in_order = keep.eval(ss, sd).cpu().numpy()
+    keep.profile(False)
+    u_keep = keep.eval(ss, sd).cpu().numpy()
+    u_rebuild = rebuild.eval(ss, sd).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(u_in_order, u_keep)
+    assert _rel(u_rebuild, u_keep) < 1e-13
+    pick = np.sort(np.random.default_rng(71).choice(g.n, 256, replace=False))
+    ref = _oracle_at_nodes(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, pick)
+    for d in range(2):
+        _assert_fmm(u_keep[d, pick], ref[d], wl.eps, f"kept rows, density {d}")
+        _assert_fmm(u_rebuild[d, pick], ref[d], wl.eps, f"rebuilt rows, density {d}")
+
+
+def test_eval_host_arrays_equal_device(ctx):
+    """qbx_eval given host arrays (densities, potentials and coefficients in
+    CPU tensors, or some of them) stages them itself: the results equal those
+    of the device-memory call, bit for bit."""
+    from paper_1602_05301_amd import qbx
+    wl = inputs.fmm_star(n_panels=128, omega=30.0, eps=1e-10, p=12, n_dens=2)
+    g = wl.geom
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    ss, sd = _dev(wl.sigma_s), _dev(wl.sigma_d)
+    u_dev, c_dev = geo.eval(ss, sd, coef=True)
+    torch.cuda.synchronize()
+    hs, hd = torch.from_numpy(wl.sigma_s), torch.from_numpy(wl.sigma_d)
+    u_host, c_host = geo.eval(hs, hd, coef=True)
+    assert u_host.device.type == "cpu" and c_host.device.type == "cpu"
+    assert np.array_equal(u_host.numpy(), u_dev.cpu().numpy())
+    assert np.array_equal(c_host.numpy(), c_dev.cpu().numpy())
+    # densities on the host, potentials on the device
+    u_mixed = torch.empty_like(u_dev)
+    geo.eval(hs, hd, u=u_mixed)
+    torch.cuda.synchronize()
+    assert np.array_equal(u_mixed.cpu().numpy(), u_dev.cpu().numpy())
+
+
+def test_context_refuses_a_second_thread(ctx):
+    """A context serves one thread at a time: while one thread is inside a
+    call (here a host-staged evaluation, which waits for its results), calls
+    on the context from another thread return QBX_E_BUSY and do nothing.
+    Every call either succeeds or is refused, and the context still gives
+    the same results afterwards."""
+    import ctypes
+    import threading
+
+    from paper_1602_05301_amd import qbx
+    own = qbx.Context(0)
+    wl = inputs.fmm_star(n_panels=1024, omega=50.0, eps=1e-10, p=14)
+    g = wl.geom
+    geo = qbx.Geometry(own, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p))
+    hs, hd = torch.from_numpy(wl.sigma_s), torch.from_numpy(wl.sigma_d)
+    ref = geo.eval(hs, hd).numpy()
+    L = qbx.lib()
+    stream = ctypes.c_void_p(own.stream.cuda_stream)
+    other, evals = [], []
+    stop = threading.Event()
+
+    def spin():
+        while not stop.is_set():
+            other.append(L.qbx_ctx_set_stream(own._h, stream))
+
+    t = threading.Thread(target=spin)
+    t.start()
+    try:
+        for _ in range(20):
+            u = torch.empty((1, g.n), dtype=torch.complex128)
+            st = L.qbx_eval(geo._h, 1, ctypes.c_void_p(hs.data_ptr()), ctypes.c_void_p(hd.data_ptr()),
+                            ctypes.c_void_p(u.data_ptr()), None)
+            evals.append((st, u))
+            if -6 in other:
+                break
+    finally:
+        stop.set()
+        t.join()
+    codes = set(other) | {st for st, _ in evals}
+    print(f"set_stream calls {len(other)}, refused {other.count(-6)}; evaluations {len(evals)}", flush=True)
+    assert codes <= {0, -6}, codes
+    assert -6 in codes
+    for st, u in evals:
+        if st == 0:
+            assert np.array_equal(u.numpy(), ref)
+    assert np.array_equal(geo.eval(hs, hd).numpy(), ref)

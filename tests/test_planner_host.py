@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(qbx.EXPORTS) == declared
-    assert L.qbx_abi_version() == 2
+    assert L.qbx_abi_version() == 3
 
 
 def _geometries():
