@@ -110,14 +110,18 @@ def stage_kernel(stage, m2l_choice):
 def m2l_algorithmic_bytes(plan, n_dens, far_fp32=False):
     """HBM bytes M2L must move at the least (Stage 4): each (level, rotation
     orbit) translation matrix read once, the multipole of every V-list source
-    box read once and the V-list sum of every target box written once."""
+    box read once and the V-list sum of every target box written once.
+    `pair_rows` is what this design writes instead of the sums: one row per
+    V-list pair, summed in list order by the downward pass."""
     st = plan.stats()
     bx = plan.boxes()
     P = plan.orders()
     vs, vi = plan.list(1)
     lev, ix, iy = bx["level"], bx["ix"].astype(np.int64), bx["iy"].astype(np.int64)
     groups, srcs, tgts = set(), set(), set()
+    rows = 0
     for b in range(st["n_boxes"]):
+        rows += (vs[b + 1] - vs[b]) * (2 * int(P[lev[b]]) + 1)
         for v in vi[vs[b]:vs[b + 1]]:
             dx, dy, r = int(ix[v] - ix[b]), int(iy[v] - iy[b]), 0
             while not (dx > 0 and dy >= 0):          # quarter turns to the orbit representative
@@ -129,7 +133,7 @@ def m2l_algorithmic_bytes(plan, n_dens, far_fp32=False):
     tab = (8 if far_fp32 else 16) * sum((2 * int(P[l]) + 1) ** 2 for l, _, _ in groups)
     vec = (8 if far_fp32 else 16) * n_dens
     return {"tables": tab, "multipoles": vec * sum(n(b) for b in srcs),
-            "locals": 16 * n_dens * sum(n(b) for b in tgts)}
+            "locals": 16 * n_dens * sum(n(b) for b in tgts), "pair_rows": vec * int(rows)}
 
 
 def measured_traffic(kname):
@@ -305,6 +309,9 @@ def main(argv=None):
     ap.add_argument("--eps", type=float, default=1e-10,
                     help="tolerance (the headline metric is quoted at 1e-10)")
     ap.add_argument("--p", type=int, default=14, help="QBX order")
+    ap.add_argument("--p-add", type=int, default=None,
+                    help="FMM order increment (default: 39, calibrated for the 32768-node star at "
+                         "eps 1e-10, p 14; the library's rule for other eps and p)")
     ap.add_argument("--far-fp32", action="store_true",
                     help="FP32 M2L/L2L (allowed for eps >= 1e-6)")
     ap.add_argument("--graph", action="store_true",
@@ -327,12 +334,17 @@ def main(argv=None):
 
     from paper_1602_05301_amd import inputs, qbx
 
-    wl = inputs.fmm_star(n_dens=args.n_dens, eps=args.eps, p=args.p)
+    p_add = args.p_add
+    if p_add is None:
+        # the increment calibrated for this workload at the headline
+        # tolerance and order; the library's default rule elsewhere
+        p_add = inputs.STAR32K_P_ADD if (args.eps, args.p) == (1e-10, 14) else -1
+    wl = inputs.fmm_star(n_dens=args.n_dens, eps=args.eps, p=args.p, p_add=p_add)
     g = wl.geom
     ctx = qbx.Context(0)
     t0 = time.perf_counter()
     geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
-                       qbx.options(p=wl.p, leaf_max=wl.leaf_max, far_fp32=args.far_fp32))
+                       qbx.options(p=wl.p, p_add=wl.p_add, leaf_max=wl.leaf_max, far_fp32=args.far_fp32))
     setup_s = time.perf_counter() - t0
     st = geo.stats()
     ss = torch.from_numpy(wl.sigma_s).cuda()
@@ -401,16 +413,31 @@ def main(argv=None):
             "launches_per_step": stages[dom][1] / args.steps}
     if dom == "m2l":
         plan = qbx.Plan(g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
-                        qbx.options(p=wl.p, leaf_max=wl.leaf_max, far_fp32=args.far_fp32))
+                        qbx.options(p=wl.p, p_add=wl.p_add, leaf_max=wl.leaf_max, far_fp32=args.far_fp32))
         ab = m2l_algorithmic_bytes(plan, wl.n_dens, args.far_fp32)
-        roof["algorithmic_bytes"] = int(sum(ab.values()))
+        roof["algorithmic_bytes"] = int(ab["tables"] + ab["multipoles"] + ab["locals"])
+        roof["algorithmic_bytes_pair_rows"] = int(ab["tables"] + ab["multipoles"] + ab["pair_rows"])
         roof["algorithmic_bytes_parts"] = ab
+        if traffic:
+            roof["traffic_over_algorithmic"] = traffic / roof["algorithmic_bytes"]
+            roof["traffic_over_algorithmic_pair_rows"] = traffic / roof["algorithmic_bytes_pair_rows"]
 
-    err = None
+    err = err_all = None
     if not args.no_check:
+        got = u.cpu().numpy()
         pick = np.sort(np.random.default_rng(0).choice(g.n, 512, replace=False))
-        rel, mx = _oracle_rel(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, u.cpu().numpy()[:, pick], pick)
+        rel, mx = _oracle_rel(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, got[:, pick], pick)
         err = {"rel_l2": rel, "max": mx, "sample": f"{pick.size} targets x {wl.n_dens} densities"}
+        # every target against the library's direct mode (itself held to the
+        # oracle by the direct-mode parity tests): the FMM's errors gather at
+        # few targets, which a sample sees only in part
+        ref_geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr,
+                               qbx.options(p=wl.p, direct=True))
+        ref = ref_geo.eval(ss, sd).cpu().numpy()
+        del ref_geo
+        err_all = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                   "max": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+                   "targets": int(g.n), "reference": "direct mode"}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "targets*densities/s", "n_gpus": 1,
@@ -434,6 +461,7 @@ def main(argv=None):
                           for k, v in stages.items() if v[1] and v[0] > 0 and work.get(k)},
         "setup_s": setup_s,
         "err_vs_oracle_sampled": err,
+        "err_vs_direct_all_targets": err_all,
     }
     legs = [x for x in args.legs.split(",") if x]
     del geo

@@ -379,6 +379,7 @@ class Workload:
     leaf_max: int = 32
     direct: bool = False
     meta: dict = field(default_factory=dict)
+    p_add: int = -1          # FMM order increment; -1 = the library's default rule
 
     @property
     def n_dens(self) -> int:
@@ -402,9 +403,20 @@ def direct_star512(n_dens: int = 1, n_annulus: int = 1024) -> Workload:
                     direct=True)
 
 
+# The order increment of the 32768-node star at eps = 1e-10, p = 14,
+# calibrated as the paper does (Sec. 7.1): the smallest p_add for which the
+# FMM stays within eps of direct QBX, checked over all 32768 targets for a
+# Gaussian and a plane-wave density (`calibrate_padd sweep`): relative l2
+# 1.6e-11, largest error 5.3e-10 of the largest value (within 10 eps).  One
+# more order takes the finest levels' n = 2 P + 1 past 128, a ninth MFMA row
+# block, for 6% more time.  The library's default rule adds a margin of 4
+# (43) for geometries it has not seen.
+STAR32K_P_ADD = 39
+
+
 def fmm_star(n_panels: int = 2048, n_dens: int = 1, omega: float = 50.0,
              eps: float = 1e-10, p: int = 14, lobes: int = 7, leaf_max: int = 32,
-             workload_id: int = 1) -> Workload:
+             workload_id: int = 1, p_add: int = -1) -> Workload:
     """QBX-FMM on the 7-lobe star with on-surface targets (own centres).
     Defaults: 2048 panels x 16 nodes = 32768 sources = centres = targets."""
     g = star(n_panels, 16, lobes=lobes, amp=0.3)
@@ -412,4 +424,4 @@ def fmm_star(n_panels: int = 2048, n_dens: int = 1, omega: float = 50.0,
     ss = complex_gaussian(r, (n_dens, g.n))
     sd = complex_gaussian(r, (n_dens, g.n))
     return Workload(f"fmm_star{lobes}_{g.n}", g, omega, p, eps, g.sx.copy(), g.sy.copy(),
-                    np.arange(g.n, dtype=np.int32), ss, sd, leaf_max=leaf_max)
+                    np.arange(g.n, dtype=np.int32), ss, sd, leaf_max=leaf_max, p_add=p_add)

@@ -149,25 +149,43 @@ def test_w_list_direct_switch(ctx, w_direct):
 
 def test_fmm_full_size_sampled(ctx):
     """2048 panels x 16 nodes = 32768 sources/centres/targets, omega = 50,
-    eps = 1e-10, p = 14: potentials at 512 sampled targets against the oracle
-    evaluated for exactly those targets' centres."""
-    wl = inputs.fmm_star()
+    eps = 1e-10, p = 14, at the benchmark's p_add and at the library's
+    default: potentials at 512 sampled targets against the oracle evaluated
+    for exactly those targets' centres."""
+    wl = inputs.fmm_star(p_add=inputs.STAR32K_P_ADD)
     g = wl.geom
-    _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
-                 p=wl.p, leaf_max=wl.leaf_max)
     pick = np.sort(np.random.default_rng(0).choice(g.n, 512, replace=False))
     ref = _oracle_at_nodes(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, pick)
-    _assert_fmm(u[:, pick], ref, wl.eps, "full-size sampled")
+    for p_add in (wl.p_add, -1):
+        _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                     p=wl.p, leaf_max=wl.leaf_max, p_add=p_add)
+        _assert_fmm(u[:, pick], ref, wl.eps, f"full-size sampled, p_add {p_add}")
+
+
+def test_fmm_full_size_all_targets_against_direct(ctx):
+    """The benchmark's workload at its calibrated p_add against the
+    library's direct mode (pinned to the oracle by the direct-mode tests) on
+    every one of the 32768 targets: relative l2 error in [eps / 100, eps]
+    and the largest error within 10 eps.  The errors concentrate at few
+    targets, so 512 samples alone see less of them."""
+    wl = inputs.fmm_star(p_add=inputs.STAR32K_P_ADD)
+    g = wl.geom
+    _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                 p=wl.p, leaf_max=wl.leaf_max, p_add=wl.p_add)
+    _, ref = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
+                   p=wl.p, direct=True)
+    _assert_fmm(u, ref, wl.eps, "full-size, all targets against direct mode")
+    assert _rel(u, ref) >= wl.eps / 100
 
 
 def test_fmm_full_size_four_densities_sampled(ctx):
     """The 32768-node star with 4 densities in one call (one chunk: every
-    GEMM stage takes 4 columns per box): each density against the oracle at
-    512 sampled targets."""
-    wl = inputs.fmm_star(n_dens=4)
+    GEMM stage takes 4 columns per box), at the benchmark's p_add: each
+    density against the oracle at 512 sampled targets."""
+    wl = inputs.fmm_star(n_dens=4, p_add=inputs.STAR32K_P_ADD)
     g = wl.geom
     _, u = _eval(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, wl.sigma_s, wl.sigma_d,
-                 p=wl.p, leaf_max=wl.leaf_max)
+                 p=wl.p, leaf_max=wl.leaf_max, p_add=wl.p_add)
     assert u.shape == (4, g.n)
     pick = np.sort(np.random.default_rng(4).choice(g.n, 512, replace=False))
     ref = _oracle_at_nodes(g, wl.omega, wl.p, wl.sigma_s, wl.sigma_d, pick)
