@@ -305,6 +305,11 @@ struct qbx_geom_s {
     cd *wy = nullptr;
     M2LTile *m2l_tiles[kDensChunk + 1] = {};
     int m2l_ntiles[kDensChunk + 1] = {};
+    // M2L tiles come in two runs: those of orders beyond the staged kernel's
+    // LDS (direct kernel, orders up to m2l_Pdirect), then the rest (orders up
+    // to m2l_Pstaged)
+    int m2l_split[kDensChunk + 1] = {};
+    int m2l_Pdirect = 0, m2l_Pstaged = 0;
     // M2M parents per level, L2L children per (level, quadrant), and their tiles
     std::vector<int> par_list, par_lvl, chl_list, chl_lvl;
     std::vector<long long> box_off_h, vy_off_h;   // host copies of box_off, vy_off
@@ -508,11 +513,16 @@ qbx_status upload(qbx_geom_s *G)
     G->m2l_groups.clear();
     G->m2l_Pmax = 0;
     G->m2l_nw = 1;
+    G->m2l_Pdirect = G->m2l_Pstaged = 0;
+    const int pstaged_max = m2l_staged_pmax();
     for (int i = 0; i < nv;) {
         int j = i;
         while (j < nv && vkey(vpos[j]) == vkey(vpos[i])) ++j;
         G->m2l_groups.push_back({vkey(vpos[i]), i, j - i});
-        G->m2l_Pmax = std::max(G->m2l_Pmax, pl.P[vkey(vpos[i]) / 40]);
+        int P = pl.P[vkey(vpos[i]) / 40];
+        G->m2l_Pmax = std::max(G->m2l_Pmax, P);
+        if (P > pstaged_max) G->m2l_Pdirect = std::max(G->m2l_Pdirect, P);
+        else G->m2l_Pstaged = std::max(G->m2l_Pstaged, P);
         i = j;
     }
     {
@@ -890,10 +900,16 @@ qbx_status ensure_tiles(qbx_geom_s *G, int nd)
     }
     if (G->m2m_tiles[nd]) return QBX_OK;
     std::vector<M2LTile> t;
-    for (const auto &grp : G->m2l_groups) {
-        int cols = grp.count * nd;
-        for (int c0 = 0; c0 < cols; c0 += kM2LTileCols)
-            t.push_back({grp.key, grp.start, c0, std::min(kM2LTileCols, cols - c0)});
+    const int pstaged_max = m2l_staged_pmax();
+    for (int pass = 0; pass < 2; ++pass) {
+        // the groups whose columns exceed the staged kernel's LDS first
+        for (const auto &grp : G->m2l_groups) {
+            if ((G->pl.P[grp.key / 40] > pstaged_max) != (pass == 0)) continue;
+            int cols = grp.count * nd;
+            for (int c0 = 0; c0 < cols; c0 += kM2LTileCols)
+                t.push_back({grp.key, grp.start, c0, std::min(kM2LTileCols, cols - c0)});
+        }
+        if (pass == 0) G->m2l_split[nd] = (int)t.size();
     }
     G->m2l_tiles[nd] = G->arena.upload(t);
     G->m2l_ntiles[nd] = (int)t.size();
@@ -1078,7 +1094,8 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         {
             STAGE(QBX_STAGE_M2L);
             LAUNCH(QBX_STAGE_M2L, G->m2l_ntiles[nd],
-                   launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_Pmax, G->m2l_nw,
+                   launch_m2l_mfma(g, nd, G->m2l_tiles[nd], G->m2l_ntiles[nd], G->m2l_split[nd],
+                                   G->m2l_Pdirect, G->m2l_Pstaged, G->m2l_nw,
                                    B.mp, B.vy, st));
         }
         if (conc) {
@@ -1366,7 +1383,8 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
         QQ(stage(FK_M2L, over([](const BItem &b, FItem &it) {
                      const qbx_geom_s *G = b.G;
                      it.r.in0 = G->m2l_tiles[b.nd]; it.r.in1 = G->mp; it.r.out0 = G->vy;
-                     it.n = G->m2l_ntiles[b.nd]; it.P = G->m2l_Pmax; it.aux = G->m2l_nw;
+                     it.n = G->m2l_ntiles[b.nd]; it.P = G->m2l_Pstaged; it.aux = G->m2l_nw;
+                     it.split = G->m2l_split[b.nd]; it.Psplit = G->m2l_Pdirect;
                      return it.n > 0;
                  }), 0));
         if (conc) {

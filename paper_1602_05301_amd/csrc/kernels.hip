@@ -2068,25 +2068,44 @@ hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, 
     return hipSuccess;
 }
 
-hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
-                           int nw, const cd *mp, cd *vy, hipStream_t s)
+static size_t m2l_staged_lds(int P) { return sizeof(cd) * 4 * ((2 * (size_t)P + 1 + 3) / 4) * M2L_XS; }
+
+int m2l_staged_pmax()
+{
+    int P = 0;
+    while (m2l_staged_lds(P + 1) <= LDS_BUDGET) ++P;
+    return P;
+}
+
+hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int nsplit,
+                           int Pdirect, int Pstaged, int nw, const cd *mp, cd *vy, hipStream_t s)
 {
     if (!ntiles) return hipSuccess;
-    int nrmax = (2 * Pmax + 1 + 15) / 16;
+    int Pmax = std::max(Pdirect, Pstaged);
+    auto direct = [&](const M2LTile *t, int n, int P) -> hipError_t {
+        int nrmax = (2 * P + 1 + 15) / 16;
+        long long nblk = (long long)n * nrmax;
+        if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+        if (nblk > 0) k_m2l_mfma_direct<<<(unsigned)nblk, 64, 0, s>>>(g, nd, t, nrmax, mp, vy);
+        return hipSuccess;
+    };
     if (g.far32) {
+        int nrmax = (2 * Pmax + 1 + 15) / 16;
         long long nblk = (long long)ntiles * nrmax;
         if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
         k_m2l_mfma32<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
-    } else {
+    } else if (nw > 0) {
         nw = std::min(nw, 16);
-        size_t lds = sizeof(cd) * 4 * ((2 * Pmax + 1 + 3) / 4) * M2L_XS;
-        if (nw > 0 && lds <= LDS_BUDGET) {
-            k_m2l_mfma<<<ntiles, 64 * nw, lds, s>>>(g, nd, tiles, mp, vy);
-        } else {
-            long long nblk = (long long)ntiles * nrmax;
-            if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-            k_m2l_mfma_direct<<<(unsigned)nblk, 64, 0, s>>>(g, nd, tiles, nrmax, mp, vy);
+        hipError_t e = direct(tiles, nsplit, Pdirect);
+        if (e != hipSuccess) return e;
+        if (ntiles > nsplit) {
+            size_t lds = m2l_staged_lds(Pstaged);
+            if (lds > LDS_BUDGET) return hipErrorInvalidValue;
+            k_m2l_mfma<<<ntiles - nsplit, 64 * nw, lds, s>>>(g, nd, tiles + nsplit, mp, vy);
         }
+    } else {
+        hipError_t e = direct(tiles, ntiles, Pmax);
+        if (e != hipSuccess) return e;
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
@@ -2369,21 +2388,39 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
         for (const auto &it : items) add(kind, 0, it.r, it.n * it.aux, it.n, 0, 256 * M2M_KS);
         break;
     case FK_M2L: {
+        // per geometry: the leading tiles whose orders exceed the staged
+        // kernel's LDS always go direct; the rest share one staged launch
+        // (direct if no geometry asks for waves per tile)
         int nw = 0;
         size_t lmax = 0;
         for (const auto &it : items)
-            if (!it.h->far32) {
+            if (!it.h->far32 && it.n > it.split) {
                 nw = std::max(nw, std::min(it.aux, 16));
-                lmax = std::max(lmax, sizeof(cd) * 4 * ((2 * (size_t)it.P + 1 + 3) / 4) * M2L_XS);
+                lmax = std::max(lmax, m2l_staged_lds(it.P));
             }
         bool staged = nw > 0 && lmax <= LDS_BUDGET;
         for (const auto &it : items) {
-            int nrmax = (2 * it.P + 1 + 15) / 16;
+            if (it.h->far32) {
+                int nrmax = (2 * std::max(it.P, it.Psplit) + 1 + 15) / 16;
+                FRec r = it.r;
+                r.i0 = nrmax;
+                add(FK_M2L32, 0, r, it.n * nrmax, it.n * nrmax, 0, 64);
+                continue;
+            }
+            if (it.split > 0) {
+                int nrd = (2 * it.Psplit + 1 + 15) / 16;
+                FRec r = it.r;
+                r.i0 = nrd;
+                add(FK_M2L_DIRECT, 0, r, it.split * (long long)nrd, it.split * (long long)nrd, 0, 64);
+            }
+            long long rest = it.n - it.split;
+            if (rest <= 0) continue;
             FRec r = it.r;
+            r.in0 = static_cast<const QBX_G M2LTile *>(it.r.in0) + it.split;
+            int nrmax = (2 * it.P + 1 + 15) / 16;
             r.i0 = nrmax;
-            if (it.h->far32) add(FK_M2L32, 0, r, it.n * nrmax, it.n * nrmax, 0, 64);
-            else if (staged) add(FK_M2L, 0, r, it.n, it.n, lmax, 64 * nw);
-            else add(FK_M2L_DIRECT, 0, r, it.n * nrmax, it.n * nrmax, 0, 64);
+            if (staged) add(FK_M2L, 0, r, rest, rest, lmax, 64 * nw);
+            else add(FK_M2L_DIRECT, 0, r, rest * nrmax, rest * nrmax, 0, 64);
         }
         break;
     }

@@ -151,6 +151,8 @@ struct FItem {
     long long n;               // work items (boxes, tiles, pairs, elements)
     int P;                     // largest expansion order involved
     int aux;                   // row blocks (M2M, L2L), waves per tile (M2L), rows (L2QBXL check)
+    int split = 0;             // M2L: leading tiles whose order needs the direct kernel
+    int Psplit = 0;            // M2L: largest order among those tiles (P: the others)
 };
 
 struct FLaunch {
@@ -185,10 +187,14 @@ hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, 
 hipError_t launch_l2l_mfma(const DevGeom &g, int nd, int L, const TTile *tiles, int ntiles, int nrb,
                            const int *clist, const cd *vy, cd *loc, hipStream_t s);
 // nw > 0: columns staged in LDS, nw waves per tile (row blocks spread over
-// them); nw = 0 (or staging beyond the LDS budget): one wave per (tile, row
-// block) with operands straight from memory.  Same sums, same order.
-hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int Pmax,
-                           int nw, const cd *mp, cd *vy, hipStream_t s);
+// them); nw = 0: one wave per (tile, row block) with operands straight from
+// memory.  Same sums, same order.  The first nsplit tiles (orders up to
+// Pdirect) have columns beyond the LDS budget and always take the direct
+// kernel; the rest have orders up to Pstaged <= m2l_staged_pmax().
+hipError_t launch_m2l_mfma(const DevGeom &g, int nd, const M2LTile *tiles, int ntiles, int nsplit,
+                           int Pdirect, int Pstaged, int nw, const cd *mp, cd *vy, hipStream_t s);
+// Largest order whose M2L columns the staged kernel holds in LDS.
+int m2l_staged_pmax();
 // V-list sums of the nbox boxes from the first of level 2 on (every level
 // >= 2) in one launch, nd (1-4) densities; launch_l2l_mfma with vy = null
 // then leaves them out of its epilogue.
