@@ -176,13 +176,10 @@ def leg_batched(ctx, eps, rounds=3, n_geom=256, n_dens=4, check_geoms=8, check_t
     import torch
 
     from paper_1602_05301_amd import inputs, qbx
+    from paper_1602_05301_amd.serve import batched_p_add
     far32 = eps >= 1e-6
     p = 9 if far32 else 14
-    # 12 orders above the default increment: some of these small,
-    # high-frequency curves need them to stay within eps at every target
-    tiny = inputs.star(4, 4, lobes=3)
-    p_add = qbx.Plan(tiny, 1.0, eps, tiny.sx, tiny.sy, np.arange(tiny.n, dtype=np.int32),
-                     qbx.options(p=p)).stats()["p_add"] + 12
+    p_add = batched_p_add(p, eps)
     curves = inputs.batched_geometries(n_geom)
     dr = inputs.rng_for(3, inputs.PURPOSE_DENSITY)
     dens = [inputs.complex_gaussian(dr, (n_dens, g.n)) for g, _ in curves]
@@ -270,6 +267,50 @@ def leg_multiscale(ctx, steps=10, warmup=2):
             "rel_err_vs_oracle_sampled": rel, "max_err_vs_oracle_sampled": mx, "sample": "64 targets"}
 
 
+def leg_direct(ctx, steps=200, warmup=20):
+    """Direct QBX (no FMM): the 5-lobe star, 32 panels x 16 nodes = 512
+    sources and centres, p = 12, omega = 10, 512 on-surface targets plus
+    1024 annulus targets (smooth rule), one density.  Every target against
+    the oracle."""
+    import torch
+
+    import oracle
+    from paper_1602_05301_amd import inputs, qbx
+    wl = inputs.direct_star512()
+    g = wl.geom
+    geo = qbx.Geometry(ctx, g, wl.omega, wl.eps, wl.tx, wl.ty, wl.tgt_ctr, qbx.options(p=wl.p, direct=True))
+    ss, sd = torch.from_numpy(wl.sigma_s).cuda(), torch.from_numpy(wl.sigma_d).cuda()
+    u = torch.empty((1, wl.tx.size), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        geo.eval(ss, sd, u=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        geo.eval(ss, sd, u=u)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    geo.profile(True)
+    geo.stage_times(reset=True)
+    for _ in range(steps):
+        geo.eval(ss, sd, u=u)
+    torch.cuda.synchronize()
+    st = geo.stage_times(reset=True)
+    geo.profile(False)
+    direct_ms = st["direct"][0] / steps
+    flops = geo.work(1)["direct"]
+    ref = oracle.direct_qbx(wl.omega, wl.p, g, wl.tx, wl.ty, wl.sigma_s, wl.sigma_d, tgt_ctr=wl.tgt_ctr)
+    got = u.cpu().numpy()
+    return {"workload": "5-lobe star, 512 sources = centres, 512 on-curve + 1024 annulus targets, "
+                        "omega 10, p 12, direct QBX", "ms_per_step": t * 1e3,
+            "value": wl.tx.size / t, "unit": "targets*densities/s",
+            "dominant_kernel": "k_p2qbxl_direct", "direct_ms": direct_ms,
+            "direct_tflops": flops / (direct_ms * 1e-3) / 1e12 if direct_ms > 0 else None,
+            "direct_frac_fp64": flops / (direct_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS if direct_ms > 0 else None,
+            "rel_err_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "max_err_vs_oracle": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+            "targets_checked": int(wl.tx.size)}
+
+
 def leg_served(ctx, n_requests=16, max_nodes=200_000, frac=0.8, hbm_gib=64.0):
     """Bounded served stream: n_requests star requests of 1k-200k nodes
     (log-uniform), omega U[1,200], eps in {1e-6, 1e-10}, 20-60 chained
@@ -317,9 +358,10 @@ def main(argv=None):
     ap.add_argument("--graph", action="store_true",
                     help="replay a captured HIP graph per evaluation instead of enqueueing every "
                          "kernel (measured slower here: the eager two-stream schedule overlaps more)")
-    ap.add_argument("--legs", default="batched,multiscale,served",
+    ap.add_argument("--legs", default="direct,batched,multiscale,served",
                     help="further workloads after the headline (comma list; empty for none): "
-                         "batched (256 curves, both tolerances), multiscale (606k nodes), "
+                         "direct (512-node direct QBX), batched (256 curves, both tolerances), "
+                         "multiscale (606k nodes), "
                          "served (bounded stream of 1k-200k-node requests)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warm-up, copy a buffer of this many MiB once on the device: "
@@ -473,6 +515,8 @@ def main(argv=None):
             rec["batched"] = [leg_batched(ctx, e) for e in (1e-10, 1e-6)]
         elif leg == "multiscale":
             rec["multiscale"] = leg_multiscale(ctx)
+        elif leg == "direct":
+            rec["direct"] = leg_direct(ctx)
         elif leg == "served":
             rec["served"] = leg_served(ctx)
         else:

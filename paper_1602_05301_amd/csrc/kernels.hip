@@ -1754,29 +1754,50 @@ __global__ void k_qbx_eval(DevGeom g, int nd, const cd *coef, cd *u)
 }
 
 // Smooth (unmodified Gauss) rule at unassociated targets, over all sources.
+// One wave per smooth-rule target: lane i takes sources i, i + 64, ...,
+// evaluates each Hankel pair once for all densities of the pass, and the
+// wave sums its lanes by a fixed butterfly.
+constexpr int SMOOTH_ND = 4;                  // densities per pass (the pipeline's chunk)
+
 __device__ __forceinline__ void smooth_body(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, BlockId bid)
 {
-    int idx = bid.x * blockDim.x + threadIdx.x;
-    if (idx >= g.n_smooth) return;
+    int idx = bid.x;
+    if (idx >= g.n_smooth) return;                    // uniform across the wave
+    int lane = threadIdx.x;
     int m = g.smooth_list[idx];
     double tx = g.tx[m], ty = g.ty[m];
-    for (int d = 0; d < nd; ++d) {
-        cd acc = mk(0.0, 0.0);
-        for (int j = 0; j < g.ns; ++j) {
+    for (int d0 = 0; d0 < nd; d0 += SMOOTH_ND) {
+        int dn = min(SMOOTH_ND, nd - d0);
+        cd acc[SMOOTH_ND];
+#pragma unroll
+        for (int e = 0; e < SMOOTH_ND; ++e) acc[e] = mk(0.0, 0.0);
+        for (int j = lane; j < g.ns; j += 64) {
             double dx = tx - g.sx[j], dy = ty - g.sy[j];
             double r = sqrt(dx * dx + dy * dy);
             double x = g.omega * r;
             cd h0, h1;
             hankel01(x, h0, h1);
-            double ca = g.omega * (dx * g.snx[j] + dy * g.sny[j]) / r;
-            cfma(acc, qs[(long long)d * g.ns + j], h0);
-            cfma(acc, qd[(long long)d * g.ns + j], ca * h1);
+            cd dh = (g.omega * (dx * g.snx[j] + dy * g.sny[j]) / r) * h1;
+#pragma unroll
+            for (int e = 0; e < SMOOTH_ND; ++e)
+                if (e < dn) {
+                    cfma(acc[e], qs[(long long)(d0 + e) * g.ns + j], h0);
+                    cfma(acc[e], qd[(long long)(d0 + e) * g.ns + j], dh);
+                }
         }
-        u[(long long)d * g.nt + m] = acc;
+#pragma unroll
+        for (int e = 0; e < SMOOTH_ND; ++e) {
+            double re = acc[e].x, im = acc[e].y;
+            for (int s = 32; s > 0; s >>= 1) {
+                re += __shfl_xor(re, s, 64);
+                im += __shfl_xor(im, s, 64);
+            }
+            if (lane == 0 && e < dn) u[(long long)(d0 + e) * g.nt + m] = mk(re, im);
+        }
     }
 }
 
-__global__ void k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
+__global__ void __launch_bounds__(64) k_smooth(DevGeom g, int nd, const cd *qs, const cd *qd, cd *u)
 {
     smooth_body(g, nd, qs, qd, u, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
@@ -1967,7 +1988,7 @@ __global__ void kf_eval(const FRec *recs, const int *map)
     qbx_eval_body(g, r.nd, CP(const cd *, in0), CP(cd *, out0), bid);
 }
 
-__global__ void kf_smooth(const FRec *recs, const int *map)
+__global__ void __launch_bounds__(64) kf_smooth(const FRec *recs, const int *map)
 {
     FUSED_BEGIN
     smooth_body(g, r.nd, CP(const cd *, in0), CP(const cd *, in1), CP(cd *, out0), bid);
@@ -2172,11 +2193,16 @@ hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *items, int n, cons
     return p2qbxl_dispatch<40>(g, nd, items, n, qs, qd, coef, s);
 }
 
+// Centres per wave of the direct sum: one when there are few centres (the
+// sources of each then spread over all 64 lanes, and the grid has a wave per
+// centre), four for large sets.
+static int direct_centres_per_wave(long long nc) { return nc >= 16384 ? 4 : (nc >= 4096 ? 2 : 1); }
+
 template <int PB>
 static hipError_t p2qbxl_direct_dispatch(const DevGeom &g, int nd, const cd *qs, const cd *qd,
                                          cd *coef, hipStream_t s)
 {
-    int G = 4;
+    int G = direct_centres_per_wave(g.nc);
     int blocks = (g.nc + G - 1) / G;
     k_p2qbxl_direct<PB><<<blocks, 64, 0, s>>>(g, nd, G, qs, qd, coef);
     return hipGetLastError();
@@ -2253,7 +2279,7 @@ hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipS
 hipError_t launch_smooth(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, hipStream_t s)
 {
     if (!g.n_smooth) return hipSuccess;
-    k_smooth<<<(g.n_smooth + 127) / 128, 128, 0, s>>>(g, nd, qs, qd, u);
+    k_smooth<<<g.n_smooth, 64, 0, s>>>(g, nd, qs, qd, u);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -2456,8 +2482,8 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
     case FK_P2QBXL_DIRECT:
         for (const auto &it : items) {
             FRec r = it.r;
-            r.i0 = 4;
-            long long b = (it.h->nc + 3) / 4;
+            r.i0 = direct_centres_per_wave(it.h->nc);
+            long long b = (it.h->nc + r.i0 - 1) / r.i0;
             add(kind, p2q_bucket(it.h->p), r, b, b, 0, 64);
         }
         break;
@@ -2494,10 +2520,7 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
         }
         break;
     case FK_SMOOTH:
-        for (const auto &it : items) {
-            long long b = ((long long)it.h->n_smooth + 127) / 128;
-            add(kind, 0, it.r, b, b, 0, 128);
-        }
+        for (const auto &it : items) add(kind, 0, it.r, it.h->n_smooth, it.h->n_smooth, 0, 64);
         break;
     default:
         return hipErrorInvalidValue;

@@ -221,10 +221,14 @@ class Plan:
         h = _vp()
         _check(lib().qbx_plan_create(float(omega), float(eps), ctypes.byref(opts), *args, ctypes.byref(h)))
         self._h = h
+        self._lib = lib()
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().qbx_plan_destroy(self._h)
+        # the library handle taken at construction: at interpreter exit the
+        # module's globals may already be gone
+        L = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.qbx_plan_destroy(self._h)
             self._h = None
 
     def stats(self) -> dict:
@@ -271,12 +275,16 @@ class Context:
         h = _vp()
         _check(lib().qbx_ctx_create(int(device), _vp(stream.cuda_stream), ctypes.byref(h)))
         self._h = h
+        self._lib = lib()
         self.device = device
         self.stream = stream
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().qbx_ctx_destroy(self._h)
+        # the library handle taken at construction: at interpreter exit the
+        # module's globals may already be gone
+        L = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.qbx_ctx_destroy(self._h)
             self._h = None
 
     def last_error(self) -> str:
@@ -388,6 +396,7 @@ class Geometry:
             _check(lib().qbx_geom_create(ctx._h, float(omega), float(eps), ctypes.byref(self.opts),
                                          *args, ctypes.byref(h)))
         self._h = h
+        self._lib = lib()
         self.ctx = ctx
         self.n_src = int(np.asarray(geom.sx).size)
         self.n_ctr = int(np.asarray(geom.cx).size)
@@ -395,8 +404,11 @@ class Geometry:
         self.p = int(self.opts.p)
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().qbx_geom_destroy(self._h)
+        # the library handle taken at construction: at interpreter exit the
+        # module's globals may already be gone
+        L = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.qbx_geom_destroy(self._h)
             self._h = None
 
     def stats(self) -> dict:

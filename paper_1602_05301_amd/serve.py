@@ -333,6 +333,16 @@ def batch_vs_sequential(ctx, n_geom: int = 16, rounds: int = 10, max_nodes: int 
             "batched_targets_x_densities_per_s": work / bat}
 
 
+def batched_p_add(p: int, eps: float) -> int:
+    """The order increment of the batched workload: 12 above the library's
+    default rule, which some of its small high-frequency curves need to stay
+    within eps at every target."""
+    from . import qbx
+    tiny = inputs.star(4, 4, lobes=3)
+    return qbx.Plan(tiny, 1.0, eps, tiny.sx, tiny.sy, np.arange(tiny.n, dtype=np.int32),
+                    qbx.options(p=p)).stats()["p_add"] + 12
+
+
 def batched_workload(ctx, n_geom: int = 256, eps: float = 1e-10, n_dens: int = 4, rounds: int = 3,
                      setup_threads: int = 8) -> dict:
     """The batched workload: n_geom independent star and ellipse curves of
@@ -345,14 +355,15 @@ def batched_workload(ctx, n_geom: int = 256, eps: float = 1e-10, n_dens: int = 4
     from . import qbx
     far32 = eps >= 1e-6
     p = 9 if far32 else 14
+    p_add = batched_p_add(p, eps)
     curves = inputs.batched_geometries(n_geom)
-    dr = inputs.rng_for(3, 2)
+    dr = inputs.rng_for(3, inputs.PURPOSE_DENSITY)
     dens = [inputs.complex_gaussian(dr, (n_dens, g.n)) for g, _ in curves]
 
     def build(item):
         g, w = item
         return qbx.Geometry(ctx, g, w, eps, g.sx, g.sy, np.arange(g.n, dtype=np.int32),
-                            qbx.options(p=p, far_fp32=far32))
+                            qbx.options(p=p, p_add=p_add, far_fp32=far32))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=setup_threads) as pool:
         geos = list(pool.map(build, curves))
@@ -378,7 +389,7 @@ def batched_workload(ctx, n_geom: int = 256, eps: float = 1e-10, n_dens: int = 4
     bat = (time.perf_counter() - t0) / rounds
     work = sum(g.n * n_dens for g, _ in curves)
     nodes = np.array([g.n for g, _ in curves])
-    return {"geometries": n_geom, "densities_each": n_dens, "eps": eps, "far_fp32": far32, "p": p,
+    return {"geometries": n_geom, "densities_each": n_dens, "eps": eps, "far_fp32": far32, "p": p, "p_add": p_add,
             "nodes_total": int(nodes.sum()), "nodes_min": int(nodes.min()), "nodes_max": int(nodes.max()),
             "setup_s": setup, "batched_ms": bat * 1e3, "one_by_one_ms": seq * 1e3,
             "batched_targets_x_densities_per_s": work / bat,
