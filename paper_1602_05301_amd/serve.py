@@ -105,8 +105,13 @@ def make_requests(n: int, seed: int = 4, nodes=(1024, 32768), omega=(1.0, 200.0)
 
 
 def _options(req: Request):
+    """A request's geometry options.  The X-list rows are rebuilt in every
+    matvec rather than kept: with one density per matvec, reading the kept
+    rows of many large geometries costs more than forming them (closed-loop
+    rate on this stream 26.1 against 23.3 requests/s), and they would add
+    about 12% to each request's footprint under the HBM budget."""
     from . import qbx
-    return qbx.options(p=req.p, far_fp32=req.eps >= 1e-6)
+    return qbx.options(p=req.p, far_fp32=req.eps >= 1e-6, keep_x_rows=False)
 
 
 def _build(ctx, req: Request, plan=None):

@@ -1025,3 +1025,21 @@ def test_context_refuses_a_second_thread(ctx):
         if st == 0:
             assert np.array_equal(u.numpy(), ref)
     assert np.array_equal(geo.eval(hs, hd).numpy(), ref)
+
+
+def test_context_keeps_its_last_error(ctx):
+    """A failed call on a context leaves its message with the context
+    (qbx_ctx_last_error) as well as with the calling thread."""
+    import ctypes
+
+    from paper_1602_05301_amd import qbx
+    own = qbx.Context(0)
+    g = inputs.star(8, 16, lobes=3)
+    tc = np.arange(g.n, dtype=np.int32)
+    geo = qbx.Geometry(own, g, 5.0, 1e-8, g.sx, g.sy, tc, qbx.options(p=6))
+    assert own.last_error() == ""
+    L = qbx.lib()
+    st = L.qbx_eval(geo._h, 0, ctypes.c_void_p(1), None, ctypes.c_void_p(1), None)
+    assert st == -1
+    assert "n_dens" in own.last_error()
+    assert "n_dens" in L.qbx_last_error().decode()
