@@ -325,6 +325,7 @@ struct qbx_geom_s {
     // the view g) and J_n(omega |m_b - c|) per L2QBXL centre (n-major),
     // built on the first evaluation
     int srad_rows = 0, crad_rows = 0;
+    int l2q_cap = 1;              // centres per L2QBXL item (at most)
     cd *sbas = nullptr, *xbas = nullptr;
     double *crad = nullptr;
     int n_xpos = 0;                 // flattened X-list positions
@@ -691,14 +692,48 @@ qbx_status upload(qbx_geom_s *G)
     }
     G->l2q = make_list(ar, pl, [&](int b) { return pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2; });
     {
-        // the same leaves, the most centres first (long workgroups start early)
-        std::vector<int> v;
+        // L2QBXL items: the same leaves' centres in runs of at most `cap`
+        // (one leaf each), packed largest first into items of at most cap
+        // centres and L2Q_SEGS runs, each run into the open item it fills
+        // best.  The largest items come first, so long workgroups start early.
+        std::vector<int> leaves;
         for (int b = 0; b < nb; ++b)
-            if (pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2) v.push_back(b);
-        std::stable_sort(v.begin(), v.end(), [&](int a, int c) {
+            if (pl.leaf[b] && has_ctr(b) && pl.lev[b] >= 2) leaves.push_back(b);
+        std::stable_sort(leaves.begin(), leaves.end(), [&](int a, int c) {
             return pl.ctr_end[a] - pl.ctr_begin[a] > pl.ctr_end[c] - pl.ctr_begin[c];
         });
-        G->l2q.d = ar.upload(v);
+        int cap = l2qbxl_item_cap(G->l2q.Pmax, G->l2q.Pmax + pl.p + 8);
+        std::vector<std::pair<int, int>> runs;
+        for (int b : leaves)
+            for (int c = pl.ctr_begin[b]; c < pl.ctr_end[b]; c += cap)
+                runs.push_back({c, std::min(c + cap, (int)pl.ctr_end[b])});
+        std::stable_sort(runs.begin(), runs.end(), [](const std::pair<int, int> &a, const std::pair<int, int> &c) {
+            return a.second - a.first > c.second - c.first;
+        });
+        std::vector<int> items, used, nrun;
+        std::vector<std::vector<int>> open(cap + 1);   // open[f]: items with f free slots and a free run
+        for (const auto &r : runs) {
+            int sz = r.second - r.first, pick = -1;
+            for (int f = sz; f < cap && pick < 0; ++f)
+                if (!open[f].empty()) {
+                    pick = open[f].back();
+                    open[f].pop_back();
+                }
+            if (pick < 0) {
+                pick = (int)used.size();
+                items.insert(items.end(), 2 * L2Q_SEGS, 0);
+                used.push_back(0);
+                nrun.push_back(0);
+            }
+            items[(size_t)pick * 2 * L2Q_SEGS + 2 * nrun[pick]] = r.first;
+            items[(size_t)pick * 2 * L2Q_SEGS + 2 * nrun[pick] + 1] = r.second;
+            ++nrun[pick];
+            used[pick] += sz;
+            if (used[pick] < cap && nrun[pick] < L2Q_SEGS) open[cap - used[pick]].push_back(pick);
+        }
+        G->l2q.n = (int)used.size();
+        G->l2q.d = ar.upload(items);
+        G->l2q_cap = cap;
     }
     // Split every leaf's W list: boxes summed directly join the near list
     // (P2QBXL), the others go through M2QBXL.
@@ -1063,7 +1098,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
             CHK(launch_fill_zero(B.loc, (long long)nd * G->total_coef, s1));
             CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, s1));
             if (G->n_wpairs > 0) CHK(hipEventRecord(C->ev_x, s1));
-            CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, s1));
+            CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, true, s1));
             // Without M2QBXL work one event marks the end of the side stream
             // and the caller's stream waits for it once, before L2L: each
             // event costs the waiting stream a few microseconds, and the near
@@ -1124,7 +1159,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         } else {
             {
                 STAGE(QBX_STAGE_P2QBXL);
-                LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, st));
+                LAUNCH(QBX_STAGE_P2QBXL, G->qbx.n, launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, false, st));
             }
             STAGE(QBX_STAGE_M2QBXL);
             LAUNCH(QBX_STAGE_M2QBXL, G->n_wpairs,
@@ -1134,7 +1169,8 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         {
             STAGE(QBX_STAGE_L2QBXL);
             if (!conc && !G->rad_ready) LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_ctr_rad(g, G->l2q.n, G->crad, G->crad_rows, st));
-            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows, B.loc, B.coef, st));
+            LAUNCH(QBX_STAGE_L2QBXL, G->l2q.n, launch_l2qbxl(g, nd, G->l2q.d, G->l2q.n, G->l2q.Pmax, G->crad, G->crad_rows,
+                                                               G->l2q_cap, B.loc, B.coef, st));
         }
         // both radial sequences are enqueued ahead of every later evaluation
         // on this geometry (P2M and L2QBXL of later calls follow them in
@@ -1424,6 +1460,7 @@ qbx_status plan_pass(const std::vector<BItem> &B, const QbxLane &L, bool conc, F
         QQ(stage(FK_L2QBXL, over([](const BItem &b, FItem &it) {
                      const qbx_geom_s *G = b.G;
                      it.r.in0 = G->l2q.d; it.r.in1 = G->crad; it.r.in2 = G->loc; it.r.out0 = G->coef;
+                     it.r.i0 = G->l2q_cap;
                      it.n = G->l2q.n; it.P = G->l2q.Pmax; it.aux = G->crad_rows;
                      return it.n > 0;
                  }), 0));

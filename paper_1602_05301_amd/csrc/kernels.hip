@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <vector>
 
@@ -762,6 +763,17 @@ __device__ __forceinline__ void l2l_mfma_body(const DevGeom &g, int nd, int L, c
     bool valid = bc < t.ncol;
     int d = col % nd;
     const cd *bptr = valid ? loc + g.l2l_poff[t.start + col / nd] * nd + (long long)d * np : nullptr;
+    // The child's local that this thread completes, loaded ahead of the
+    // K loop (it is not written in this launch: the loop reads the
+    // parents' level), so that its round trip overlaps the loop.
+    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    int row = rb * 16 + r;
+    bool own = c < t.ncol && row < nc;
+    int oc = t.col0 + c;
+    int pos = t.start + oc / nd;
+    long long dr = (long long)(oc % nd) * nc + row;
+    long long base = own ? g.l2l_coff[pos] * nd + dr : 0;
+    cd acc = own ? loc[base] : mk(0.0, 0.0);
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
     int kb0, kb1;
     ksplit(NKp, L2L_KS, w, &kb0, &kb1);
@@ -769,19 +781,12 @@ __device__ __forceinline__ void l2l_mfma_body(const DevGeom &g, int nd, int L, c
                 np, lane, yr, yi);
     tb_store(part[w], lane, yr, yi);
     __syncthreads();
-    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-    int row = rb * 16 + r;
-    if (c >= t.ncol || row >= nc) return;
-    int oc = t.col0 + c;
-    int pos = t.start + oc / nd;
-    long long dr = (long long)(oc % nd) * nc + row;
-    long long base = g.l2l_coff[pos] * nd + dr;
+    if (!own) return;
     // V-list rows of the child follow each other, nc * nd apart
     // vy null: the V-list rows are already in loc
     const cd *vr = vy ? vy + g.l2l_vy0[pos] * nd + dr : nullptr;
     int nv = vy ? g.l2l_nv[pos] : 0;
     long long vs = (long long)nc * nd;
-    cd acc = loc[base];
 #pragma unroll 4
     for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs];
     loc[base] = acc + tb_sum(part, L2L_KS, r, c);
@@ -815,6 +820,15 @@ __device__ __forceinline__ void l2l_mfma32_body(const DevGeom &g, int nd, int L,
     bool valid = bc < t.ncol;
     int d = col % nd;
     const cd *bptr = valid ? loc + g.l2l_poff[t.start + col / nd] * nd + (long long)d * np : nullptr;
+    // the child's local this thread completes, loaded ahead of the K loop
+    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    int row = rb * 16 + r;
+    bool own = c < t.ncol && row < nc;
+    int oc = t.col0 + c;
+    int pos = t.start + oc / nd;
+    long long dr = (long long)(oc % nd) * nc + row;
+    long long base = own ? g.l2l_coff[pos] * nd + dr : 0;
+    cd acc = own ? loc[base] : mk(0.0, 0.0);
     f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
     int kb0, kb1;
     ksplit(NKp, L2L_KS, w, &kb0, &kb1);
@@ -823,18 +837,11 @@ __device__ __forceinline__ void l2l_mfma32_body(const DevGeom &g, int nd, int L,
 #pragma unroll
     for (int i = 0; i < 4; ++i) { part[w][lane][i] = (double)yr[i]; part[w][lane][4 + i] = (double)yi[i]; }
     __syncthreads();
-    int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-    int row = rb * 16 + r;
-    if (c >= t.ncol || row >= nc) return;
-    int oc = t.col0 + c;
-    int pos = t.start + oc / nd;
-    long long dr = (long long)(oc % nd) * nc + row;
-    long long base = g.l2l_coff[pos] * nd + dr;
+    if (!own) return;
     // vy null: the V-list rows are already in loc
     const cd *vr = vy ? vy + g.l2l_vy0[pos] * nd + dr : nullptr;
     int nv = vy ? g.l2l_nv[pos] : 0;
     long long vs = (long long)nc * nd;
-    cd acc = loc[base];
 #pragma unroll 4
     for (int v = 0; v < nv; ++v) acc = acc + vr[v * vs];
     loc[base] = acc + tb_sum32(part, L2L_KS, r, c);
@@ -1271,10 +1278,18 @@ __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int 
     }
 }
 
+// A capped grid: workgroup b takes items b, 2G-1-b, 2G+b, ... (G = gridDim.x),
+// back and forth over the list, which the host sorts by decreasing work, so
+// the workgroups' totals stay close.  Each item's body begins and ends its LDS
+// use behind barriers, so items follow each other in a workgroup safely.
 template <int PB>
-__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *items, const cd *qs, const cd *qd, cd *coef)
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, int n_items, const int *items, const cd *qs, const cd *qd, cd *coef)
 {
-    p2qbxl_body<PB>(g, nd, items, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+    int G = gridDim.x;
+    for (int r = 0; r * G < n_items; ++r) {
+        int b = r * G + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (b < n_items) p2qbxl_body<PB>(g, nd, items, qs, qd, coef, BlockId{b, 0, n_items});
+    }
 }
 
 // Direct mode: all sources to every centre (Sec. 3.2, oversampled coefficient sum).
@@ -1574,65 +1589,109 @@ __global__ void k_wsum(DevGeom g, int nd, const int *leaf_list, const int *leaf_
 // centre and a quarter of the n range; gt enters a sliding register window
 // (its phase is a running product), J_n comes from an LDS table filled by
 // Miller's recurrence, one lane per centre.
+//
+// Work items pack centres: an item is up to L2Q_SEGS runs of consecutive
+// centres, each run inside one leaf, at most `cap` centres in all (the host
+// splits large leaves into runs and packs the runs, largest first, best
+// fit).  A leaf's centres alone would leave a third of the lanes idle on a
+// typical curve (about 11 centres per leaf against 16 slots).  Each centre's
+// arithmetic is the same whichever item it lands in.
 // ---------------------------------------------------------------------------
-constexpr int L2Q_THREADS = 256;   // lanes per leaf (at least QCG_MAX)
+constexpr int L2Q_THREADS = 256;   // lanes per item: 16 slots x 4 l-blocks x 4 quarters
 
-size_t l2qbxl_lds_bytes(int nd, int P, int p, int cg)
+size_t l2qbxl_lds_bytes(int P, int cap, int rows)
 {
-    int np = 2 * P + 1, N = P + p + QBLK - 1;
-    return sizeof(cd) * ((size_t)nd * np + (size_t)cg) +
-           sizeof(double) * ((size_t)cg * (N + 1));
+    // one density's locals of every run, the centres' directions, their J_n rows
+    return sizeof(cd) * ((size_t)L2Q_SEGS * (2 * P + 1) + (size_t)cap) + sizeof(double) * (size_t)cap * rows;
 }
 
-__device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG, BlockId bid)
+int l2qbxl_item_cap(int Pmax, int rows)
+{
+    int cap = L2Q_CAP_MAX;
+    while (cap > 1 && l2qbxl_lds_bytes(Pmax, cap, rows) > LDS_BUDGET) cap >>= 1;
+    return cap;
+}
+
+__device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int *items, const double *crad,
+                                            const cd *loc, cd *coef, int cap, int rows, BlockId bid)
 {
     extern __shared__ double lds_raw[];
-    int b = list[bid.x];
-    int l = g.blev[b];
-    int P = g.Plev[l], np = 2 * P + 1;
+    const int *it = items + 2 * L2Q_SEGS * bid.x;
+    // runs: centres [c0, c1) of leaf b, slots [so, so + c1 - c0), locals at Gb + go
+    int rc0[L2Q_SEGS], rb[L2Q_SEGS], rP[L2Q_SEGS], so[L2Q_SEGS + 1], go[L2Q_SEGS];
+    int T = 0, gsum = 0;
+#pragma unroll
+    for (int r = 0; r < L2Q_SEGS; ++r) {
+        int c0 = it[2 * r], c1 = it[2 * r + 1];
+        rc0[r] = c0;
+        so[r] = T;
+        go[r] = gsum;
+        rb[r] = c1 > c0 ? g.ctr_box[c0] : 0;
+        rP[r] = c1 > c0 ? g.Plev[g.blev[rb[r]]] : 0;
+        if (c1 > c0) {
+            T += c1 - c0;
+            gsum += 2 * rP[r] + 1;
+        }
+    }
+    so[L2Q_SEGS] = T;
     int p = g.p, nq = 2 * p + 1;
     int nblk = (nq + QBLK - 1) / QBLK;
-    int N = P + p + QBLK - 1;                          // largest |n| any lane reads
-    int c0 = g.ctr_begin[b], c1 = g.ctr_end[b];
     int tid = threadIdx.x;
-    cd *Gb = reinterpret_cast<cd *>(lds_raw);          // [nd][np]
-    cd *U = Gb + nd * np;                              // [QCG]
-    double *Jt = reinterpret_cast<double *>(U + QCG);  // [QCG][N+1]
-    const double *iw = g.invW + g.Woff[l];
-    const cd *src = loc + g.box_off[b] * nd;
-    for (int i = tid; i < nd * np; i += blockDim.x) {
-        int k = i % np - P;
-        Gb[i] = iw[k < 0 ? -k : k] * src[i];
+    cd *Gb = reinterpret_cast<cd *>(lds_raw);          // [gsum]: run r's local at go[r]
+    cd *U = Gb + gsum;                                 // [cap]
+    double *Jt = reinterpret_cast<double *>(U + cap);  // [cap][rows]
+    auto run_of = [&](int t) {
+        int r = 0;
+#pragma unroll
+        for (int q = 1; q < L2Q_SEGS; ++q) r += t >= so[q];
+        return r;
+    };
+    for (int t = tid; t < T; t += blockDim.x) {
+        int r = run_of(t), b = rb[r], i = rc0[r] + t - so[r];
+        double dx = g.bcx[b] - g.cx[i], dy = g.bcy[b] - g.cy[i];
+        double rr = sqrt(dx * dx + dy * dy);
+        U[t] = rr > 0.0 ? mk(dx / rr, dy / rr) : mk(1.0, 0.0);
     }
-    double mx = g.bcx[b], my = g.bcy[b];
-    for (int cg0 = c0; cg0 < c1; cg0 += QCG) {
-        int cnt = min(QCG, c1 - cg0);
-        __syncthreads();
-        if (tid < cnt) {
-            int i = cg0 + tid;
-            double dx = mx - g.cx[i], dy = my - g.cy[i];
-            double r = sqrt(dx * dx + dy * dy);
-            U[tid] = r > 0.0 ? mk(dx / r, dy / r) : mk(1.0, 0.0);
+    for (int i = tid; i < T * rows; i += blockDim.x) {
+        int n = i / T, t = i - n * T;
+        int r = run_of(t);
+        if (n <= rP[r] + p + QBLK - 1)
+            Jt[t * rows + n] = crad[(long long)n * g.nc + rc0[r] + t - so[r]];
+    }
+    for (int d = 0; d < nd; ++d) {
+        if (d > 0) __syncthreads();                    // the previous density's readers are done
+        for (int i = tid; i < gsum; i += blockDim.x) {
+            int r = 0;
+#pragma unroll
+            for (int q = 1; q < L2Q_SEGS; ++q) r += i >= go[q] && so[q] < T;
+            int P = rP[r], np = 2 * P + 1, k = i - go[r] - P;
+            const double *iw = g.invW + g.Woff[g.blev[rb[r]]];
+            Gb[i] = iw[k < 0 ? -k : k] * loc[g.box_off[rb[r]] * nd + (long long)d * np + k + P];
         }
-        for (int i = tid; i < cnt * (N + 1); i += blockDim.x) {
-            int n = i / cnt, t = i - n * cnt;
-            Jt[t * (N + 1) + n] = crad[(long long)n * g.nc + cg0 + t];
-        }
         __syncthreads();
-        int items = nd * cnt * nblk;
-        for (int it0 = 0; it0 < items; it0 += (int)blockDim.x / QSPLIT) {
-            int it = it0 + tid / QSPLIT, sp = tid % QSPLIT;
-            bool active = it < items;
-            int t = active ? it % cnt : 0;
-            int rest = active ? it / cnt : 0;
-            int d = rest / nblk;
-            int l0 = -p + QBLK * (rest % nblk);
+        int nitems = T * nblk;
+        for (int it0 = 0; it0 < nitems; it0 += (int)blockDim.x / QSPLIT) {
+            int iq = it0 + tid / QSPLIT, sp = tid % QSPLIT;
+            bool active = iq < nitems;
+            int t = active ? iq % T : 0;
+            int l0 = -p + QBLK * (active ? iq / T : 0);
+            int r = run_of(t);
+            int P = rP[r];
             cd acc[QBLK], win[QBLK];
 #pragma unroll
             for (int e = 0; e < QBLK; ++e) { acc[e] = mk(0.0, 0.0); win[e] = mk(0.0, 0.0); }
-            const double *jt = Jt + t * (N + 1);
-            const cd *G = Gb + d * np + P;
+            const double *jt = Jt + t * rows;
+            const cd *G = Gb + go[r] + P;
             cd u = U[t];
+            int ci = rc0[r] + t - so[r];
+#ifdef L2Q_PREFETCH
+            // the coefficients this lane adds to, loaded ahead of the sums
+            cd old[QBLK];
+#pragma unroll
+            for (int e = 0; e < QBLK; ++e)
+                old[e] = (active && sp == 0 && l0 + e <= p) ? coef[((long long)d * nq + l0 + e + p) * g.nc + ci]
+                                                            : mk(0.0, 0.0);
+#endif
             if (active) {
                 int na, nb;
                 chunk_of(l0 - P, l0 + QBLK - 1 + P, sp, &na, &nb);
@@ -1676,13 +1735,16 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
             }
             if (active && sp == 0) {
                 cd ul = unit_ipow(u, l0);                     // u^l
-                int ci = cg0 + t;
 #pragma unroll
                 for (int e = 0; e < QBLK; ++e) {
                     int ell = l0 + e;
                     if (ell <= p) {
                         cd *o = coef + ((long long)d * nq + ell + p) * g.nc + ci;
+#ifdef L2Q_PREFETCH
+                        *o = old[e] + ul * acc[e];
+#else
                         *o = *o + ul * acc[e];
+#endif
                     }
                     ul = ul * u;
                 }
@@ -1691,9 +1753,9 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
     }
 }
 
-__global__ void __launch_bounds__(L2Q_THREADS) k_l2qbxl(DevGeom g, int nd, const int *list, const double *crad, const cd *loc, cd *coef, int QCG)
+__global__ void __launch_bounds__(L2Q_THREADS) k_l2qbxl(DevGeom g, int nd, const int *items, const double *crad, const cd *loc, cd *coef, int cap, int rows)
 {
-    l2qbxl_body(g, nd, list, crad, loc, coef, QCG, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+    l2qbxl_body(g, nd, items, crad, loc, coef, cap, rows, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -1979,7 +2041,7 @@ __global__ void __launch_bounds__(L2Q_THREADS) kf_l2qbxl(const FRec *recs, const
 {
     FUSED_BEGIN
     l2qbxl_body(g, r.nd, CP(const int *, in0), CP(const double *, in1), CP(const cd *, in2), CP(cd *, out0), r.i0,
-                bid);
+                (int)r.n64, bid);
 }
 
 __global__ void kf_eval(const FRec *recs, const int *map)
@@ -2068,6 +2130,20 @@ hipError_t launch_p2m(const DevGeom &g, int nd, const int *list, int n, int Pmax
     }
     QBX_LAUNCH_CHECK();
     return hipSuccess;
+}
+
+// Compute units of the current device (cached per device).
+static int device_cu_count()
+{
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
 }
 
 hipError_t launch_m2m_mfma(const DevGeom &g, int nd, int l, const TTile *tiles, int ntiles,
@@ -2172,25 +2248,40 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
     return hipSuccess;
 }
 
+// Workgroups per CU of the near-field launch when it runs beside the other
+// stream.  At 228 VGPRs a lane two of its waves fill a SIMD's registers; with
+// one workgroup per item the near field takes every CU, and the latency-bound
+// M2M levels of the other stream wait for it to drain before their workgroups
+// get one.  Two workgroups per CU (one wave per SIMD) leave room for them.
+// Measured on the 32768-node star: 0.470 ms a step against 0.487-0.490 with
+// one workgroup per item (1: 0.522, 3: 0.495, 4: 0.486).  Alone on the
+// device (in order) the launch takes one workgroup per item.
+#ifndef P2Q_WG_PER_CU
+#define P2Q_WG_PER_CU 2
+#endif
+
+
 template <int PB>
 static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
-                                  const cd *qd, cd *coef, hipStream_t s)
+                                  const cd *qd, cd *coef, bool beside, hipStream_t s)
 {
-    k_p2qbxl<PB><<<n, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, items, qs, qd, coef);
+    int grid = n;
+    if (beside && P2Q_WG_PER_CU > 0) grid = std::min(n, P2Q_WG_PER_CU * device_cu_count());
+    k_p2qbxl<PB><<<grid, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, n, items, qs, qd, coef);
     return hipGetLastError();
 }
 
 hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
-                         const cd *qd, cd *coef, hipStream_t s)
+                         const cd *qd, cd *coef, bool beside, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, items, n, qs, qd, coef, s);
-    if (g.p <= 12) return p2qbxl_dispatch<12>(g, nd, items, n, qs, qd, coef, s);
-    if (g.p <= 14) return p2qbxl_dispatch<14>(g, nd, items, n, qs, qd, coef, s);
-    if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, items, n, qs, qd, coef, s);
-    if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, items, n, qs, qd, coef, s);
-    if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, items, n, qs, qd, coef, s);
-    return p2qbxl_dispatch<40>(g, nd, items, n, qs, qd, coef, s);
+    if (g.p <= 8) return p2qbxl_dispatch<8>(g, nd, items, n, qs, qd, coef, beside, s);
+    if (g.p <= 12) return p2qbxl_dispatch<12>(g, nd, items, n, qs, qd, coef, beside, s);
+    if (g.p <= 14) return p2qbxl_dispatch<14>(g, nd, items, n, qs, qd, coef, beside, s);
+    if (g.p <= 16) return p2qbxl_dispatch<16>(g, nd, items, n, qs, qd, coef, beside, s);
+    if (g.p <= 24) return p2qbxl_dispatch<24>(g, nd, items, n, qs, qd, coef, beside, s);
+    if (g.p <= 32) return p2qbxl_dispatch<32>(g, nd, items, n, qs, qd, coef, beside, s);
+    return p2qbxl_dispatch<40>(g, nd, items, n, qs, qd, coef, beside, s);
 }
 
 // Centres per wave of the direct sum: one when there are few centres (the
@@ -2255,15 +2346,14 @@ hipError_t launch_ctr_rad(const DevGeom &g, int nleaf, double *crad, int crad_ro
     return hipSuccess;
 }
 
-hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
-                         int crad_rows, const cd *loc, cd *coef, hipStream_t s)
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *items, int n, int Pmax, double *crad,
+                         int crad_rows, int cap, const cd *loc, cd *coef, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    if (Pmax + g.p + QBLK > crad_rows) return hipErrorInvalidValue;
-    int cg = pick_cg(l2qbxl_lds_bytes, nd, Pmax, g.p);
-    size_t lds = l2qbxl_lds_bytes(nd, Pmax, g.p, cg);
+    if (Pmax + g.p + QBLK > crad_rows || cap < 1 || cap > L2Q_CAP_MAX) return hipErrorInvalidValue;
+    size_t lds = l2qbxl_lds_bytes(Pmax, cap, crad_rows);
     if (lds > LDS_BUDGET) return hipErrorInvalidValue;
-    k_l2qbxl<<<n, L2Q_THREADS, lds, s>>>(g, nd, list, crad, loc, coef, cg);
+    k_l2qbxl<<<n, L2Q_THREADS, lds, s>>>(g, nd, items, crad, loc, coef, cap, crad_rows);
     QBX_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -2300,7 +2390,7 @@ hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hi
 //   FILL           out0 = array, n64 = elements                      [n = elements]
 //   CHARGES        in0 = sigma_S, in1 = sigma_D, out0 = qS, out1 = qD
 //   SRC_RAD        i0 = rows, out0 = J table                         [n = P2M leaves]
-//   CTR_RAD        i0 = rows, out0 = J table                         [n = L2QBXL leaves]
+//   CTR_RAD        i0 = rows, out0 = J table                         [n = L2QBXL items]
 //   P2M            in0 = leaf list, in1 = qS, in2 = qD, in3 = J table, out0 = multipoles  [n, P]
 //   M2M            i0 = level, in0 = its tiles, in1 = parent list, out0 = multipoles   [n = tiles, aux = row blocks]
 //   M2L            in0 = tiles, in1 = multipoles, out0 = pair rows  [n = tiles, P, aux = waves per tile]
@@ -2312,7 +2402,7 @@ hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hi
 //   M2QBXL         in0 = pairs, in1 = pair row offsets, in2 = multipoles, out0 = pair rows  [n = pairs, P = largest W order]
 //   WSUM           in0 = leaf list, in1 = per-leaf first pair, in2 = pair row offsets, in3 = pair rows,
 //                  out0 = coefficients                               [n = leaves]
-//   L2QBXL         in0 = leaf list, in1 = J table, in2 = locals, out0 = coefficients  [n, P, aux = J table rows]
+//   L2QBXL         i0 = item capacity, in0 = items, in1 = J table, in2 = locals, out0 = coefficients  [n, P, aux = J table rows]
 //   EVAL           in0 = coefficients, out0 = u
 //   SMOOTH         in0 = qS, in1 = qD, out0 = u
 // Per geometry, pass sizes, centre groups and tile shapes are those of its
@@ -2503,13 +2593,13 @@ hipError_t fused_plan(FBuf &fb, int kind, const std::vector<FItem> &items, std::
         for (const auto &it : items) add(kind, 0, it.r, it.n, it.n, 0, 256);
         break;
     case FK_L2QBXL:
+        // r.i0: the items' centre capacity; aux: the J_n table's rows
         for (const auto &it : items) {
-            if (it.P + it.h->p + QBLK > it.aux) return hipErrorInvalidValue;
-            int cg = pick_cg(l2qbxl_lds_bytes, it.r.nd, it.P, it.h->p);
-            size_t lds = l2qbxl_lds_bytes(it.r.nd, it.P, it.h->p, cg);
+            if (it.P + it.h->p + QBLK > it.aux || it.r.i0 < 1 || it.r.i0 > L2Q_CAP_MAX) return hipErrorInvalidValue;
+            size_t lds = l2qbxl_lds_bytes(it.P, it.r.i0, it.aux);
             if (lds > LDS_BUDGET) return hipErrorInvalidValue;
             FRec r = it.r;
-            r.i0 = cg;
+            r.n64 = it.aux;
             add(kind, 0, r, it.n, it.n, lds, L2Q_THREADS);
         }
         break;

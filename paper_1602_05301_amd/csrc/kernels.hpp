@@ -150,7 +150,7 @@ struct FItem {
     FRec r;
     long long n;               // work items (boxes, tiles, pairs, elements)
     int P;                     // largest expansion order involved
-    int aux;                   // row blocks (M2M, L2L), waves per tile (M2L), rows (L2QBXL check)
+    int aux;                   // row blocks (M2M, L2L), waves per tile (M2L), J_n rows (L2QBXL)
     int split = 0;             // M2L: leading tiles whose order needs the direct kernel
     int Psplit = 0;            // M2L: largest order among those tiles (P: the others)
 };
@@ -206,8 +206,10 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
 // that leaf's near-list sources qsrc_idx[q0, q1).  The lanes form
 // CG = min(c1 - c0, P2Q_THREADS / 2) centre slots of P2Q_THREADS / CG parts.
 constexpr int P2Q_THREADS = 128;
+// beside: the launch runs concurrently with the other stream's chain (its
+// grid is then capped so that the chain's launches find room on every CU)
 hipError_t launch_p2qbxl(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
-                         const cd *qd, cd *coef, hipStream_t s);
+                         const cd *qd, cd *coef, bool beside, hipStream_t s);
 hipError_t launch_p2qbxl_direct(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *coef,
                                 hipStream_t s);
 hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long long *pair_off,
@@ -215,8 +217,15 @@ hipError_t launch_m2qbxl(const DevGeom &g, int nd, const int2 *pairs, const long
                          const int *leaf_pair_start, int nleaf, cd *coef, hipStream_t s);
 // J_n sequences of the L2QBXL centres (leaves of level >= 2), into crad
 hipError_t launch_ctr_rad(const DevGeom &g, int nleaf, double *crad, int crad_rows, hipStream_t s);
-hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *list, int n, int Pmax, double *crad,
-                         int crad_rows, const cd *loc, cd *coef, hipStream_t s);
+// L2QBXL work items: L2Q_SEGS runs {c0, c1} of consecutive centres, each run
+// inside one leaf of level >= 2 (c0 == c1: unused), at most `cap` centres in
+// all.  l2qbxl_item_cap gives the largest cap (<= L2Q_CAP_MAX) whose staging
+// fits the LDS budget for leaves of order up to Pmax and J_n rows of `rows`.
+constexpr int L2Q_SEGS = 4;
+constexpr int L2Q_CAP_MAX = 16;
+int l2qbxl_item_cap(int Pmax, int rows);
+hipError_t launch_l2qbxl(const DevGeom &g, int nd, const int *items, int n, int Pmax, double *crad,
+                         int crad_rows, int cap, const cd *loc, cd *coef, hipStream_t s);
 hipError_t launch_qbx_eval(const DevGeom &g, int nd, const cd *coef, cd *u, hipStream_t s);
 hipError_t launch_smooth(const DevGeom &g, int nd, const cd *qs, const cd *qd, cd *u, hipStream_t s);
 hipError_t launch_coef_out(const DevGeom &g, int nd, const cd *coef, cd *out, hipStream_t s);
