@@ -1684,14 +1684,6 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
             const cd *G = Gb + go[r] + P;
             cd u = U[t];
             int ci = rc0[r] + t - so[r];
-#ifdef L2Q_PREFETCH
-            // the coefficients this lane adds to, loaded ahead of the sums
-            cd old[QBLK];
-#pragma unroll
-            for (int e = 0; e < QBLK; ++e)
-                old[e] = (active && sp == 0 && l0 + e <= p) ? coef[((long long)d * nq + l0 + e + p) * g.nc + ci]
-                                                            : mk(0.0, 0.0);
-#endif
             if (active) {
                 int na, nb;
                 chunk_of(l0 - P, l0 + QBLK - 1 + P, sp, &na, &nb);
@@ -1740,11 +1732,7 @@ __device__ __forceinline__ void l2qbxl_body(const DevGeom &g, int nd, const int 
                     int ell = l0 + e;
                     if (ell <= p) {
                         cd *o = coef + ((long long)d * nq + ell + p) * g.nc + ci;
-#ifdef L2Q_PREFETCH
-                        *o = old[e] + ul * acc[e];
-#else
                         *o = *o + ul * acc[e];
-#endif
                     }
                     ul = ul * u;
                 }
