@@ -218,7 +218,11 @@ def leg_batched(ctx, eps, rounds=3, n_geom=256, n_dens=4, check_geoms=8, check_t
         pick = np.sort(rng.choice(g.n, check_targets, replace=False))
         rel, mx = _oracle_rel(g, w, p, dens[i], dens[i], ub[i].cpu().numpy()[:, pick], pick)
         worst = [max(worst[0], rel), max(worst[1], mx)]
-    flops = sum(sum(geo.work(n_dens).values()) for geo in geos)
+    stage_flops = {}
+    for geo in geos:
+        for k, v in geo.work(n_dens).items():
+            stage_flops[k] = stage_flops.get(k, 0.0) + v
+    flops = sum(stage_flops.values())
     nodes = np.array([g.n for g, _ in curves])
     return {"workload": f"{n_geom} star/ellipse curves, {int(nodes.min())}-{int(nodes.max())} nodes "
                         f"({int(nodes.sum())} in all), omega U[5,150], {n_dens} densities each",
@@ -226,6 +230,7 @@ def leg_batched(ctx, eps, rounds=3, n_geom=256, n_dens=4, check_geoms=8, check_t
             "batched_ms": bat * 1e3, "one_by_one_ms": seq * 1e3,
             "value": work / bat, "one_by_one_value": work / seq, "unit": "targets*densities/s",
             "algorithmic_tflops": flops / bat / 1e12,
+            "algorithmic_gflop_per_batch": {k: v / 1e9 for k, v in stage_flops.items() if v > 0},
             "batched_equals_alone": bool(same),
             "rel_err_vs_oracle_sampled": worst[0], "max_err_vs_oracle_sampled": worst[1],
             "sample": f"{check_geoms} geometries x {check_targets} targets x {n_dens} densities"}
