@@ -310,7 +310,20 @@ __global__ void __launch_bounds__(64) k_p2m(DevGeom g, const int *list, const cd
 // (rb * NK + kb) * 64.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int TB_U = 2;      // k-blocks whose table operands are loaded ahead
+#ifndef QBX_TB_U
+#define QBX_TB_U 2
+#endif
+constexpr int TB_U = QBX_TB_U;   // k-blocks whose table operands are loaded ahead
+
+// Keeps the loads issued above it ahead of the matrix-core work below it:
+// left alone, the scheduler sinks the next k-blocks' loads below the wait
+// for the current ones, and the loop then waits on a full memory round trip
+// every step.
+#ifdef QBX_NO_FENCE
+#define QBX_LOADS_AHEAD() ((void)0)
+#else
+#define QBX_LOADS_AHEAD() __builtin_amdgcn_sched_barrier(0)
+#endif
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8).
 // Map them so that XCD x works through its own contiguous range of tiles:
@@ -443,8 +456,10 @@ __device__ __forceinline__ void trans_block(const cd *Arow, int kb0, int kb1, co
     tb_load(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
         tb_load(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        QBX_LOADS_AHEAD();
         tb_mfma<ROT>(a0, b0, y, e);
         tb_load(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        QBX_LOADS_AHEAD();
         if (kb + TB_U < kb1) tb_mfma<ROT>(a1, b1, y, e);
     }
     cplx3_done(y, yr, yi);
@@ -495,6 +510,7 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
         for (int kb = 0; kb < NK; kb += 2 * TB_U) {
 #pragma unroll
             for (int u = 0; u < TB_U; ++u) a1[u] = Ab[min(kb + TB_U + u, NK - 1) * 64];
+            QBX_LOADS_AHEAD();
 #pragma unroll
             for (int u = 0; u < TB_U; ++u) {
                 int kk = kb + u;
@@ -504,6 +520,7 @@ __device__ __forceinline__ void m2l_mfma_body(const DevGeom &g, int nd, const M2
             }
 #pragma unroll
             for (int u = 0; u < TB_U; ++u) a0[u] = Ab[min(kb + 2 * TB_U + u, NK - 1) * 64];
+            QBX_LOADS_AHEAD();
             if (kb + TB_U < NK) {
 #pragma unroll
                 for (int u = 0; u < TB_U; ++u) {
@@ -632,8 +649,10 @@ __device__ __forceinline__ void trans_block32(const cf *Arow, int kb0, int kb1, 
     tb_load32(Arow, kb0, kb1, bs, bvalid, nin, lane, a0, b0);
     for (int kb = kb0; kb < kb1; kb += 2 * TB_U) {
         tb_load32(Arow, kb + TB_U, kb1, bs, bvalid, nin, lane, a1, b1);
+        QBX_LOADS_AHEAD();
         tb_mfma32<ROT>(a0, b0, y, e);
         tb_load32(Arow, kb + 2 * TB_U, kb1, bs, bvalid, nin, lane, a0, b0);
+        QBX_LOADS_AHEAD();
         if (kb + TB_U < kb1) tb_mfma32<ROT>(a1, b1, y, e);
     }
 #pragma unroll
