@@ -611,12 +611,26 @@ qbx_status upload(qbx_geom_s *G)
             for (int c = pl.child_begin[b]; c >= 0 && c < pl.child_begin[b] + pl.child_count[b]; ++c)
                 child4[(size_t)b * 4 + ((pl.bix[c] & 1) | ((pl.biy[c] & 1) << 1))] = c;
         g.child4 = ar.upload(child4);
+        // Parents of each level ordered by which of their four children
+        // exist, so that most M2M tiles hold parents with the same children:
+        // the waves of a child quadrant missing from a whole tile then skip
+        // their product instead of multiplying zeros.  Each parent's sum is
+        // the same whichever tile it lands in.
+        auto cmask = [&](int b) {
+            int m = 0;
+            for (int c = pl.child_begin[b]; c < pl.child_begin[b] + pl.child_count[b]; ++c)
+                m |= 1 << ((pl.bix[c] & 1) | ((pl.biy[c] & 1) << 1));
+            return m;
+        };
         G->par_list.clear();
         G->par_lvl.assign(pl.nlev + 1, 0);
         for (int l = 0; l < pl.nlev; ++l) {
-            G->par_lvl[l] = (int)G->par_list.size();
+            size_t s0 = G->par_list.size();
+            G->par_lvl[l] = (int)s0;
             for (int b = pl.level_start[l]; b < pl.level_start[l + 1]; ++b)
                 if (!pl.leaf[b] && l >= 2) G->par_list.push_back(b);
+            std::stable_sort(G->par_list.begin() + s0, G->par_list.end(),
+                             [&](int a, int c) { return cmask(a) < cmask(c); });
         }
         G->par_lvl[pl.nlev] = (int)G->par_list.size();
         G->chl_list.clear();

@@ -2266,14 +2266,21 @@ hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pm
 #ifndef P2Q_WG_PER_CU
 #define P2Q_WG_PER_CU 2
 #endif
+// The cap pays only while the near field is short next to the other
+// stream's chain (the 32768-node star: 3454 items, 13.5 per CU).  With many
+// items per CU, as on the 606k-node multiscale set with leaves of 64, the
+// near field is the longer stream, and capped it becomes the critical path.
+#ifndef P2Q_CAP_ITEMS_PER_CU
+#define P2Q_CAP_ITEMS_PER_CU 16
+#endif
 
 
 template <int PB>
 static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
                                   const cd *qd, cd *coef, bool beside, hipStream_t s)
 {
-    int grid = n;
-    if (beside && P2Q_WG_PER_CU > 0) grid = std::min(n, P2Q_WG_PER_CU * device_cu_count());
+    int grid = n, cus = device_cu_count();
+    if (beside && P2Q_WG_PER_CU > 0 && n <= P2Q_CAP_ITEMS_PER_CU * cus) grid = std::min(n, P2Q_WG_PER_CU * cus);
     k_p2qbxl<PB><<<grid, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, n, items, qs, qd, coef);
     return hipGetLastError();
 }
