@@ -720,9 +720,12 @@ __device__ __forceinline__ cd tb_sum(const double (*part)[64][9], int nw, int r,
 
 // Stage 2b: M2M into the non-leaf boxes of level l.  Block = (tile of 16
 // (parent, density) columns, row block); wave w applies the child-quadrant
-// (w % 4) matrix over half (w / 4) of its k-blocks; the eight partial blocks
-// are summed in wave order.
-constexpr int M2M_KS = 2;
+// (w % 4) matrix over part w / 4 of its k-blocks (M2M_KS parts); the partial
+// blocks are summed in wave order.  One part (four waves, 18 KiB of LDS) lets
+// the workgroups of a level find room beside the near field on the other
+// stream: the step 0.452 to 0.446 ms, though each level alone is slower than
+// with two parts (M2M in order 101 against 105 us).
+constexpr int M2M_KS = 1;
 
 __device__ __forceinline__ void m2m_mfma_body(const DevGeom &g, int nd, int l, const TTile *tiles, const int *plist, cd *mp, BlockId bid)
 {
