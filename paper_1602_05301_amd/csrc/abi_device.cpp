@@ -1110,7 +1110,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
                 CHK(launch_x_bas(g, G->n_xpos, G->xbas, s1));
             }
             CHK(launch_fill_zero(B.loc, (long long)nd * G->total_coef, s1));
-            CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, s1));
+            CHK(launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, true, s1));
             if (G->n_wpairs > 0) CHK(hipEventRecord(C->ev_x, s1));
             CHK(launch_p2qbxl(g, nd, G->qbx.d, G->qbx.n, B.qs, B.qd, B.coef, true, s1));
             // Without M2QBXL work one event marks the end of the side stream
@@ -1152,7 +1152,7 @@ qbx_status run_pipeline(qbx_geom_s *G, int nd, const cd *ss, const cd *sd, cd *u
         } else {
             STAGE(QBX_STAGE_P2L_X);
             if (!G->rad_ready) LAUNCH(QBX_STAGE_P2L_X, G->n_xpos, launch_x_bas(g, G->n_xpos, G->xbas, st));
-            LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, st));
+            LAUNCH(QBX_STAGE_P2L_X, G->xl.n, launch_p2l_x(g, nd, G->xl.d, G->xl.n, G->xl.Pmax, B.qs, B.qd, B.loc, false, st));
         }
         {
             // V-list sums in list order for every level at once, then L2L

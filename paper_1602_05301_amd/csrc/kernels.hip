@@ -1131,6 +1131,19 @@ __global__ void __launch_bounds__(64) k_p2l_xc(DevGeom g, const int *list, const
     p2l_xc_body<ND>(g, list, qs, qd, loc, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
 }
 
+// The capped form beside the other stream: the grid walks the boxes back and
+// forth, as the near field does.  (Its loop keeps more registers live, 96
+// against 64 VGPRs, so launches that are not capped take the plain form.)
+template <int ND>
+__global__ void __launch_bounds__(64) k_p2l_xc_capped(DevGeom g, int n, const int *list, const cd *qs, const cd *qd, cd *loc)
+{
+    int G = gridDim.x;
+    for (int r = 0; r * G < n; ++r) {
+        int b = r * G + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (b < n) p2l_xc_body<ND>(g, list, qs, qd, loc, BlockId{b, (int)blockIdx.y, n});
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stage 3: P2QBXL.  alpha_l(c) += qS O_l(s-c) + qD (w/2)(nu O_{l-1} - conj(nu) O_{l+1}).
 // With z = s - c = (x/omega) u, |u| = 1, O_{+-m} = (+-1)^m H_m u^{+-m} and the
@@ -1300,12 +1313,20 @@ __device__ __forceinline__ void p2qbxl_body(const DevGeom &g, int nd, const int 
     }
 }
 
+template <int PB>
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, const int *items, const cd *qs, const cd *qd, cd *coef)
+{
+    p2qbxl_body<PB>(g, nd, items, qs, qd, coef, BlockId{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x});
+}
+
 // A capped grid: workgroup b takes items b, 2G-1-b, 2G+b, ... (G = gridDim.x),
 // back and forth over the list, which the host sorts by decreasing work, so
 // the workgroups' totals stay close.  Each item's body begins and ends its LDS
-// use behind barriers, so items follow each other in a workgroup safely.
+// use behind barriers, so items follow each other in a workgroup safely.  (The
+// loop costs registers, 231 against 228 VGPRs with a little scratch, so
+// launches that are not capped take the plain form.)
 template <int PB>
-__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl(DevGeom g, int nd, int n_items, const int *items, const cd *qs, const cd *qd, cd *coef)
+__global__ void __launch_bounds__(P2Q_THREADS) k_p2qbxl_capped(DevGeom g, int nd, int n_items, const int *items, const cd *qs, const cd *qd, cd *coef)
 {
     int G = gridDim.x;
     for (int r = 0; r * G < n_items; ++r) {
@@ -2227,15 +2248,37 @@ hipError_t launch_down_all(const DevGeom &g, int nd, int nbox, const cd *vy, cd 
     return hipSuccess;
 }
 
+// The X-list P2L beside the other stream, like the near field after it, is
+// capped so that the first M2M levels and P2M find room: 4 waves per CU (one
+// per SIMD), while the launch has at most 32 waves per CU (the star: 2466
+// boxes x 2 runs of orders, 19 per CU).  Step 0.446 to 0.440 ms; 2 waves per
+// CU: 0.475 ms.
+#ifndef XC_WAVES_PER_CU
+#define XC_WAVES_PER_CU 4
+#endif
+constexpr int XC_CAP_WAVES_PER_CU = 32;
+
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                        const cd *qd, cd *loc, hipStream_t s)
+                        const cd *qd, cd *loc, bool beside, hipStream_t s)
 {
     if (!n) return hipSuccess;
     if (nd < 1 || nd > 4) return hipErrorInvalidValue;
     if (g.xbas) {
         // rows kept with the geometry (launch_x_bas)
-        dim3 grid(n, order_runs(Pmax));
+        int runs = order_runs(Pmax), cus = device_cu_count();
         size_t lds = p2l_xc_lds_bytes(nd);
+        if (beside && XC_WAVES_PER_CU > 0 && (long long)n * runs <= (long long)XC_CAP_WAVES_PER_CU * cus) {
+            dim3 grid(std::min(n, std::max(1, XC_WAVES_PER_CU * cus / runs)), runs);
+            switch (nd) {
+            case 1: k_p2l_xc_capped<1><<<grid, 64, lds, s>>>(g, n, list, qs, qd, loc); break;
+            case 2: k_p2l_xc_capped<2><<<grid, 64, lds, s>>>(g, n, list, qs, qd, loc); break;
+            case 3: k_p2l_xc_capped<3><<<grid, 64, lds, s>>>(g, n, list, qs, qd, loc); break;
+            default: k_p2l_xc_capped<4><<<grid, 64, lds, s>>>(g, n, list, qs, qd, loc); break;
+            }
+            QBX_LAUNCH_CHECK();
+            return hipSuccess;
+        }
+        dim3 grid(n, runs);
         switch (nd) {
         case 1: k_p2l_xc<1><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
         case 2: k_p2l_xc<2><<<grid, 64, lds, s>>>(g, list, qs, qd, loc); break;
@@ -2282,9 +2325,12 @@ template <int PB>
 static hipError_t p2qbxl_dispatch(const DevGeom &g, int nd, const int *items, int n, const cd *qs,
                                   const cd *qd, cd *coef, bool beside, hipStream_t s)
 {
-    int grid = n, cus = device_cu_count();
-    if (beside && P2Q_WG_PER_CU > 0 && n <= P2Q_CAP_ITEMS_PER_CU * cus) grid = std::min(n, P2Q_WG_PER_CU * cus);
-    k_p2qbxl<PB><<<grid, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, n, items, qs, qd, coef);
+    int cus = device_cu_count();
+    if (beside && P2Q_WG_PER_CU > 0 && n <= P2Q_CAP_ITEMS_PER_CU * cus)
+        k_p2qbxl_capped<PB><<<std::min(n, P2Q_WG_PER_CU * cus), P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(
+            g, nd, n, items, qs, qd, coef);
+    else
+        k_p2qbxl<PB><<<n, P2Q_THREADS, p2qbxl_lds_bytes(), s>>>(g, nd, items, qs, qd, coef);
     return hipGetLastError();
 }
 

@@ -200,7 +200,7 @@ int m2l_staged_pmax();
 // then leaves them out of its epilogue.
 hipError_t launch_down_all(const DevGeom &g, int nd, int nbox, const cd *vy, cd *loc, hipStream_t s);
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
-                        const cd *qd, cd *loc, hipStream_t s);
+                        const cd *qd, cd *loc, bool beside, hipStream_t s);
 // P2QBXL: one workgroup of P2Q_THREADS lanes per work item.  An item is
 // four ints {c0, c1, q0, q1}: centres [c0, c1) of one leaf (sorted order) and
 // that leaf's near-list sources qsrc_idx[q0, q1).  The lanes form
