@@ -199,6 +199,9 @@ int m2l_staged_pmax();
 // >= 2) in one launch, nd (1-4) densities; launch_l2l_mfma with vy = null
 // then leaves them out of its epilogue.
 hipError_t launch_down_all(const DevGeom &g, int nd, int nbox, const cd *vy, cd *loc, hipStream_t s);
+// X-list P2L into the locals of the listed boxes.  beside: the launch runs
+// concurrently with the other stream's chain (a short launch is then capped
+// so that the chain's launches find room on every CU).
 hipError_t launch_p2l_x(const DevGeom &g, int nd, const int *list, int n, int Pmax, const cd *qs,
                         const cd *qd, cd *loc, bool beside, hipStream_t s);
 // P2QBXL: one workgroup of P2Q_THREADS lanes per work item.  An item is
