@@ -2282,9 +2282,9 @@ qbx_status qbx_geom_autotune(qbx_geom G, int32_t n_dens, int32_t *choice_out)
     bool prof = G->profile, graph = G->graph_on;
     G->profile = false;
     G->graph_on = false;
-    // rounds over the candidates in turn (drift of clocks and caches hits
+    // passes over the candidates in turn (drift of clocks and caches hits
     // them alike); a sample is kEvals evaluations back to back and each
-    // candidate keeps its fastest sample; round 0 warms up.  Another
+    // candidate keeps its fastest sample; the first pass warms up.  Another
     // candidate replaces the default only when it is kMargin faster: the
     // candidates differ by a few per cent of an evaluation at most, about
     // the spread of single samples.
