@@ -310,9 +310,9 @@ qbx_status qbx_geom_profile(qbx_geom geom, int32_t enable);
 qbx_status qbx_eval_batch(qbx_ctx ctx, int32_t n_geom, const qbx_geom *geoms, const int32_t *n_dens,
                           const void *const *sigma_s, const void *const *sigma_d, void *const *u);
 /* qbx_geom_autotune: pick the M2L kernel configuration that makes this
- * geometry's evaluation fastest.  The candidates take turns over 9 rounds,
+ * geometry's evaluation fastest.  The candidates take turns over 9 passes,
  * each a sample of 4 whole evaluations with n_dens zero densities (HIP
- * events on the context's stream; the first round warms up; temporary device
+ * events on the context's stream; the first pass warms up; temporary device
  * buffers; synchronises the stream), and each keeps its fastest sample.
  * Candidates: columns staged in LDS with w waves per tile, w the row-block
  * count of most V pairs (the default) or about half of it, and the
